@@ -1,0 +1,251 @@
+"""Synthetic FMO-like exciton-vibration chains (Frenkel-Holstein model).
+
+The paper's model (Sec. II.C, eq:holstein) is a 7-site FMO complex whose site
+energies, couplings and discretised spectral density come from the
+literature.  Those numbers are not available here, so every parameter is
+drawn from fixed distributions with a seeded PCG64 generator, in a fixed
+draw order:
+
+1. site energies  E[n_e]              ~ U(12200, 12600) cm^-1
+2. |J| for i<j in row-major order     ~ U(5, 100) cm^-1
+3. the sign of each J (same order)    equiprobable +-1
+4. mode frequencies omega[n_e, nm]    ~ U(100, 1600) cm^-1
+5. Huang-Rhys factors S[n_e, nm]      ~ U(0.01, 0.1)   (g = sqrt(S))
+
+Chain ordering (Sec. II.C): electronic sites in the order odd-descending
+then even-ascending (for 7 sites: 7,5,3,1,2,4,6), each followed directly by
+its own vibrational modes.  Electronic sites have local dimension 2
+(|0> empty, |1> one exciton); a mode truncated to ``levels`` has the number
+basis |0>..|levels-1>.
+
+Nothing here evolves a state; :func:`initial_mps_raw` only places numbers
+into tensors.  Canonicalisation and normalisation are left to the consumer.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+
+@dataclass
+class ChainParams:
+    n_e: int
+    n_modes: int
+    levels: int
+    E: np.ndarray          # (n_e,) cm^-1
+    J: np.ndarray          # (n_e, n_e) cm^-1, symmetric, zero diagonal
+    omega: np.ndarray      # (n_e, n_modes) cm^-1
+    S: np.ndarray          # (n_e, n_modes) Huang-Rhys factors
+    seed: int = 0
+    realisation: Optional[int] = None
+    extra: dict = field(default_factory=dict)
+
+
+def draw_params(n_e: int, n_modes: int, levels: int, seed: int = 0,
+                realisation: Optional[int] = None,
+                disorder_sigma: float = 100.0,
+                coupling: bool = True) -> ChainParams:
+    """Draw model parameters in the fixed order stated in the module doc.
+
+    ``realisation`` r >= 0 adds static disorder E_m += N(0, sigma) drawn from
+    ``default_rng([seed, r])``.  ``coupling=False`` zeroes the Huang-Rhys
+    factors after drawing them (the g = 0 limit), keeping the other draws
+    identical.
+    """
+    rng = np.random.default_rng(seed)
+    E = rng.uniform(12200.0, 12600.0, size=n_e)
+    npair = n_e * (n_e - 1) // 2
+    mag = rng.uniform(5.0, 100.0, size=npair)
+    sign = np.where(rng.integers(0, 2, size=npair) == 0, -1.0, 1.0)
+    J = np.zeros((n_e, n_e))
+    k = 0
+    for i in range(n_e):
+        for j in range(i + 1, n_e):
+            J[i, j] = J[j, i] = sign[k] * mag[k]
+            k += 1
+    omega = rng.uniform(100.0, 1600.0, size=(n_e, n_modes))
+    S = rng.uniform(0.01, 0.1, size=(n_e, n_modes))
+    if not coupling:
+        S = np.zeros_like(S)
+    if realisation is not None:
+        rr = np.random.default_rng([seed, realisation])
+        E = E + rr.normal(0.0, disorder_sigma, size=n_e)
+    return ChainParams(n_e, n_modes, levels, E, J, omega, S, seed, realisation)
+
+
+def electronic_order(n_e: int) -> List[int]:
+    """0-based electronic site indices in chain order (odd desc, even asc, 1-based)."""
+    odd = [m for m in range(n_e, 0, -1) if m % 2 == 1]
+    even = [m for m in range(1, n_e + 1) if m % 2 == 0]
+    return [m - 1 for m in odd + even]
+
+
+def chain_sites(p: ChainParams):
+    """List of chain sites as tuples ('el', m, None, 2) or ('vib', m, lam, levels)."""
+    sites = []
+    for m in electronic_order(p.n_e):
+        sites.append(("el", m, None, 2))
+        for lam in range(p.n_modes):
+            sites.append(("vib", m, lam, p.levels))
+    return sites
+
+
+def bond_dims(phys: List[int], M: int) -> List[int]:
+    """Bond dims M_b = min(M, prod(d[:b]), prod(d[b:])), M_0 = M_N = 1."""
+    n = len(phys)
+    out = [1]
+    for b in range(1, n):
+        left = 1
+        for d in phys[:b]:
+            left = min(left * d, M)
+        right = 1
+        for d in phys[b:]:
+            right = min(right * d, M)
+        out.append(min(M, left, right))
+    out.append(1)
+    return out
+
+
+def _sector_counts(sites, b):
+    """(#el sites, product of vib dims) on each side of bond b, dims capped."""
+    cap = 1 << 40
+    nel_l = sum(1 for s in sites[:b] if s[0] == "el")
+    nel_r = sum(1 for s in sites[b:] if s[0] == "el")
+    vl = 1
+    for s in sites[:b]:
+        if s[0] == "vib":
+            vl = min(vl * s[3], cap)
+    vr = 1
+    for s in sites[b:]:
+        if s[0] == "vib":
+            vr = min(vr * s[3], cap)
+    # left states with q excitons (q in {0,1}); right states with 1-q excitons
+    left = {0: vl, 1: nel_l * vl}
+    right = {0: vr, 1: nel_r * vr}
+    return left, right
+
+
+def initial_mps_raw(p: ChainParams, M: int, eta: float = 0.0,
+                    phi_seed: int = 1, exciton_site: int = 0):
+    """Raw initial MPS tensors (M_b, d, M_{b+1}) complex128, not canonical.
+
+    eta == 0: the Hartree product state (exciton on electronic site
+    ``exciton_site``, every mode in |0>), zero-padded to the bond dims.
+
+    eta > 0: bond index 0 of every bond carries the product state and the
+    other indices a seeded random block.  In site tensor i:
+      A[0, s, 0]    = product state (1 on the occupied level)
+      A[0, s, k>0]  = eta * G_in     (leave the product channel)
+      A[j>0, s, k>0] = G_blk         (random block, O(1) entries)
+      A[j>0, s, 0]  = eta * G_out    (return; O(1) on the last site)
+    so the state is the product state plus a random part of weight ~eta that
+    fills every bond index with Schmidt values far above round-off (the
+    bases are then fixed by the state, not by how a QR completes a
+    rank-deficient matrix).  All random entries are graded by exciton number:
+    every bond index carries a label q in {0,1} (excitons to its left; index
+    0 carries the product state's label) and an entry is nonzero only when
+    the labels match the local exciton number, so the state lies in the
+    one-exciton sector.  Random entries on vibrational level k are scaled by
+    0.7^k so that highly excited modes carry less weight.
+    """
+    sites = chain_sites(p)
+    phys = [s[3] for s in sites]
+    n = len(sites)
+    dims = bond_dims(phys, M)
+
+    def occ(s):  # product-state local level
+        return 1 if (s[0] == "el" and s[1] == exciton_site) else 0
+
+    prod = []
+    for i, s in enumerate(sites):
+        A = np.zeros((dims[i], phys[i], dims[i + 1]), dtype=np.complex128)
+        A[0, occ(s), 0] = 1.0
+        prod.append(A)
+    if eta == 0.0:
+        return prod
+
+    # exciton-number labels of every bond index
+    prod_q = [0] * (n + 1)
+    q = 0
+    for i, s in enumerate(sites):
+        q += occ(s)
+        prod_q[i + 1] = q
+    labels = [[0]]
+    for b in range(1, n):
+        m = dims[b]
+        left, right = _sector_counts(sites, b)
+        cap = {qq: min(left[qq], right[1 - qq]) for qq in (0, 1)}
+        n0 = min(cap[0], m // 2)
+        n1 = min(cap[1], m - n0)
+        if n0 + n1 < m:
+            n0 = min(cap[0], m - n1)
+        if n0 + n1 < m or (n0 if prod_q[b] == 0 else n1) < 1:
+            raise ValueError(f"bond {b}: one-exciton sector too small for M={M}")
+        lab = [prod_q[b]]
+        lab += [0] * (n0 - (prod_q[b] == 0)) + [1] * (n1 - (prod_q[b] == 1))
+        labels.append(lab)
+    labels.append([1])
+
+    rng = np.random.default_rng(phi_seed)
+    out = []
+    for i, s in enumerate(sites):
+        d = phys[i]
+        lq = np.asarray(labels[i])
+        rq = np.asarray(labels[i + 1])
+        shape = (len(lq), d, len(rq))
+        re = rng.standard_normal(shape)
+        im = rng.standard_normal(shape)
+        G = (re + 1j * im) / np.sqrt(2.0)
+        if s[0] == "el":
+            nloc = np.arange(d)
+            lvl = np.ones(d)
+        else:
+            nloc = np.zeros(d, dtype=int)
+            lvl = 0.7 ** np.arange(d)
+        mask = lq[:, None, None] + nloc[None, :, None] == rq[None, None, :]
+        # expected squared norm of every row (j, :, :) is 1
+        w2 = (mask * (lvl ** 2)[None, :, None]).sum(axis=(1, 2))
+        G = np.where(mask, G, 0.0) * lvl[None, :, None] / np.sqrt(np.maximum(w2, 1e-300))[:, None, None]
+        A = prod[i].copy()
+        A[0, :, 1:] = eta * G[0, :, 1:]
+        A[1:, :, 1:] = G[1:, :, 1:]
+        A[1:, :, 0] = G[1:, :, 0] * (1.0 if i == n - 1 else eta)
+        out.append(A)
+    return out
+
+
+# Named workloads, by the model and run sizes they stand for.
+WORKLOADS = {
+    # 3 electronic sites x 1 mode x 4 levels, full bond dimension, exact product state
+    "fmo3x1x4_M16": dict(n_e=3, n_modes=1, levels=4, M=16, dt_fs=1.0, steps=50,
+                         seed=0, eta=0.0),
+    # 7 electronic sites x 10 modes x 8 levels, M = 32, FP64
+    "fmo7x10x8_M32": dict(n_e=7, n_modes=10, levels=8, M=32, dt_fs=2.0, steps=500,
+                          seed=0, eta=1e-2, phi_seed=1),
+    # same chain at M = 128, mixed precision, Krylov dim 20
+    "fmo7x10x8_M128": dict(n_e=7, n_modes=10, levels=8, M=128, dt_fs=2.0, steps=1000,
+                           seed=0, eta=1e-2, phi_seed=1, kdim=20),
+    # 7 electronic sites x 30 modes x 10 levels, M = 256
+    "fmo7x30x10_M256": dict(n_e=7, n_modes=30, levels=10, M=256, dt_fs=1.0, steps=200,
+                            seed=0, eta=1e-2, phi_seed=1),
+}
+
+
+def ensemble_bond(seed: int, r: int) -> int:
+    """Bond dimension of disorder realisation r, uniform over {32, 64, 96, 128}."""
+    rr = np.random.default_rng([seed, r, 1])
+    return int((32, 64, 96, 128)[rr.integers(0, 4)])
+
+
+def workload(name: str):
+    """Return (params, sites, phys, bond dims, raw initial MPS, run settings)."""
+    w = dict(WORKLOADS[name])
+    p = draw_params(w["n_e"], w["n_modes"], w["levels"], w["seed"])
+    sites = chain_sites(p)
+    phys = [s[3] for s in sites]
+    dims = bond_dims(phys, w["M"])
+    mps = initial_mps_raw(p, w["M"], w.get("eta", 0.0), w.get("phi_seed", 1))
+    return p, sites, phys, dims, mps, w

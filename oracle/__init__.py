@@ -1,0 +1,24 @@
+"""Plain, slow FP64 CPU oracle for one-site TDVP-PS (and TDVP-MU).
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product package may import, call or
+execute anything here; only the tests, the smoke check and the CPU-baseline
+leg of the benchmark do.  The oracle shares no code with the HIP path: it
+builds its own Hamiltonian, its own MPO (a different channel construction
+from the library's), and does every contraction with numpy.einsum, every QR
+with numpy.linalg.qr and every small exponential through numpy.linalg.eigh.
+
+Modules
+  model   Frenkel-Holstein Hamiltonian: dense matrix and MPO (Sec. II.C)
+  mps     canonical forms, environments, local operators, observables
+          (Sec. II.A, eq:QR, eq:tdvp1_h, eq:tdvp1_H, eq:tdvp2_D)
+  krylov  Lanczos approximation of exp(z A) x (Sec. II.A.2, TDVP-PS)
+  ps      the projector-splitting time step (eq:ps_trotter, eq:tdvp2_C/D)
+  dense   exact propagation and a dense-projector form of the PS step
+  mu      TDVP-MU with matrix-unfolding regularisation, VMF/RK45
+          (eq:tdvp1_C, eq:tdvp1_mu_L, eq:reg2)
+
+Pins: every function above is checked in tests/test_oracle_*.py against a
+closed form, a library routine on tiny inputs, brute force, or an exact
+invariant.  TDVP-MU vs TDVP-PS agreement is "parity unpinned" (the paper
+states it only qualitatively).
+"""
