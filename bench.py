@@ -1,0 +1,156 @@
+"""TDVP-PS throughput on one MI355X.
+
+A step is one full symmetric TDVP-PS time step of the whole chain (left-to-
+right and right-to-left sweeps: forward Lanczos solves, QR gauge shifts,
+environment updates, backward bond solves, centre moves) followed by the
+observables (norm, energy, populations) written to device memory; inputs
+are resident in HBM before the timed region starts.
+
+Default workload: 7 electronic sites x 10 modes x 8 levels (77 MPS sites),
+bond dim 32, dt = 2 fs, complex128, Krylov dim 20.
+Prints ONE JSON line (see the keys below).
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp64_mfma_tflops": 78.6, "fp32_mfma_tflops": 157.3, "hbm_gbs": 8000.0}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="fmo7x10x8_M32")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--kmax", type=int, default=20)
+    ap.add_argument("--tol", type=float, default=0.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=1)
+    return ap.parse_args()
+
+
+def cpu_baseline(name, nsteps):
+    """The oracle (plain numpy FP64, untuned) on a bounded sample of the same workload."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+    from inputs import workload
+    from oracle import model, mps as om, ps
+
+    p, sites, phys, dims, raw, w = workload(name)
+    Ws, _ = model.mpo(p, sites)
+    m = om.right_canonicalize(raw)
+    R = om.build_right_envs(m, Ws)
+    tau = w["dt_fs"] * model.AU_PER_FS
+    t0 = time.perf_counter()
+    for _ in range(nsteps):
+        m, R, _ = ps.ps_step(m, Ws, R, tau, kmax=20)
+        om.site_populations(m, sites, p.n_e)
+    dt = time.perf_counter() - t0
+    threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+    return {"value": nsteps / dt, "unit": "steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{nsteps} step(s) of {name} incl. populations, numpy FP64 "
+                      f"({os.cpu_count()} host CPUs visible)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the ensemble would shard realisations across GPUs, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from inputs import workload
+    from paper_1907_12044_amd import tdvp
+
+    p, sites, phys, dims, raw, w = workload(args.workload)
+    prec = tdvp.FP64 if args.precision == "fp64" else tdvp.FP32
+    run = tdvp.PsRun(p, sites, raw, device=0, precision=prec, kmax=args.kmax, tol=args.tol)
+    tau = w["dt_fs"] * tdvp.AU_PER_FS
+    nsolve = 4 * len(sites)
+    klog = torch.zeros(nsolve, dtype=torch.int32, device="cuda:0")
+    obs = torch.zeros((max(args.steps, 1), 2 + p.n_e), dtype=torch.float64, device="cuda:0")
+
+    for _ in range(args.warmup):
+        run.step(tau, 1)
+        run.observe(obs[0])
+    torch.cuda.synchronize()
+
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        run.step(tau, 1)
+        run.observe(obs[s])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / max(args.steps, 1)
+    host_obs = obs.cpu().numpy()
+
+    # one more step with a Krylov log, then one per kernel class with event timing
+    tdvp.set_krylov_log(run.ctx, klog)
+    run.step(tau, 1)
+    tdvp.set_krylov_log(run.ctx, None)
+    ks = klog.cpu().numpy()
+    ks = ks[ks > 0]
+    prof = {}
+    for name, cls in (("gemm", tdvp.PROF_GEMM), ("wapply", tdvp.PROF_WAPPLY),
+                      ("lanczos", tdvp.PROF_LANCZOS), ("qr", tdvp.PROF_QR)):
+        tdvp.profile(run.ctx, cls)
+        run.step(tau, 1)
+        ms, n, f, b = tdvp.profile_read(run.ctx)
+        tdvp.profile(run.ctx, 0)
+        prof[name] = {"ms_per_step": ms, "launches": n, "flop": f, "bytes": b}
+
+    g = prof["gemm"]
+    heff_tflops = g["flop"] / (ms_per_step * 1e-3) / 1e12
+    dom = max(prof, key=lambda k: prof[k]["ms_per_step"])
+    d = prof[dom]
+    if dom == "gemm":
+        peak = PEAK["fp64_mfma_tflops"] if prec == tdvp.FP64 else PEAK["fp32_mfma_tflops"]
+        ach = d["flop"] / (d["ms_per_step"] * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s"}
+    else:
+        ach = d["bytes"] / (d["ms_per_step"] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": ach, "peak": PEAK["hbm_gbs"], "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = dom
+    roof["avg_launch_us"] = 1e3 * d["ms_per_step"] / max(d["launches"], 1)
+
+    line = {
+        "metric": "TDVP-PS steps/s (H_eff TFLOP/s alongside)",
+        "value": 1e3 / ms_per_step,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128" if prec == tdvp.FP64 else "c64 contractions / c128 Krylov+QR",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "sites": len(sites), "bond_dim": w["M"],
+                   "mpo_bond_max": max(run.mpo.bond), "dt_fs": w["dt_fs"], "kmax": args.kmax,
+                   "tol": args.tol, "precision": args.precision},
+        "heff_tflops": heff_tflops,
+        "krylov_mean": float(ks.mean()) if ks.size else None,
+        "profile_ms_per_step": {k: round(v["ms_per_step"], 3) for k, v in prof.items()},
+        "roofline": roof,
+        "final_populations": [float(x) for x in host_obs[-1, 2:]],
+        "final_norm": float(host_obs[-1, 0]),
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_steps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,215 @@
+/*
+ * tdvp.h -- C ABI of libtdvp: one-site TDVP projector-splitting (TDVP-PS) time
+ * evolution of a matrix product state on one AMD MI355X (gfx950) GPU.
+ *
+ * Problem statement (Li, Ren, Shuai, "Numerical Assessment for Accuracy and
+ * GPU Acceleration of TD-DMRG Time Evolution Schemes"):
+ *   MPS  |psi> = sum A^{s_1} A^{s_2} ... A^{s_N}               (Sec. II.A, eq:mps)
+ *   MPO  H     = sum W^{s'_1 s_1} ... W^{s'_N s_N}             (Sec. II.A, eq:mpo)
+ *   environments h[1:i-1], h[i+1:N]                           (eq:tdvp1_h1i, eq:tdvp1_hiN, eq:tdvp1_h)
+ *   forward site equation  i dC/dt = H[i] C                   (eq:tdvp2_C, eq:tdvp1_H)
+ *   backward bond equation i dD/dt = h[1:i] h[i+1:N] D         (eq:tdvp2_D)
+ *   symmetric splitting of exp(-i P H tau)                    (eq:ps_trotter)
+ *
+ * Conventions
+ *  - Sites are numbered 0..n-1, bonds 0..n; site i sits between bonds i and
+ *    i+1.  bond[0] = bond[n] = 1 for both the MPS and the MPO.
+ *  - Complex numbers are stored interleaved (re, im).  "c128" = two doubles,
+ *    "c64" = two floats.  All arrays are row-major (last index fastest).
+ *  - MPS site tensor i: c128 (bond[i], phys[i], bond[i+1]).
+ *  - MPO site tensor i: c128 (W_i, d_out, d_in, W_{i+1}); d_out is the bra
+ *    (row) index s' of W^{s' s} in eq:mpo.
+ *  - Environment at bond b: (M_b, W_b, M_b) indexed [bra, channel, ket], bra
+ *    conjugated (eq:tdvp1_h).  left[b] contracts sites 0..b-1, right[b]
+ *    contracts sites b..n-1; left[0] = right[n] = 1.  Element type: c128 in
+ *    TDVP_FP64 mode, c64 in the mixed modes.
+ *  - Every pointer to tensor data is DEVICE memory owned by the caller; the
+ *    library never allocates, frees or keeps it beyond the call, except the
+ *    workspace passed to tdvp_set_workspace, which must stay valid while
+ *    the context uses it.  Descriptor arrays (phys, bond, site pointer
+ *    tables) are HOST memory, read during the call only.
+ *  - Every call is asynchronous on the context's HIP stream unless stated
+ *    otherwise; results are ready after the stream is synchronised.
+ *  - Errors: argument and shape errors return at once and enqueue nothing.
+ *    A failed HIP call returns TDVP_E_DEVICE.  No C++ exception crosses the
+ *    ABI.  A context is not thread safe; use one per host thread.
+ */
+#ifndef TDVP_H
+#define TDVP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TDVP_OK = 0,
+  TDVP_E_ARG = 1,        /* null pointer, negative size, bad enum           */
+  TDVP_E_SHAPE = 2,      /* inconsistent bond / phys / channel dimensions   */
+  TDVP_E_DEVICE = 3,     /* a HIP runtime call failed                       */
+  TDVP_E_WORKSPACE = 4,  /* no workspace set, or too small for the call     */
+  TDVP_E_NUMERIC = 5,    /* non-finite norm found by tdvp_observe           */
+  TDVP_E_UNSUPPORTED = 6 /* sizes beyond the compiled limits                */
+} tdvp_status;
+
+typedef enum {
+  TDVP_FP64 = 0,  /* every contraction in FP64 (complex128)                   */
+  TDVP_FP32 = 1   /* contractions and environments in FP32 (complex64) with
+                     FP32 accumulation; Lanczos orthogonalisation, norms,
+                     the small exponential, QR and the MPS stay FP64          */
+} tdvp_precision;
+
+typedef struct tdvp_ctx tdvp_ctx;
+
+/* MPS descriptor (eq:mps).  site[i]: device c128 (bond[i], phys[i], bond[i+1]). */
+typedef struct {
+  int32_t n;
+  const int32_t *phys;   /* host [n]   */
+  const int32_t *bond;   /* host [n+1] */
+  void *const *site;     /* host [n] of device pointers */
+} tdvp_mps;
+
+/* MPO descriptor (eq:mpo).  site[i]: device c128 (bond[i], phys[i], phys[i], bond[i+1]).
+ * energy_shift: constant removed from H, added back by tdvp_observe. */
+typedef struct {
+  int32_t n;
+  const int32_t *phys;   /* host [n]   (must equal the MPS phys) */
+  const int32_t *bond;   /* host [n+1] channel dims W_b          */
+  const void *const *site;
+  double energy_shift;
+} tdvp_mpo;
+
+/* Environments (eq:tdvp1_h1i, eq:tdvp1_hiN): host tables of n+1 device
+ * pointers each; left[b] and right[b] have (bond_mps[b], bond_mpo[b], bond_mps[b]). */
+typedef struct {
+  void *const *left;
+  void *const *right;
+} tdvp_envs;
+
+/* Create a context on HIP device `device`, bound to `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  *ctx receives the handle. */
+tdvp_status tdvp_create(tdvp_ctx **ctx, int device, void *hip_stream, tdvp_precision prec);
+tdvp_status tdvp_destroy(tdvp_ctx *ctx);
+tdvp_status tdvp_set_stream(tdvp_ctx *ctx, void *hip_stream);
+const char *tdvp_status_string(tdvp_status s);
+/* Bytes per environment element for the context's precision (16 or 8). */
+int tdvp_env_elem_bytes(const tdvp_ctx *ctx);
+
+/* Workspace bytes needed to run every call below on this chain with
+ * Krylov dimension up to kmax (1 <= kmax <= 32).  Host-only computation. */
+tdvp_status tdvp_workspace_bytes(const tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo,
+                                 int kmax, size_t *bytes);
+/* Hand the context a device workspace of `bytes` bytes (256-byte aligned).
+ * Enqueues a small initialisation kernel on the stream. */
+tdvp_status tdvp_set_workspace(tdvp_ctx *ctx, void *dev, size_t bytes);
+
+/* Environment update (eq:tdvp1_h with A = L or R, one site at a time).
+ * dir = +1: env_out = h[1:i] from env_in = h[1:i-1] and the left-canonical
+ *           site tensor A (Ml, d, Mr); env_in (Ml, Wl, Ml), env_out (Mr, Wr, Mr).
+ * dir = -1: env_out = h[i:N] from env_in = h[i+1:N] and the right-canonical
+ *           A (Ml, d, Mr); env_in (Mr, Wr, Mr), env_out (Ml, Wl, Ml).
+ * A is c128; W is the MPO site tensor (Wl, d, d, Wr); envs use the context's
+ * element type.  env_out must not alias env_in. */
+tdvp_status tdvp_env_update(tdvp_ctx *ctx, int dir, const void *env_in, const void *A,
+                            const void *W, int Ml, int d, int Mr, int Wl, int Wr, void *env_out);
+
+/* Effective-Hamiltonian application.
+ * W != NULL: y = H[i] x with H[i] = h[1:i-1] W h[i+1:N] (eq:tdvp1_H, eq:tdvp2_C);
+ *   Lenv (Ml, Wl, Ml), Renv (Mr, Wr, Mr), x, y c128 (Ml, d, Mr).
+ * W == NULL: the bond operator of eq:tdvp2_D, y = sum_w Lenv[:,w,:] x Renv[:,w,:]^T;
+ *   d must be 1, Wl == Wr, x and y c128 (Ml, Mr).
+ * y must not alias x. */
+tdvp_status tdvp_heff_apply(tdvp_ctx *ctx, const void *Lenv, const void *W, const void *Renv,
+                            int Ml, int d, int Mr, int Wl, int Wr, const void *x, void *y);
+
+/* Krylov propagator y = exp(z Heff) x (Sec. II.A.2, local integrator of
+ * eq:tdvp2_C / eq:tdvp2_D): Lanczos with full FP64 reorthogonalisation,
+ * k <= min(kmax, dim) vectors, stop at breakdown beta_j <= 1e-12 |Heff v_j|
+ * or, if tol > 0, when |z beta_j [exp(z T_k) e_1]_k| < tol; the small
+ * exponential exp(z T_k) e_1 is evaluated on the device in FP64.
+ * Operator arguments as in tdvp_heff_apply (W == NULL: bond operator).
+ * x and y are c128 and may alias.  k_used_dev (device int32, may be NULL)
+ * receives the number of Krylov vectors used. */
+tdvp_status tdvp_lanczos_expm(tdvp_ctx *ctx, const void *Lenv, const void *W, const void *Renv,
+                              int Ml, int d, int Mr, int Wl, int Wr, double z_re, double z_im,
+                              int kmax, double tol, const void *x, void *y, int32_t *k_used_dev);
+
+/* Thin QR of a tall c128 matrix (eq:QR): A (m x n, m >= n, row-major) = Q R,
+ * Q (m x n) with orthonormal columns, R (n x n) upper triangular with real
+ * non-negative diagonal (Householder, FP64).  Q and R row-major; Q may alias A. */
+tdvp_status tdvp_qr(tdvp_ctx *ctx, const void *A, int m, int n, void *Q, void *R);
+
+/* Right-canonicalise an MPS in place (RQ sweep n-1 -> 1, Sec. II.A) and
+ * normalise the centre tensor at site 0. */
+tdvp_status tdvp_right_canonicalize(tdvp_ctx *ctx, const tdvp_mps *mps);
+
+/* Build every right environment right[n-1..1] of a right-canonical MPS and
+ * set left[0] = right[n] = 1 (left[1..n-1] are produced by the sweep). */
+tdvp_status tdvp_envs_build(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo,
+                            const tdvp_envs *envs);
+
+/* nsteps symmetric TDVP-PS steps of size dt (eq:ps_trotter): a left-to-right
+ * then a right-to-left sweep with dt/2, the two forward factors on the last
+ * site merged into one exp(-i dt H[n-1]).  Entry and exit: right-canonical
+ * MPS, centre at site 0, right[1..n-1] valid for it.  kmax/tol as in
+ * tdvp_lanczos_expm.  MPS tensors and environments are updated in place. */
+tdvp_status tdvp_ps_step(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo,
+                         const tdvp_envs *envs, double dt, int nsteps, int kmax, double tol);
+
+/* Observables of a right-canonical MPS (Sec. III.A): out_dev (device double
+ * [2 + n_el]) receives <psi|psi>, <psi|H|psi> + energy_shift * <psi|psi>, and
+ * the populations <psi|a+_m a_m|psi> of the electronic sites el_sites[m]
+ * (host array of site indices; local dim 2, level 1 = occupied).  Not
+ * divided by the norm.  Needs envs->right[1] valid. */
+tdvp_status tdvp_observe(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo,
+                         const tdvp_envs *envs, const int32_t *el_sites, int n_el,
+                         double *out_dev);
+
+/* Krylov log: while set, every Lanczos solve of tdvp_ps_step writes its
+ * Krylov dimension to dev[slot] (device int32), slots counted from 0 at the
+ * start of each tdvp_ps_step call in launch order (2n - 1 forward and
+ * 2n - 2 backward solves per step); solves beyond `capacity` are not logged.
+ * capacity = 0 switches the log off. */
+tdvp_status tdvp_set_krylov_log(tdvp_ctx *ctx, int32_t *dev, int capacity);
+
+/* Kernel timing for roofline reports.  tdvp_profile(ctx, cls) starts
+ * recording HIP events on the context stream around every later launch of
+ * kernel class cls (0 = off), together with the algorithmic FLOP and HBM
+ * bytes of each launch (operands read once, results written once).
+ * tdvp_profile_read synchronises the stream and returns the summed event
+ * time (ms), the launch count and the summed FLOP and bytes. */
+enum {
+  TDVP_PROF_OFF = 0,
+  TDVP_PROF_GEMM = 1,     /* complex MFMA contractions                    */
+  TDVP_PROF_WAPPLY = 2,   /* MPO channel stage                            */
+  TDVP_PROF_LANCZOS = 3,  /* Lanczos vector kernels and small exponential */
+  TDVP_PROF_QR = 4        /* Householder QR                               */
+};
+tdvp_status tdvp_profile(tdvp_ctx *ctx, int kernel_class);
+tdvp_status tdvp_profile_read(tdvp_ctx *ctx, double *ms, int64_t *launches, double *flops,
+                              double *bytes);
+
+/* Frenkel-Holstein MPO (Sec. II.C, eq:holstein) written into HOST buffers.
+ * Chain sites are given by kind[i] (0 = electronic two-level site, 1 = mode),
+ * owner[i] (electronic index 0..n_e-1 the site belongs to) and phys[i].
+ * eps[n_e] site energies and J[n_e*n_e] couplings, w[i] and g[i] the mode
+ * frequency and dimensionless coupling of mode site i (ignored for electronic
+ * sites), all in the energy unit of the caller.  The channel construction
+ * uses complementary operators so that W_b = 2 + 2 min(k, n_e - k) + [inside
+ * a mode block] with k electronic sites left of bond b.
+ * Pass W_out = NULL to query: bond_out[n+1] and *total_elems (sum of site
+ * tensor sizes in complex numbers) are filled.  Then call again with W_out
+ * (host c128 of total_elems) to receive the tensors concatenated in site
+ * order.  Host-only; no device needed. */
+tdvp_status tdvp_holstein_mpo(int n, const int32_t *kind, const int32_t *owner, const int32_t *phys,
+                              int n_e, const double *eps, const double *J, const double *w,
+                              const double *g, int32_t *bond_out, int64_t *total_elems,
+                              double *W_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TDVP_H */

@@ -1,0 +1,680 @@
+// C ABI of libtdvp and the host driver of the TDVP-PS sweep.
+//
+// The driver only enqueues kernels on the context's stream; nothing in a
+// step synchronises with the host.  Per site of a half sweep (eq:ps_trotter,
+// eq:tdvp2_C, eq:tdvp2_D, eq:QR):
+//   forward  : Lanczos exp(-i h H[i]) on C_i     (H[i] x = 3 contraction stages)
+//   gauge    : QR (left-to-right) or QR of C^H (right-to-left), FP64
+//   env      : h[1:i] or h[i:N] update (3 contraction stages)
+//   backward : Lanczos exp(+i h K) on the bond matrix D (2 stages per K x)
+//   centre   : C_{i+1} = D R_{i+1}  (or C_{i-1} = L_{i-1} D), one GEMM whose
+//              result feeds the next forward solve directly.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "common.h"
+
+using namespace tdvp;
+
+namespace {
+// One timed launch: HIP events on the context stream around a kernel of the
+// selected class, with the algorithmic FLOP and byte counts of that launch.
+struct ProfRec {
+  hipEvent_t a, b;
+  double flops, bytes;
+};
+}  // namespace
+
+struct tdvp_ctx {
+  int device;
+  hipStream_t stream;
+  tdvp_precision prec;
+  char *ws;
+  size_t ws_bytes;
+  int prof_class;                 // 0: timing off
+  std::vector<ProfRec> prof;
+  std::vector<hipEvent_t> pool;
+  size_t pool_used;
+  int32_t *klog;                  // device log of Krylov dimensions (may be null)
+  int klog_cap, klog_pos;
+};
+
+namespace {
+
+#define CK(x)                                  \
+  do {                                         \
+    hipError_t e_ = (x);                       \
+    if (e_ != hipSuccess) return TDVP_E_DEVICE; \
+  } while (0)
+
+#define CS(x)                      \
+  do {                             \
+    tdvp_status s_ = (x);          \
+    if (s_ != TDVP_OK) return s_;  \
+  } while (0)
+
+size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+DType env_type(const tdvp_ctx *c) { return c->prec == TDVP_FP64 ? F64 : F32; }
+int env_bytes(const tdvp_ctx *c) { return c->prec == TDVP_FP64 ? 16 : 8; }
+
+// Workspace carve-up for a problem whose largest local vector has n complex
+// entries and largest MPO bond is wmax.  The Lanczos state sits at offset 0
+// for every layout, so its counter stays zero between calls.
+struct Layout {
+  size_t st, pp, U, T1, T2, Y, D, tmp, qr, obs, total;
+  int64_t n;
+};
+
+Layout layout(int64_t n, int wmax, int kmax, int es) {
+  Layout L;
+  size_t o = 0;
+  L.n = n;
+  L.st = o; o += al256(sizeof(LzState));
+  L.pp = o; o += al256(sizeof(LzPartials));
+  L.U = o; o += al256((size_t)(kmax + 1) * n * 16);
+  L.T1 = o; o += al256((size_t)wmax * n * es);
+  L.T2 = o; o += al256((size_t)wmax * n * es);
+  L.Y = o; o += al256((size_t)wmax * n * es);
+  L.D = o; o += al256((size_t)n * 16);
+  L.tmp = o; o += al256((size_t)n * 16);
+  L.qr = o; o += al256((size_t)2 * n * 16 + 4096);
+  L.obs = o; o += al256((size_t)3 * n * 16 + 4096);
+  L.total = o;
+  return L;
+}
+
+template <typename T> T *at(tdvp_ctx *c, size_t off) { return reinterpret_cast<T *>(c->ws + off); }
+
+hipEvent_t pool_event(tdvp_ctx *c) {
+  if (c->pool_used == c->pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    c->pool.push_back(e);
+  }
+  return c->pool[c->pool_used++];
+}
+
+// Start/stop a timed launch of class `cls` (no-op unless that class is profiled).
+int prof_begin(tdvp_ctx *c, int cls) {
+  if (c->prof_class != cls) return -1;
+  ProfRec r{pool_event(c), pool_event(c), 0.0, 0.0};
+  if (!r.a || !r.b) return -1;
+  hipEventRecord(r.a, c->stream);
+  c->prof.push_back(r);
+  return (int)c->prof.size() - 1;
+}
+void prof_end(tdvp_ctx *c, int idx, double flops, double bytes) {
+  if (idx < 0) return;
+  hipEventRecord(c->prof[idx].b, c->stream);
+  c->prof[idx].flops = flops;
+  c->prof[idx].bytes = bytes;
+}
+
+int esz(DType t) { return t == F64 ? 16 : 8; }
+
+// cgemm with timing: algorithmic FLOP 8 M N K per batch; bytes = operands once + output once.
+hipError_t gemm_t(tdvp_ctx *c, DType ta, DType tb, DType tc, const GemmArgs &g) {
+  const int id = prof_begin(c, TDVP_PROF_GEMM);
+  const hipError_t e = cgemm(ta, tb, tc, g, c->stream);
+  const double M = g.M, N = g.N, K = g.K, B = g.batch;
+  prof_end(c, id, 8.0 * M * N * K * B,
+           (g.bsa ? B : 1.0) * M * K * esz(ta) + (g.bsb ? B : 1.0) * K * N * esz(tb) + B * M * N * esz(tc));
+  return e;
+}
+
+hipError_t wapply_t(tdvp_ctx *c, DType t, const WApplyArgs &a) {
+  const int id = prof_begin(c, TDVP_PROF_WAPPLY);
+  const hipError_t e = wapply(t, a, c->stream);
+  const double io = (double)a.A * a.C * a.d * esz(t);
+  prof_end(c, id, 0.0, io * (a.Wl + a.Wr));
+  return e;
+}
+
+// One linear operator of a local equation: H[i] (W != NULL) or the bond
+// operator K of eq:tdvp2_D (W == NULL, d == 1, Wl == Wr).
+struct Op {
+  const void *L, *W, *R;
+  int Ml, d, Mr, Wl, Wr;
+  int64_t size() const { return (int64_t)Ml * d * Mr; }
+  int parts() const { return Wl; }
+};
+
+// y_parts[p] (p < Wl) with sum_p y_parts[p] = Op x.  x is c128.
+tdvp_status apply_op(tdvp_ctx *c, const Layout &lay, const Op &op, const double2 *x, const int *skip) {
+  const DType et = env_type(c), ct = et;
+  const int64_t n = op.size();
+  void *T1 = c->ws + lay.T1, *T2 = c->ws + lay.T2, *Y = c->ws + lay.Y;
+  if (op.W) {
+    // stage 1: T1[wr][l s][r'] = sum_r x[l s][r] R[r'][wr][r]
+    GemmArgs g{};
+    g.A = x; g.B = op.R; g.C = T1;
+    g.M = op.Ml * op.d; g.N = op.Mr; g.K = op.Mr; g.batch = op.Wr;
+    g.sam = op.Mr; g.sak = 1; g.sbk = 1; g.sbn = (int64_t)op.Wr * op.Mr;
+    g.scm = op.Mr; g.scn = 1;
+    g.bsa = 0; g.bsb = op.Mr; g.bsc = n;
+    g.skip = skip;
+    CK(gemm_t(c, F64, et, ct, g));
+    // stage 2: T2[wl][l][s'][r'] = sum_{s, wr} W[wl][s'][s][wr] T1[wr][l][s][r']
+    WApplyArgs w{};
+    w.in = T1; w.out = T2; w.W = op.W;
+    w.Wl = op.Wl; w.Wr = op.Wr; w.d = op.d; w.A = op.Ml; w.C = op.Mr;
+    w.w_in_right = 1;
+    w.si_w = n; w.si_s = op.Mr; w.si_a = (int64_t)op.d * op.Mr; w.si_c = 1;
+    w.so_w = n; w.so_s = op.Mr; w.so_a = (int64_t)op.d * op.Mr; w.so_c = 1;
+    w.skip = skip;
+    CK(wapply_t(c, ct, w));
+    // stage 3 (batched over wl): Y[wl][l'][s' r'] = sum_l L[l'][wl][l] T2[wl][l][s' r']
+    GemmArgs h{};
+    h.A = op.L; h.B = T2; h.C = Y;
+    h.M = op.Ml; h.N = op.d * op.Mr; h.K = op.Ml; h.batch = op.Wl;
+    h.sam = (int64_t)op.Wl * op.Ml; h.sak = 1; h.sbk = (int64_t)op.d * op.Mr; h.sbn = 1;
+    h.scm = (int64_t)op.d * op.Mr; h.scn = 1;
+    h.bsa = op.Ml; h.bsb = n; h.bsc = n;
+    h.skip = skip;
+    CK(gemm_t(c, et, ct, ct, h));
+  } else {
+    // bond operator: T1[w][l][r'] = sum_r D[l][r] R[r'][w][r]; Y[w][l'][r'] = sum_l L[l'][w][l] T1[w][l][r']
+    GemmArgs g{};
+    g.A = x; g.B = op.R; g.C = T1;
+    g.M = op.Ml; g.N = op.Mr; g.K = op.Mr; g.batch = op.Wr;
+    g.sam = op.Mr; g.sak = 1; g.sbk = 1; g.sbn = (int64_t)op.Wr * op.Mr;
+    g.scm = op.Mr; g.scn = 1;
+    g.bsa = 0; g.bsb = op.Mr; g.bsc = n;
+    g.skip = skip;
+    CK(gemm_t(c, F64, et, ct, g));
+    GemmArgs h{};
+    h.A = op.L; h.B = T1; h.C = Y;
+    h.M = op.Ml; h.N = op.Mr; h.K = op.Ml; h.batch = op.Wl;
+    h.sam = (int64_t)op.Wl * op.Ml; h.sak = 1; h.sbk = op.Mr; h.sbn = 1;
+    h.scm = op.Mr; h.scn = 1;
+    h.bsa = op.Ml; h.bsb = n; h.bsc = n;
+    h.skip = skip;
+    CK(gemm_t(c, et, ct, ct, h));
+  }
+  return TDVP_OK;
+}
+
+tdvp_status run_lanczos(tdvp_ctx *c, const Layout &lay, const Op &op, double zr, double zi,
+                        int kmax, double tol, const void *x, void *y, int32_t *kused) {
+  const int64_t n = op.size();
+  const int keff = (int)std::min<int64_t>(kmax, n);
+  LzState *st = at<LzState>(c, lay.st);
+  LzPartials *pp = at<LzPartials>(c, lay.pp);
+  double2 *U = at<double2>(c, lay.U);
+  const double vb = 16.0 * n;
+  int id = prof_begin(c, TDVP_PROF_LANCZOS);
+  CK(lz_start(st, pp, (const double2 *)x, U, n, keff, zr, zi, tol, c->stream));
+  prof_end(c, id, 4.0 * n, 2.0 * vb);
+  for (int j = 0; j < keff; ++j) {
+    CS(apply_op(c, lay, op, U + (int64_t)j * n, &st->stop));
+    id = prof_begin(c, TDVP_PROF_LANCZOS);
+    CK(lz_dots(st, pp, env_type(c), c->ws + lay.Y, op.parts(), n, U, n, j, n, c->stream));
+    prof_end(c, id, 8.0 * (j + 1) * n, (double)op.parts() * n * env_bytes(c) + vb + (j + 1) * vb);
+    id = prof_begin(c, TDVP_PROF_LANCZOS);
+    CK(lz_update(st, pp, U, n, j, n, c->stream));
+    prof_end(c, id, 8.0 * (j + 1) * n, 2.0 * vb + (j + 1) * vb);
+  }
+  if (!kused && c->klog && c->klog_pos < c->klog_cap) kused = c->klog + c->klog_pos++;
+  id = prof_begin(c, TDVP_PROF_LANCZOS);
+  CK(lz_finish(st, U, n, n, (double2 *)y, kused, c->stream));
+  prof_end(c, id, 8.0 * keff * n, keff * vb + vb);
+  return TDVP_OK;
+}
+
+// dir = +1: out (Mr, Wr, Mr) = h[1:i] from in (Ml, Wl, Ml).  dir = -1: out (Ml, Wl, Ml) from in (Mr, Wr, Mr).
+tdvp_status env_update(tdvp_ctx *c, const Layout &lay, int dir, const void *in, const void *A,
+                       const void *W, int Ml, int d, int Mr, int Wl, int Wr, void *out) {
+  const DType et = env_type(c), ct = et;
+  const int64_t n = (int64_t)Ml * d * Mr;
+  void *T1 = c->ws + lay.T1, *T2 = c->ws + lay.T2;
+  if (dir > 0) {
+    // T1[l'][wl][s][li] = sum_l L[l'][wl][l] A[l][s][li]
+    GemmArgs g{};
+    g.A = in; g.B = A; g.C = T1;
+    g.M = Ml * Wl; g.N = d * Mr; g.K = Ml; g.batch = 1;
+    g.sam = Ml; g.sak = 1; g.sbk = (int64_t)d * Mr; g.sbn = 1; g.scm = (int64_t)d * Mr; g.scn = 1;
+    CK(gemm_t(c, et, F64, ct, g));
+    // T2[l'][s'][wr][li] = sum_{wl, s} W[wl][s'][s][wr] T1[l'][wl][s][li]
+    WApplyArgs w{};
+    w.in = T1; w.out = T2; w.W = W;
+    w.Wl = Wl; w.Wr = Wr; w.d = d; w.A = Ml; w.C = Mr; w.w_in_right = 0;
+    w.si_w = (int64_t)d * Mr; w.si_s = Mr; w.si_a = (int64_t)Wl * d * Mr; w.si_c = 1;
+    w.so_w = Mr; w.so_s = (int64_t)Wr * Mr; w.so_a = (int64_t)d * Wr * Mr; w.so_c = 1;
+    CK(wapply_t(c, ct, w));
+    // out[q][wr][li] = sum_{l', s'} conj(A[l'][s'][q]) T2[l'][s'][wr][li]
+    GemmArgs h{};
+    h.A = A; h.B = T2; h.C = out;
+    h.M = Mr; h.N = Wr * Mr; h.K = Ml * d; h.batch = 1;
+    h.sam = 1; h.sak = Mr; h.conjA = 1; h.sbk = (int64_t)Wr * Mr; h.sbn = 1;
+    h.scm = (int64_t)Wr * Mr; h.scn = 1;
+    CK(gemm_t(c, F64, ct, et, h));
+  } else {
+    // T1[wr][k][t][q] = sum_r A[k][t][r] R[q][wr][r]   (as stage 1 of H[i] x)
+    GemmArgs g{};
+    g.A = A; g.B = in; g.C = T1;
+    g.M = Ml * d; g.N = Mr; g.K = Mr; g.batch = Wr;
+    g.sam = Mr; g.sak = 1; g.sbk = 1; g.sbn = (int64_t)Wr * Mr;
+    g.scm = Mr; g.scn = 1; g.bsa = 0; g.bsb = Mr; g.bsc = n;
+    CK(gemm_t(c, F64, et, ct, g));
+    // T2[wl][k][s][q] = sum_{t, wr} W[wl][s][t][wr] T1[wr][k][t][q]
+    WApplyArgs w{};
+    w.in = T1; w.out = T2; w.W = W;
+    w.Wl = Wl; w.Wr = Wr; w.d = d; w.A = Ml; w.C = Mr; w.w_in_right = 1;
+    w.si_w = n; w.si_s = Mr; w.si_a = (int64_t)d * Mr; w.si_c = 1;
+    w.so_w = n; w.so_s = Mr; w.so_a = (int64_t)d * Mr; w.so_c = 1;
+    CK(wapply_t(c, ct, w));
+    // out[b][wl][k] = sum_{s, q} conj(A[b][s][q]) T2[wl][k][s][q]
+    GemmArgs h{};
+    h.A = A; h.B = T2; h.C = out;
+    h.M = Ml; h.N = Wl * Ml; h.K = d * Mr; h.batch = 1;
+    h.sam = (int64_t)d * Mr; h.sak = 1; h.conjA = 1; h.sbk = 1; h.sbn = (int64_t)d * Mr;
+    h.scm = (int64_t)Wl * Ml; h.scn = 1;
+    CK(gemm_t(c, F64, ct, et, h));
+  }
+  return TDVP_OK;
+}
+
+// Householder QR of an m x n complex matrix plus forming the thin Q:
+// 2 (4 m n^2 - 4 n^3 / 3) complex-equivalent real FLOP (factor + Q).
+double qr_flops(double m, double n) { return 2.0 * 8.0 * (m * n * n - n * n * n / 3.0); }
+
+// Left-to-right gauge: C (Ml d x Mr, row-major) = Q D; Q written back to C.
+tdvp_status qr_left(tdvp_ctx *c, const Layout &lay, double2 *C, int Ml, int d, int Mr, double2 *D) {
+  QrArgs q{};
+  q.A = C; q.a_rs = Mr; q.a_cs = 1;
+  q.Q = C; q.q_rs = Mr; q.q_cs = 1;
+  q.R = D; q.r_rs = Mr; q.r_cs = 1;
+  q.m = Ml * d; q.n = Mr;
+  q.work = at<double2>(c, lay.qr);
+  const int id = prof_begin(c, TDVP_PROF_QR);
+  CK(qr(q, c->stream));
+  prof_end(c, id, qr_flops(q.m, q.n), 16.0 * (2.0 * q.m * q.n + (double)q.n * q.n));
+  return TDVP_OK;
+}
+
+// Right-to-left gauge: C (Ml x d Mr) = D Rt with Rt right-isometric (written
+// back to C) and D = R^H from the QR of C^H.
+tdvp_status qr_right(tdvp_ctx *c, const Layout &lay, double2 *C, int Ml, int d, int Mr, double2 *D) {
+  const int64_t cols = (int64_t)d * Mr;
+  QrArgs q{};
+  q.A = C; q.a_rs = 1; q.a_cs = cols; q.conjA = 1;
+  q.Q = C; q.q_rs = 1; q.q_cs = cols; q.conjQ = 1;
+  q.R = D; q.r_rs = 1; q.r_cs = Ml; q.conjR = 1;
+  q.m = (int)cols; q.n = Ml;
+  q.work = at<double2>(c, lay.qr);
+  const int id = prof_begin(c, TDVP_PROF_QR);
+  CK(qr(q, c->stream));
+  prof_end(c, id, qr_flops(q.m, q.n), 16.0 * (2.0 * q.m * q.n + (double)q.n * q.n));
+  return TDVP_OK;
+}
+
+// out (m x nn) = A (m x k) B (k x nn), all c128 row-major.
+tdvp_status matmul(tdvp_ctx *c, const double2 *A, const double2 *B, double2 *out, int m, int k, int nn) {
+  GemmArgs g{};
+  g.A = A; g.B = B; g.C = out;
+  g.M = m; g.N = nn; g.K = k; g.batch = 1;
+  g.sam = k; g.sak = 1; g.sbk = nn; g.sbn = 1; g.scm = nn; g.scn = 1;
+  CK(gemm_t(c, F64, F64, F64, g));
+  return TDVP_OK;
+}
+
+struct Chain {
+  int n;
+  std::vector<int> phys, bond, wbond;
+  int64_t nmax;
+  int wmax, mmax;
+};
+
+tdvp_status check_chain(const tdvp_mps *mps, const tdvp_mpo *mpo, Chain *ch) {
+  if (!mps || !mps->phys || !mps->bond || !mps->site || mps->n <= 0) return TDVP_E_ARG;
+  const int n = mps->n;
+  ch->n = n;
+  ch->phys.assign(mps->phys, mps->phys + n);
+  ch->bond.assign(mps->bond, mps->bond + n + 1);
+  if (ch->bond[0] != 1 || ch->bond[n] != 1) return TDVP_E_SHAPE;
+  ch->nmax = 1;
+  ch->mmax = 1;
+  for (int i = 0; i < n; ++i) {
+    if (ch->phys[i] < 1 || ch->bond[i] < 1 || !mps->site[i]) return TDVP_E_SHAPE;
+    ch->nmax = std::max<int64_t>(ch->nmax, (int64_t)ch->bond[i] * ch->phys[i] * ch->bond[i + 1]);
+    ch->nmax = std::max<int64_t>(ch->nmax, (int64_t)ch->bond[i] * ch->bond[i]);
+    ch->mmax = std::max(ch->mmax, ch->bond[i]);
+    // QR shapes of both sweep directions must be tall
+    if (i < n - 1 && (int64_t)ch->bond[i] * ch->phys[i] < ch->bond[i + 1]) return TDVP_E_SHAPE;
+    if (i > 0 && (int64_t)ch->phys[i] * ch->bond[i + 1] < ch->bond[i]) return TDVP_E_SHAPE;
+  }
+  if (ch->mmax > 256) return TDVP_E_UNSUPPORTED;
+  ch->wmax = 1;
+  if (mpo) {
+    if (mpo->n != n || !mpo->phys || !mpo->bond || !mpo->site) return TDVP_E_ARG;
+    ch->wbond.assign(mpo->bond, mpo->bond + n + 1);
+    if (ch->wbond[0] != 1 || ch->wbond[n] != 1) return TDVP_E_SHAPE;
+    for (int i = 0; i < n; ++i) {
+      if (mpo->phys[i] != ch->phys[i] || !mpo->site[i] || ch->wbond[i] < 1) return TDVP_E_SHAPE;
+      ch->wmax = std::max(ch->wmax, ch->wbond[i]);
+      if ((int64_t)ch->wbond[i + 1] * ch->phys[i] > 1024 || (int64_t)ch->wbond[i] * ch->phys[i] > 1024)
+        return TDVP_E_UNSUPPORTED;
+    }
+  }
+  return TDVP_OK;
+}
+
+tdvp_status need(const tdvp_ctx *c, const Layout &lay) {
+  if (!c->ws) return TDVP_E_WORKSPACE;
+  if (c->ws_bytes < lay.total) return TDVP_E_WORKSPACE;
+  return TDVP_OK;
+}
+
+
+
+}  // namespace
+
+extern "C" {
+
+const char *tdvp_status_string(tdvp_status s) {
+  switch (s) {
+    case TDVP_OK: return "ok";
+    case TDVP_E_ARG: return "invalid argument";
+    case TDVP_E_SHAPE: return "inconsistent shapes";
+    case TDVP_E_DEVICE: return "HIP runtime error";
+    case TDVP_E_WORKSPACE: return "workspace missing or too small";
+    case TDVP_E_NUMERIC: return "non-finite value";
+    case TDVP_E_UNSUPPORTED: return "size beyond compiled limits";
+  }
+  return "unknown status";
+}
+
+tdvp_status tdvp_create(tdvp_ctx **ctx, int device, void *hip_stream, tdvp_precision prec) {
+  if (!ctx) return TDVP_E_ARG;
+  if (prec != TDVP_FP64 && prec != TDVP_FP32) return TDVP_E_ARG;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return TDVP_E_DEVICE;
+  tdvp_ctx *c = new (std::nothrow) tdvp_ctx;
+  if (!c) return TDVP_E_DEVICE;
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  c->prec = prec;
+  c->ws = nullptr;
+  c->ws_bytes = 0;
+  c->prof_class = 0;
+  c->pool_used = 0;
+  c->klog = nullptr;
+  c->klog_cap = 0;
+  c->klog_pos = 0;
+  *ctx = c;
+  return TDVP_OK;
+}
+
+tdvp_status tdvp_destroy(tdvp_ctx *ctx) {
+  if (!ctx) return TDVP_E_ARG;
+  for (hipEvent_t e : ctx->pool) hipEventDestroy(e);
+  delete ctx;
+  return TDVP_OK;
+}
+
+tdvp_status tdvp_set_stream(tdvp_ctx *ctx, void *hip_stream) {
+  if (!ctx) return TDVP_E_ARG;
+  ctx->stream = (hipStream_t)hip_stream;
+  return TDVP_OK;
+}
+
+int tdvp_env_elem_bytes(const tdvp_ctx *ctx) { return ctx ? env_bytes(ctx) : 0; }
+
+tdvp_status tdvp_set_krylov_log(tdvp_ctx *ctx, int32_t *dev, int capacity) {
+  if (!ctx || capacity < 0 || (capacity > 0 && !dev)) return TDVP_E_ARG;
+  ctx->klog = capacity > 0 ? dev : nullptr;
+  ctx->klog_cap = capacity;
+  ctx->klog_pos = 0;
+  return TDVP_OK;
+}
+
+tdvp_status tdvp_profile(tdvp_ctx *ctx, int kernel_class) {
+  if (!ctx || kernel_class < 0 || kernel_class > TDVP_PROF_QR) return TDVP_E_ARG;
+  ctx->prof_class = kernel_class;
+  ctx->prof.clear();
+  ctx->pool_used = 0;
+  return TDVP_OK;
+}
+
+tdvp_status tdvp_profile_read(tdvp_ctx *ctx, double *ms, int64_t *launches, double *flops, double *bytes) {
+  if (!ctx || !ms || !launches || !flops || !bytes) return TDVP_E_ARG;
+  CK(hipStreamSynchronize(ctx->stream));
+  double t = 0.0, f = 0.0, b = 0.0;
+  for (const ProfRec &r : ctx->prof) {
+    float e = 0.0f;
+    CK(hipEventElapsedTime(&e, r.a, r.b));
+    t += e;
+    f += r.flops;
+    b += r.bytes;
+  }
+  *ms = t;
+  *launches = (int64_t)ctx->prof.size();
+  *flops = f;
+  *bytes = b;
+  return TDVP_OK;
+}
+
+tdvp_status tdvp_workspace_bytes(const tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo,
+                                 int kmax, size_t *bytes) {
+  if (!ctx || !bytes || kmax < 1 || kmax > KMAX) return TDVP_E_ARG;
+  Chain ch;
+  CS(check_chain(mps, mpo, &ch));
+  *bytes = layout(ch.nmax, ch.wmax, kmax, env_bytes(ctx)).total;
+  return TDVP_OK;
+}
+
+tdvp_status tdvp_set_workspace(tdvp_ctx *ctx, void *dev, size_t bytes) {
+  if (!ctx || !dev) return TDVP_E_ARG;
+  if (((uintptr_t)dev & 255) != 0) return TDVP_E_ARG;
+  if (bytes < al256(sizeof(LzState))) return TDVP_E_WORKSPACE;
+  ctx->ws = (char *)dev;
+  ctx->ws_bytes = bytes;
+  CK(hipSetDevice(ctx->device));
+  CK(set_dev_int(&reinterpret_cast<LzState *>(ctx->ws)->counter, 0, ctx->stream));
+  CK(set_dev_int(&reinterpret_cast<LzState *>(ctx->ws)->stop, 1, ctx->stream));
+  return TDVP_OK;
+}
+
+tdvp_status tdvp_env_update(tdvp_ctx *ctx, int dir, const void *env_in, const void *A, const void *W,
+                            int Ml, int d, int Mr, int Wl, int Wr, void *env_out) {
+  if (!ctx || !env_in || !A || !W || !env_out || (dir != 1 && dir != -1)) return TDVP_E_ARG;
+  if (Ml < 1 || d < 1 || Mr < 1 || Wl < 1 || Wr < 1) return TDVP_E_SHAPE;
+  if ((int64_t)std::max(Wl, Wr) * d > 1024) return TDVP_E_UNSUPPORTED;
+  const Layout lay = layout((int64_t)Ml * d * Mr, std::max(Wl, Wr), 1, env_bytes(ctx));
+  CS(need(ctx, lay));
+  CK(hipSetDevice(ctx->device));
+  return env_update(ctx, lay, dir, env_in, A, W, Ml, d, Mr, Wl, Wr, env_out);
+}
+
+tdvp_status tdvp_heff_apply(tdvp_ctx *ctx, const void *Lenv, const void *W, const void *Renv, int Ml,
+                            int d, int Mr, int Wl, int Wr, const void *x, void *y) {
+  if (!ctx || !Lenv || !Renv || !x || !y) return TDVP_E_ARG;
+  if (Ml < 1 || d < 1 || Mr < 1 || Wl < 1 || Wr < 1) return TDVP_E_SHAPE;
+  if (!W && (d != 1 || Wl != Wr)) return TDVP_E_SHAPE;
+  if ((int64_t)std::max(Wl, Wr) * d > 1024) return TDVP_E_UNSUPPORTED;
+  const Op op{Lenv, W, Renv, Ml, d, Mr, Wl, Wr};
+  const Layout lay = layout(op.size(), std::max(Wl, Wr), 1, env_bytes(ctx));
+  CS(need(ctx, lay));
+  CK(hipSetDevice(ctx->device));
+  CS(apply_op(ctx, lay, op, (const double2 *)x, nullptr));
+  CK(sum_partials(env_type(ctx), ctx->ws + lay.Y, op.parts(), op.size(), op.size(), (double2 *)y,
+                  ctx->stream));
+  return TDVP_OK;
+}
+
+tdvp_status tdvp_lanczos_expm(tdvp_ctx *ctx, const void *Lenv, const void *W, const void *Renv, int Ml,
+                              int d, int Mr, int Wl, int Wr, double z_re, double z_im, int kmax,
+                              double tol, const void *x, void *y, int32_t *k_used_dev) {
+  if (!ctx || !Lenv || !Renv || !x || !y) return TDVP_E_ARG;
+  if (kmax < 1 || kmax > KMAX || !(tol >= 0.0)) return TDVP_E_ARG;
+  if (Ml < 1 || d < 1 || Mr < 1 || Wl < 1 || Wr < 1) return TDVP_E_SHAPE;
+  if (!W && (d != 1 || Wl != Wr)) return TDVP_E_SHAPE;
+  if ((int64_t)std::max(Wl, Wr) * d > 1024) return TDVP_E_UNSUPPORTED;
+  const Op op{Lenv, W, Renv, Ml, d, Mr, Wl, Wr};
+  const Layout lay = layout(op.size(), std::max(Wl, Wr), kmax, env_bytes(ctx));
+  CS(need(ctx, lay));
+  CK(hipSetDevice(ctx->device));
+  return run_lanczos(ctx, lay, op, z_re, z_im, kmax, tol, x, y, k_used_dev);
+}
+
+tdvp_status tdvp_qr(tdvp_ctx *ctx, const void *A, int m, int n, void *Q, void *R) {
+  if (!ctx || !A || !Q || !R) return TDVP_E_ARG;
+  if (n < 1 || m < n) return TDVP_E_SHAPE;
+  if (n > 256) return TDVP_E_UNSUPPORTED;
+  const Layout lay = layout((int64_t)m * n, 1, 1, env_bytes(ctx));
+  CS(need(ctx, lay));
+  CK(hipSetDevice(ctx->device));
+  QrArgs q{};
+  q.A = (const double2 *)A; q.a_rs = n; q.a_cs = 1;
+  q.Q = (double2 *)Q; q.q_rs = n; q.q_cs = 1;
+  q.R = (double2 *)R; q.r_rs = n; q.r_cs = 1;
+  q.m = m; q.n = n;
+  q.work = at<double2>(ctx, lay.qr);
+  CK(qr(q, ctx->stream));
+  return TDVP_OK;
+}
+
+tdvp_status tdvp_right_canonicalize(tdvp_ctx *ctx, const tdvp_mps *mps) {
+  if (!ctx) return TDVP_E_ARG;
+  Chain ch;
+  CS(check_chain(mps, nullptr, &ch));
+  const Layout lay = layout(ch.nmax, 1, 1, env_bytes(ctx));
+  CS(need(ctx, lay));
+  CK(hipSetDevice(ctx->device));
+  double2 *D = at<double2>(ctx, lay.D), *tmp = at<double2>(ctx, lay.tmp);
+  for (int i = ch.n - 1; i >= 1; --i) {
+    const int Ml = ch.bond[i], d = ch.phys[i], Mr = ch.bond[i + 1];
+    CS(qr_right(ctx, lay, (double2 *)mps->site[i], Ml, d, Mr, D));
+    const int Mp = ch.bond[i - 1], dp = ch.phys[i - 1];
+    CS(matmul(ctx, (const double2 *)mps->site[i - 1], D, tmp, Mp * dp, Ml, Ml));
+    CK(copy_c128((double2 *)mps->site[i - 1], tmp, (int64_t)Mp * dp * Ml, ctx->stream));
+  }
+  CK(normalize_c128((double2 *)mps->site[0], (int64_t)ch.phys[0] * ch.bond[1], ctx->stream));
+  return TDVP_OK;
+}
+
+tdvp_status tdvp_envs_build(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo,
+                            const tdvp_envs *envs) {
+  if (!ctx || !envs || !envs->left || !envs->right) return TDVP_E_ARG;
+  Chain ch;
+  CS(check_chain(mps, mpo, &ch));
+  const Layout lay = layout(ch.nmax, ch.wmax, 1, env_bytes(ctx));
+  CS(need(ctx, lay));
+  CK(hipSetDevice(ctx->device));
+  const int n = ch.n;
+  if (!envs->left[0] || !envs->right[n]) return TDVP_E_ARG;
+  CK(fill_one(envs->left[0], env_type(ctx), ctx->stream));
+  CK(fill_one(envs->right[n], env_type(ctx), ctx->stream));
+  for (int i = n - 1; i >= 1; --i) {
+    if (!envs->right[i] || !envs->right[i + 1]) return TDVP_E_ARG;
+    CS(env_update(ctx, lay, -1, envs->right[i + 1], mps->site[i], mpo->site[i], ch.bond[i], ch.phys[i],
+                  ch.bond[i + 1], ch.wbond[i], ch.wbond[i + 1], envs->right[i]));
+  }
+  return TDVP_OK;
+}
+
+tdvp_status tdvp_ps_step(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo,
+                         const tdvp_envs *envs, double dt, int nsteps, int kmax, double tol) {
+  if (!ctx || !envs || !envs->left || !envs->right) return TDVP_E_ARG;
+  if (nsteps < 0 || kmax < 1 || kmax > KMAX || !(tol >= 0.0) || !std::isfinite(dt)) return TDVP_E_ARG;
+  Chain ch;
+  CS(check_chain(mps, mpo, &ch));
+  const int n = ch.n;
+  for (int b = 0; b <= n; ++b)
+    if (!envs->left[b] || !envs->right[b]) return TDVP_E_ARG;
+  const Layout lay = layout(ch.nmax, ch.wmax, kmax, env_bytes(ctx));
+  CS(need(ctx, lay));
+  CK(hipSetDevice(ctx->device));
+  double2 *D = at<double2>(ctx, lay.D), *tmp = at<double2>(ctx, lay.tmp);
+  const double h = 0.5 * dt;
+  ctx->klog_pos = 0;
+  auto site = [&](int i) { return (double2 *)mps->site[i]; };
+  for (int step = 0; step < nsteps; ++step) {
+    // left-to-right half sweep
+    const double2 *xin = site(0);
+    for (int i = 0; i < n; ++i) {
+      const int Ml = ch.bond[i], d = ch.phys[i], Mr = ch.bond[i + 1];
+      const bool last = (i == n - 1);
+      const Op f{envs->left[i], mpo->site[i], envs->right[i + 1], Ml, d, Mr, ch.wbond[i], ch.wbond[i + 1]};
+      CS(run_lanczos(ctx, lay, f, 0.0, -(last ? dt : h), kmax, tol, xin, site(i), nullptr));
+      if (last) break;
+      CS(qr_left(ctx, lay, site(i), Ml, d, Mr, D));
+      CS(env_update(ctx, lay, +1, envs->left[i], site(i), mpo->site[i], Ml, d, Mr, ch.wbond[i],
+                    ch.wbond[i + 1], envs->left[i + 1]));
+      const int Wb = ch.wbond[i + 1];
+      const Op b{envs->left[i + 1], nullptr, envs->right[i + 1], Mr, 1, Mr, Wb, Wb};
+      CS(run_lanczos(ctx, lay, b, 0.0, +h, kmax, tol, D, D, nullptr));
+      const int dn = ch.phys[i + 1], Mn = ch.bond[i + 2];
+      CS(matmul(ctx, D, site(i + 1), tmp, Mr, Mr, dn * Mn));
+      xin = tmp;
+    }
+    // right-to-left half sweep (the last site was advanced by dt above)
+    for (int i = n - 1; i >= 0; --i) {
+      const int Ml = ch.bond[i], d = ch.phys[i], Mr = ch.bond[i + 1];
+      if (i < n - 1) {
+        const Op f{envs->left[i], mpo->site[i], envs->right[i + 1], Ml, d, Mr, ch.wbond[i], ch.wbond[i + 1]};
+        CS(run_lanczos(ctx, lay, f, 0.0, -h, kmax, tol, xin, site(i), nullptr));
+      }
+      if (i == 0) break;
+      CS(qr_right(ctx, lay, site(i), Ml, d, Mr, D));
+      CS(env_update(ctx, lay, -1, envs->right[i + 1], site(i), mpo->site[i], Ml, d, Mr, ch.wbond[i],
+                    ch.wbond[i + 1], envs->right[i]));
+      const int Wb = ch.wbond[i];
+      const Op b{envs->left[i], nullptr, envs->right[i], Ml, 1, Ml, Wb, Wb};
+      CS(run_lanczos(ctx, lay, b, 0.0, +h, kmax, tol, D, D, nullptr));
+      const int Mp = ch.bond[i - 1], dp = ch.phys[i - 1];
+      CS(matmul(ctx, site(i - 1), D, tmp, Mp * dp, Ml, Ml));
+      xin = tmp;
+    }
+  }
+  return TDVP_OK;
+}
+
+tdvp_status tdvp_observe(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo, const tdvp_envs *envs,
+                         const int32_t *el_sites, int n_el, double *out_dev) {
+  if (!ctx || !envs || !out_dev || n_el < 0 || (n_el > 0 && !el_sites)) return TDVP_E_ARG;
+  Chain ch;
+  CS(check_chain(mps, mpo, &ch));
+  const int n = ch.n;
+  for (int m = 0; m < n_el; ++m)
+    if (el_sites[m] < 0 || el_sites[m] >= n || ch.phys[el_sites[m]] != 2) return TDVP_E_SHAPE;
+  if (!envs->left || !envs->right || !envs->left[0] || !envs->right[1 < n ? 1 : n]) return TDVP_E_ARG;
+  const Layout lay = layout(ch.nmax, ch.wmax, 1, env_bytes(ctx));
+  CS(need(ctx, lay));
+  CK(hipSetDevice(ctx->device));
+  const double2 *C0 = (const double2 *)mps->site[0];
+  const int64_t n0 = (int64_t)ch.phys[0] * ch.bond[1];
+  CK(dot2d(C0, C0, 1, (int)n0, 0, 1, out_dev + 0, ctx->stream));
+  const Op e{envs->left[0], mpo->site[0], envs->right[1], 1, ch.phys[0], ch.bond[1], ch.wbond[0], ch.wbond[1]};
+  CS(apply_op(ctx, lay, e, C0, nullptr));
+  CK(dot_partials(C0, env_type(ctx), ctx->ws + lay.Y, e.parts(), e.size(), e.size(), out_dev + 1,
+                  ctx->stream));
+  CK(axpy_scalar(out_dev + 1, out_dev + 0, mpo->energy_shift, ctx->stream));
+  if (n_el == 0) return TDVP_OK;
+  int last = 0;
+  for (int m = 0; m < n_el; ++m) last = std::max(last, (int)el_sites[m]);
+  double2 *E = at<double2>(ctx, lay.obs), *E2 = E + lay.n, *T = E + 2 * lay.n;
+  CK(fill_one(E, F64, ctx->stream));
+  for (int i = 0; i <= last; ++i) {
+    const int Ml = ch.bond[i], d = ch.phys[i], Mr = ch.bond[i + 1];
+    const double2 *A = (const double2 *)mps->site[i];
+    CS(matmul(ctx, E, A, T, Ml, Ml, d * Mr));                 // T[l'][s][r] = sum_l E[l'][l] A[l][s][r]
+    for (int m = 0; m < n_el; ++m)
+      if (el_sites[m] == i)
+        CK(dot2d(A + Mr, T + Mr, Ml, Mr, (int64_t)d * Mr, 1, out_dev + 2 + m, ctx->stream));
+    if (i == last) break;
+    GemmArgs g{};                                             // E2[r'][r] = sum conj(A[l'][s][r']) T[l'][s][r]
+    g.A = A; g.B = T; g.C = E2;
+    g.M = Mr; g.N = Mr; g.K = Ml * d; g.batch = 1;
+    g.sam = 1; g.sak = Mr; g.conjA = 1; g.sbk = Mr; g.sbn = 1; g.scm = Mr; g.scn = 1;
+    CK(gemm_t(ctx, F64, F64, F64, g));
+    std::swap(E, E2);
+  }
+  return TDVP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,92 @@
+// Internal declarations shared by the libtdvp translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/tdvp.h"
+
+namespace tdvp {
+
+constexpr int KMAX = 32;          // largest Krylov dimension compiled in
+constexpr int LZ_GRID = 128;      // work-groups of the Lanczos vector kernels
+constexpr int LZ_BLOCK = 256;
+
+enum DType { F64 = 0, F32 = 1 };
+
+// Complex GEMM  C[b][m,n] = sum_k opA(A)[b][m,k] * opB(B)[b][k,n]
+// with arbitrary element strides (in complex elements) and optional
+// conjugation.  Batches b = 0..batch-1.  Optional `skip`: if non-null and
+// *skip != 0 the kernel returns at once (used to predicate Krylov steps).
+struct GemmArgs {
+  const void *A; const void *B; void *C;
+  int M, N, K, batch;
+  int64_t sam, sak, sbk, sbn, scm, scn;
+  int64_t bsa, bsb, bsc;     // batch strides
+  int conjA, conjB;
+  const int *skip;
+};
+
+hipError_t cgemm(DType ta, DType tb, DType tc, const GemmArgs &g, hipStream_t s);
+
+// Sparse MPO-channel contraction (stage 2 of H_eff / environment update):
+//   out[wo][so][a][c] = sum_{wi, si} Wt(wo, so, si, wi) * in[wi][si][a][c]
+// where Wt reads the MPO tensor W (Wl, d, d, Wr) c128 either as
+// W[wo][so][si][wi] (w_in_right = 1: input channel is the right MPO bond) or
+// W[wi][so][si][wo] (w_in_right = 0).  Strides in complex elements.
+struct WApplyArgs {
+  const void *in; void *out; const void *W;
+  int Wl, Wr, d, A, C;
+  int w_in_right;
+  int64_t si_w, si_s, si_a, si_c;   // input strides (w, s, a, c)
+  int64_t so_w, so_s, so_a, so_c;   // output strides
+  const int *skip;
+};
+hipError_t wapply(DType t, const WApplyArgs &a, hipStream_t s);
+
+// Lanczos state kept in device memory for the solve in flight.
+struct LzState {
+  double alpha[KMAX];
+  double beta[KMAX];
+  double scale[KMAX + 1];     // v_j = scale_j * u_j
+  double aw[KMAX];            // |H v_j|
+  double xnorm;
+  double cre[KMAX + 1], cim[KMAX + 1];   // c_i = <v_i, H v_j> of the current step
+  int stop;                   // != 0: no further Lanczos step
+  int k;                      // vectors in the basis so far
+  int kmax;
+  int counter;                // last-block counter (always returns to 0)
+  double z_re, z_im, tol;
+};
+
+struct LzPartials {
+  double dre[LZ_GRID][KMAX + 1];
+  double dim[LZ_GRID][KMAX + 1];
+  double w2[LZ_GRID];
+};
+
+hipError_t lz_start(LzState *st, LzPartials *pp, const double2 *x, double2 *u0, int64_t n,
+                    int kmax, double zr, double zi, double tol, hipStream_t s);
+hipError_t lz_dots(LzState *st, LzPartials *pp, DType ty, const void *ypart, int P, int64_t pstride,
+                   double2 *U, int64_t ldu, int j, int64_t n, hipStream_t s);
+hipError_t lz_update(LzState *st, LzPartials *pp, double2 *U, int64_t ldu, int j, int64_t n,
+                     hipStream_t s);
+hipError_t lz_finish(LzState *st, const double2 *U, int64_t ldu, int64_t n, double2 *y,
+                     int32_t *k_used, hipStream_t s);
+
+// Householder QR of an m x n (m >= n) c128 matrix given by strides; writes
+// Q (m x n) and R (n x n) through output strides, with optional conjugation
+// on input and outputs.  work: m*n c128 + 2n c128.
+struct QrArgs {
+  const double2 *A; int64_t a_rs, a_cs; int conjA;
+  double2 *Q; int64_t q_rs, q_cs; int conjQ;
+  double2 *R; int64_t r_rs, r_cs; int conjR;
+  int m, n;
+  double2 *work;
+};
+hipError_t qr(const QrArgs &a, hipStream_t s);
+
+}  // namespace tdvp
+
+#include "util.h"

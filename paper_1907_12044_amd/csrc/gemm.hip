@@ -1,0 +1,175 @@
+// Complex GEMM on CDNA4 matrix cores (MFMA), FP64 or FP32 arithmetic.
+//
+// Every dense contraction of the TDVP-PS step (stages 1 and 3 of H[i] x,
+// the bond operator of eq:tdvp2_D, the environment update eq:tdvp1_h and the
+// centre move C_{i+1} = D R_{i+1}) is a (batched) complex GEMM with
+// arbitrary strides.  A complex product is four real MFMAs on split
+// real/imaginary planes held in LDS:
+//   Cr += Ar Br - Ai Bi,   Ci += Ar Bi + Ai Br.
+// Tiles: a 256-thread work-group (4 wave64) owns a BM x BN output tile, each
+// wave a (BM/2) x (BN/2) quarter built from 16x16 MFMA blocks
+// (v_mfma_f64_16x16x4_f64 / v_mfma_f32_16x16x4_f32).  Operand lane layout of
+// the 16x16x4 shapes: A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k,
+// D[i][j] in lane j + 16 (i / 4), register i % 4.
+#include "common.h"
+
+namespace tdvp {
+
+namespace {
+
+template <typename T> struct Cplx;
+template <> struct Cplx<double> { using type = double2; };
+template <> struct Cplx<float> { using type = float2; };
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Acc;
+template <> struct Acc<double> { using type = f64x4; };
+template <> struct Acc<float> { using type = f32x4; };
+
+__device__ __forceinline__ f64x4 mfma16(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <typename TA, typename TB, typename TC, typename TM, int BM, int BN, int BK>
+__global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs g) {
+  if (g.skip && *g.skip) return;
+  using VA = typename Cplx<TA>::type;
+  using VB = typename Cplx<TB>::type;
+  using VC = typename Cplx<TC>::type;
+  using AccT = typename Acc<TM>::type;
+  constexpr int PAD = 1;
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int TI = WM / 16, TJ = WN / 16;
+  __shared__ TM As[2][BK][BM + PAD];
+  __shared__ TM Bs[2][BK][BN + PAD];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int bm0 = blockIdx.y * BM;
+  const int bn0 = blockIdx.x * BN;
+  const int bz = blockIdx.z;
+  const VA *A = reinterpret_cast<const VA *>(g.A) + (int64_t)bz * g.bsa;
+  const VB *B = reinterpret_cast<const VB *>(g.B) + (int64_t)bz * g.bsb;
+  VC *C = reinterpret_cast<VC *>(g.C) + (int64_t)bz * g.bsc;
+  const int M = g.M, N = g.N, K = g.K;
+  const bool a_kfast = (g.sak == 1);
+  const bool b_nfast = (g.sbn == 1) || (g.sbk != 1);
+  const TM sa = g.conjA ? TM(-1) : TM(1);
+  const TM sb = g.conjB ? TM(-1) : TM(1);
+  const int wm0 = (wave >> 1) * WM;
+  const int wn0 = (wave & 1) * WN;
+
+  AccT cr[TI][TJ], ci[TI][TJ];
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) {
+      cr[i][j] = AccT{0, 0, 0, 0};
+      ci[i][j] = AccT{0, 0, 0, 0};
+    }
+
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    for (int e = tid; e < BM * BK; e += 256) {
+      int mm, kk;
+      if (a_kfast) { kk = e % BK; mm = e / BK; } else { mm = e % BM; kk = e / BM; }
+      const int gm = bm0 + mm, gk = k0 + kk;
+      TM re = 0, im = 0;
+      if (gm < M && gk < K) {
+        const VA v = A[(int64_t)gm * g.sam + (int64_t)gk * g.sak];
+        re = (TM)v.x;
+        im = sa * (TM)v.y;
+      }
+      As[0][kk][mm] = re;
+      As[1][kk][mm] = im;
+    }
+    for (int e = tid; e < BK * BN; e += 256) {
+      int kk, nn;
+      if (b_nfast) { nn = e % BN; kk = e / BN; } else { kk = e % BK; nn = e / BK; }
+      const int gn = bn0 + nn, gk = k0 + kk;
+      TM re = 0, im = 0;
+      if (gn < N && gk < K) {
+        const VB v = B[(int64_t)gk * g.sbk + (int64_t)gn * g.sbn];
+        re = (TM)v.x;
+        im = sb * (TM)v.y;
+      }
+      Bs[0][kk][nn] = re;
+      Bs[1][kk][nn] = im;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      const int kr = ks + (lane >> 4);
+      TM ar[TI], ai[TI], an[TI], br[TJ], bi[TJ];
+#pragma unroll
+      for (int i = 0; i < TI; ++i) {
+        ar[i] = As[0][kr][wm0 + i * 16 + (lane & 15)];
+        ai[i] = As[1][kr][wm0 + i * 16 + (lane & 15)];
+        an[i] = -ai[i];
+      }
+#pragma unroll
+      for (int j = 0; j < TJ; ++j) {
+        br[j] = Bs[0][kr][wn0 + j * 16 + (lane & 15)];
+        bi[j] = Bs[1][kr][wn0 + j * 16 + (lane & 15)];
+      }
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) {
+          cr[i][j] = mfma16(ar[i], br[j], cr[i][j]);
+          cr[i][j] = mfma16(an[i], bi[j], cr[i][j]);
+          ci[i][j] = mfma16(ar[i], bi[j], ci[i][j]);
+          ci[i][j] = mfma16(ai[i], br[j], ci[i][j]);
+        }
+    }
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = bm0 + wm0 + i * 16 + 4 * (lane >> 4) + r;
+        const int col = bn0 + wn0 + j * 16 + (lane & 15);
+        if (row < M && col < N) {
+          VC v;
+          v.x = (TC)cr[i][j][r];
+          v.y = (TC)ci[i][j][r];
+          C[(int64_t)row * g.scm + (int64_t)col * g.scn] = v;
+        }
+      }
+}
+
+template <typename TA, typename TB, typename TC, typename TM>
+hipError_t launch(const GemmArgs &g, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+  const int64_t tiles64 = (int64_t)((g.M + 63) / 64) * ((g.N + 63) / 64) * g.batch;
+  if (tiles64 >= 240) {
+    dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, g.batch);
+    hipLaunchKernelGGL((cgemm_kernel<TA, TB, TC, TM, 64, 64, 16>), grid, dim3(256), 0, s, g);
+  } else {
+    dim3 grid((g.N + 31) / 32, (g.M + 31) / 32, g.batch);
+    hipLaunchKernelGGL((cgemm_kernel<TA, TB, TC, TM, 32, 32, 16>), grid, dim3(256), 0, s, g);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t cgemm(DType ta, DType tb, DType tc, const GemmArgs &g, hipStream_t s) {
+  if (ta == F64 && tb == F64 && tc == F64) return launch<double, double, double, double>(g, s);
+  if (ta == F64 && tb == F32 && tc == F32) return launch<double, float, float, float>(g, s);
+  if (ta == F32 && tb == F64 && tc == F32) return launch<float, double, float, float>(g, s);
+  if (ta == F32 && tb == F32 && tc == F32) return launch<float, float, float, float>(g, s);
+  if (ta == F64 && tb == F64 && tc == F32) return launch<double, double, float, float>(g, s);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace tdvp

@@ -1,0 +1,387 @@
+// Lanczos propagator y = exp(z H) x for the local equations eq:tdvp2_C and
+// eq:tdvp2_D (Sec. II.A.2): Krylov basis, three-term recurrence with full
+// classical Gram-Schmidt re-orthogonalisation, small exponential of the
+// tridiagonal projected matrix T -- all in FP64 on the device.
+//
+// Basis vectors are stored unnormalised: v_j = scale_j u_j.  Step j is
+//   w   = H u_j                                (operator kernels, P partial sums)
+//   c_i = scale_i scale_j <u_i, w>,  i <= j    (lz_dots)
+//   u_{j+1} = scale_j w - sum_i c_i scale_i u_i,  beta_j = |u_{j+1}|
+//   alpha_j = Re c_j,  scale_{j+1} = 1 / beta_j (lz_update)
+// so no separate normalisation pass is needed; the next H application acts
+// on u_{j+1} directly.  Grid-wide sums are made deterministic by writing one
+// partial per work-group and letting the last work-group to finish (ticket
+// from an atomic counter) add the partials in work-group order.  Later
+// kernels of a finished solve return at once (LzState::stop), so a fixed
+// sequence of launches serves every Krylov length.
+#include "common.h"
+
+namespace tdvp {
+
+namespace {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Sum of v over a 256-thread block, result valid in every thread.
+__device__ double block_sum(double v, double *sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
+  return t;
+}
+
+// Ticket of the last block: true in every thread of the block that finished last.
+__device__ bool last_block(int *counter) {
+  __shared__ int is_last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // system scope: the ticket is taken in memory, coherent across the XCDs' L2s
+    const int t = __hip_atomic_fetch_add(counter, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_SYSTEM);
+    is_last = (t == (int)gridDim.x - 1);
+  }
+  __syncthreads();
+  if (is_last) __threadfence();
+  return is_last != 0;
+}
+
+__device__ __forceinline__ void reset_counter(int *counter) {
+  __hip_atomic_store(counter, 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// exp(z T) e_1 for the k x k real symmetric tridiagonal T(alpha, beta),
+// computed by one wave64 (lane i holds component i): T is shifted by the
+// mean of its diagonal (the shift returns as the scalar factor
+// exp(z shift)); the interval is cut into s pieces with |z| |T'| / s <= 2
+// (Gershgorin bound) and on each piece the Taylor series of exp is summed
+// until its terms fall below 1e-17 of the running sum (at most 40 terms).
+// Writes k complex coefficients to (outr, outi).
+__device__ void exp_tridiag_e1_wave(const double *alpha, const double *beta, int k, double zr,
+                                    double zi, double *outr, double *outi) {
+  const int lane = threadIdx.x & 63;
+  const bool act = lane < k;
+  double a = act ? alpha[lane] : 0.0;
+  const double bu = (lane + 1 < k) ? beta[lane] : 0.0;       // T[lane][lane+1]
+  const double shift = wave_sum(a) / (double)k;
+  a = act ? a - shift : 0.0;
+  const double bd = __shfl_up(bu, 1, 64);                    // T[lane][lane-1]
+  const double bdl = (lane > 0 && act) ? bd : 0.0;
+  const double gersh = wave_max(fabs(a) + fabs(bu) + fabs(bdl));
+  const double zabs = sqrt(zr * zr + zi * zi);
+  const double pieces = ceil(zabs * gersh / 2.0);
+  // a non-finite T (from a non-finite input) gives one piece: the result is
+  // non-finite but the loop stays bounded
+  int ns = (pieces >= 1.0 && pieces <= 65536.0) ? (int)pieces : (pieces > 65536.0 ? 65536 : 1);
+  const double hr = zr / ns, hi = zi / ns;
+  double vr = (lane == 0) ? 1.0 : 0.0, vi = 0.0;
+  for (int s = 0; s < ns; ++s) {
+    double tr = vr, ti = vi, sr = vr, si = vi;
+    for (int t = 1; t <= 40; ++t) {
+      const double tmr = __shfl_up(tr, 1, 64), tmi = __shfl_up(ti, 1, 64);
+      const double tpr = __shfl_down(tr, 1, 64), tpi = __shfl_down(ti, 1, 64);
+      double xr = a * tr + bdl * tmr + bu * tpr;
+      double xi = a * ti + bdl * tmi + bu * tpi;
+      if (!act) { xr = 0.0; xi = 0.0; }
+      const double inv = 1.0 / (double)t;
+      tr = (hr * xr - hi * xi) * inv;
+      ti = (hr * xi + hi * xr) * inv;
+      sr += tr;
+      si += ti;
+      const double tmag = wave_max(fabs(tr) + fabs(ti));
+      const double smag = wave_max(fabs(sr) + fabs(si));
+      if (tmag <= 1e-17 * smag) break;
+    }
+    vr = sr;
+    vi = si;
+  }
+  // multiply by exp(z shift)
+  const double er = exp(zr * shift);
+  double sn, cs;
+  sincos(zi * shift, &sn, &cs);
+  const double pr = er * cs, pi = er * sn;
+  if (act) {
+    outr[lane] = vr * pr - vi * pi;
+    outi[lane] = vr * pi + vi * pr;
+  }
+}
+
+__global__ __launch_bounds__(LZ_BLOCK) void lz_start_kernel(LzState *st, LzPartials *pp,
+                                                            const double2 *x, double2 *u0,
+                                                            int64_t n, int kmax, double zr,
+                                                            double zi, double tol) {
+  __shared__ double sh[8];
+  double s = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const double2 v = x[e];
+    u0[e] = v;
+    s += v.x * v.x + v.y * v.y;
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) pp->w2[blockIdx.x] = s;
+  if (last_block(&st->counter)) {
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int b = 0; b < (int)gridDim.x; ++b) t += pp->w2[b];
+      const double xn = sqrt(t);
+      st->xnorm = xn;
+      st->scale[0] = xn > 0.0 ? 1.0 / xn : 0.0;
+      st->stop = (xn > 0.0 && isfinite(xn)) ? 0 : 1;
+      st->k = 0;
+      st->kmax = kmax;
+      st->z_re = zr;
+      st->z_im = zi;
+      st->tol = tol;
+      reset_counter(&st->counter);
+    }
+  }
+}
+
+// w = sum_p ypart[p] -> U[j+1]; per-block partial dots with u_0..u_j and |w|^2.
+template <typename TY, int JB>
+__global__ __launch_bounds__(LZ_BLOCK) void lz_dots_kernel(LzState *st, LzPartials *pp,
+                                                           const TY *ypart, int P,
+                                                           int64_t pstride, double2 *U,
+                                                           int64_t ldu, int j, int64_t n) {
+  if (st->stop) return;
+  __shared__ double sh[4][2 * JB + 1];
+  double dr[JB], di[JB];
+#pragma unroll
+  for (int i = 0; i < JB; ++i) { dr[i] = 0.0; di[i] = 0.0; }
+  double w2 = 0.0;
+  double2 *wdst = U + (int64_t)(j + 1) * ldu;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double wr = 0.0, wi = 0.0;
+    for (int p = 0; p < P; ++p) {
+      const TY v = ypart[(int64_t)p * pstride + e];
+      wr += (double)v.x;
+      wi += (double)v.y;
+    }
+    wdst[e] = make_double2(wr, wi);
+    w2 += wr * wr + wi * wi;
+#pragma unroll
+    for (int i = 0; i < JB; ++i) {
+      if (i <= j) {
+        const double2 u = U[(int64_t)i * ldu + e];
+        dr[i] += u.x * wr + u.y * wi;
+        di[i] += u.x * wi - u.y * wr;
+      }
+    }
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < JB; ++i) {
+    if (i <= j) {
+      const double a = wave_sum(dr[i]);
+      const double b = wave_sum(di[i]);
+      if (lane == 0) { sh[wave][2 * i] = a; sh[wave][2 * i + 1] = b; }
+    }
+  }
+  {
+    const double a = wave_sum(w2);
+    if (lane == 0) sh[wave][2 * JB] = a;
+  }
+  __syncthreads();
+  if (threadIdx.x <= j) {
+    const int i = threadIdx.x;
+    double a = 0.0, b = 0.0;
+    for (int w = 0; w < 4; ++w) { a += sh[w][2 * i]; b += sh[w][2 * i + 1]; }
+    pp->dre[blockIdx.x][i] = a;
+    pp->dim[blockIdx.x][i] = b;
+  }
+  if (threadIdx.x == 0) {
+    double a = 0.0;
+    for (int w = 0; w < 4; ++w) a += sh[w][2 * JB];
+    pp->w2[blockIdx.x] = a;
+  }
+  if (last_block(&st->counter)) {
+    if (threadIdx.x <= j) {
+      const int i = threadIdx.x;
+      double a = 0.0, b = 0.0;
+      for (int blk = 0; blk < (int)gridDim.x; ++blk) { a += pp->dre[blk][i]; b += pp->dim[blk][i]; }
+      const double sc = st->scale[i] * st->scale[j];
+      st->cre[i] = a * sc;
+      st->cim[i] = b * sc;
+      if (i == j) st->alpha[j] = a * sc;
+    }
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int blk = 0; blk < (int)gridDim.x; ++blk) t += pp->w2[blk];
+      st->aw[j] = sqrt(t) * st->scale[j];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) reset_counter(&st->counter);
+  }
+}
+
+// u_{j+1} = scale_j w - sum_{i<=j} c_i scale_i u_i ; beta_j = |u_{j+1}|.
+template <int JB>
+__global__ __launch_bounds__(LZ_BLOCK) void lz_update_kernel(LzState *st, LzPartials *pp,
+                                                             double2 *U, int64_t ldu, int j,
+                                                             int64_t n) {
+  if (st->stop) return;
+  __shared__ double sh[8];
+  __shared__ double cr[JB], ci[JB];
+  __shared__ double coefr[KMAX], coefi[KMAX];
+  if (threadIdx.x <= j) {
+    const int i = threadIdx.x;
+    cr[i] = st->cre[i] * st->scale[i];
+    ci[i] = st->cim[i] * st->scale[i];
+  }
+  __syncthreads();
+  const double sj = st->scale[j];
+  double2 *w = U + (int64_t)(j + 1) * ldu;
+  double s2 = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const double2 wv = w[e];
+    double xr = sj * wv.x, xi = sj * wv.y;
+#pragma unroll
+    for (int i = 0; i < JB; ++i) {
+      if (i <= j) {
+        const double2 u = U[(int64_t)i * ldu + e];
+        xr -= cr[i] * u.x - ci[i] * u.y;
+        xi -= cr[i] * u.y + ci[i] * u.x;
+      }
+    }
+    w[e] = make_double2(xr, xi);
+    s2 += xr * xr + xi * xi;
+  }
+  s2 = block_sum(s2, sh);
+  if (threadIdx.x == 0) pp->w2[blockIdx.x] = s2;
+  if (last_block(&st->counter)) {
+    __shared__ int stop_s;
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int blk = 0; blk < (int)gridDim.x; ++blk) t += pp->w2[blk];
+      const double b = sqrt(t);
+      const int k = j + 1;
+      st->k = k;
+      int stop = 0;
+      if (k >= st->kmax || !(b > 1e-12 * st->aw[j]) || !isfinite(b)) stop = 1;
+      if (!stop) {
+        st->beta[j] = b;
+        st->scale[j + 1] = 1.0 / b;
+      }
+      stop_s = stop;
+    }
+    __syncthreads();
+    if (!stop_s && st->tol > 0.0 && threadIdx.x < 64) {
+      // a-posteriori estimate |z beta_j [exp(z T_k) e_1]_{k-1}|
+      exp_tridiag_e1_wave(st->alpha, st->beta, j + 1, st->z_re, st->z_im, coefr, coefi);
+      if (threadIdx.x == 0) {
+        const double zabs = sqrt(st->z_re * st->z_re + st->z_im * st->z_im);
+        const double c = sqrt(coefr[j] * coefr[j] + coefi[j] * coefi[j]);
+        if (zabs * st->beta[j] * c < st->tol) stop_s = 1;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      st->stop = stop_s;
+      reset_counter(&st->counter);
+    }
+  }
+}
+
+// y = |x| sum_i [exp(z T_k) e_1]_i v_i.  Every block evaluates the small
+// exponential redundantly (wave 0), then combines its slice of the basis.
+__global__ __launch_bounds__(LZ_BLOCK) void lz_finish_kernel(LzState *st, const double2 *U,
+                                                             int64_t ldu, int64_t n, double2 *y,
+                                                             int32_t *k_used) {
+  __shared__ double cr[KMAX], ci[KMAX];
+  const int k = st->k;
+  const double xn = st->xnorm;
+  const bool zero = !(xn > 0.0) || k <= 0;
+  if (!zero && threadIdx.x < 64)
+    exp_tridiag_e1_wave(st->alpha, st->beta, k, st->z_re, st->z_im, cr, ci);
+  __syncthreads();
+  if (!zero && threadIdx.x < k) {
+    const double sc = xn * st->scale[threadIdx.x];
+    cr[threadIdx.x] *= sc;
+    ci[threadIdx.x] *= sc;
+  }
+  __syncthreads();
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double yr = 0.0, yi = 0.0;
+    if (!zero) {
+      for (int i = 0; i < k; ++i) {
+        const double2 u = U[(int64_t)i * ldu + e];
+        yr += cr[i] * u.x - ci[i] * u.y;
+        yi += cr[i] * u.y + ci[i] * u.x;
+      }
+    }
+    y[e] = make_double2(yr, yi);
+  }
+  if (k_used && blockIdx.x == 0 && threadIdx.x == 0) *k_used = k;
+}
+
+int grid_for(int64_t n) {
+  int64_t g = (n + LZ_BLOCK - 1) / LZ_BLOCK;
+  if (g > LZ_GRID) g = LZ_GRID;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+}  // namespace
+
+hipError_t lz_start(LzState *st, LzPartials *pp, const double2 *x, double2 *u0, int64_t n,
+                    int kmax, double zr, double zi, double tol, hipStream_t s) {
+  hipLaunchKernelGGL(lz_start_kernel, dim3(grid_for(n)), dim3(LZ_BLOCK), 0, s, st, pp, x, u0, n,
+                     kmax, zr, zi, tol);
+  return hipGetLastError();
+}
+
+hipError_t lz_dots(LzState *st, LzPartials *pp, DType ty, const void *ypart, int P, int64_t pstride,
+                   double2 *U, int64_t ldu, int j, int64_t n, hipStream_t s) {
+  const dim3 g(grid_for(n)), b(LZ_BLOCK);
+#define LZ_DOTS(T, JB)                                                                         \
+  hipLaunchKernelGGL((lz_dots_kernel<T, JB>), g, b, 0, s, st, pp, (const T *)ypart, P, pstride, \
+                     U, ldu, j, n)
+  if (ty == F64) {
+    if (j < 4) LZ_DOTS(double2, 4);
+    else if (j < 8) LZ_DOTS(double2, 8);
+    else if (j < 16) LZ_DOTS(double2, 16);
+    else LZ_DOTS(double2, 32);
+  } else {
+    if (j < 4) LZ_DOTS(float2, 4);
+    else if (j < 8) LZ_DOTS(float2, 8);
+    else if (j < 16) LZ_DOTS(float2, 16);
+    else LZ_DOTS(float2, 32);
+  }
+#undef LZ_DOTS
+  return hipGetLastError();
+}
+
+hipError_t lz_update(LzState *st, LzPartials *pp, double2 *U, int64_t ldu, int j, int64_t n,
+                     hipStream_t s) {
+  const dim3 g(grid_for(n)), b(LZ_BLOCK);
+  if (j < 4) hipLaunchKernelGGL((lz_update_kernel<4>), g, b, 0, s, st, pp, U, ldu, j, n);
+  else if (j < 8) hipLaunchKernelGGL((lz_update_kernel<8>), g, b, 0, s, st, pp, U, ldu, j, n);
+  else if (j < 16) hipLaunchKernelGGL((lz_update_kernel<16>), g, b, 0, s, st, pp, U, ldu, j, n);
+  else hipLaunchKernelGGL((lz_update_kernel<32>), g, b, 0, s, st, pp, U, ldu, j, n);
+  return hipGetLastError();
+}
+
+hipError_t lz_finish(LzState *st, const double2 *U, int64_t ldu, int64_t n, double2 *y,
+                     int32_t *k_used, hipStream_t s) {
+  hipLaunchKernelGGL(lz_finish_kernel, dim3(grid_for(n)), dim3(LZ_BLOCK), 0, s, st, U, ldu, n, y,
+                     k_used);
+  return hipGetLastError();
+}
+
+}  // namespace tdvp

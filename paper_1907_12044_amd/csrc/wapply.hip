@@ -1,0 +1,106 @@
+// Stage 2 of the effective-Hamiltonian and environment contractions: the
+// MPO site tensor W^{s' s}_{w w'} (eq:mpo) applied over the channel and
+// physical indices,
+//   out[wo][so][a][c] = sum_{wi, si} W(wo, so, si, wi) in[wi][si][a][c].
+// An MPO of a sum of local terms is block sparse over (w, w'): for each
+// output row (wo, so) the work-group first compacts the nonzero
+// coefficients (in a fixed order, so results are deterministic), then every
+// thread forms one (a, c) output from those few terms.  The pass is bound by
+// HBM traffic (read in, write out); c is the fastest index on both sides.
+#include "common.h"
+
+namespace tdvp {
+
+namespace {
+
+constexpr int MAXNZ = 1024;
+
+template <typename T> struct Cplx;
+template <> struct Cplx<double> { using type = double2; };
+template <> struct Cplx<float> { using type = float2; };
+
+template <typename T>
+__global__ __launch_bounds__(256) void wapply_kernel(WApplyArgs p) {
+  if (p.skip && *p.skip) return;
+  using V = typename Cplx<T>::type;
+  __shared__ T cre[MAXNZ], cim[MAXNZ];
+  __shared__ int cw[MAXNZ], cs[MAXNZ];
+  __shared__ int nnz_s;
+  const int d = p.d;
+  const int wo = blockIdx.y / d, so = blockIdx.y % d;
+  const int Win = p.w_in_right ? p.Wr : p.Wl;
+  const double2 *W = reinterpret_cast<const double2 *>(p.W);
+  const int ncand = Win * d;
+  // ordered compaction of nonzero coefficients by wave 0
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    int base = 0;
+    for (int c0 = 0; c0 < ncand; c0 += 64) {
+      const int c = c0 + lane;
+      double2 v = make_double2(0.0, 0.0);
+      int wi = 0, si = 0;
+      if (c < ncand) {
+        wi = c / d;
+        si = c % d;
+        int64_t idx;
+        if (p.w_in_right)   // W[wo][so][si][wi], shape (Wl, d, d, Wr)
+          idx = (((int64_t)wo * d + so) * d + si) * p.Wr + wi;
+        else                // W[wi][so][si][wo]
+          idx = (((int64_t)wi * d + so) * d + si) * p.Wr + wo;
+        v = W[idx];
+      }
+      const bool nz = (c < ncand) && (v.x != 0.0 || v.y != 0.0);
+      const unsigned long long mask = __ballot(nz);
+      const unsigned long long below = (lane == 0) ? 0ull : (mask & ((~0ull) >> (64 - lane)));
+      const int pos = base + __popcll(below);
+      if (nz && pos < MAXNZ) {
+        cre[pos] = (T)v.x;
+        cim[pos] = (T)v.y;
+        cw[pos] = wi;
+        cs[pos] = si;
+      }
+      base += __popcll(mask);
+    }
+    if (lane == 0) nnz_s = base < MAXNZ ? base : MAXNZ;
+  }
+  __syncthreads();
+  const int nnz = nnz_s;
+  const V *in = reinterpret_cast<const V *>(p.in);
+  V *out = reinterpret_cast<V *>(p.out);
+  const int64_t total = (int64_t)p.A * p.C;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t a = e / p.C, c = e % p.C;
+    const V *ip = in + a * p.si_a + c * p.si_c;
+    T re = 0, im = 0;
+    for (int t = 0; t < nnz; ++t) {
+      const V v = ip[(int64_t)cw[t] * p.si_w + (int64_t)cs[t] * p.si_s];
+      re += cre[t] * v.x - cim[t] * v.y;
+      im += cre[t] * v.y + cim[t] * v.x;
+    }
+    V o;
+    o.x = re;
+    o.y = im;
+    out[(int64_t)wo * p.so_w + (int64_t)so * p.so_s + a * p.so_a + c * p.so_c] = o;
+  }
+}
+
+}  // namespace
+
+hipError_t wapply(DType t, const WApplyArgs &a, hipStream_t s) {
+  const int Wout = a.w_in_right ? a.Wl : a.Wr;
+  const int Win = a.w_in_right ? a.Wr : a.Wl;
+  if (Win * a.d > MAXNZ) return hipErrorInvalidValue;
+  const int64_t total = (int64_t)a.A * a.C;
+  if (total <= 0 || Wout <= 0) return hipSuccess;
+  int gx = (int)((total + 255) / 256);
+  if (gx > 64) gx = 64;
+  dim3 grid(gx, Wout * a.d);
+  if (t == F64)
+    hipLaunchKernelGGL(wapply_kernel<double>, grid, dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(wapply_kernel<float>, grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace tdvp

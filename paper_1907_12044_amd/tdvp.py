@@ -1,0 +1,369 @@
+"""Thin ctypes binding of libtdvp (include/tdvp.h).
+
+Only argument marshalling happens here: torch tensors provide device memory
+and the HIP stream, every step of the TDVP-PS path runs in the library's
+kernels.  If the library is not built the import of any entry point raises;
+there is no CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_int, c_int32, c_int64, c_size_t, c_void_p
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtdvp.so")
+
+FP64 = 0
+FP32 = 1
+
+HARTREE_PER_CM = 4.556335252767e-6   # 1 cm^-1 in hartree
+AU_PER_FS = 41.341373335             # 1 fs in atomic units of time
+
+
+class TdvpError(RuntimeError):
+    pass
+
+
+class _Mps(ctypes.Structure):
+    _fields_ = [("n", c_int32), ("phys", POINTER(c_int32)), ("bond", POINTER(c_int32)),
+                ("site", POINTER(c_void_p))]
+
+
+class _Mpo(ctypes.Structure):
+    _fields_ = [("n", c_int32), ("phys", POINTER(c_int32)), ("bond", POINTER(c_int32)),
+                ("site", POINTER(c_void_p)), ("energy_shift", c_double)]
+
+
+class _Envs(ctypes.Structure):
+    _fields_ = [("left", POINTER(c_void_p)), ("right", POINTER(c_void_p))]
+
+
+EXPORTS = {
+    "tdvp_create": (c_int, [POINTER(c_void_p), c_int, c_void_p, c_int]),
+    "tdvp_destroy": (c_int, [c_void_p]),
+    "tdvp_set_stream": (c_int, [c_void_p, c_void_p]),
+    "tdvp_status_string": (ctypes.c_char_p, [c_int]),
+    "tdvp_env_elem_bytes": (c_int, [c_void_p]),
+    "tdvp_workspace_bytes": (c_int, [c_void_p, POINTER(_Mps), POINTER(_Mpo), c_int, POINTER(c_size_t)]),
+    "tdvp_set_workspace": (c_int, [c_void_p, c_void_p, c_size_t]),
+    "tdvp_env_update": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_int, c_int, c_int,
+                                c_int, c_int, c_void_p]),
+    "tdvp_heff_apply": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_int,
+                                c_int, c_void_p, c_void_p]),
+    "tdvp_lanczos_expm": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_int,
+                                  c_int, c_double, c_double, c_int, c_double, c_void_p, c_void_p,
+                                  c_void_p]),
+    "tdvp_qr": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p]),
+    "tdvp_right_canonicalize": (c_int, [c_void_p, POINTER(_Mps)]),
+    "tdvp_envs_build": (c_int, [c_void_p, POINTER(_Mps), POINTER(_Mpo), POINTER(_Envs)]),
+    "tdvp_ps_step": (c_int, [c_void_p, POINTER(_Mps), POINTER(_Mpo), POINTER(_Envs), c_double, c_int,
+                             c_int, c_double]),
+    "tdvp_observe": (c_int, [c_void_p, POINTER(_Mps), POINTER(_Mpo), POINTER(_Envs), POINTER(c_int32),
+                             c_int, c_void_p]),
+    "tdvp_set_krylov_log": (c_int, [c_void_p, c_void_p, c_int]),
+    "tdvp_profile": (c_int, [c_void_p, c_int]),
+    "tdvp_profile_read": (c_int, [c_void_p, POINTER(c_double), POINTER(c_int64), POINTER(c_double),
+                                  POINTER(c_double)]),
+    "tdvp_holstein_mpo": (c_int, [c_int, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32), c_int,
+                                  POINTER(c_double), POINTER(c_double), POINTER(c_double),
+                                  POINTER(c_double), POINTER(c_int32), POINTER(c_int64),
+                                  POINTER(c_double)]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libtdvp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise TdvpError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status, what):
+    if status != 0:
+        msg = lib().tdvp_status_string(status).decode()
+        raise TdvpError(f"{what}: {msg} (status {status})")
+
+
+def _ptr(t):
+    return c_void_p(t.data_ptr())
+
+
+def _i32(a):
+    return (c_int32 * len(a))(*[int(v) for v in a])
+
+
+# ---------------------------------------------------------------- host MPO
+
+def holstein_mpo(kind, owner, phys, eps, J, w, g):
+    """Frenkel-Holstein MPO tensors (host numpy complex128), built by the library."""
+    n = len(kind)
+    n_e = int(np.asarray(eps).size)
+    bond = (c_int32 * (n + 1))()
+    total = c_int64(0)
+    k, o, p = _i32(kind), _i32(owner), _i32(phys)
+    epsa = np.ascontiguousarray(eps, dtype=np.float64)
+    Ja = np.ascontiguousarray(J, dtype=np.float64).reshape(-1)
+    wa = np.ascontiguousarray(w, dtype=np.float64)
+    ga = np.ascontiguousarray(g, dtype=np.float64)
+    dp = POINTER(c_double)
+    _check(lib().tdvp_holstein_mpo(n, k, o, p, n_e, epsa.ctypes.data_as(dp), Ja.ctypes.data_as(dp),
+                                   wa.ctypes.data_as(dp), ga.ctypes.data_as(dp), bond,
+                                   ctypes.byref(total), None), "tdvp_holstein_mpo(query)")
+    out = np.zeros(2 * total.value, dtype=np.float64)
+    _check(lib().tdvp_holstein_mpo(n, k, o, p, n_e, epsa.ctypes.data_as(dp), Ja.ctypes.data_as(dp),
+                                   wa.ctypes.data_as(dp), ga.ctypes.data_as(dp), bond,
+                                   ctypes.byref(total), out.ctypes.data_as(dp)), "tdvp_holstein_mpo")
+    cpx = out.view(np.complex128)
+    Ws = []
+    off = 0
+    for i in range(n):
+        shape = (bond[i], phys[i], phys[i], bond[i + 1])
+        size = int(np.prod(shape))
+        Ws.append(cpx[off:off + size].reshape(shape).copy())
+        off += size
+    return Ws, [bond[i] for i in range(n + 1)]
+
+
+def fmo_model(params, sites):
+    """MPO inputs of an FMO-like chain: energies in hartree, constant offset removed.
+
+    Returns (Ws, mpo_bond, energy_shift) where H' = H - energy_shift on the
+    one-exciton sector (shift = mean site energy + zero-point energy).
+    """
+    E = np.asarray(params.E) * HARTREE_PER_CM
+    Ebar = float(np.mean(E))
+    eps = E - Ebar
+    J = np.asarray(params.J) * HARTREE_PER_CM
+    kind, owner, phys, w, g = [], [], [], [], []
+    for s in sites:
+        kind.append(0 if s[0] == "el" else 1)
+        owner.append(s[1])
+        phys.append(s[3])
+        if s[0] == "el":
+            w.append(0.0)
+            g.append(0.0)
+        else:
+            w.append(params.omega[s[1], s[2]] * HARTREE_PER_CM)
+            g.append(np.sqrt(params.S[s[1], s[2]]))
+    shift = Ebar + 0.5 * float(np.sum(w))
+    Ws, bond = holstein_mpo(kind, owner, phys, eps, J, w, g)
+    return Ws, bond, shift
+
+
+# ---------------------------------------------------------------- device objects
+
+class Context:
+    """A libtdvp context bound to a torch CUDA (HIP) stream, plus its workspace."""
+
+    def __init__(self, device=0, precision=FP64, stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        self.precision = precision
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = c_void_p()
+        _check(lib().tdvp_create(ctypes.byref(h), device, c_void_p(stream.cuda_stream), precision),
+               "tdvp_create")
+        self.h = h
+        self.ws = None
+
+    @property
+    def env_dtype(self):
+        return self.torch.complex128 if self.precision == FP64 else self.torch.complex64
+
+    def reserve(self, nbytes):
+        """Make sure the workspace holds at least nbytes (a torch uint8 buffer)."""
+        if self.ws is None or self.ws.numel() < nbytes:
+            self.ws = self.torch.empty(int(nbytes) + 256, dtype=self.torch.uint8, device=self.device)
+            base = self.ws.data_ptr()
+            off = (-base) % 256
+            _check(lib().tdvp_set_workspace(self.h, c_void_p(base + off), int(nbytes)),
+                   "tdvp_set_workspace")
+
+    def close(self):
+        if self.h:
+            lib().tdvp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class DeviceMps:
+    """MPS site tensors (complex128 torch tensors on the GPU) with a C descriptor."""
+
+    def __init__(self, tensors, device):
+        import torch
+        self.t = [torch.as_tensor(np.ascontiguousarray(A), dtype=torch.complex128).to(device)
+                  for A in tensors]
+        self.phys = [A.shape[1] for A in self.t]
+        self.bond = [self.t[0].shape[0]] + [A.shape[2] for A in self.t]
+        self._phys = _i32(self.phys)
+        self._bond = _i32(self.bond)
+        self._site = (c_void_p * len(self.t))(*[A.data_ptr() for A in self.t])
+        self.desc = _Mps(len(self.t), self._phys, self._bond, self._site)
+
+    def numpy(self):
+        return [A.cpu().numpy() for A in self.t]
+
+
+class DeviceMpo:
+    def __init__(self, Ws, bond, shift, device):
+        import torch
+        self.t = [torch.as_tensor(np.ascontiguousarray(W), dtype=torch.complex128).to(device) for W in Ws]
+        self.phys = [W.shape[1] for W in self.t]
+        self.bond = list(bond)
+        self.shift = float(shift)
+        self._phys = _i32(self.phys)
+        self._bond = _i32(self.bond)
+        self._site = (c_void_p * len(self.t))(*[W.data_ptr() for W in self.t])
+        self.desc = _Mpo(len(self.t), self._phys, self._bond, self._site, self.shift)
+
+
+class DeviceEnvs:
+    def __init__(self, mps_bond, mpo_bond, dtype, device):
+        import torch
+        n = len(mps_bond) - 1
+        self.left = [torch.zeros((mps_bond[b], mpo_bond[b], mps_bond[b]), dtype=dtype, device=device)
+                     for b in range(n + 1)]
+        self.right = [torch.zeros((mps_bond[b], mpo_bond[b], mps_bond[b]), dtype=dtype, device=device)
+                      for b in range(n + 1)]
+        self._l = (c_void_p * (n + 1))(*[t.data_ptr() for t in self.left])
+        self._r = (c_void_p * (n + 1))(*[t.data_ptr() for t in self.right])
+        self.desc = _Envs(self._l, self._r)
+
+
+# ---------------------------------------------------------------- entry points
+
+def workspace_bytes(ctx, mps, mpo, kmax):
+    b = c_size_t(0)
+    _check(lib().tdvp_workspace_bytes(ctx.h, ctypes.byref(mps.desc),
+                                      ctypes.byref(mpo.desc) if mpo is not None else None,
+                                      kmax, ctypes.byref(b)), "tdvp_workspace_bytes")
+    return b.value
+
+
+def env_update(ctx, direction, env_in, A, W, Ml, d, Mr, Wl, Wr, env_out):
+    _check(lib().tdvp_env_update(ctx.h, direction, _ptr(env_in), _ptr(A), _ptr(W), Ml, d, Mr, Wl, Wr,
+                                 _ptr(env_out)), "tdvp_env_update")
+
+
+def heff_apply(ctx, Lenv, W, Renv, Ml, d, Mr, Wl, Wr, x, y):
+    _check(lib().tdvp_heff_apply(ctx.h, _ptr(Lenv), _ptr(W) if W is not None else None, _ptr(Renv),
+                                 Ml, d, Mr, Wl, Wr, _ptr(x), _ptr(y)), "tdvp_heff_apply")
+
+
+def lanczos_expm(ctx, Lenv, W, Renv, Ml, d, Mr, Wl, Wr, z, kmax, tol, x, y, k_used=None):
+    _check(lib().tdvp_lanczos_expm(ctx.h, _ptr(Lenv), _ptr(W) if W is not None else None, _ptr(Renv),
+                                   Ml, d, Mr, Wl, Wr, float(np.real(z)), float(np.imag(z)), kmax,
+                                   float(tol), _ptr(x), _ptr(y),
+                                   _ptr(k_used) if k_used is not None else None), "tdvp_lanczos_expm")
+
+
+def qr(ctx, A, m, n, Q, R):
+    _check(lib().tdvp_qr(ctx.h, _ptr(A), m, n, _ptr(Q), _ptr(R)), "tdvp_qr")
+
+
+def right_canonicalize(ctx, mps):
+    _check(lib().tdvp_right_canonicalize(ctx.h, ctypes.byref(mps.desc)), "tdvp_right_canonicalize")
+
+
+def envs_build(ctx, mps, mpo, envs):
+    _check(lib().tdvp_envs_build(ctx.h, ctypes.byref(mps.desc), ctypes.byref(mpo.desc),
+                                 ctypes.byref(envs.desc)), "tdvp_envs_build")
+
+
+def ps_step(ctx, mps, mpo, envs, dt, nsteps=1, kmax=20, tol=0.0):
+    _check(lib().tdvp_ps_step(ctx.h, ctypes.byref(mps.desc), ctypes.byref(mpo.desc),
+                              ctypes.byref(envs.desc), float(dt), int(nsteps), int(kmax), float(tol)),
+           "tdvp_ps_step")
+
+
+def observe(ctx, mps, mpo, envs, el_sites, out):
+    arr = _i32(el_sites)
+    _check(lib().tdvp_observe(ctx.h, ctypes.byref(mps.desc), ctypes.byref(mpo.desc),
+                              ctypes.byref(envs.desc), arr, len(el_sites), _ptr(out)), "tdvp_observe")
+
+
+PROF_GEMM, PROF_WAPPLY, PROF_LANCZOS, PROF_QR = 1, 2, 3, 4
+
+
+def set_krylov_log(ctx, buf):
+    """Log the Krylov dimension of every solve of the next ps_step calls into buf (int32)."""
+    if buf is None:
+        _check(lib().tdvp_set_krylov_log(ctx.h, None, 0), "tdvp_set_krylov_log")
+    else:
+        _check(lib().tdvp_set_krylov_log(ctx.h, _ptr(buf), buf.numel()), "tdvp_set_krylov_log")
+
+
+def profile(ctx, kernel_class):
+    _check(lib().tdvp_profile(ctx.h, kernel_class), "tdvp_profile")
+
+
+def profile_read(ctx):
+    """(total ms, launches, algorithmic FLOP, algorithmic bytes) of the profiled launches."""
+    ms, n, f, b = c_double(), c_int64(), c_double(), c_double()
+    _check(lib().tdvp_profile_read(ctx.h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(f),
+                                   ctypes.byref(b)), "tdvp_profile_read")
+    return ms.value, n.value, f.value, b.value
+
+
+# ---------------------------------------------------------------- a whole run
+
+class PsRun:
+    """An FMO-like chain evolved with TDVP-PS on one GPU.
+
+    ``raw_mps`` are the (non-canonical) initial site tensors; they are
+    right-canonicalised and normalised on the device, the right environments
+    built, and every later step runs through tdvp_ps_step.
+    """
+
+    def __init__(self, params, sites, raw_mps, device=0, precision=FP64, kmax=20, tol=0.0):
+        import torch
+        self.torch = torch
+        self.ctx = Context(device, precision)
+        dev = self.ctx.device
+        self.sites = sites
+        self.n_e = params.n_e
+        Ws, wbond, shift = fmo_model(params, sites)
+        self.mpo = DeviceMpo(Ws, wbond, shift, dev)
+        self.mps = DeviceMps(raw_mps, dev)
+        self.envs = DeviceEnvs(self.mps.bond, wbond, self.ctx.env_dtype, dev)
+        self.kmax = kmax
+        self.tol = tol
+        self.ctx.reserve(workspace_bytes(self.ctx, self.mps, self.mpo, kmax))
+        self.el_sites = [0] * params.n_e
+        for i, s in enumerate(sites):
+            if s[0] == "el":
+                self.el_sites[s[1]] = i
+        self.obs = torch.zeros(2 + params.n_e, dtype=torch.float64, device=dev)
+        right_canonicalize(self.ctx, self.mps)
+        envs_build(self.ctx, self.mps, self.mpo, self.envs)
+
+    def step(self, dt_au, nsteps=1):
+        ps_step(self.ctx, self.mps, self.mpo, self.envs, dt_au, nsteps, self.kmax, self.tol)
+
+    def observe(self, out=None):
+        """Device tensor [norm^2, energy, populations...] (enqueued, not synchronised)."""
+        out = self.obs if out is None else out
+        observe(self.ctx, self.mps, self.mpo, self.envs, self.el_sites, out)
+        return out

@@ -1,0 +1,236 @@
+"""Parity of each HIP entry point with the oracle, element by element.
+
+Shapes span several GEMM tiles (32 and 64 wide) with ragged tails, physical
+dims 1, 2, 8 and 10, and MPO channel dims up to 9 with block-sparse W.
+Tolerances: FP64 mode 1e-12 relative (round-off of a few hundred-term
+sums); FP32 mode 2e-5 relative (FP32 accumulation, K <= 2560 terms).
+"""
+
+import numpy as np
+import pytest
+
+from inputs import random_complex, random_mpo_like
+from inputs.randt import random_hermitian_env
+from oracle import mps as om
+from oracle.krylov import expm_lanczos
+
+from gpu_util import require_gpu, dev, host, relerr
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [  # Ml, d, Mr, Wl, Wr
+    (1, 2, 2, 1, 5),
+    (7, 2, 13, 3, 4),
+    (32, 8, 32, 7, 9),
+    (40, 8, 33, 9, 5),
+    (65, 2, 70, 9, 9),
+    (96, 10, 100, 5, 3),
+]
+
+
+@pytest.fixture(scope="module")
+def ctxs():
+    torch = require_gpu()
+    from paper_1907_12044_amd import tdvp
+    c64 = tdvp.Context(0, tdvp.FP64)
+    c32 = tdvp.Context(0, tdvp.FP32)
+    for c in (c64, c32):
+        c.reserve(1 << 30)
+    yield {"fp64": c64, "fp32": c32}
+    torch.cuda.synchronize()
+
+
+def _env_dtype(ctx):
+    import torch
+    return torch.complex128 if ctx.precision == 0 else torch.complex64
+
+
+def _tol(prec):
+    return 1e-12 if prec == "fp64" else 2e-5
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_heff_apply_matches_oracle(ctxs, prec, shape):
+    from paper_1907_12044_amd import tdvp
+    ctx = ctxs[prec]
+    Ml, d, Mr, Wl, Wr = shape
+    seed = sum(shape)
+    L = random_hermitian_env(Ml, Wl, seed)
+    R = random_hermitian_env(Mr, Wr, seed + 1)
+    W = random_mpo_like(Wl, d, Wr, seed + 2, density=0.4)
+    x = random_complex((Ml, d, Mr), seed + 3)
+    if prec == "fp32":   # the oracle sees the same FP32-rounded environments
+        L = L.astype(np.complex64).astype(np.complex128)
+        R = R.astype(np.complex64).astype(np.complex128)
+    y = dev(np.zeros_like(x))
+    tdvp.heff_apply(ctx, dev(L, _env_dtype(ctx)), dev(W), dev(R, _env_dtype(ctx)),
+                    Ml, d, Mr, Wl, Wr, dev(x), y)
+    ref = om.heff(L, W, R, x)
+    assert relerr(host(y), ref) < _tol(prec)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("Ml,Mr,W", [(1, 1, 1), (16, 16, 5), (33, 40, 9), (128, 128, 9), (200, 256, 3)])
+def test_bond_operator_matches_oracle(ctxs, prec, Ml, Mr, W):
+    from paper_1907_12044_amd import tdvp
+    ctx = ctxs[prec]
+    L = random_hermitian_env(Ml, W, Ml + 5)
+    R = random_hermitian_env(Mr, W, Mr + 6)
+    if prec == "fp32":
+        L = L.astype(np.complex64).astype(np.complex128)
+        R = R.astype(np.complex64).astype(np.complex128)
+    D = random_complex((Ml, Mr), 77)
+    y = dev(np.zeros_like(D))
+    tdvp.heff_apply(ctx, dev(L, _env_dtype(ctx)), None, dev(R, _env_dtype(ctx)), Ml, 1, Mr, W, W,
+                    dev(D), y)
+    assert relerr(host(y), om.bond_op(L, R, D)) < _tol(prec)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_env_update_both_directions_match_oracle(ctxs, prec, shape):
+    from paper_1907_12044_amd import tdvp
+    ctx = ctxs[prec]
+    Ml, d, Mr, Wl, Wr = shape
+    seed = 3 * sum(shape)
+    A = random_complex((Ml, d, Mr), seed)
+    W = random_mpo_like(Wl, d, Wr, seed + 1, density=0.4)
+    Lin = random_hermitian_env(Ml, Wl, seed + 2)
+    Rin = random_hermitian_env(Mr, Wr, seed + 3)
+    if prec == "fp32":
+        Lin = Lin.astype(np.complex64).astype(np.complex128)
+        Rin = Rin.astype(np.complex64).astype(np.complex128)
+    et = _env_dtype(ctx)
+    out = dev(np.zeros((Mr, Wr, Mr), complex), et)
+    tdvp.env_update(ctx, +1, dev(Lin, et), dev(A), dev(W), Ml, d, Mr, Wl, Wr, out)
+    assert relerr(host(out), om.env_left(Lin, A, W)) < _tol(prec)
+    out = dev(np.zeros((Ml, Wl, Ml), complex), et)
+    tdvp.env_update(ctx, -1, dev(Rin, et), dev(A), dev(W), Ml, d, Mr, Wl, Wr, out)
+    assert relerr(host(out), om.env_right(Rin, A, W)) < _tol(prec)
+
+
+@pytest.mark.parametrize("shape,z,kmax", [
+    ((1, 2, 2, 1, 5), -0.9j, 20),
+    ((7, 2, 13, 3, 4), -2.5j, 20),
+    ((32, 8, 32, 7, 9), -1.0j, 20),
+    ((40, 8, 33, 9, 5), 0.7j, 12),
+    ((65, 2, 70, 9, 9), -3.0j, 32),
+])
+def test_lanczos_expm_matches_oracle(ctxs, shape, z, kmax):
+    import torch
+    from paper_1907_12044_amd import tdvp
+    ctx = ctxs["fp64"]
+    Ml, d, Mr, Wl, Wr = shape
+    seed = 5 * sum(shape)
+    L = random_hermitian_env(Ml, Wl, seed)
+    R = random_hermitian_env(Mr, Wr, seed + 1)
+    W0 = random_mpo_like(Wl, d, Wr, seed + 2, density=0.4)
+    # Hermitian MPO site: W[w, s', s, w'] = conj(W[w, s, s', w'])
+    W = 0.5 * (W0 + np.conj(np.transpose(W0, (0, 2, 1, 3))))
+    x = random_complex((Ml, d, Mr), seed + 3)
+    # scale the operator so |z| |H| is moderate
+    Hx = om.heff(L, W, R, x)
+    s = 1.0 / max(np.linalg.norm(Hx) / np.linalg.norm(x), 1e-30)
+    W = W * s
+    xd = dev(x)
+    kd = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+    tdvp.lanczos_expm(ctx, dev(L), dev(W), dev(R), Ml, d, Mr, Wl, Wr, z, kmax, 0.0, xd, xd, kd)
+    info = {}
+    ref = expm_lanczos(lambda v: om.heff(L, W, R, v), x, z, kmax=kmax, info=info)
+    assert int(host(kd)[0]) == info["k"]
+    assert relerr(host(xd), ref) < 1e-11
+
+
+def test_lanczos_full_space_is_exact_and_zero_vector(ctxs):
+    import scipy.linalg
+    import torch
+    from paper_1907_12044_amd import tdvp
+    ctx = ctxs["fp64"]
+    Ml, d, Mr, Wl, Wr = 3, 2, 2, 2, 3
+    L = random_hermitian_env(Ml, Wl, 1)
+    R = random_hermitian_env(Mr, Wr, 2)
+    W0 = random_mpo_like(Wl, d, Wr, 3, density=1.0)
+    W = 0.5 * (W0 + np.conj(np.transpose(W0, (0, 2, 1, 3))))
+    n = Ml * d * Mr
+    H = np.zeros((n, n), complex)
+    for c in range(n):
+        e = np.zeros(n, complex)
+        e[c] = 1
+        H[:, c] = om.heff(L, W, R, e.reshape(Ml, d, Mr)).reshape(-1)
+    x = random_complex((Ml, d, Mr), 4)
+    xd = dev(x)
+    kd = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+    tdvp.lanczos_expm(ctx, dev(L), dev(W), dev(R), Ml, d, Mr, Wl, Wr, -0.3j, 20, 0.0, xd, xd, kd)
+    ref = scipy.linalg.expm(-0.3j * H) @ x.reshape(-1)
+    assert relerr(host(xd).reshape(-1), ref) < 1e-12
+    assert int(host(kd)[0]) <= n
+    zd = dev(np.zeros((Ml, d, Mr), complex))
+    yd = dev(np.ones((Ml, d, Mr), complex))
+    tdvp.lanczos_expm(ctx, dev(L), dev(W), dev(R), Ml, d, Mr, Wl, Wr, -0.3j, 20, 0.0, zd, yd, kd)
+    assert np.all(host(yd) == 0) and int(host(kd)[0]) == 0
+
+
+def test_lanczos_tolerance_stop(ctxs):
+    import torch
+    from paper_1907_12044_amd import tdvp
+    ctx = ctxs["fp64"]
+    Ml, d, Mr, Wl, Wr = 32, 8, 32, 5, 5
+    L = random_hermitian_env(Ml, Wl, 8)
+    R = random_hermitian_env(Mr, Wr, 9)
+    W0 = random_mpo_like(Wl, d, Wr, 10, density=0.5)
+    W = 0.5 * (W0 + np.conj(np.transpose(W0, (0, 2, 1, 3))))
+    x = random_complex((Ml, d, Mr), 11)
+    Hx = om.heff(L, W, R, x)
+    W = W * 0.3 / (np.linalg.norm(Hx) / np.linalg.norm(x))
+    xd = dev(x)
+    kd = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+    tdvp.lanczos_expm(ctx, dev(L), dev(W), dev(R), Ml, d, Mr, Wl, Wr, -1j, 32, 1e-10, xd, xd, kd)
+    info = {}
+    ref = expm_lanczos(lambda v: om.heff(L, W, R, v), x, -1j, kmax=32, tol=1e-10, info=info)
+    assert int(host(kd)[0]) == info["k"] and info["k"] < 32
+    assert relerr(host(xd), ref) < 1e-11
+
+
+@pytest.mark.parametrize("m,n", [(1, 1), (4, 2), (16, 16), (256, 32), (257, 33), (1024, 128), (2560, 256)])
+def test_qr_matches_oracle(ctxs, m, n):
+    from paper_1907_12044_amd import tdvp
+    ctx = ctxs["fp64"]
+    A = random_complex((m, n), m + n)
+    Q = dev(np.zeros((m, n), complex))
+    R = dev(np.zeros((n, n), complex))
+    tdvp.qr(ctx, dev(A), m, n, Q, R)
+    Qh, Rh = host(Q), host(R)
+    assert np.abs(Qh.conj().T @ Qh - np.eye(n)).max() < 1e-13
+    assert relerr(Qh @ Rh, A) < 1e-13
+    assert np.abs(np.tril(Rh, -1)).max() == 0.0
+    assert np.all(np.diag(Rh).real >= 0) and np.abs(np.diag(Rh).imag).max() == 0.0
+    Qo, Ro = om.qr_pos(A)
+    assert relerr(Rh, Ro) < 1e-11 and relerr(Qh, Qo) < 1e-10
+
+
+def test_qr_rank_deficient_is_still_orthonormal(ctxs):
+    from paper_1907_12044_amd import tdvp
+    ctx = ctxs["fp64"]
+    m, n = 40, 8
+    A = np.zeros((m, n), complex)
+    A[:, 0] = random_complex(m, 3)
+    A[:, 3] = 2.0 * A[:, 0]
+    Q = dev(np.zeros((m, n), complex))
+    R = dev(np.zeros((n, n), complex))
+    tdvp.qr(ctx, dev(A), m, n, Q, R)
+    Qh, Rh = host(Q), host(R)
+    assert np.abs(Qh.conj().T @ Qh - np.eye(n)).max() < 1e-13
+    assert relerr(Qh @ Rh, A) < 1e-13
+
+
+def test_bad_arguments_are_rejected(ctxs):
+    from paper_1907_12044_amd import tdvp
+    ctx = ctxs["fp64"]
+    x = dev(np.zeros((2, 2, 2), complex))
+    with pytest.raises(tdvp.TdvpError):
+        tdvp.heff_apply(ctx, x, None, x, 2, 2, 2, 1, 1, x, x)    # W = NULL needs d = 1
+    with pytest.raises(tdvp.TdvpError):
+        tdvp.lanczos_expm(ctx, x, x, x, 2, 2, 2, 1, 1, -1j, 33, 0.0, x, x)   # kmax > 32
+    with pytest.raises(tdvp.TdvpError):
+        tdvp.qr(ctx, x, 2, 3, x, x)                               # m < n

@@ -1,0 +1,132 @@
+"""Parity of the full TDVP-PS step on the GPU (tdvp_ps_step) with the oracle.
+
+* 3 electronic sites x 1 mode x 4 levels, full bond dimension 16, 50 steps of
+  1 fs: equal to exact propagation exp(-iHt) psi(0) (and to the oracle);
+* the same chain at truncated bond dims 4 and 8: equal to the oracle's
+  dense state after 20 steps;
+* 7 x 10 x 8 (77 sites), M = 32, 2 fs: populations, norm and energy equal to
+  the oracle's after 3 steps (1e-10), and, at the full run length the
+  benchmark uses, norm and energy conserved (properties that hold at any size);
+* FP32 contraction mode on the same chain: populations within 1e-5 of the
+  FP64 oracle.
+"""
+
+import numpy as np
+import pytest
+
+from inputs import draw_params, chain_sites, initial_mps_raw, workload
+from oracle import model, mps as om, ps, dense
+
+from gpu_util import require_gpu, host
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_run(p, sites, raw, precision=0, kmax=20, tol=0.0):
+    from paper_1907_12044_amd import tdvp
+    return tdvp.PsRun(p, sites, raw, 0, precision, kmax, tol)
+
+
+def _oracle_init(p, sites, raw):
+    Ws, _ = model.mpo(p, sites)
+    return Ws, om.right_canonicalize(raw)
+
+
+def test_canonical_form_matches_oracle():
+    require_gpu()
+    p, sites, phys, dims, raw, w = workload("fmo7x10x8_M32")
+    run = _gpu_run(p, sites, raw)
+    g = run.mps.numpy()
+    _, o = _oracle_init(p, sites, raw)
+    # full-rank bonds: the right-canonical form with real positive R diagonals is unique
+    err = max(np.abs(a - b).max() for a, b in zip(g, o))
+    assert err < 1e-8
+    assert om.norm2(g) == pytest.approx(1.0, abs=1e-13)
+
+
+def test_full_bond_dimension_equals_exact_propagation():
+    require_gpu()
+    p, sites, phys, dims, raw, w = workload("fmo3x1x4_M16")
+    H, _ = model.dense_hamiltonian(p, sites)
+    tau = w["dt_fs"] * model.AU_PER_FS
+    run = _gpu_run(p, sites, raw)
+    psi0 = om.mps_to_dense(run.mps.numpy())
+    run.step(tau, w["steps"])
+    psi = om.mps_to_dense(run.mps.numpy())
+    ref = dense.exact_evolve(H, psi0, [w["steps"] * tau])[0]
+    assert np.abs(psi - ref).max() < 1e-10
+    obs = host(run.observe())
+    pops_ref = om.site_populations(run.mps.numpy(), sites, p.n_e)
+    assert np.abs(obs[2:] - pops_ref).max() < 1e-12
+    assert obs[0] == pytest.approx(1.0, abs=1e-12)
+
+
+@pytest.mark.parametrize("M", [4, 8])
+def test_truncated_bond_dimension_equals_oracle(M):
+    require_gpu()
+    p = draw_params(3, 1, 4, seed=0)
+    sites = chain_sites(p)
+    raw = initial_mps_raw(p, M, 1e-2, 1)
+    tau = model.AU_PER_FS
+    run = _gpu_run(p, sites, raw)
+    run.step(tau, 20)
+    Ws, m0 = _oracle_init(p, sites, raw)
+    m, _ = ps.evolve(m0, Ws, tau, 20, kmax=20)
+    assert np.abs(om.mps_to_dense(run.mps.numpy()) - om.mps_to_dense(m)).max() < 1e-10
+
+
+def test_fmo77_m32_fp64_matches_oracle():
+    require_gpu()
+    p, sites, phys, dims, raw, w = workload("fmo7x10x8_M32")
+    tau = w["dt_fs"] * model.AU_PER_FS
+    nsteps = 3
+    run = _gpu_run(p, sites, raw)
+    e0 = host(run.observe()).copy()
+    run.step(tau, nsteps)
+    obs = host(run.observe())
+    Ws, m0 = _oracle_init(p, sites, raw)
+    m, _ = ps.evolve(m0, Ws, tau, nsteps, kmax=20)
+    pops = om.site_populations(m, sites, p.n_e)
+    E = om.expectation_mpo(m, Ws).real
+    shift = model.shifted_terms(p, sites)[4]
+    assert np.abs(obs[2:] - pops).max() < 1e-10
+    assert abs(obs[0] - om.norm2(m)) < 1e-12
+    assert abs((obs[1] - shift * obs[0]) - E) < 1e-10 * max(abs(E), model.HARTREE_PER_CM)
+    # gauge-invariant overlap of the two states
+    g = run.mps.numpy()
+    ov = np.ones((1, 1), complex)
+    for A, B in zip(g, m):
+        ov = np.tensordot(np.tensordot(ov, A, axes=([1], [0])), B.conj(), axes=([0, 1], [0, 1]))
+    assert 1.0 - abs(ov[0, 0]) < 1e-10
+    # the step conserves norm and energy
+    assert abs(obs[0] - e0[0]) < 1e-12 and abs(obs[1] - e0[1]) < 1e-9 * abs(e0[1])
+
+
+def test_fmo77_m32_full_length_conserves_norm_and_energy():
+    require_gpu()
+    p, sites, phys, dims, raw, w = workload("fmo7x10x8_M32")
+    tau = w["dt_fs"] * model.AU_PER_FS
+    run = _gpu_run(p, sites, raw)
+    e0 = host(run.observe()).copy()
+    run.step(tau, 50)
+    obs = host(run.observe())
+    assert abs(obs[0] - 1.0) < 1e-11
+    # shifted energy (the large constant cancels) conserved to round-off
+    shift = run.mpo.shift
+    assert abs((obs[1] - shift * obs[0]) - (e0[1] - shift * e0[0])) < 1e-11
+    assert np.all(obs[2:] >= -1e-14) and abs(obs[2:].sum() - obs[0]) < 1e-10
+
+
+def test_fmo77_m32_fp32_populations_within_1e5():
+    require_gpu()
+    p, sites, phys, dims, raw, w = workload("fmo7x10x8_M32")
+    tau = w["dt_fs"] * model.AU_PER_FS
+    nsteps = 3
+    run = _gpu_run(p, sites, raw, precision=1)
+    run.step(tau, nsteps)
+    obs = host(run.observe())
+    Ws, m0 = _oracle_init(p, sites, raw)
+    m, _ = ps.evolve(m0, Ws, tau, nsteps, kmax=20)
+    pops = om.site_populations(m, sites, p.n_e)
+    assert np.abs(obs[2:] - pops).max() < 1e-5
+    assert abs(obs[0] - 1.0) < 1e-6
