@@ -33,6 +33,7 @@ def parse():
     ap.add_argument("--kmax", type=int, default=20)
     ap.add_argument("--tol", type=float, default=0.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--eager", action="store_true", help="launch kernels one by one (no step graph)")
     ap.add_argument("--cpu-steps", type=int, default=1)
     return ap.parse_args()
 
@@ -73,11 +74,14 @@ def main():
 
     p, sites, phys, dims, raw, w = workload(args.workload)
     prec = tdvp.FP64 if args.precision == "fp64" else tdvp.FP32
-    run = tdvp.PsRun(p, sites, raw, device=0, precision=prec, kmax=args.kmax, tol=args.tol)
+    run = tdvp.PsRun(p, sites, raw, device=0, precision=prec, kmax=args.kmax, tol=args.tol,
+                     graph=not args.eager)
     tau = w["dt_fs"] * tdvp.AU_PER_FS
     nsolve = 4 * len(sites)
-    klog = torch.zeros(nsolve, dtype=torch.int32, device="cuda:0")
-    obs = torch.zeros((max(args.steps, 1), 2 + p.n_e), dtype=torch.float64, device="cuda:0")
+    with torch.cuda.stream(run.stream):
+        klog = torch.zeros(nsolve, dtype=torch.int32, device="cuda:0")
+        obs = torch.zeros((max(args.steps, 1), 2 + p.n_e), dtype=torch.float64, device="cuda:0")
+    torch.cuda.synchronize()
 
     for _ in range(args.warmup):
         run.step(tau, 1)
@@ -97,6 +101,7 @@ def main():
     tdvp.set_krylov_log(run.ctx, klog)
     run.step(tau, 1)
     tdvp.set_krylov_log(run.ctx, None)
+    torch.cuda.synchronize()
     ks = klog.cpu().numpy()
     ks = ks[ks > 0]
     prof = {}
@@ -139,7 +144,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "sites": len(sites), "bond_dim": w["M"],
                    "mpo_bond_max": max(run.mpo.bond), "dt_fs": w["dt_fs"], "kmax": args.kmax,
-                   "tol": args.tol, "precision": args.precision},
+                   "tol": args.tol, "precision": args.precision, "graph": not args.eager},
         "heff_tflops": heff_tflops,
         "krylov_mean": float(ks.mean()) if ks.size else None,
         "profile_ms_per_step": {k: round(v["ms_per_step"], 3) for k, v in prof.items()},

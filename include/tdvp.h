@@ -158,6 +158,14 @@ tdvp_status tdvp_envs_build(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *
 tdvp_status tdvp_ps_step(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo,
                          const tdvp_envs *envs, double dt, int nsteps, int kmax, double tol);
 
+/* Graph mode (enable != 0): tdvp_ps_step captures one whole step into a HIP
+ * graph the first time it sees a given set of buffers, sizes, dt, kmax and
+ * tol, and replays that graph for every later step with the same
+ * arguments (the captured kernels read the buffers in place, so the caller
+ * must keep them alive).  The context's stream must not be the NULL stream.
+ * Steps run eagerly while a Krylov log or kernel timing is active. */
+tdvp_status tdvp_set_graph(tdvp_ctx *ctx, int enable);
+
 /* Observables of a right-canonical MPS (Sec. III.A): out_dev (device double
  * [2 + n_el]) receives <psi|psi>, <psi|H|psi> + energy_shift * <psi|psi>, and
  * the populations <psi|a+_m a_m|psi> of the electronic sites el_sites[m]

@@ -40,6 +40,10 @@ struct tdvp_ctx {
   size_t pool_used;
   int32_t *klog;                  // device log of Krylov dimensions (may be null)
   int klog_cap, klog_pos;
+  int graph_mode;                 // replay a captured step graph
+  hipGraph_t graph;
+  hipGraphExec_t gexec;
+  std::vector<uint64_t> gkey;     // what the captured graph was built for
 };
 
 namespace {
@@ -62,8 +66,7 @@ DType env_type(const tdvp_ctx *c) { return c->prec == TDVP_FP64 ? F64 : F32; }
 int env_bytes(const tdvp_ctx *c) { return c->prec == TDVP_FP64 ? 16 : 8; }
 
 // Workspace carve-up for a problem whose largest local vector has n complex
-// entries and largest MPO bond is wmax.  The Lanczos state sits at offset 0
-// for every layout, so its counter stays zero between calls.
+// entries and largest MPO bond is wmax.
 struct Layout {
   size_t st, pp, U, T1, T2, Y, D, tmp, qr, obs, total;
   int64_t n;
@@ -207,7 +210,7 @@ tdvp_status run_lanczos(tdvp_ctx *c, const Layout &lay, const Op &op, double zr,
   double2 *U = at<double2>(c, lay.U);
   const double vb = 16.0 * n;
   int id = prof_begin(c, TDVP_PROF_LANCZOS);
-  CK(lz_start(st, pp, (const double2 *)x, U, n, keff, zr, zi, tol, c->stream));
+  CK(lz_start(st, pp, (const double2 *)x, U, n, zr, zi, tol, c->stream));
   prof_end(c, id, 4.0 * n, 2.0 * vb);
   for (int j = 0; j < keff; ++j) {
     CS(apply_op(c, lay, op, U + (int64_t)j * n, &st->stop));
@@ -220,7 +223,7 @@ tdvp_status run_lanczos(tdvp_ctx *c, const Layout &lay, const Op &op, double zr,
   }
   if (!kused && c->klog && c->klog_pos < c->klog_cap) kused = c->klog + c->klog_pos++;
   id = prof_begin(c, TDVP_PROF_LANCZOS);
-  CK(lz_finish(st, U, n, n, (double2 *)y, kused, c->stream));
+  CK(lz_finish(st, U, n, n, keff, (double2 *)y, kused, c->stream));
   prof_end(c, id, 8.0 * keff * n, keff * vb + vb);
   return TDVP_OK;
 }
@@ -405,6 +408,12 @@ tdvp_status tdvp_create(tdvp_ctx **ctx, int device, void *hip_stream, tdvp_preci
   c->klog = nullptr;
   c->klog_cap = 0;
   c->klog_pos = 0;
+  c->graph_mode = 0;
+  c->graph = nullptr;
+  c->gexec = nullptr;
+  if (hipSetDevice(device) != hipSuccess) { delete c; return TDVP_E_DEVICE; }
+  static bool inited = false;
+  if (!inited) { inited = true; qr_init(); }
   *ctx = c;
   return TDVP_OK;
 }
@@ -412,6 +421,8 @@ tdvp_status tdvp_create(tdvp_ctx **ctx, int device, void *hip_stream, tdvp_preci
 tdvp_status tdvp_destroy(tdvp_ctx *ctx) {
   if (!ctx) return TDVP_E_ARG;
   for (hipEvent_t e : ctx->pool) hipEventDestroy(e);
+  if (ctx->gexec) hipGraphExecDestroy(ctx->gexec);
+  if (ctx->graph) hipGraphDestroy(ctx->graph);
   delete ctx;
   return TDVP_OK;
 }
@@ -474,7 +485,6 @@ tdvp_status tdvp_set_workspace(tdvp_ctx *ctx, void *dev, size_t bytes) {
   ctx->ws = (char *)dev;
   ctx->ws_bytes = bytes;
   CK(hipSetDevice(ctx->device));
-  CK(set_dev_int(&reinterpret_cast<LzState *>(ctx->ws)->counter, 0, ctx->stream));
   CK(set_dev_int(&reinterpret_cast<LzState *>(ctx->ws)->stop, 1, ctx->stream));
   return TDVP_OK;
 }
@@ -577,21 +587,15 @@ tdvp_status tdvp_envs_build(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *
   return TDVP_OK;
 }
 
-tdvp_status tdvp_ps_step(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo,
-                         const tdvp_envs *envs, double dt, int nsteps, int kmax, double tol) {
-  if (!ctx || !envs || !envs->left || !envs->right) return TDVP_E_ARG;
-  if (nsteps < 0 || kmax < 1 || kmax > KMAX || !(tol >= 0.0) || !std::isfinite(dt)) return TDVP_E_ARG;
-  Chain ch;
-  CS(check_chain(mps, mpo, &ch));
+namespace {
+
+// Enqueue nsteps symmetric PS steps (eq:ps_trotter) on the context stream.
+tdvp_status enqueue_steps(tdvp_ctx *ctx, const Layout &lay, const Chain &ch, const tdvp_mps *mps,
+                          const tdvp_mpo *mpo, const tdvp_envs *envs, double dt, int nsteps,
+                          int kmax, double tol) {
   const int n = ch.n;
-  for (int b = 0; b <= n; ++b)
-    if (!envs->left[b] || !envs->right[b]) return TDVP_E_ARG;
-  const Layout lay = layout(ch.nmax, ch.wmax, kmax, env_bytes(ctx));
-  CS(need(ctx, lay));
-  CK(hipSetDevice(ctx->device));
   double2 *D = at<double2>(ctx, lay.D), *tmp = at<double2>(ctx, lay.tmp);
   const double h = 0.5 * dt;
-  ctx->klog_pos = 0;
   auto site = [&](int i) { return (double2 *)mps->site[i]; };
   for (int step = 0; step < nsteps; ++step) {
     // left-to-right half sweep
@@ -631,6 +635,62 @@ tdvp_status tdvp_ps_step(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo
       xin = tmp;
     }
   }
+  return TDVP_OK;
+}
+
+}  // namespace
+
+tdvp_status tdvp_set_graph(tdvp_ctx *ctx, int enable) {
+  if (!ctx) return TDVP_E_ARG;
+  ctx->graph_mode = enable ? 1 : 0;
+  return TDVP_OK;
+}
+
+tdvp_status tdvp_ps_step(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo,
+                         const tdvp_envs *envs, double dt, int nsteps, int kmax, double tol) {
+  if (!ctx || !envs || !envs->left || !envs->right) return TDVP_E_ARG;
+  if (nsteps < 0 || kmax < 1 || kmax > KMAX || !(tol >= 0.0) || !std::isfinite(dt)) return TDVP_E_ARG;
+  Chain ch;
+  CS(check_chain(mps, mpo, &ch));
+  const int n = ch.n;
+  for (int b = 0; b <= n; ++b)
+    if (!envs->left[b] || !envs->right[b]) return TDVP_E_ARG;
+  const Layout lay = layout(ch.nmax, ch.wmax, kmax, env_bytes(ctx));
+  CS(need(ctx, lay));
+  CK(hipSetDevice(ctx->device));
+  ctx->klog_pos = 0;
+  if (!ctx->graph_mode || ctx->prof_class != 0 || ctx->klog || !ctx->stream || nsteps == 0)
+    return enqueue_steps(ctx, lay, ch, mps, mpo, envs, dt, nsteps, kmax, tol);
+  // graph mode: capture one step for these buffers and settings, then replay it
+  std::vector<uint64_t> key;
+  auto put = [&](const void *p) { key.push_back((uint64_t)(uintptr_t)p); };
+  uint64_t bits;
+  std::memcpy(&bits, &dt, 8); key.push_back(bits);
+  std::memcpy(&bits, &tol, 8); key.push_back(bits);
+  key.push_back((uint64_t)kmax);
+  key.push_back((uint64_t)(int)ctx->prec);
+  put(ctx->ws); put(ctx->stream);
+  for (int i = 0; i < n; ++i) { put(mps->site[i]); put(mpo->site[i]); }
+  for (int b = 0; b <= n; ++b) {
+    put(envs->left[b]); put(envs->right[b]);
+    key.push_back((uint64_t)ch.bond[b] << 32 | (uint32_t)ch.wbond[b]);
+  }
+  for (int i = 0; i < n; ++i) key.push_back((uint64_t)ch.phys[i]);
+  if (!ctx->gexec || key != ctx->gkey) {
+    if (ctx->gexec) { hipGraphExecDestroy(ctx->gexec); ctx->gexec = nullptr; }
+    if (ctx->graph) { hipGraphDestroy(ctx->graph); ctx->graph = nullptr; }
+    ctx->gkey.clear();
+    CK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeRelaxed));
+    const tdvp_status st = enqueue_steps(ctx, lay, ch, mps, mpo, envs, dt, 1, kmax, tol);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(ctx->stream, &g);
+    if (st != TDVP_OK) { if (g) hipGraphDestroy(g); return st; }
+    if (ec != hipSuccess || !g) return TDVP_E_DEVICE;
+    ctx->graph = g;
+    CK(hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0));
+    ctx->gkey = key;
+  }
+  for (int s = 0; s < nsteps; ++s) CK(hipGraphLaunch(ctx->gexec, ctx->stream));
   return TDVP_OK;
 }
 

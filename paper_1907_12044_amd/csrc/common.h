@@ -45,34 +45,38 @@ struct WApplyArgs {
 };
 hipError_t wapply(DType t, const WApplyArgs &a, hipStream_t s);
 
-// Lanczos state kept in device memory for the solve in flight.
+// Lanczos state kept in device memory for the solve in flight.  Scalars
+// are written by work-group 0 of the kernel that reduces them; every
+// work-group of a kernel derives the same values from the same partials in
+// the same order, so all of them take the same decisions.
 struct LzState {
   double alpha[KMAX];
   double beta[KMAX];
   double scale[KMAX + 1];     // v_j = scale_j * u_j
   double aw[KMAX];            // |H v_j|
   double xnorm;
-  double cre[KMAX + 1], cim[KMAX + 1];   // c_i = <v_i, H v_j> of the current step
-  int stop;                   // != 0: no further Lanczos step
-  int k;                      // vectors in the basis so far
-  int kmax;
-  int counter;                // last-block counter (always returns to 0)
+  int stop;                   // != 0: the basis is final (k vectors)
+  int k;
   double z_re, z_im, tol;
 };
 
+// Per-work-group partial sums.  Norm partials (lz_start, lz_update) and dot
+// partials (lz_dots) live in separate arrays so a kernel never reads the
+// array it writes.
 struct LzPartials {
+  double nrm[LZ_GRID];
   double dre[LZ_GRID][KMAX + 1];
   double dim[LZ_GRID][KMAX + 1];
   double w2[LZ_GRID];
 };
 
 hipError_t lz_start(LzState *st, LzPartials *pp, const double2 *x, double2 *u0, int64_t n,
-                    int kmax, double zr, double zi, double tol, hipStream_t s);
+                    double zr, double zi, double tol, hipStream_t s);
 hipError_t lz_dots(LzState *st, LzPartials *pp, DType ty, const void *ypart, int P, int64_t pstride,
                    double2 *U, int64_t ldu, int j, int64_t n, hipStream_t s);
 hipError_t lz_update(LzState *st, LzPartials *pp, double2 *U, int64_t ldu, int j, int64_t n,
                      hipStream_t s);
-hipError_t lz_finish(LzState *st, const double2 *U, int64_t ldu, int64_t n, double2 *y,
+hipError_t lz_finish(LzState *st, const double2 *U, int64_t ldu, int64_t n, int keff, double2 *y,
                      int32_t *k_used, hipStream_t s);
 
 // Householder QR of an m x n (m >= n) c128 matrix given by strides; writes
@@ -86,6 +90,7 @@ struct QrArgs {
   double2 *work;
 };
 hipError_t qr(const QrArgs &a, hipStream_t s);
+void qr_init();   // once per process, outside stream capture
 
 }  // namespace tdvp
 

@@ -9,8 +9,9 @@
 // Tiles: a 256-thread work-group (4 wave64) owns a BM x BN output tile, each
 // wave a (BM/2) x (BN/2) quarter built from 16x16 MFMA blocks
 // (v_mfma_f64_16x16x4_f64 / v_mfma_f32_16x16x4_f32).  Operand lane layout of
-// the 16x16x4 shapes: A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k,
-// D[i][j] in lane j + 16 (i / 4), register i % 4.
+// the 16x16x4 shapes: A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k;
+// result D[i][j] in lane j + 16 (i / 4), register i % 4 for f32, but in lane
+// j + 16 (i % 4), register i / 4 for f64.
 #include "common.h"
 
 namespace tdvp {
@@ -43,6 +44,7 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs g) {
   using VC = typename Cplx<TC>::type;
   using AccT = typename Acc<TM>::type;
   constexpr int PAD = 1;
+  constexpr bool IS_F64 = sizeof(TM) == 8;
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int TI = WM / 16, TJ = WN / 16;
   __shared__ TM As[2][BK][BM + PAD];
@@ -136,7 +138,10 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs g) {
     for (int j = 0; j < TJ; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = bm0 + wm0 + i * 16 + 4 * (lane >> 4) + r;
+        // output row inside the 16x16 block: f64 MFMA puts row 4 r + lane/16 in
+        // register r, f32 MFMA row 4 (lane/16) + r (measured lane layouts)
+        const int rr = IS_F64 ? (4 * r + (lane >> 4)) : (4 * (lane >> 4) + r);
+        const int row = bm0 + wm0 + i * 16 + rr;
         const int col = bn0 + wn0 + j * 16 + (lane & 15);
         if (row < M && col < N) {
           VC v;

@@ -5,15 +5,17 @@
 //
 // Basis vectors are stored unnormalised: v_j = scale_j u_j.  Step j is
 //   w   = H u_j                                (operator kernels, P partial sums)
-//   c_i = scale_i scale_j <u_i, w>,  i <= j    (lz_dots)
-//   u_{j+1} = scale_j w - sum_i c_i scale_i u_i,  beta_j = |u_{j+1}|
-//   alpha_j = Re c_j,  scale_{j+1} = 1 / beta_j (lz_update)
-// so no separate normalisation pass is needed; the next H application acts
-// on u_{j+1} directly.  Grid-wide sums are made deterministic by writing one
-// partial per work-group and letting the last work-group to finish (ticket
-// from an atomic counter) add the partials in work-group order.  Later
-// kernels of a finished solve return at once (LzState::stop), so a fixed
-// sequence of launches serves every Krylov length.
+//   c_i = scale_i scale_j <u_i, w>,  i <= j    (lz_dots writes partial dots)
+//   u_{j+1} = scale_j w - sum_i c_i scale_i u_i (lz_update reduces the dots
+//   alpha_j = Re c_j                             and writes partial norms)
+//   beta_j = |u_{j+1}|, scale_{j+1} = 1/beta_j  (reduced by lz_dots of step j+1)
+// so no separate normalisation pass is needed.  Grid-wide sums are never
+// finished inside the kernel that produces them: each kernel writes one
+// partial per work-group, and every work-group of the NEXT kernel adds those
+// partials in work-group order (kernel boundaries order the memory; no
+// atomics or fences).  The breakdown test for step j-1 is therefore taken at
+// the start of lz_dots(j); a stopped solve makes every later kernel return
+// at once, so one fixed launch sequence serves every Krylov length.
 #include "common.h"
 
 namespace tdvp {
@@ -41,25 +43,6 @@ __device__ double block_sum(double v, double *sh) {
   double t = 0.0;
   for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
   return t;
-}
-
-// Ticket of the last block: true in every thread of the block that finished last.
-__device__ bool last_block(int *counter) {
-  __shared__ int is_last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    // system scope: the ticket is taken in memory, coherent across the XCDs' L2s
-    const int t = __hip_atomic_fetch_add(counter, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_SYSTEM);
-    is_last = (t == (int)gridDim.x - 1);
-  }
-  __syncthreads();
-  if (is_last) __threadfence();
-  return is_last != 0;
-}
-
-__device__ __forceinline__ void reset_counter(int *counter) {
-  __hip_atomic_store(counter, 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // exp(z T) e_1 for the k x k real symmetric tridiagonal T(alpha, beta),
@@ -120,8 +103,8 @@ __device__ void exp_tridiag_e1_wave(const double *alpha, const double *beta, int
 
 __global__ __launch_bounds__(LZ_BLOCK) void lz_start_kernel(LzState *st, LzPartials *pp,
                                                             const double2 *x, double2 *u0,
-                                                            int64_t n, int kmax, double zr,
-                                                            double zi, double tol) {
+                                                            int64_t n, double zr, double zi,
+                                                            double tol) {
   __shared__ double sh[8];
   double s = 0.0;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
@@ -131,26 +114,21 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_start_kernel(LzState *st, LzParti
     s += v.x * v.x + v.y * v.y;
   }
   s = block_sum(s, sh);
-  if (threadIdx.x == 0) pp->w2[blockIdx.x] = s;
-  if (last_block(&st->counter)) {
-    if (threadIdx.x == 0) {
-      double t = 0.0;
-      for (int b = 0; b < (int)gridDim.x; ++b) t += pp->w2[b];
-      const double xn = sqrt(t);
-      st->xnorm = xn;
-      st->scale[0] = xn > 0.0 ? 1.0 / xn : 0.0;
-      st->stop = (xn > 0.0 && isfinite(xn)) ? 0 : 1;
+  if (threadIdx.x == 0) {
+    pp->nrm[blockIdx.x] = s;
+    if (blockIdx.x == 0) {
+      st->stop = 0;
       st->k = 0;
-      st->kmax = kmax;
       st->z_re = zr;
       st->z_im = zi;
       st->tol = tol;
-      reset_counter(&st->counter);
     }
   }
 }
 
-// w = sum_p ypart[p] -> U[j+1]; per-block partial dots with u_0..u_j and |w|^2.
+// Start of step j: close step j-1 (beta_{j-1}, breakdown and tolerance
+// tests, scale_j), then w = sum_p ypart[p] -> U[j+1] with per-block partial
+// dots <u_i, w> (i <= j) and |w|^2.
 template <typename TY, int JB>
 __global__ __launch_bounds__(LZ_BLOCK) void lz_dots_kernel(LzState *st, LzPartials *pp,
                                                            const TY *ypart, int P,
@@ -158,6 +136,53 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_dots_kernel(LzState *st, LzPartia
                                                            int64_t ldu, int j, int64_t n) {
   if (st->stop) return;
   __shared__ double sh[4][2 * JB + 1];
+  __shared__ int stop_s;
+  __shared__ double coefr[KMAX], coefi[KMAX];
+  const int G = gridDim.x;
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int b = 0; b < G; ++b) t += pp->nrm[b];
+    const double nv = sqrt(t);
+    int stop = 0;
+    if (j == 0) {
+      if (!(nv > 0.0) || !isfinite(nv)) stop = 1;
+      if (blockIdx.x == 0) {
+        st->xnorm = nv;
+        st->scale[0] = stop ? 0.0 : 1.0 / nv;
+      }
+    } else {
+      if (!(nv > 1e-12 * st->aw[j - 1]) || !isfinite(nv)) stop = 1;
+      if (!stop && blockIdx.x == 0) {
+        st->beta[j - 1] = nv;
+        st->scale[j] = 1.0 / nv;
+      }
+    }
+    stop_s = stop;
+  }
+  __syncthreads();
+  if (!stop_s && j > 0 && st->tol > 0.0) {
+    // a-posteriori estimate |z beta_{j-1} [exp(z T_j) e_1]_{j-1}| (every block alike)
+    double t = 0.0;
+    for (int b = 0; b < G; ++b) t += pp->nrm[b];
+    const double bj = sqrt(t);
+    if (threadIdx.x < 64) {
+      // T_j needs beta_0 .. beta_{j-2}, all written by earlier kernels
+      exp_tridiag_e1_wave(st->alpha, st->beta, j, st->z_re, st->z_im, coefr, coefi);
+      if (threadIdx.x == 0) {
+        const double zabs = sqrt(st->z_re * st->z_re + st->z_im * st->z_im);
+        const double c = sqrt(coefr[j - 1] * coefr[j - 1] + coefi[j - 1] * coefi[j - 1]);
+        if (zabs * bj * c < st->tol) stop_s = 1;
+      }
+    }
+    __syncthreads();
+  }
+  if (stop_s) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      st->k = j;
+      st->stop = 1;
+    }
+    return;
+  }
   double dr[JB], di[JB];
 #pragma unroll
   for (int i = 0; i < JB; ++i) { dr[i] = 0.0; di[i] = 0.0; }
@@ -208,27 +233,9 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_dots_kernel(LzState *st, LzPartia
     for (int w = 0; w < 4; ++w) a += sh[w][2 * JB];
     pp->w2[blockIdx.x] = a;
   }
-  if (last_block(&st->counter)) {
-    if (threadIdx.x <= j) {
-      const int i = threadIdx.x;
-      double a = 0.0, b = 0.0;
-      for (int blk = 0; blk < (int)gridDim.x; ++blk) { a += pp->dre[blk][i]; b += pp->dim[blk][i]; }
-      const double sc = st->scale[i] * st->scale[j];
-      st->cre[i] = a * sc;
-      st->cim[i] = b * sc;
-      if (i == j) st->alpha[j] = a * sc;
-    }
-    if (threadIdx.x == 0) {
-      double t = 0.0;
-      for (int blk = 0; blk < (int)gridDim.x; ++blk) t += pp->w2[blk];
-      st->aw[j] = sqrt(t) * st->scale[j];
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) reset_counter(&st->counter);
-  }
 }
 
-// u_{j+1} = scale_j w - sum_{i<=j} c_i scale_i u_i ; beta_j = |u_{j+1}|.
+// u_{j+1} = scale_j w - sum_{i<=j} c_i scale_i u_i ; per-block |u_{j+1}|^2.
 template <int JB>
 __global__ __launch_bounds__(LZ_BLOCK) void lz_update_kernel(LzState *st, LzPartials *pp,
                                                              double2 *U, int64_t ldu, int j,
@@ -236,14 +243,24 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_update_kernel(LzState *st, LzPart
   if (st->stop) return;
   __shared__ double sh[8];
   __shared__ double cr[JB], ci[JB];
-  __shared__ double coefr[KMAX], coefi[KMAX];
+  const int G = gridDim.x;
+  const double sj = st->scale[j];
   if (threadIdx.x <= j) {
     const int i = threadIdx.x;
-    cr[i] = st->cre[i] * st->scale[i];
-    ci[i] = st->cim[i] * st->scale[i];
+    double a = 0.0, b = 0.0;
+    for (int blk = 0; blk < G; ++blk) { a += pp->dre[blk][i]; b += pp->dim[blk][i]; }
+    const double si = st->scale[i];
+    const double sc = si * sj;
+    cr[i] = a * sc * si;      // c_i scale_i
+    ci[i] = b * sc * si;
+    if (i == j && blockIdx.x == 0) st->alpha[j] = a * sc;
+  }
+  if (threadIdx.x == 32 && blockIdx.x == 0) {
+    double t = 0.0;
+    for (int blk = 0; blk < G; ++blk) t += pp->w2[blk];
+    st->aw[j] = sqrt(t) * sj;
   }
   __syncthreads();
-  const double sj = st->scale[j];
   double2 *w = U + (int64_t)(j + 1) * ldu;
   double s2 = 0.0;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
@@ -262,48 +279,17 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_update_kernel(LzState *st, LzPart
     s2 += xr * xr + xi * xi;
   }
   s2 = block_sum(s2, sh);
-  if (threadIdx.x == 0) pp->w2[blockIdx.x] = s2;
-  if (last_block(&st->counter)) {
-    __shared__ int stop_s;
-    if (threadIdx.x == 0) {
-      double t = 0.0;
-      for (int blk = 0; blk < (int)gridDim.x; ++blk) t += pp->w2[blk];
-      const double b = sqrt(t);
-      const int k = j + 1;
-      st->k = k;
-      int stop = 0;
-      if (k >= st->kmax || !(b > 1e-12 * st->aw[j]) || !isfinite(b)) stop = 1;
-      if (!stop) {
-        st->beta[j] = b;
-        st->scale[j + 1] = 1.0 / b;
-      }
-      stop_s = stop;
-    }
-    __syncthreads();
-    if (!stop_s && st->tol > 0.0 && threadIdx.x < 64) {
-      // a-posteriori estimate |z beta_j [exp(z T_k) e_1]_{k-1}|
-      exp_tridiag_e1_wave(st->alpha, st->beta, j + 1, st->z_re, st->z_im, coefr, coefi);
-      if (threadIdx.x == 0) {
-        const double zabs = sqrt(st->z_re * st->z_re + st->z_im * st->z_im);
-        const double c = sqrt(coefr[j] * coefr[j] + coefi[j] * coefi[j]);
-        if (zabs * st->beta[j] * c < st->tol) stop_s = 1;
-      }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      st->stop = stop_s;
-      reset_counter(&st->counter);
-    }
-  }
+  if (threadIdx.x == 0) pp->nrm[blockIdx.x] = s2;
 }
 
-// y = |x| sum_i [exp(z T_k) e_1]_i v_i.  Every block evaluates the small
+// y = |x| sum_i [exp(z T_k) e_1]_i v_i with k = the final basis size (keff
+// unless the solve stopped early).  Every block evaluates the small
 // exponential redundantly (wave 0), then combines its slice of the basis.
 __global__ __launch_bounds__(LZ_BLOCK) void lz_finish_kernel(LzState *st, const double2 *U,
-                                                             int64_t ldu, int64_t n, double2 *y,
-                                                             int32_t *k_used) {
+                                                             int64_t ldu, int64_t n, int keff,
+                                                             double2 *y, int32_t *k_used) {
   __shared__ double cr[KMAX], ci[KMAX];
-  const int k = st->k;
+  const int k = st->stop ? st->k : keff;
   const double xn = st->xnorm;
   const bool zero = !(xn > 0.0) || k <= 0;
   if (!zero && threadIdx.x < 64)
@@ -327,11 +313,13 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_finish_kernel(LzState *st, const 
     }
     y[e] = make_double2(yr, yi);
   }
-  if (k_used && blockIdx.x == 0 && threadIdx.x == 0) *k_used = k;
+  if (k_used && blockIdx.x == 0 && threadIdx.x == 0) *k_used = zero ? 0 : k;
 }
 
+// Work-groups for an n-element vector pass: about 4 elements per thread, at
+// most LZ_GRID groups (so the partial sums stay short).
 int grid_for(int64_t n) {
-  int64_t g = (n + LZ_BLOCK - 1) / LZ_BLOCK;
+  int64_t g = (n + 4 * LZ_BLOCK - 1) / (4 * LZ_BLOCK);
   if (g > LZ_GRID) g = LZ_GRID;
   if (g < 1) g = 1;
   return (int)g;
@@ -340,9 +328,9 @@ int grid_for(int64_t n) {
 }  // namespace
 
 hipError_t lz_start(LzState *st, LzPartials *pp, const double2 *x, double2 *u0, int64_t n,
-                    int kmax, double zr, double zi, double tol, hipStream_t s) {
+                    double zr, double zi, double tol, hipStream_t s) {
   hipLaunchKernelGGL(lz_start_kernel, dim3(grid_for(n)), dim3(LZ_BLOCK), 0, s, st, pp, x, u0, n,
-                     kmax, zr, zi, tol);
+                     zr, zi, tol);
   return hipGetLastError();
 }
 
@@ -377,10 +365,10 @@ hipError_t lz_update(LzState *st, LzPartials *pp, double2 *U, int64_t ldu, int j
   return hipGetLastError();
 }
 
-hipError_t lz_finish(LzState *st, const double2 *U, int64_t ldu, int64_t n, double2 *y,
+hipError_t lz_finish(LzState *st, const double2 *U, int64_t ldu, int64_t n, int keff, double2 *y,
                      int32_t *k_used, hipStream_t s) {
-  hipLaunchKernelGGL(lz_finish_kernel, dim3(grid_for(n)), dim3(LZ_BLOCK), 0, s, st, U, ldu, n, y,
-                     k_used);
+  hipLaunchKernelGGL(lz_finish_kernel, dim3(grid_for(n)), dim3(LZ_BLOCK), 0, s, st, U, ldu, n, keff,
+                     y, k_used);
   return hipGetLastError();
 }
 

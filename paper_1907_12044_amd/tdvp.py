@@ -65,6 +65,7 @@ EXPORTS = {
     "tdvp_observe": (c_int, [c_void_p, POINTER(_Mps), POINTER(_Mpo), POINTER(_Envs), POINTER(c_int32),
                              c_int, c_void_p]),
     "tdvp_set_krylov_log": (c_int, [c_void_p, c_void_p, c_int]),
+    "tdvp_set_graph": (c_int, [c_void_p, c_int]),
     "tdvp_profile": (c_int, [c_void_p, c_int]),
     "tdvp_profile_read": (c_int, [c_void_p, POINTER(c_double), POINTER(c_int64), POINTER(c_double),
                                   POINTER(c_double)]),
@@ -292,6 +293,10 @@ def envs_build(ctx, mps, mpo, envs):
                                  ctypes.byref(envs.desc)), "tdvp_envs_build")
 
 
+def set_graph(ctx, enable):
+    _check(lib().tdvp_set_graph(ctx.h, 1 if enable else 0), "tdvp_set_graph")
+
+
 def ps_step(ctx, mps, mpo, envs, dt, nsteps=1, kmax=20, tol=0.0):
     _check(lib().tdvp_ps_step(ctx.h, ctypes.byref(mps.desc), ctypes.byref(mpo.desc),
                               ctypes.byref(envs.desc), float(dt), int(nsteps), int(kmax), float(tol)),
@@ -334,28 +339,35 @@ class PsRun:
 
     ``raw_mps`` are the (non-canonical) initial site tensors; they are
     right-canonicalised and normalised on the device, the right environments
-    built, and every later step runs through tdvp_ps_step.
+    built, and every later step runs through tdvp_ps_step.  The run owns a
+    HIP stream of its own (a captured step graph needs a non-NULL stream);
+    every tensor of the run is created on that stream.
     """
 
-    def __init__(self, params, sites, raw_mps, device=0, precision=FP64, kmax=20, tol=0.0):
+    def __init__(self, params, sites, raw_mps, device=0, precision=FP64, kmax=20, tol=0.0,
+                 graph=True):
         import torch
         self.torch = torch
-        self.ctx = Context(device, precision)
+        self.stream = torch.cuda.Stream(device=device)
+        self.ctx = Context(device, precision, stream=self.stream)
         dev = self.ctx.device
         self.sites = sites
         self.n_e = params.n_e
-        Ws, wbond, shift = fmo_model(params, sites)
-        self.mpo = DeviceMpo(Ws, wbond, shift, dev)
-        self.mps = DeviceMps(raw_mps, dev)
-        self.envs = DeviceEnvs(self.mps.bond, wbond, self.ctx.env_dtype, dev)
-        self.kmax = kmax
-        self.tol = tol
-        self.ctx.reserve(workspace_bytes(self.ctx, self.mps, self.mpo, kmax))
-        self.el_sites = [0] * params.n_e
-        for i, s in enumerate(sites):
-            if s[0] == "el":
-                self.el_sites[s[1]] = i
-        self.obs = torch.zeros(2 + params.n_e, dtype=torch.float64, device=dev)
+        with torch.cuda.stream(self.stream):
+            Ws, wbond, shift = fmo_model(params, sites)
+            self.mpo = DeviceMpo(Ws, wbond, shift, dev)
+            self.mps = DeviceMps(raw_mps, dev)
+            self.envs = DeviceEnvs(self.mps.bond, wbond, self.ctx.env_dtype, dev)
+            self.kmax = kmax
+            self.tol = tol
+            self.ctx.reserve(workspace_bytes(self.ctx, self.mps, self.mpo, kmax))
+            self.el_sites = [0] * params.n_e
+            for i, s in enumerate(sites):
+                if s[0] == "el":
+                    self.el_sites[s[1]] = i
+            self.obs = torch.zeros(2 + params.n_e, dtype=torch.float64, device=dev)
+        self.stream.synchronize()
+        set_graph(self.ctx, graph)
         right_canonicalize(self.ctx, self.mps)
         envs_build(self.ctx, self.mps, self.mpo, self.envs)
 
@@ -363,7 +375,19 @@ class PsRun:
         ps_step(self.ctx, self.mps, self.mpo, self.envs, dt_au, nsteps, self.kmax, self.tol)
 
     def observe(self, out=None):
-        """Device tensor [norm^2, energy, populations...] (enqueued, not synchronised)."""
+        """Device tensor [norm^2, energy, populations...] (enqueued on the run's stream)."""
         out = self.obs if out is None else out
         observe(self.ctx, self.mps, self.mpo, self.envs, self.el_sites, out)
         return out
+
+    def observe_host(self):
+        out = self.observe()
+        self.stream.synchronize()
+        return out.cpu().numpy().copy()
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def mps_numpy(self):
+        self.stream.synchronize()
+        return self.mps.numpy()
