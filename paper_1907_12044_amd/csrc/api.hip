@@ -84,7 +84,7 @@ Layout layout(int64_t n, int wmax, int kmax, int es) {
   L.Y = o; o += al256((size_t)wmax * n * es);
   L.D = o; o += al256((size_t)n * 16);
   L.tmp = o; o += al256((size_t)n * 16);
-  L.qr = o; o += al256((size_t)2 * n * 16 + 4096);
+  L.qr = o; o += al256((size_t)2 * n * 16 + 16 * 1024);   // QR: 2 m n + 2 n complex (n <= 256)
   L.obs = o; o += al256((size_t)3 * n * 16 + 4096);
   L.total = o;
   return L;

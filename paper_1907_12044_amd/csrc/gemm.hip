@@ -160,8 +160,9 @@ hipError_t launch(const GemmArgs &g, hipStream_t s) {
     dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, g.batch);
     hipLaunchKernelGGL((cgemm_kernel<TA, TB, TC, TM, 64, 64, 16>), grid, dim3(256), 0, s, g);
   } else {
+    // small problems: 32 x 32 tiles, K in steps of 32 (one LDS phase for K <= 32)
     dim3 grid((g.N + 31) / 32, (g.M + 31) / 32, g.batch);
-    hipLaunchKernelGGL((cgemm_kernel<TA, TB, TC, TM, 32, 32, 16>), grid, dim3(256), 0, s, g);
+    hipLaunchKernelGGL((cgemm_kernel<TA, TB, TC, TM, 32, 32, 32>), grid, dim3(256), 0, s, g);
   }
   return hipGetLastError();
 }

@@ -139,9 +139,16 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_dots_kernel(LzState *st, LzPartia
   __shared__ int stop_s;
   __shared__ double coefr[KMAX], coefi[KMAX];
   const int G = gridDim.x;
-  if (threadIdx.x == 0) {
+  __shared__ double nrm_s;
+  if (threadIdx.x < 64) {   // fixed-order tree sum of the previous kernel's partial norms
     double t = 0.0;
-    for (int b = 0; b < G; ++b) t += pp->nrm[b];
+    for (int b = threadIdx.x; b < G; b += 64) t += pp->nrm[b];
+    t = wave_sum(t);
+    if (threadIdx.x == 0) nrm_s = t;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double t = nrm_s;
     const double nv = sqrt(t);
     int stop = 0;
     if (j == 0) {
@@ -162,9 +169,7 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_dots_kernel(LzState *st, LzPartia
   __syncthreads();
   if (!stop_s && j > 0 && st->tol > 0.0) {
     // a-posteriori estimate |z beta_{j-1} [exp(z T_j) e_1]_{j-1}| (every block alike)
-    double t = 0.0;
-    for (int b = 0; b < G; ++b) t += pp->nrm[b];
-    const double bj = sqrt(t);
+    const double bj = sqrt(nrm_s);
     if (threadIdx.x < 64) {
       // T_j needs beta_0 .. beta_{j-2}, all written by earlier kernels
       exp_tridiag_e1_wave(st->alpha, st->beta, j, st->z_re, st->z_im, coefr, coefi);
@@ -183,54 +188,73 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_dots_kernel(LzState *st, LzPartia
     }
     return;
   }
-  double dr[JB], di[JB];
+  // Chunks of 256 elements.  Phase 1: w for the chunk (one element per
+  // thread) into LDS and U[j+1].  Phase 2: thread (g, t), g = tid / 32,
+  // t = tid % 32, accumulates <u_i, w> over the chunk for i = g, g+8, g+16,
+  // g+24: 32 independent loads per thread per chunk.
+  constexpr int NQ = (JB + 7) / 8;
+  __shared__ double2 wl[LZ_BLOCK];
+  __shared__ double w2s[LZ_BLOCK / 64];
+  const int g8 = threadIdx.x >> 5, t32 = threadIdx.x & 31;
+  double ar[NQ], ai[NQ];
 #pragma unroll
-  for (int i = 0; i < JB; ++i) { dr[i] = 0.0; di[i] = 0.0; }
+  for (int q = 0; q < NQ; ++q) { ar[q] = 0.0; ai[q] = 0.0; }
   double w2 = 0.0;
   double2 *wdst = U + (int64_t)(j + 1) * ldu;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t c0 = (int64_t)blockIdx.x * LZ_BLOCK; c0 < n; c0 += (int64_t)G * LZ_BLOCK) {
+    const int64_t e = c0 + threadIdx.x;
     double wr = 0.0, wi = 0.0;
-    for (int p = 0; p < P; ++p) {
-      const TY v = ypart[(int64_t)p * pstride + e];
-      wr += (double)v.x;
-      wi += (double)v.y;
+    if (e < n) {
+#pragma unroll 4
+      for (int p = 0; p < P; ++p) {
+        const TY v = ypart[(int64_t)p * pstride + e];
+        wr += (double)v.x;
+        wi += (double)v.y;
+      }
+      wdst[e] = make_double2(wr, wi);
+      w2 += wr * wr + wi * wi;
     }
-    wdst[e] = make_double2(wr, wi);
-    w2 += wr * wr + wi * wi;
+    wl[threadIdx.x] = make_double2(wr, wi);
+    __syncthreads();
 #pragma unroll
-    for (int i = 0; i < JB; ++i) {
+    for (int q = 0; q < NQ; ++q) {
+      const int i = g8 + 8 * q;
       if (i <= j) {
-        const double2 u = U[(int64_t)i * ldu + e];
-        dr[i] += u.x * wr + u.y * wi;
-        di[i] += u.x * wi - u.y * wr;
+        const double2 *ui = U + (int64_t)i * ldu + c0;
+#pragma unroll
+        for (int t = 0; t < LZ_BLOCK / 32; ++t) {
+          const int el = t32 + 32 * t;
+          if (c0 + el < n) {
+            const double2 u = ui[el];
+            const double2 w = wl[el];
+            ar[q] += u.x * w.x + u.y * w.y;
+            ai[q] += u.x * w.y - u.y * w.x;
+          }
+        }
       }
     }
+    __syncthreads();
   }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // reduce over the 32 threads of each group (half a wave), fixed tree
 #pragma unroll
-  for (int i = 0; i < JB; ++i) {
-    if (i <= j) {
-      const double a = wave_sum(dr[i]);
-      const double b = wave_sum(di[i]);
-      if (lane == 0) { sh[wave][2 * i] = a; sh[wave][2 * i + 1] = b; }
+  for (int q = 0; q < NQ; ++q) {
+#pragma unroll
+    for (int o = 16; o > 0; o >>= 1) {
+      ar[q] += __shfl_xor(ar[q], o, 32);
+      ai[q] += __shfl_xor(ai[q], o, 32);
+    }
+    const int i = g8 + 8 * q;
+    if (t32 == 0 && i <= j) {
+      pp->dre[blockIdx.x][i] = ar[q];
+      pp->dim[blockIdx.x][i] = ai[q];
     }
   }
-  {
-    const double a = wave_sum(w2);
-    if (lane == 0) sh[wave][2 * JB] = a;
-  }
+  w2 = wave_sum(w2);
+  if ((threadIdx.x & 63) == 0) w2s[threadIdx.x >> 6] = w2;
   __syncthreads();
-  if (threadIdx.x <= j) {
-    const int i = threadIdx.x;
-    double a = 0.0, b = 0.0;
-    for (int w = 0; w < 4; ++w) { a += sh[w][2 * i]; b += sh[w][2 * i + 1]; }
-    pp->dre[blockIdx.x][i] = a;
-    pp->dim[blockIdx.x][i] = b;
-  }
   if (threadIdx.x == 0) {
     double a = 0.0;
-    for (int w = 0; w < 4; ++w) a += sh[w][2 * JB];
+    for (int w = 0; w < LZ_BLOCK / 64; ++w) a += w2s[w];
     pp->w2[blockIdx.x] = a;
   }
 }
@@ -267,13 +291,11 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_update_kernel(LzState *st, LzPart
        e += (int64_t)gridDim.x * blockDim.x) {
     const double2 wv = w[e];
     double xr = sj * wv.x, xi = sj * wv.y;
-#pragma unroll
-    for (int i = 0; i < JB; ++i) {
-      if (i <= j) {
-        const double2 u = U[(int64_t)i * ldu + e];
-        xr -= cr[i] * u.x - ci[i] * u.y;
-        xi -= cr[i] * u.y + ci[i] * u.x;
-      }
+#pragma unroll 8
+    for (int i = 0; i <= j; ++i) {
+      const double2 u = U[(int64_t)i * ldu + e];
+      xr -= cr[i] * u.x - ci[i] * u.y;
+      xi -= cr[i] * u.y + ci[i] * u.x;
     }
     w[e] = make_double2(xr, xi);
     s2 += xr * xr + xi * xi;
@@ -316,10 +338,10 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_finish_kernel(LzState *st, const 
   if (k_used && blockIdx.x == 0 && threadIdx.x == 0) *k_used = zero ? 0 : k;
 }
 
-// Work-groups for an n-element vector pass: about 4 elements per thread, at
-// most LZ_GRID groups (so the partial sums stay short).
+// Work-groups for an n-element vector pass: one element per thread, at most
+// LZ_GRID groups (so the partial sums stay short).
 int grid_for(int64_t n) {
-  int64_t g = (n + 4 * LZ_BLOCK - 1) / (4 * LZ_BLOCK);
+  int64_t g = (n + LZ_BLOCK - 1) / LZ_BLOCK;
   if (g > LZ_GRID) g = LZ_GRID;
   if (g < 1) g = 1;
   return (int)g;

@@ -192,7 +192,7 @@ def test_lanczos_tolerance_stop(ctxs):
     assert relerr(host(xd), ref) < 1e-11
 
 
-@pytest.mark.parametrize("m,n", [(1, 1), (4, 2), (16, 16), (256, 32), (257, 33), (1024, 128), (2560, 256)])
+@pytest.mark.parametrize("m,n", [(1, 1), (4, 2), (16, 16), (256, 32), (257, 33), (700, 45), (1024, 128), (1500, 100), (2560, 256)])
 def test_qr_matches_oracle(ctxs, m, n):
     from paper_1907_12044_amd import tdvp
     ctx = ctxs["fp64"]
