@@ -199,6 +199,23 @@ tdvp_status tdvp_profile(tdvp_ctx *ctx, int kernel_class);
 tdvp_status tdvp_profile_read(tdvp_ctx *ctx, double *ms, int64_t *launches, double *flops,
                               double *bytes);
 
+/* Batched form of tdvp_ps_step / tdvp_observe for an ensemble of nb
+ * independent chains of IDENTICAL shapes (phys, bond and MPO channel dims;
+ * e.g. static-disorder realisations that share one bond dimension):
+ * every kernel of the step covers all nb instances in one launch.
+ * mps, mpo, envs are arrays of nb descriptors whose tensors must be laid
+ * out at constant strides (instance r's tensor = instance 0's tensor +
+ * r * stride, one stride per site / bond), as when each site tensor of the
+ * ensemble is one (nb, ...) array; TDVP_E_ARG otherwise.  The workspace
+ * must hold nb times tdvp_workspace_bytes of one chain.  Observables go to
+ * out_dev[r * (2 + n_el) + ...] per instance.  Results per instance are
+ * identical to the single-chain calls. */
+tdvp_status tdvp_ps_step_batched(tdvp_ctx *ctx, int nb, const tdvp_mps *mps, const tdvp_mpo *mpo,
+                                 const tdvp_envs *envs, double dt, int nsteps, int kmax, double tol);
+tdvp_status tdvp_observe_batched(tdvp_ctx *ctx, int nb, const tdvp_mps *mps, const tdvp_mpo *mpo,
+                                 const tdvp_envs *envs, const int32_t *el_sites, int n_el,
+                                 double *out_dev);
+
 /* Frenkel-Holstein MPO (Sec. II.C, eq:holstein) written into HOST buffers.
  * Chain sites are given by kind[i] (0 = electronic two-level site, 1 = mode),
  * owner[i] (electronic index 0..n_e-1 the site belongs to) and phys[i].

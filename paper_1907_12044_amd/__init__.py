@@ -13,6 +13,7 @@ from .tdvp import (  # noqa: F401
     DeviceEnvs,
     DeviceMpo,
     DeviceMps,
+    PsEnsemble,
     PsRun,
     TdvpError,
     env_update,

@@ -137,20 +137,41 @@ hipError_t wapply_t(tdvp_ctx *c, DType t, const WApplyArgs &a) {
   return e;
 }
 
+// Instances handled together (identical shapes): count, and the stride of
+// each instance's workspace slice in bytes.  A single problem is count = 1.
+struct Bi {
+  int R = 1;
+  int64_t ws = 0;
+  int64_t wsel(int es) const { return ws / es; }   // workspace stride in elements of size es
+  int64_t wsint() const { return ws / 4; }
+};
+
+Inst inst_of(const Bi &b, int64_t sa, int64_t sb, int64_t sc, int64_t sskip) {
+  Inst in;
+  in.count = b.R;
+  in.a = sa; in.b = sb; in.c = sc; in.skip = sskip;
+  return in;
+}
+
 // One linear operator of a local equation: H[i] (W != NULL) or the bond
-// operator K of eq:tdvp2_D (W == NULL, d == 1, Wl == Wr).
+// operator K of eq:tdvp2_D (W == NULL, d == 1, Wl == Wr).  sL, sW, sR are
+// the instance strides (elements) of the two environments and of W.
 struct Op {
   const void *L, *W, *R;
   int Ml, d, Mr, Wl, Wr;
+  int64_t sL = 0, sW = 0, sR = 0;
   int64_t size() const { return (int64_t)Ml * d * Mr; }
   int parts() const { return Wl; }
 };
 
-// y_parts[p] (p < Wl) with sum_p y_parts[p] = Op x.  x is c128.
-tdvp_status apply_op(tdvp_ctx *c, const Layout &lay, const Op &op, const double2 *x, const int *skip) {
+// y_parts[p] (p < Wl) with sum_p y_parts[p] = Op x.  x is c128 with instance stride sx.
+tdvp_status apply_op(tdvp_ctx *c, const Layout &lay, const Op &op, const double2 *x, int64_t sx,
+                     const int *skip, const Bi &b) {
   const DType et = env_type(c), ct = et;
+  const int es = env_bytes(c);
   const int64_t n = op.size();
   void *T1 = c->ws + lay.T1, *T2 = c->ws + lay.T2, *Y = c->ws + lay.Y;
+  const int64_t wse = b.wsel(es), wsk = skip ? b.wsint() : 0;
   if (op.W) {
     // stage 1: T1[wr][l s][r'] = sum_r x[l s][r] R[r'][wr][r]
     GemmArgs g{};
@@ -160,6 +181,7 @@ tdvp_status apply_op(tdvp_ctx *c, const Layout &lay, const Op &op, const double2
     g.scm = op.Mr; g.scn = 1;
     g.bsa = 0; g.bsb = op.Mr; g.bsc = n;
     g.skip = skip;
+    g.inst = inst_of(b, sx, op.sR, wse, wsk);
     CK(gemm_t(c, F64, et, ct, g));
     // stage 2: T2[wl][l][s'][r'] = sum_{s, wr} W[wl][s'][s][wr] T1[wr][l][s][r']
     WApplyArgs w{};
@@ -169,6 +191,7 @@ tdvp_status apply_op(tdvp_ctx *c, const Layout &lay, const Op &op, const double2
     w.si_w = n; w.si_s = op.Mr; w.si_a = (int64_t)op.d * op.Mr; w.si_c = 1;
     w.so_w = n; w.so_s = op.Mr; w.so_a = (int64_t)op.d * op.Mr; w.so_c = 1;
     w.skip = skip;
+    w.inst = inst_of(b, wse, op.sW, wse, wsk);
     CK(wapply_t(c, ct, w));
     // stage 3 (batched over wl): Y[wl][l'][s' r'] = sum_l L[l'][wl][l] T2[wl][l][s' r']
     GemmArgs h{};
@@ -178,6 +201,7 @@ tdvp_status apply_op(tdvp_ctx *c, const Layout &lay, const Op &op, const double2
     h.scm = (int64_t)op.d * op.Mr; h.scn = 1;
     h.bsa = op.Ml; h.bsb = n; h.bsc = n;
     h.skip = skip;
+    h.inst = inst_of(b, op.sL, wse, wse, wsk);
     CK(gemm_t(c, et, ct, ct, h));
   } else {
     // bond operator: T1[w][l][r'] = sum_r D[l][r] R[r'][w][r]; Y[w][l'][r'] = sum_l L[l'][w][l] T1[w][l][r']
@@ -188,6 +212,7 @@ tdvp_status apply_op(tdvp_ctx *c, const Layout &lay, const Op &op, const double2
     g.scm = op.Mr; g.scn = 1;
     g.bsa = 0; g.bsb = op.Mr; g.bsc = n;
     g.skip = skip;
+    g.inst = inst_of(b, sx, op.sR, wse, wsk);
     CK(gemm_t(c, F64, et, ct, g));
     GemmArgs h{};
     h.A = op.L; h.B = T1; h.C = Y;
@@ -196,43 +221,55 @@ tdvp_status apply_op(tdvp_ctx *c, const Layout &lay, const Op &op, const double2
     h.scm = op.Mr; h.scn = 1;
     h.bsa = op.Ml; h.bsb = n; h.bsc = n;
     h.skip = skip;
+    h.inst = inst_of(b, op.sL, wse, wse, wsk);
     CK(gemm_t(c, et, ct, ct, h));
   }
   return TDVP_OK;
 }
 
+// y = exp(z Op) x for every instance; x, y c128 with instance strides sx, sy.
 tdvp_status run_lanczos(tdvp_ctx *c, const Layout &lay, const Op &op, double zr, double zi,
-                        int kmax, double tol, const void *x, void *y, int32_t *kused) {
+                        int kmax, double tol, const void *x, int64_t sx, void *y, int64_t sy,
+                        int32_t *kused, const Bi &b) {
   const int64_t n = op.size();
   const int keff = (int)std::min<int64_t>(kmax, n);
   LzState *st = at<LzState>(c, lay.st);
   LzPartials *pp = at<LzPartials>(c, lay.pp);
   double2 *U = at<double2>(c, lay.U);
-  const double vb = 16.0 * n;
+  LzInst li;
+  li.count = b.R; li.wss = b.ws; li.xs = sx; li.ys = sy;
+  const double vb = 16.0 * n * b.R;
   int id = prof_begin(c, TDVP_PROF_LANCZOS);
-  CK(lz_start(st, pp, (const double2 *)x, U, n, zr, zi, tol, c->stream));
-  prof_end(c, id, 4.0 * n, 2.0 * vb);
+  CK(lz_start(st, pp, (const double2 *)x, U, n, zr, zi, tol, keff, li, c->stream));
+  prof_end(c, id, 4.0 * n * b.R, 2.0 * vb);
   for (int j = 0; j < keff; ++j) {
-    CS(apply_op(c, lay, op, U + (int64_t)j * n, &st->stop));
+    CS(apply_op(c, lay, op, U + (int64_t)j * n, b.wsel(16), &st->stop, b));
     id = prof_begin(c, TDVP_PROF_LANCZOS);
-    CK(lz_dots(st, pp, env_type(c), c->ws + lay.Y, op.parts(), n, U, n, j, n, c->stream));
-    prof_end(c, id, 8.0 * (j + 1) * n, (double)op.parts() * n * env_bytes(c) + vb + (j + 1) * vb);
+    CK(lz_dots(st, pp, env_type(c), c->ws + lay.Y, op.parts(), n, U, n, j, n, li, c->stream));
+    prof_end(c, id, 8.0 * (j + 1) * n * b.R,
+             (double)op.parts() * n * env_bytes(c) * b.R + vb + (j + 1) * vb);
     id = prof_begin(c, TDVP_PROF_LANCZOS);
-    CK(lz_update(st, pp, U, n, j, n, c->stream));
-    prof_end(c, id, 8.0 * (j + 1) * n, 2.0 * vb + (j + 1) * vb);
+    CK(lz_update(st, pp, U, n, j, n, li, c->stream));
+    prof_end(c, id, 8.0 * (j + 1) * n * b.R, 2.0 * vb + (j + 1) * vb);
   }
-  if (!kused && c->klog && c->klog_pos < c->klog_cap) kused = c->klog + c->klog_pos++;
+  if (!kused && c->klog && c->klog_pos + b.R <= c->klog_cap) {
+    kused = c->klog + c->klog_pos;
+    c->klog_pos += b.R;
+  }
   id = prof_begin(c, TDVP_PROF_LANCZOS);
-  CK(lz_finish(st, U, n, n, keff, (double2 *)y, kused, c->stream));
-  prof_end(c, id, 8.0 * keff * n, keff * vb + vb);
+  CK(lz_finish(st, U, n, n, keff, (double2 *)y, kused, li, c->stream));
+  prof_end(c, id, 8.0 * keff * n * b.R, keff * vb + vb);
   return TDVP_OK;
 }
 
 // dir = +1: out (Mr, Wr, Mr) = h[1:i] from in (Ml, Wl, Ml).  dir = -1: out (Ml, Wl, Ml) from in (Mr, Wr, Mr).
+// Instance strides (elements): sin, sout (environments), sA (site tensor), sW (MPO).
 tdvp_status env_update(tdvp_ctx *c, const Layout &lay, int dir, const void *in, const void *A,
-                       const void *W, int Ml, int d, int Mr, int Wl, int Wr, void *out) {
+                       const void *W, int Ml, int d, int Mr, int Wl, int Wr, void *out,
+                       const Bi &b, int64_t sin, int64_t sA, int64_t sW, int64_t sout) {
   const DType et = env_type(c), ct = et;
   const int64_t n = (int64_t)Ml * d * Mr;
+  const int64_t wse = b.wsel(env_bytes(c));
   void *T1 = c->ws + lay.T1, *T2 = c->ws + lay.T2;
   if (dir > 0) {
     // T1[l'][wl][s][li] = sum_l L[l'][wl][l] A[l][s][li]
@@ -240,6 +277,7 @@ tdvp_status env_update(tdvp_ctx *c, const Layout &lay, int dir, const void *in, 
     g.A = in; g.B = A; g.C = T1;
     g.M = Ml * Wl; g.N = d * Mr; g.K = Ml; g.batch = 1;
     g.sam = Ml; g.sak = 1; g.sbk = (int64_t)d * Mr; g.sbn = 1; g.scm = (int64_t)d * Mr; g.scn = 1;
+    g.inst = inst_of(b, sin, sA, wse, 0);
     CK(gemm_t(c, et, F64, ct, g));
     // T2[l'][s'][wr][li] = sum_{wl, s} W[wl][s'][s][wr] T1[l'][wl][s][li]
     WApplyArgs w{};
@@ -247,6 +285,7 @@ tdvp_status env_update(tdvp_ctx *c, const Layout &lay, int dir, const void *in, 
     w.Wl = Wl; w.Wr = Wr; w.d = d; w.A = Ml; w.C = Mr; w.w_in_right = 0;
     w.si_w = (int64_t)d * Mr; w.si_s = Mr; w.si_a = (int64_t)Wl * d * Mr; w.si_c = 1;
     w.so_w = Mr; w.so_s = (int64_t)Wr * Mr; w.so_a = (int64_t)d * Wr * Mr; w.so_c = 1;
+    w.inst = inst_of(b, wse, sW, wse, 0);
     CK(wapply_t(c, ct, w));
     // out[q][wr][li] = sum_{l', s'} conj(A[l'][s'][q]) T2[l'][s'][wr][li]
     GemmArgs h{};
@@ -254,6 +293,7 @@ tdvp_status env_update(tdvp_ctx *c, const Layout &lay, int dir, const void *in, 
     h.M = Mr; h.N = Wr * Mr; h.K = Ml * d; h.batch = 1;
     h.sam = 1; h.sak = Mr; h.conjA = 1; h.sbk = (int64_t)Wr * Mr; h.sbn = 1;
     h.scm = (int64_t)Wr * Mr; h.scn = 1;
+    h.inst = inst_of(b, sA, wse, sout, 0);
     CK(gemm_t(c, F64, ct, et, h));
   } else {
     // T1[wr][k][t][q] = sum_r A[k][t][r] R[q][wr][r]   (as stage 1 of H[i] x)
@@ -262,6 +302,7 @@ tdvp_status env_update(tdvp_ctx *c, const Layout &lay, int dir, const void *in, 
     g.M = Ml * d; g.N = Mr; g.K = Mr; g.batch = Wr;
     g.sam = Mr; g.sak = 1; g.sbk = 1; g.sbn = (int64_t)Wr * Mr;
     g.scm = Mr; g.scn = 1; g.bsa = 0; g.bsb = Mr; g.bsc = n;
+    g.inst = inst_of(b, sA, sin, wse, 0);
     CK(gemm_t(c, F64, et, ct, g));
     // T2[wl][k][s][q] = sum_{t, wr} W[wl][s][t][wr] T1[wr][k][t][q]
     WApplyArgs w{};
@@ -269,6 +310,7 @@ tdvp_status env_update(tdvp_ctx *c, const Layout &lay, int dir, const void *in, 
     w.Wl = Wl; w.Wr = Wr; w.d = d; w.A = Ml; w.C = Mr; w.w_in_right = 1;
     w.si_w = n; w.si_s = Mr; w.si_a = (int64_t)d * Mr; w.si_c = 1;
     w.so_w = n; w.so_s = Mr; w.so_a = (int64_t)d * Mr; w.so_c = 1;
+    w.inst = inst_of(b, wse, sW, wse, 0);
     CK(wapply_t(c, ct, w));
     // out[b][wl][k] = sum_{s, q} conj(A[b][s][q]) T2[wl][k][s][q]
     GemmArgs h{};
@@ -276,6 +318,7 @@ tdvp_status env_update(tdvp_ctx *c, const Layout &lay, int dir, const void *in, 
     h.M = Ml; h.N = Wl * Ml; h.K = d * Mr; h.batch = 1;
     h.sam = (int64_t)d * Mr; h.sak = 1; h.conjA = 1; h.sbk = 1; h.sbn = (int64_t)d * Mr;
     h.scm = (int64_t)Wl * Ml; h.scn = 1;
+    h.inst = inst_of(b, sA, wse, sout, 0);
     CK(gemm_t(c, F64, ct, et, h));
   }
   return TDVP_OK;
@@ -285,23 +328,32 @@ tdvp_status env_update(tdvp_ctx *c, const Layout &lay, int dir, const void *in, 
 // 2 (4 m n^2 - 4 n^3 / 3) complex-equivalent real FLOP (factor + Q).
 double qr_flops(double m, double n) { return 2.0 * 8.0 * (m * n * n - n * n * n / 3.0); }
 
+tdvp_status run_qr(tdvp_ctx *c, QrArgs &q) {
+  const int id = prof_begin(c, TDVP_PROF_QR);
+  CK(qr(q, c->stream));
+  prof_end(c, id, qr_flops(q.m, q.n) * q.inst.count,
+           16.0 * (2.0 * q.m * q.n + (double)q.n * q.n) * q.inst.count);
+  return TDVP_OK;
+}
+
 // Left-to-right gauge: C (Ml d x Mr, row-major) = Q D; Q written back to C.
-tdvp_status qr_left(tdvp_ctx *c, const Layout &lay, double2 *C, int Ml, int d, int Mr, double2 *D) {
+// sC: instance stride of C; D lives in the workspace.
+tdvp_status qr_left(tdvp_ctx *c, const Layout &lay, double2 *C, int Ml, int d, int Mr, double2 *D,
+                    const Bi &b, int64_t sC) {
   QrArgs q{};
   q.A = C; q.a_rs = Mr; q.a_cs = 1;
   q.Q = C; q.q_rs = Mr; q.q_cs = 1;
   q.R = D; q.r_rs = Mr; q.r_cs = 1;
   q.m = Ml * d; q.n = Mr;
   q.work = at<double2>(c, lay.qr);
-  const int id = prof_begin(c, TDVP_PROF_QR);
-  CK(qr(q, c->stream));
-  prof_end(c, id, qr_flops(q.m, q.n), 16.0 * (2.0 * q.m * q.n + (double)q.n * q.n));
-  return TDVP_OK;
+  q.inst = inst_of(b, sC, sC, b.wsel(16), b.wsel(16));
+  return run_qr(c, q);
 }
 
 // Right-to-left gauge: C (Ml x d Mr) = D Rt with Rt right-isometric (written
 // back to C) and D = R^H from the QR of C^H.
-tdvp_status qr_right(tdvp_ctx *c, const Layout &lay, double2 *C, int Ml, int d, int Mr, double2 *D) {
+tdvp_status qr_right(tdvp_ctx *c, const Layout &lay, double2 *C, int Ml, int d, int Mr, double2 *D,
+                     const Bi &b, int64_t sC) {
   const int64_t cols = (int64_t)d * Mr;
   QrArgs q{};
   q.A = C; q.a_rs = 1; q.a_cs = cols; q.conjA = 1;
@@ -309,18 +361,18 @@ tdvp_status qr_right(tdvp_ctx *c, const Layout &lay, double2 *C, int Ml, int d, 
   q.R = D; q.r_rs = 1; q.r_cs = Ml; q.conjR = 1;
   q.m = (int)cols; q.n = Ml;
   q.work = at<double2>(c, lay.qr);
-  const int id = prof_begin(c, TDVP_PROF_QR);
-  CK(qr(q, c->stream));
-  prof_end(c, id, qr_flops(q.m, q.n), 16.0 * (2.0 * q.m * q.n + (double)q.n * q.n));
-  return TDVP_OK;
+  q.inst = inst_of(b, sC, sC, b.wsel(16), b.wsel(16));
+  return run_qr(c, q);
 }
 
-// out (m x nn) = A (m x k) B (k x nn), all c128 row-major.
-tdvp_status matmul(tdvp_ctx *c, const double2 *A, const double2 *B, double2 *out, int m, int k, int nn) {
+// out (m x nn) = A (m x k) B (k x nn), all c128 row-major; instance strides sa, sb, so.
+tdvp_status matmul(tdvp_ctx *c, const double2 *A, const double2 *B, double2 *out, int m, int k, int nn,
+                   const Bi &b = Bi(), int64_t sa = 0, int64_t sb = 0, int64_t so = 0) {
   GemmArgs g{};
   g.A = A; g.B = B; g.C = out;
   g.M = m; g.N = nn; g.K = k; g.batch = 1;
   g.sam = k; g.sak = 1; g.sbk = nn; g.sbn = 1; g.scm = nn; g.scn = 1;
+  g.inst = inst_of(b, sa, sb, so, 0);
   CK(gemm_t(c, F64, F64, F64, g));
   return TDVP_OK;
 }
@@ -497,7 +549,7 @@ tdvp_status tdvp_env_update(tdvp_ctx *ctx, int dir, const void *env_in, const vo
   const Layout lay = layout((int64_t)Ml * d * Mr, std::max(Wl, Wr), 1, env_bytes(ctx));
   CS(need(ctx, lay));
   CK(hipSetDevice(ctx->device));
-  return env_update(ctx, lay, dir, env_in, A, W, Ml, d, Mr, Wl, Wr, env_out);
+  return env_update(ctx, lay, dir, env_in, A, W, Ml, d, Mr, Wl, Wr, env_out, Bi(), 0, 0, 0, 0);
 }
 
 tdvp_status tdvp_heff_apply(tdvp_ctx *ctx, const void *Lenv, const void *W, const void *Renv, int Ml,
@@ -510,7 +562,7 @@ tdvp_status tdvp_heff_apply(tdvp_ctx *ctx, const void *Lenv, const void *W, cons
   const Layout lay = layout(op.size(), std::max(Wl, Wr), 1, env_bytes(ctx));
   CS(need(ctx, lay));
   CK(hipSetDevice(ctx->device));
-  CS(apply_op(ctx, lay, op, (const double2 *)x, nullptr));
+  CS(apply_op(ctx, lay, op, (const double2 *)x, 0, nullptr, Bi()));
   CK(sum_partials(env_type(ctx), ctx->ws + lay.Y, op.parts(), op.size(), op.size(), (double2 *)y,
                   ctx->stream));
   return TDVP_OK;
@@ -528,7 +580,7 @@ tdvp_status tdvp_lanczos_expm(tdvp_ctx *ctx, const void *Lenv, const void *W, co
   const Layout lay = layout(op.size(), std::max(Wl, Wr), kmax, env_bytes(ctx));
   CS(need(ctx, lay));
   CK(hipSetDevice(ctx->device));
-  return run_lanczos(ctx, lay, op, z_re, z_im, kmax, tol, x, y, k_used_dev);
+  return run_lanczos(ctx, lay, op, z_re, z_im, kmax, tol, x, 0, y, 0, k_used_dev, Bi());
 }
 
 tdvp_status tdvp_qr(tdvp_ctx *ctx, const void *A, int m, int n, void *Q, void *R) {
@@ -558,7 +610,7 @@ tdvp_status tdvp_right_canonicalize(tdvp_ctx *ctx, const tdvp_mps *mps) {
   double2 *D = at<double2>(ctx, lay.D), *tmp = at<double2>(ctx, lay.tmp);
   for (int i = ch.n - 1; i >= 1; --i) {
     const int Ml = ch.bond[i], d = ch.phys[i], Mr = ch.bond[i + 1];
-    CS(qr_right(ctx, lay, (double2 *)mps->site[i], Ml, d, Mr, D));
+    CS(qr_right(ctx, lay, (double2 *)mps->site[i], Ml, d, Mr, D, Bi(), 0));
     const int Mp = ch.bond[i - 1], dp = ch.phys[i - 1];
     CS(matmul(ctx, (const double2 *)mps->site[i - 1], D, tmp, Mp * dp, Ml, Ml));
     CK(copy_c128((double2 *)mps->site[i - 1], tmp, (int64_t)Mp * dp * Ml, ctx->stream));
@@ -582,57 +634,77 @@ tdvp_status tdvp_envs_build(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *
   for (int i = n - 1; i >= 1; --i) {
     if (!envs->right[i] || !envs->right[i + 1]) return TDVP_E_ARG;
     CS(env_update(ctx, lay, -1, envs->right[i + 1], mps->site[i], mpo->site[i], ch.bond[i], ch.phys[i],
-                  ch.bond[i + 1], ch.wbond[i], ch.wbond[i + 1], envs->right[i]));
+                  ch.bond[i + 1], ch.wbond[i], ch.wbond[i + 1], envs->right[i], Bi(), 0, 0, 0, 0));
   }
   return TDVP_OK;
 }
 
 namespace {
 
-// Enqueue nsteps symmetric PS steps (eq:ps_trotter) on the context stream.
+// Per-instance strides (elements) of every tensor of the chain, for a
+// batch of identical-shape chains stored at constant strides.
+struct Strides {
+  std::vector<int64_t> site, mpo, envl, envr;
+  void zeros(int n) { site.assign(n, 0); mpo.assign(n, 0); envl.assign(n + 1, 0); envr.assign(n + 1, 0); }
+};
+
+// Enqueue nsteps symmetric PS steps (eq:ps_trotter) on the context stream
+// for b.R instances (instance 0 given by the descriptors, the others at the
+// strides s).
 tdvp_status enqueue_steps(tdvp_ctx *ctx, const Layout &lay, const Chain &ch, const tdvp_mps *mps,
                           const tdvp_mpo *mpo, const tdvp_envs *envs, double dt, int nsteps,
-                          int kmax, double tol) {
+                          int kmax, double tol, const Bi &b, const Strides &s) {
   const int n = ch.n;
   double2 *D = at<double2>(ctx, lay.D), *tmp = at<double2>(ctx, lay.tmp);
+  const int64_t wsx = b.wsel(16);   // instance stride of workspace c128 buffers
   const double h = 0.5 * dt;
   auto site = [&](int i) { return (double2 *)mps->site[i]; };
   for (int step = 0; step < nsteps; ++step) {
     // left-to-right half sweep
     const double2 *xin = site(0);
+    int64_t sxin = s.site[0];
     for (int i = 0; i < n; ++i) {
       const int Ml = ch.bond[i], d = ch.phys[i], Mr = ch.bond[i + 1];
       const bool last = (i == n - 1);
-      const Op f{envs->left[i], mpo->site[i], envs->right[i + 1], Ml, d, Mr, ch.wbond[i], ch.wbond[i + 1]};
-      CS(run_lanczos(ctx, lay, f, 0.0, -(last ? dt : h), kmax, tol, xin, site(i), nullptr));
+      Op f{envs->left[i], mpo->site[i], envs->right[i + 1], Ml, d, Mr, ch.wbond[i], ch.wbond[i + 1]};
+      f.sL = s.envl[i]; f.sW = s.mpo[i]; f.sR = s.envr[i + 1];
+      CS(run_lanczos(ctx, lay, f, 0.0, -(last ? dt : h), kmax, tol, xin, sxin, site(i), s.site[i],
+                     nullptr, b));
       if (last) break;
-      CS(qr_left(ctx, lay, site(i), Ml, d, Mr, D));
+      CS(qr_left(ctx, lay, site(i), Ml, d, Mr, D, b, s.site[i]));
       CS(env_update(ctx, lay, +1, envs->left[i], site(i), mpo->site[i], Ml, d, Mr, ch.wbond[i],
-                    ch.wbond[i + 1], envs->left[i + 1]));
+                    ch.wbond[i + 1], envs->left[i + 1], b, s.envl[i], s.site[i], s.mpo[i],
+                    s.envl[i + 1]));
       const int Wb = ch.wbond[i + 1];
-      const Op b{envs->left[i + 1], nullptr, envs->right[i + 1], Mr, 1, Mr, Wb, Wb};
-      CS(run_lanczos(ctx, lay, b, 0.0, +h, kmax, tol, D, D, nullptr));
+      Op k{envs->left[i + 1], nullptr, envs->right[i + 1], Mr, 1, Mr, Wb, Wb};
+      k.sL = s.envl[i + 1]; k.sR = s.envr[i + 1];
+      CS(run_lanczos(ctx, lay, k, 0.0, +h, kmax, tol, D, wsx, D, wsx, nullptr, b));
       const int dn = ch.phys[i + 1], Mn = ch.bond[i + 2];
-      CS(matmul(ctx, D, site(i + 1), tmp, Mr, Mr, dn * Mn));
+      CS(matmul(ctx, D, site(i + 1), tmp, Mr, Mr, dn * Mn, b, wsx, s.site[i + 1], wsx));
       xin = tmp;
+      sxin = wsx;
     }
     // right-to-left half sweep (the last site was advanced by dt above)
     for (int i = n - 1; i >= 0; --i) {
       const int Ml = ch.bond[i], d = ch.phys[i], Mr = ch.bond[i + 1];
       if (i < n - 1) {
-        const Op f{envs->left[i], mpo->site[i], envs->right[i + 1], Ml, d, Mr, ch.wbond[i], ch.wbond[i + 1]};
-        CS(run_lanczos(ctx, lay, f, 0.0, -h, kmax, tol, xin, site(i), nullptr));
+        Op f{envs->left[i], mpo->site[i], envs->right[i + 1], Ml, d, Mr, ch.wbond[i], ch.wbond[i + 1]};
+        f.sL = s.envl[i]; f.sW = s.mpo[i]; f.sR = s.envr[i + 1];
+        CS(run_lanczos(ctx, lay, f, 0.0, -h, kmax, tol, xin, sxin, site(i), s.site[i], nullptr, b));
       }
       if (i == 0) break;
-      CS(qr_right(ctx, lay, site(i), Ml, d, Mr, D));
+      CS(qr_right(ctx, lay, site(i), Ml, d, Mr, D, b, s.site[i]));
       CS(env_update(ctx, lay, -1, envs->right[i + 1], site(i), mpo->site[i], Ml, d, Mr, ch.wbond[i],
-                    ch.wbond[i + 1], envs->right[i]));
+                    ch.wbond[i + 1], envs->right[i], b, s.envr[i + 1], s.site[i], s.mpo[i],
+                    s.envr[i]));
       const int Wb = ch.wbond[i];
-      const Op b{envs->left[i], nullptr, envs->right[i], Ml, 1, Ml, Wb, Wb};
-      CS(run_lanczos(ctx, lay, b, 0.0, +h, kmax, tol, D, D, nullptr));
+      Op k{envs->left[i], nullptr, envs->right[i], Ml, 1, Ml, Wb, Wb};
+      k.sL = s.envl[i]; k.sR = s.envr[i];
+      CS(run_lanczos(ctx, lay, k, 0.0, +h, kmax, tol, D, wsx, D, wsx, nullptr, b));
       const int Mp = ch.bond[i - 1], dp = ch.phys[i - 1];
-      CS(matmul(ctx, site(i - 1), D, tmp, Mp * dp, Ml, Ml));
+      CS(matmul(ctx, site(i - 1), D, tmp, Mp * dp, Ml, Ml, b, s.site[i - 1], wsx, wsx));
       xin = tmp;
+      sxin = wsx;
     }
   }
   return TDVP_OK;
@@ -648,20 +720,153 @@ tdvp_status tdvp_set_graph(tdvp_ctx *ctx, int enable) {
 
 tdvp_status tdvp_ps_step(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo,
                          const tdvp_envs *envs, double dt, int nsteps, int kmax, double tol) {
-  if (!ctx || !envs || !envs->left || !envs->right) return TDVP_E_ARG;
+  return tdvp_ps_step_batched(ctx, 1, mps, mpo, envs, dt, nsteps, kmax, tol);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Observables for b.R instances (see tdvp_observe); out has instance stride so.
+tdvp_status observe_impl(tdvp_ctx *ctx, const Layout &lay, const Chain &ch, const tdvp_mps *mps,
+                         const tdvp_mpo *mpo, const tdvp_envs *envs, const int32_t *el_sites, int n_el,
+                         double *out_dev, int64_t so, const double *shifts, const Bi &b,
+                         const Strides &s) {
+  const int n = ch.n;
+  const int64_t wsx = b.wsel(16);
+  const double2 *C0 = (const double2 *)mps->site[0];
+  const int64_t n0 = (int64_t)ch.phys[0] * ch.bond[1];
+  CK(dot2d(C0, C0, 1, (int)n0, 0, 1, out_dev + 0, ctx->stream, b.R, s.site[0], s.site[0], so));
+  Op e{envs->left[0], mpo->site[0], envs->right[1], 1, ch.phys[0], ch.bond[1], ch.wbond[0], ch.wbond[1]};
+  e.sL = s.envl[0]; e.sW = s.mpo[0]; e.sR = s.envr[1];
+  CS(apply_op(ctx, lay, e, C0, s.site[0], nullptr, b));
+  CK(dot_partials(C0, env_type(ctx), ctx->ws + lay.Y, e.parts(), e.size(), e.size(), out_dev + 1,
+                  ctx->stream, b.R, s.site[0], b.wsel(env_bytes(ctx)), so));
+  for (int r = 0; r < b.R; ++r)
+    CK(axpy_scalar(out_dev + 1 + r * so, out_dev + r * so, shifts[r], ctx->stream));
+  if (n_el == 0) return TDVP_OK;
+  int last = 0;
+  for (int m = 0; m < n_el; ++m) last = std::max(last, (int)el_sites[m]);
+  double2 *E = at<double2>(ctx, lay.obs), *E2 = E + lay.n, *T = E + 2 * lay.n;
+  CK(fill_one(E, F64, ctx->stream, b.R, wsx));
+  for (int i = 0; i <= last && i < n; ++i) {
+    const int Ml = ch.bond[i], d = ch.phys[i], Mr = ch.bond[i + 1];
+    const double2 *A = (const double2 *)mps->site[i];
+    // T[l'][s][r] = sum_l E[l'][l] A[l][s][r]
+    CS(matmul(ctx, E, A, T, Ml, Ml, d * Mr, b, wsx, s.site[i], wsx));
+    for (int m = 0; m < n_el; ++m)
+      if (el_sites[m] == i)
+        CK(dot2d(A + Mr, T + Mr, Ml, Mr, (int64_t)d * Mr, 1, out_dev + 2 + m, ctx->stream, b.R,
+                 s.site[i], wsx, so));
+    if (i == last) break;
+    GemmArgs g{};   // E2[r'][r] = sum conj(A[l'][s][r']) T[l'][s][r]
+    g.A = A; g.B = T; g.C = E2;
+    g.M = Mr; g.N = Mr; g.K = Ml * d; g.batch = 1;
+    g.sam = 1; g.sak = Mr; g.conjA = 1; g.sbk = Mr; g.sbn = 1; g.scm = Mr; g.scn = 1;
+    g.inst = inst_of(b, s.site[i], wsx, wsx, 0);
+    CK(gemm_t(ctx, F64, F64, F64, g));
+    std::swap(E, E2);
+  }
+  return TDVP_OK;
+}
+
+// Instance strides of a batch of nb identical-shape chains: instance r's
+// tensor = instance 0's + r * stride, checked for every r.  Returns false if
+// the tensors are not laid out that way.
+bool batch_strides(int nb, const tdvp_mps *mps, const tdvp_mpo *mpo, const tdvp_envs *envs,
+                   const Chain &ch, int es, Strides *s) {
+  const int n = ch.n;
+  s->zeros(n);
+  if (nb <= 1) return true;
+  auto stride = [&](const void *p0, const void *p1, int esz, int64_t *out) {
+    const int64_t d = (const char *)p1 - (const char *)p0;
+    if (d % esz != 0) return false;
+    *out = d / esz;
+    return true;
+  };
+  for (int i = 0; i < n; ++i) {
+    if (!stride(mps[0].site[i], mps[1].site[i], 16, &s->site[i])) return false;
+    if (!stride(mpo[0].site[i], mpo[1].site[i], 16, &s->mpo[i])) return false;
+  }
+  for (int bb = 0; bb <= n; ++bb) {
+    if (!stride(envs[0].left[bb], envs[1].left[bb], es, &s->envl[bb])) return false;
+    if (!stride(envs[0].right[bb], envs[1].right[bb], es, &s->envr[bb])) return false;
+  }
+  for (int r = 2; r < nb; ++r) {
+    for (int i = 0; i < n; ++i) {
+      if ((const char *)mps[r].site[i] != (const char *)mps[0].site[i] + 16 * r * s->site[i]) return false;
+      if ((const char *)mpo[r].site[i] != (const char *)mpo[0].site[i] + 16 * r * s->mpo[i]) return false;
+    }
+    for (int bb = 0; bb <= n; ++bb) {
+      if ((const char *)envs[r].left[bb] != (const char *)envs[0].left[bb] + (int64_t)es * r * s->envl[bb])
+        return false;
+      if ((const char *)envs[r].right[bb] != (const char *)envs[0].right[bb] + (int64_t)es * r * s->envr[bb])
+        return false;
+    }
+  }
+  return true;
+}
+
+tdvp_status check_batch(tdvp_ctx *ctx, int nb, const tdvp_mps *mps, const tdvp_mpo *mpo,
+                        const tdvp_envs *envs, Chain *ch, Strides *s) {
+  if (!ctx || nb < 1 || !mps || !mpo || !envs) return TDVP_E_ARG;
+  CS(check_chain(&mps[0], &mpo[0], ch));
+  for (int r = 0; r < nb; ++r) {
+    Chain c2;
+    CS(check_chain(&mps[r], &mpo[r], &c2));
+    if (c2.phys != ch->phys || c2.bond != ch->bond || c2.wbond != ch->wbond) return TDVP_E_SHAPE;
+    if (!envs[r].left || !envs[r].right) return TDVP_E_ARG;
+    for (int bb = 0; bb <= ch->n; ++bb)
+      if (!envs[r].left[bb] || !envs[r].right[bb]) return TDVP_E_ARG;
+  }
+  if (!batch_strides(nb, mps, mpo, envs, *ch, env_bytes(ctx), s)) return TDVP_E_ARG;
+  return TDVP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tdvp_status tdvp_observe(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo, const tdvp_envs *envs,
+                         const int32_t *el_sites, int n_el, double *out_dev) {
+  return tdvp_observe_batched(ctx, 1, mps, mpo, envs, el_sites, n_el, out_dev);
+}
+
+tdvp_status tdvp_observe_batched(tdvp_ctx *ctx, int nb, const tdvp_mps *mps, const tdvp_mpo *mpo,
+                                 const tdvp_envs *envs, const int32_t *el_sites, int n_el,
+                                 double *out_dev) {
+  if (!ctx || !out_dev || n_el < 0 || (n_el > 0 && !el_sites)) return TDVP_E_ARG;
+  Chain ch;
+  Strides s;
+  CS(check_batch(ctx, nb, mps, mpo, envs, &ch, &s));
+  for (int m = 0; m < n_el; ++m)
+    if (el_sites[m] < 0 || el_sites[m] >= ch.n || ch.phys[el_sites[m]] != 2) return TDVP_E_SHAPE;
+  const Layout lay = layout(ch.nmax, ch.wmax, 1, env_bytes(ctx));
+  Bi b;
+  b.R = nb;
+  b.ws = (int64_t)lay.total;
+  if (!ctx->ws || ctx->ws_bytes < (size_t)nb * lay.total) return TDVP_E_WORKSPACE;
+  CK(hipSetDevice(ctx->device));
+  std::vector<double> shifts(nb);
+  for (int r = 0; r < nb; ++r) shifts[r] = mpo[r].energy_shift;
+  return observe_impl(ctx, lay, ch, mps, mpo, envs, el_sites, n_el, out_dev, 2 + n_el, shifts.data(), b, s);
+}
+
+tdvp_status tdvp_ps_step_batched(tdvp_ctx *ctx, int nb, const tdvp_mps *mps, const tdvp_mpo *mpo,
+                                 const tdvp_envs *envs, double dt, int nsteps, int kmax, double tol) {
   if (nsteps < 0 || kmax < 1 || kmax > KMAX || !(tol >= 0.0) || !std::isfinite(dt)) return TDVP_E_ARG;
   Chain ch;
-  CS(check_chain(mps, mpo, &ch));
-  const int n = ch.n;
-  for (int b = 0; b <= n; ++b)
-    if (!envs->left[b] || !envs->right[b]) return TDVP_E_ARG;
+  Strides s;
+  CS(check_batch(ctx, nb, mps, mpo, envs, &ch, &s));
   const Layout lay = layout(ch.nmax, ch.wmax, kmax, env_bytes(ctx));
-  CS(need(ctx, lay));
+  Bi b;
+  b.R = nb;
+  b.ws = (int64_t)lay.total;
+  if (!ctx->ws || ctx->ws_bytes < (size_t)nb * lay.total) return TDVP_E_WORKSPACE;
   CK(hipSetDevice(ctx->device));
   ctx->klog_pos = 0;
   if (!ctx->graph_mode || ctx->prof_class != 0 || ctx->klog || !ctx->stream || nsteps == 0)
-    return enqueue_steps(ctx, lay, ch, mps, mpo, envs, dt, nsteps, kmax, tol);
-  // graph mode: capture one step for these buffers and settings, then replay it
+    return enqueue_steps(ctx, lay, ch, &mps[0], &mpo[0], &envs[0], dt, nsteps, kmax, tol, b, s);
   std::vector<uint64_t> key;
   auto put = [&](const void *p) { key.push_back((uint64_t)(uintptr_t)p); };
   uint64_t bits;
@@ -669,19 +874,24 @@ tdvp_status tdvp_ps_step(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo
   std::memcpy(&bits, &tol, 8); key.push_back(bits);
   key.push_back((uint64_t)kmax);
   key.push_back((uint64_t)(int)ctx->prec);
+  key.push_back((uint64_t)nb);
   put(ctx->ws); put(ctx->stream);
-  for (int i = 0; i < n; ++i) { put(mps->site[i]); put(mpo->site[i]); }
-  for (int b = 0; b <= n; ++b) {
-    put(envs->left[b]); put(envs->right[b]);
-    key.push_back((uint64_t)ch.bond[b] << 32 | (uint32_t)ch.wbond[b]);
+  for (int i = 0; i < ch.n; ++i) {
+    put(mps[0].site[i]); put(mpo[0].site[i]);
+    key.push_back((uint64_t)s.site[i]); key.push_back((uint64_t)s.mpo[i]);
+    key.push_back((uint64_t)ch.phys[i]);
   }
-  for (int i = 0; i < n; ++i) key.push_back((uint64_t)ch.phys[i]);
+  for (int bb = 0; bb <= ch.n; ++bb) {
+    put(envs[0].left[bb]); put(envs[0].right[bb]);
+    key.push_back((uint64_t)s.envl[bb]); key.push_back((uint64_t)s.envr[bb]);
+    key.push_back((uint64_t)ch.bond[bb] << 32 | (uint32_t)ch.wbond[bb]);
+  }
   if (!ctx->gexec || key != ctx->gkey) {
     if (ctx->gexec) { hipGraphExecDestroy(ctx->gexec); ctx->gexec = nullptr; }
     if (ctx->graph) { hipGraphDestroy(ctx->graph); ctx->graph = nullptr; }
     ctx->gkey.clear();
     CK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeRelaxed));
-    const tdvp_status st = enqueue_steps(ctx, lay, ch, mps, mpo, envs, dt, 1, kmax, tol);
+    const tdvp_status st = enqueue_steps(ctx, lay, ch, &mps[0], &mpo[0], &envs[0], dt, 1, kmax, tol, b, s);
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(ctx->stream, &g);
     if (st != TDVP_OK) { if (g) hipGraphDestroy(g); return st; }
@@ -690,50 +900,7 @@ tdvp_status tdvp_ps_step(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo
     CK(hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0));
     ctx->gkey = key;
   }
-  for (int s = 0; s < nsteps; ++s) CK(hipGraphLaunch(ctx->gexec, ctx->stream));
-  return TDVP_OK;
-}
-
-tdvp_status tdvp_observe(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo, const tdvp_envs *envs,
-                         const int32_t *el_sites, int n_el, double *out_dev) {
-  if (!ctx || !envs || !out_dev || n_el < 0 || (n_el > 0 && !el_sites)) return TDVP_E_ARG;
-  Chain ch;
-  CS(check_chain(mps, mpo, &ch));
-  const int n = ch.n;
-  for (int m = 0; m < n_el; ++m)
-    if (el_sites[m] < 0 || el_sites[m] >= n || ch.phys[el_sites[m]] != 2) return TDVP_E_SHAPE;
-  if (!envs->left || !envs->right || !envs->left[0] || !envs->right[1 < n ? 1 : n]) return TDVP_E_ARG;
-  const Layout lay = layout(ch.nmax, ch.wmax, 1, env_bytes(ctx));
-  CS(need(ctx, lay));
-  CK(hipSetDevice(ctx->device));
-  const double2 *C0 = (const double2 *)mps->site[0];
-  const int64_t n0 = (int64_t)ch.phys[0] * ch.bond[1];
-  CK(dot2d(C0, C0, 1, (int)n0, 0, 1, out_dev + 0, ctx->stream));
-  const Op e{envs->left[0], mpo->site[0], envs->right[1], 1, ch.phys[0], ch.bond[1], ch.wbond[0], ch.wbond[1]};
-  CS(apply_op(ctx, lay, e, C0, nullptr));
-  CK(dot_partials(C0, env_type(ctx), ctx->ws + lay.Y, e.parts(), e.size(), e.size(), out_dev + 1,
-                  ctx->stream));
-  CK(axpy_scalar(out_dev + 1, out_dev + 0, mpo->energy_shift, ctx->stream));
-  if (n_el == 0) return TDVP_OK;
-  int last = 0;
-  for (int m = 0; m < n_el; ++m) last = std::max(last, (int)el_sites[m]);
-  double2 *E = at<double2>(ctx, lay.obs), *E2 = E + lay.n, *T = E + 2 * lay.n;
-  CK(fill_one(E, F64, ctx->stream));
-  for (int i = 0; i <= last; ++i) {
-    const int Ml = ch.bond[i], d = ch.phys[i], Mr = ch.bond[i + 1];
-    const double2 *A = (const double2 *)mps->site[i];
-    CS(matmul(ctx, E, A, T, Ml, Ml, d * Mr));                 // T[l'][s][r] = sum_l E[l'][l] A[l][s][r]
-    for (int m = 0; m < n_el; ++m)
-      if (el_sites[m] == i)
-        CK(dot2d(A + Mr, T + Mr, Ml, Mr, (int64_t)d * Mr, 1, out_dev + 2 + m, ctx->stream));
-    if (i == last) break;
-    GemmArgs g{};                                             // E2[r'][r] = sum conj(A[l'][s][r']) T[l'][s][r]
-    g.A = A; g.B = T; g.C = E2;
-    g.M = Mr; g.N = Mr; g.K = Ml * d; g.batch = 1;
-    g.sam = 1; g.sak = Mr; g.conjA = 1; g.sbk = Mr; g.sbn = 1; g.scm = Mr; g.scn = 1;
-    CK(gemm_t(ctx, F64, F64, F64, g));
-    std::swap(E, E2);
-  }
+  for (int st = 0; st < nsteps; ++st) CK(hipGraphLaunch(ctx->gexec, ctx->stream));
   return TDVP_OK;
 }
 

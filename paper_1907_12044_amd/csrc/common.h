@@ -15,6 +15,15 @@ constexpr int LZ_BLOCK = 256;
 
 enum DType { F64 = 0, F32 = 1 };
 
+// Independent problem instances of identical shape handled by one launch
+// (the disorder ensemble): instance r reads/writes every operand at
+// base + r * (its instance stride, in elements of that operand; the skip
+// flag stride is in ints).  count = 1 with zero strides is one problem.
+struct Inst {
+  int count = 1;
+  int64_t a = 0, b = 0, c = 0, skip = 0;
+};
+
 // Complex GEMM  C[b][m,n] = sum_k opA(A)[b][m,k] * opB(B)[b][k,n]
 // with arbitrary element strides (in complex elements) and optional
 // conjugation.  Batches b = 0..batch-1.  Optional `skip`: if non-null and
@@ -26,6 +35,7 @@ struct GemmArgs {
   int64_t bsa, bsb, bsc;     // batch strides
   int conjA, conjB;
   const int *skip;
+  Inst inst;                 // a = A, b = B, c = C strides
 };
 
 hipError_t cgemm(DType ta, DType tb, DType tc, const GemmArgs &g, hipStream_t s);
@@ -42,6 +52,7 @@ struct WApplyArgs {
   int64_t si_w, si_s, si_a, si_c;   // input strides (w, s, a, c)
   int64_t so_w, so_s, so_a, so_c;   // output strides
   const int *skip;
+  Inst inst;                        // a = in, b = W, c = out strides
 };
 hipError_t wapply(DType t, const WApplyArgs &a, hipStream_t s);
 
@@ -57,6 +68,7 @@ struct LzState {
   double xnorm;
   int stop;                   // != 0: the basis is final (k vectors)
   int k;
+  int keff;                   // largest basis for this solve: min(kmax, dim)
   double z_re, z_im, tol;
 };
 
@@ -70,14 +82,21 @@ struct LzPartials {
   double w2[LZ_GRID];
 };
 
+// Lanczos kernels over `inst.count` instances: instance r uses the state,
+// partials, basis and partial outputs at (base + r * wss bytes) and the
+// input/output vectors x, y at + r * xs / ys elements.
+struct LzInst {
+  int count = 1;
+  int64_t wss = 0, xs = 0, ys = 0;
+};
 hipError_t lz_start(LzState *st, LzPartials *pp, const double2 *x, double2 *u0, int64_t n,
-                    double zr, double zi, double tol, hipStream_t s);
+                    double zr, double zi, double tol, int keff, const LzInst &in, hipStream_t s);
 hipError_t lz_dots(LzState *st, LzPartials *pp, DType ty, const void *ypart, int P, int64_t pstride,
-                   double2 *U, int64_t ldu, int j, int64_t n, hipStream_t s);
+                   double2 *U, int64_t ldu, int j, int64_t n, const LzInst &in, hipStream_t s);
 hipError_t lz_update(LzState *st, LzPartials *pp, double2 *U, int64_t ldu, int j, int64_t n,
-                     hipStream_t s);
+                     const LzInst &in, hipStream_t s);
 hipError_t lz_finish(LzState *st, const double2 *U, int64_t ldu, int64_t n, int keff, double2 *y,
-                     int32_t *k_used, hipStream_t s);
+                     int32_t *k_used, const LzInst &in, hipStream_t s);
 
 // Householder QR of an m x n (m >= n) c128 matrix given by strides; writes
 // Q (m x n) and R (n x n) through output strides, with optional conjugation
@@ -88,6 +107,7 @@ struct QrArgs {
   double2 *R; int64_t r_rs, r_cs; int conjR;
   int m, n;
   double2 *work;
+  Inst inst;      // a = A, b = Q, c = R strides; skip = work stride (elements)
 };
 hipError_t qr(const QrArgs &a, hipStream_t s);
 void qr_init();   // once per process, outside stream capture

@@ -38,7 +38,9 @@ __device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
 
 template <typename TA, typename TB, typename TC, typename TM, int BM, int BN, int BK>
 __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs g) {
-  if (g.skip && *g.skip) return;
+  const int bz = blockIdx.z % g.batch;      // batch index
+  const int ri = blockIdx.z / g.batch;      // instance index
+  if (g.skip && g.skip[(int64_t)ri * g.inst.skip]) return;
   using VA = typename Cplx<TA>::type;
   using VB = typename Cplx<TB>::type;
   using VC = typename Cplx<TC>::type;
@@ -55,10 +57,9 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs g) {
   const int wave = tid >> 6;
   const int bm0 = blockIdx.y * BM;
   const int bn0 = blockIdx.x * BN;
-  const int bz = blockIdx.z;
-  const VA *A = reinterpret_cast<const VA *>(g.A) + (int64_t)bz * g.bsa;
-  const VB *B = reinterpret_cast<const VB *>(g.B) + (int64_t)bz * g.bsb;
-  VC *C = reinterpret_cast<VC *>(g.C) + (int64_t)bz * g.bsc;
+  const VA *A = reinterpret_cast<const VA *>(g.A) + (int64_t)bz * g.bsa + (int64_t)ri * g.inst.a;
+  const VB *B = reinterpret_cast<const VB *>(g.B) + (int64_t)bz * g.bsb + (int64_t)ri * g.inst.b;
+  VC *C = reinterpret_cast<VC *>(g.C) + (int64_t)bz * g.bsc + (int64_t)ri * g.inst.c;
   const int M = g.M, N = g.N, K = g.K;
   const bool a_kfast = (g.sak == 1);
   const bool b_nfast = (g.sbn == 1) || (g.sbk != 1);
@@ -154,14 +155,17 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs g) {
 
 template <typename TA, typename TB, typename TC, typename TM>
 hipError_t launch(const GemmArgs &g, hipStream_t s) {
-  if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+  if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.inst.count <= 0) return hipSuccess;
+  const int nz = g.batch * g.inst.count;
+  // the tile shape depends on one instance's problem only, so a batched
+  // launch computes every instance exactly as a single launch would
   const int64_t tiles64 = (int64_t)((g.M + 63) / 64) * ((g.N + 63) / 64) * g.batch;
   if (tiles64 >= 240) {
-    dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, g.batch);
+    dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, nz);
     hipLaunchKernelGGL((cgemm_kernel<TA, TB, TC, TM, 64, 64, 16>), grid, dim3(256), 0, s, g);
   } else {
     // small problems: 32 x 32 tiles, K in steps of 32 (one LDS phase for K <= 32)
-    dim3 grid((g.N + 31) / 32, (g.M + 31) / 32, g.batch);
+    dim3 grid((g.N + 31) / 32, (g.M + 31) / 32, nz);
     hipLaunchKernelGGL((cgemm_kernel<TA, TB, TC, TM, 32, 32, 32>), grid, dim3(256), 0, s, g);
   }
   return hipGetLastError();

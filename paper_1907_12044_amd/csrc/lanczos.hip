@@ -16,11 +16,17 @@
 // atomics or fences).  The breakdown test for step j-1 is therefore taken at
 // the start of lz_dots(j); a stopped solve makes every later kernel return
 // at once, so one fixed launch sequence serves every Krylov length.
+#include <type_traits>
+
 #include "common.h"
 
 namespace tdvp {
 
 namespace {
+
+template <typename T> __device__ __forceinline__ T *shift_bytes(T *p, int64_t bytes) {
+  return reinterpret_cast<T *>(reinterpret_cast<char *>(const_cast<typename std::remove_const<T>::type *>(p)) + bytes);
+}
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -104,7 +110,12 @@ __device__ void exp_tridiag_e1_wave(const double *alpha, const double *beta, int
 __global__ __launch_bounds__(LZ_BLOCK) void lz_start_kernel(LzState *st, LzPartials *pp,
                                                             const double2 *x, double2 *u0,
                                                             int64_t n, double zr, double zi,
-                                                            double tol) {
+                                                            double tol, int keff, LzInst in) {
+  const int64_t wo = (int64_t)blockIdx.y * in.wss;
+  st = shift_bytes(st, wo);
+  pp = shift_bytes(pp, wo);
+  u0 = shift_bytes(u0, wo);
+  x += (int64_t)blockIdx.y * in.xs;
   __shared__ double sh[8];
   double s = 0.0;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
@@ -119,6 +130,7 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_start_kernel(LzState *st, LzParti
     if (blockIdx.x == 0) {
       st->stop = 0;
       st->k = 0;
+      st->keff = keff;
       st->z_re = zr;
       st->z_im = zi;
       st->tol = tol;
@@ -133,9 +145,16 @@ template <typename TY, int JB>
 __global__ __launch_bounds__(LZ_BLOCK) void lz_dots_kernel(LzState *st, LzPartials *pp,
                                                            const TY *ypart, int P,
                                                            int64_t pstride, double2 *U,
-                                                           int64_t ldu, int j, int64_t n) {
+                                                           int64_t ldu, int j, int64_t n,
+                                                           LzInst in) {
+  {
+    const int64_t wo = (int64_t)blockIdx.y * in.wss;
+    st = shift_bytes(st, wo);
+    pp = shift_bytes(pp, wo);
+    ypart = shift_bytes(ypart, wo);
+    U = shift_bytes(U, wo);
+  }
   if (st->stop) return;
-  __shared__ double sh[4][2 * JB + 1];
   __shared__ int stop_s;
   __shared__ double coefr[KMAX], coefi[KMAX];
   const int G = gridDim.x;
@@ -158,7 +177,7 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_dots_kernel(LzState *st, LzPartia
         st->scale[0] = stop ? 0.0 : 1.0 / nv;
       }
     } else {
-      if (!(nv > 1e-12 * st->aw[j - 1]) || !isfinite(nv)) stop = 1;
+      if (!(nv > 1e-12 * st->aw[j - 1]) || !isfinite(nv) || j >= st->keff) stop = 1;
       if (!stop && blockIdx.x == 0) {
         st->beta[j - 1] = nv;
         st->scale[j] = 1.0 / nv;
@@ -263,7 +282,13 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_dots_kernel(LzState *st, LzPartia
 template <int JB>
 __global__ __launch_bounds__(LZ_BLOCK) void lz_update_kernel(LzState *st, LzPartials *pp,
                                                              double2 *U, int64_t ldu, int j,
-                                                             int64_t n) {
+                                                             int64_t n, LzInst in) {
+  {
+    const int64_t wo = (int64_t)blockIdx.y * in.wss;
+    st = shift_bytes(st, wo);
+    pp = shift_bytes(pp, wo);
+    U = shift_bytes(U, wo);
+  }
   if (st->stop) return;
   __shared__ double sh[8];
   __shared__ double cr[JB], ci[JB];
@@ -309,7 +334,15 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_update_kernel(LzState *st, LzPart
 // exponential redundantly (wave 0), then combines its slice of the basis.
 __global__ __launch_bounds__(LZ_BLOCK) void lz_finish_kernel(LzState *st, const double2 *U,
                                                              int64_t ldu, int64_t n, int keff,
-                                                             double2 *y, int32_t *k_used) {
+                                                             double2 *y, int32_t *k_used,
+                                                             LzInst in) {
+  {
+    const int64_t wo = (int64_t)blockIdx.y * in.wss;
+    st = shift_bytes(st, wo);
+    U = shift_bytes(U, wo);
+    y += (int64_t)blockIdx.y * in.ys;
+    if (k_used) k_used += blockIdx.y;
+  }
   __shared__ double cr[KMAX], ci[KMAX];
   const int k = st->stop ? st->k : keff;
   const double xn = st->xnorm;
@@ -350,18 +383,18 @@ int grid_for(int64_t n) {
 }  // namespace
 
 hipError_t lz_start(LzState *st, LzPartials *pp, const double2 *x, double2 *u0, int64_t n,
-                    double zr, double zi, double tol, hipStream_t s) {
-  hipLaunchKernelGGL(lz_start_kernel, dim3(grid_for(n)), dim3(LZ_BLOCK), 0, s, st, pp, x, u0, n,
-                     zr, zi, tol);
+                    double zr, double zi, double tol, int keff, const LzInst &in, hipStream_t s) {
+  hipLaunchKernelGGL(lz_start_kernel, dim3(grid_for(n), in.count), dim3(LZ_BLOCK), 0, s, st, pp, x,
+                     u0, n, zr, zi, tol, keff, in);
   return hipGetLastError();
 }
 
 hipError_t lz_dots(LzState *st, LzPartials *pp, DType ty, const void *ypart, int P, int64_t pstride,
-                   double2 *U, int64_t ldu, int j, int64_t n, hipStream_t s) {
-  const dim3 g(grid_for(n)), b(LZ_BLOCK);
+                   double2 *U, int64_t ldu, int j, int64_t n, const LzInst &in, hipStream_t s) {
+  const dim3 g(grid_for(n), in.count), b(LZ_BLOCK);
 #define LZ_DOTS(T, JB)                                                                         \
   hipLaunchKernelGGL((lz_dots_kernel<T, JB>), g, b, 0, s, st, pp, (const T *)ypart, P, pstride, \
-                     U, ldu, j, n)
+                     U, ldu, j, n, in)
   if (ty == F64) {
     if (j < 4) LZ_DOTS(double2, 4);
     else if (j < 8) LZ_DOTS(double2, 8);
@@ -378,19 +411,19 @@ hipError_t lz_dots(LzState *st, LzPartials *pp, DType ty, const void *ypart, int
 }
 
 hipError_t lz_update(LzState *st, LzPartials *pp, double2 *U, int64_t ldu, int j, int64_t n,
-                     hipStream_t s) {
-  const dim3 g(grid_for(n)), b(LZ_BLOCK);
-  if (j < 4) hipLaunchKernelGGL((lz_update_kernel<4>), g, b, 0, s, st, pp, U, ldu, j, n);
-  else if (j < 8) hipLaunchKernelGGL((lz_update_kernel<8>), g, b, 0, s, st, pp, U, ldu, j, n);
-  else if (j < 16) hipLaunchKernelGGL((lz_update_kernel<16>), g, b, 0, s, st, pp, U, ldu, j, n);
-  else hipLaunchKernelGGL((lz_update_kernel<32>), g, b, 0, s, st, pp, U, ldu, j, n);
+                     const LzInst &in, hipStream_t s) {
+  const dim3 g(grid_for(n), in.count), b(LZ_BLOCK);
+  if (j < 4) hipLaunchKernelGGL((lz_update_kernel<4>), g, b, 0, s, st, pp, U, ldu, j, n, in);
+  else if (j < 8) hipLaunchKernelGGL((lz_update_kernel<8>), g, b, 0, s, st, pp, U, ldu, j, n, in);
+  else if (j < 16) hipLaunchKernelGGL((lz_update_kernel<16>), g, b, 0, s, st, pp, U, ldu, j, n, in);
+  else hipLaunchKernelGGL((lz_update_kernel<32>), g, b, 0, s, st, pp, U, ldu, j, n, in);
   return hipGetLastError();
 }
 
 hipError_t lz_finish(LzState *st, const double2 *U, int64_t ldu, int64_t n, int keff, double2 *y,
-                     int32_t *k_used, hipStream_t s) {
-  hipLaunchKernelGGL(lz_finish_kernel, dim3(grid_for(n)), dim3(LZ_BLOCK), 0, s, st, U, ldu, n, keff,
-                     y, k_used);
+                     int32_t *k_used, const LzInst &in, hipStream_t s) {
+  hipLaunchKernelGGL(lz_finish_kernel, dim3(grid_for(n), in.count), dim3(LZ_BLOCK), 0, s, st, U,
+                     ldu, n, keff, y, k_used, in);
   return hipGetLastError();
 }
 

@@ -32,6 +32,13 @@ __device__ __forceinline__ double wsum(double v) {
 template <bool IN_LDS>
 __global__ __launch_bounds__(QR_THREADS) void qr_kernel(QrArgs p) {
   extern __shared__ double2 lds_mat[];
+  {   // instance blockIdx.x
+    const int64_t r = blockIdx.x;
+    p.A += r * p.inst.a;
+    p.Q += r * p.inst.b;
+    p.R += r * p.inst.c;
+    p.work += r * p.inst.skip;
+  }
   const int m = p.m, n = p.n;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr int NW = QR_THREADS / 64;
@@ -213,6 +220,7 @@ struct PanelArgs {
   double *tau;        // [n]
   double2 *alpha;     // [n]
   int m, n, c0, nb;
+  int64_t ws;         // instance stride of the work area (complex elements), instance = blockIdx.y
 };
 
 __device__ __forceinline__ double bsum256(double v, double *sh) {
@@ -225,6 +233,13 @@ __device__ __forceinline__ double bsum256(double v, double *sh) {
 
 __global__ __launch_bounds__(PB_THREADS) void qr_panel_kernel(PanelArgs a) {
   extern __shared__ double2 P[];
+  {
+    const int64_t o = (int64_t)blockIdx.y * a.ws;
+    a.Aw += o;
+    a.Vst += o;
+    a.alpha += o;
+    a.tau = reinterpret_cast<double *>(reinterpret_cast<double2 *>(a.tau) + o);
+  }
   __shared__ double sh[4];
   __shared__ double tau_p[8];
   __shared__ double2 al_p[8];
@@ -346,11 +361,20 @@ struct FormArgs {
   int m, n, nb;
   double2 *Q; int64_t q_rs, q_cs; int conjQ;
   double2 *R; int64_t r_rs, r_cs; int conjR;
+  int64_t ws, qs, rs;  // instance strides (work, Q, R), instance = blockIdx.y
 };
 
 // Q column c = H_0 ... H_c e_c (one wave per column), and R column c.
 __global__ __launch_bounds__(PB_THREADS) void qr_form_kernel(FormArgs a) {
   extern __shared__ double2 V[];
+  {
+    const int64_t r = blockIdx.y;
+    a.Aw += r * a.ws;
+    a.alpha += r * a.ws;
+    a.tau = reinterpret_cast<const double *>(reinterpret_cast<const double2 *>(a.tau) + r * a.ws);
+    a.Q += r * a.qs;
+    a.R += r * a.rs;
+  }
   const int m = a.m, n = a.n;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int c = blockIdx.x * (PB_THREADS / 64) + wave;
@@ -433,6 +457,8 @@ __global__ __launch_bounds__(PB_THREADS) void qr_form_kernel(FormArgs a) {
 }
 
 __global__ void qr_load_kernel(QrArgs p) {
+  p.A += (int64_t)blockIdx.y * p.inst.a;
+  p.work += (int64_t)blockIdx.y * p.inst.skip;
   const int64_t tot = (int64_t)p.m * p.n;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
        e += (int64_t)gridDim.x * blockDim.x) {
@@ -465,14 +491,16 @@ void qr_init() {
 hipError_t qr(const QrArgs &a, hipStream_t s) {
   if (a.n > 256 || a.m < a.n || a.n <= 0) return hipErrorInvalidValue;
   const int64_t elems = (int64_t)a.m * a.n;
+  const int R = a.inst.count;
+  if (R <= 0) return hipSuccess;
   if (lds_ok && elems <= QR_LDS_ELEMS) {
-    hipLaunchKernelGGL(qr_kernel<true>, dim3(1), dim3(QR_THREADS), elems * sizeof(double2), s, a);
+    hipLaunchKernelGGL(qr_kernel<true>, dim3(R), dim3(QR_THREADS), elems * sizeof(double2), s, a);
     return hipGetLastError();
   }
   int nb = PANEL_LDS_ELEMS / a.m;
   if (nb > 8) nb = 8;
   if (!panel_ok || a.m > 64 * RPL || nb < 1) {
-    hipLaunchKernelGGL(qr_kernel<false>, dim3(1), dim3(QR_THREADS), 0, s, a);
+    hipLaunchKernelGGL(qr_kernel<false>, dim3(R), dim3(QR_THREADS), 0, s, a);
     return hipGetLastError();
   }
   // workspace: Aw (m n) | Vst (m n) | alpha (n) | tau (n doubles)
@@ -483,20 +511,21 @@ hipError_t qr(const QrArgs &a, hipStream_t s) {
   {
     int64_t g = (elems + 255) / 256;
     if (g > 1024) g = 1024;
-    hipLaunchKernelGGL(qr_load_kernel, dim3((int)g), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(qr_load_kernel, dim3((int)g, R), dim3(256), 0, s, a);
   }
   for (int c0 = 0; c0 < a.n; c0 += nb) {
     const int nbp = (c0 + nb <= a.n) ? nb : a.n - c0;
     const int trailing = a.n - c0 - nbp;
     int groups = (trailing + (PB_THREADS / 64) - 1) / (PB_THREADS / 64);
     if (groups < 1) groups = 1;
-    PanelArgs pa{Aw, Vst, tau, alpha, a.m, a.n, c0, nbp};
-    hipLaunchKernelGGL(qr_panel_kernel, dim3(groups), dim3(PB_THREADS),
+    PanelArgs pa{Aw, Vst, tau, alpha, a.m, a.n, c0, nbp, a.inst.skip};
+    hipLaunchKernelGGL(qr_panel_kernel, dim3(groups, R), dim3(PB_THREADS),
                        (size_t)(a.m - c0) * nbp * sizeof(double2), s, pa);
   }
-  FormArgs fa{Vst, tau, alpha, a.m, a.n, nb, a.Q, a.q_rs, a.q_cs, a.conjQ, a.R, a.r_rs, a.r_cs, a.conjR};
+  FormArgs fa{Vst, tau, alpha, a.m, a.n, nb, a.Q, a.q_rs, a.q_cs, a.conjQ, a.R, a.r_rs, a.r_cs, a.conjR,
+              a.inst.skip, a.inst.b, a.inst.c};
   const int groups = (a.n + (PB_THREADS / 64) - 1) / (PB_THREADS / 64);
-  hipLaunchKernelGGL(qr_form_kernel, dim3(groups), dim3(PB_THREADS),
+  hipLaunchKernelGGL(qr_form_kernel, dim3(groups, R), dim3(PB_THREADS),
                      (size_t)a.m * nb * sizeof(double2), s, fa);
   return hipGetLastError();
 }

@@ -28,9 +28,9 @@ __device__ double bsum(double v) {
   return t;
 }
 
-__global__ void fill_one_kernel(void *p, int t) {
-  if (t == F64) reinterpret_cast<double2 *>(p)[0] = make_double2(1.0, 0.0);
-  else reinterpret_cast<float2 *>(p)[0] = make_float2(1.0f, 0.0f);
+__global__ void fill_one_kernel(void *p, int t, int64_t is) {
+  if (t == F64) reinterpret_cast<double2 *>(p)[threadIdx.x * is] = make_double2(1.0, 0.0);
+  else reinterpret_cast<float2 *>(p)[threadIdx.x * is] = make_float2(1.0f, 0.0f);
 }
 
 __global__ void copy_kernel(double2 *dst, const double2 *src, int64_t n) {
@@ -43,7 +43,11 @@ __global__ void set_int_kernel(int *p, int v) { *p = v; }
 
 template <typename TY>
 __global__ __launch_bounds__(RT) void dot_partials_kernel(const double2 *a, const TY *y, int P,
-                                                          int64_t pstride, int64_t n, double *out) {
+                                                          int64_t pstride, int64_t n, double *out,
+                                                          int64_t ia, int64_t iy, int64_t io) {
+  a += blockIdx.x * ia;
+  y += blockIdx.x * iy;
+  out += blockIdx.x * io;
   double s = 0.0;
   for (int64_t e = threadIdx.x; e < n; e += RT) {
     double yr = 0.0, yi = 0.0;
@@ -59,7 +63,11 @@ __global__ __launch_bounds__(RT) void dot_partials_kernel(const double2 *a, cons
 }
 
 __global__ __launch_bounds__(RT) void dot2d_kernel(const double2 *a, const double2 *b, int rows,
-                                                   int cols, int64_t rs, int64_t cs, double *out) {
+                                                   int cols, int64_t rs, int64_t cs, double *out,
+                                                   int64_t ia, int64_t ib, int64_t io) {
+  a += blockIdx.x * ia;
+  b += blockIdx.x * ib;
+  out += blockIdx.x * io;
   double s = 0.0;
   const int64_t tot = (int64_t)rows * cols;
   for (int64_t e = threadIdx.x; e < tot; e += RT) {
@@ -85,7 +93,9 @@ __global__ void sum_partials_kernel(const TY *y, int P, int64_t pstride, int64_t
   }
 }
 
-__global__ void axpy_scalar_kernel(double *dst, const double *src, double c) { *dst += c * *src; }
+__global__ void axpy_scalar_kernel(double *dst, const double *src, double c, int64_t is) {
+  dst[threadIdx.x * is] += c * src[threadIdx.x * is];
+}
 
 __global__ __launch_bounds__(RT) void normalize_kernel(double2 *a, int64_t n) {
   double s = 0.0;
@@ -102,8 +112,8 @@ __global__ __launch_bounds__(RT) void normalize_kernel(double2 *a, int64_t n) {
 
 }  // namespace
 
-hipError_t fill_one(void *p, DType t, hipStream_t s) {
-  hipLaunchKernelGGL(fill_one_kernel, dim3(1), dim3(1), 0, s, p, (int)t);
+hipError_t fill_one(void *p, DType t, hipStream_t s, int count, int64_t is) {
+  hipLaunchKernelGGL(fill_one_kernel, dim3(1), dim3(count), 0, s, p, (int)t, is);
   return hipGetLastError();
 }
 
@@ -121,19 +131,20 @@ hipError_t set_dev_int(int *p, int v, hipStream_t s) {
 }
 
 hipError_t dot_partials(const double2 *a, DType ty, const void *y, int P, int64_t pstride, int64_t n,
-                        double *out, hipStream_t s) {
+                        double *out, hipStream_t s, int count, int64_t ia, int64_t iy, int64_t io) {
   if (ty == F64)
-    hipLaunchKernelGGL(dot_partials_kernel<double2>, dim3(1), dim3(RT), 0, s, a,
-                       (const double2 *)y, P, pstride, n, out);
+    hipLaunchKernelGGL(dot_partials_kernel<double2>, dim3(count), dim3(RT), 0, s, a,
+                       (const double2 *)y, P, pstride, n, out, ia, iy, io);
   else
-    hipLaunchKernelGGL(dot_partials_kernel<float2>, dim3(1), dim3(RT), 0, s, a,
-                       (const float2 *)y, P, pstride, n, out);
+    hipLaunchKernelGGL(dot_partials_kernel<float2>, dim3(count), dim3(RT), 0, s, a,
+                       (const float2 *)y, P, pstride, n, out, ia, iy, io);
   return hipGetLastError();
 }
 
 hipError_t dot2d(const double2 *a, const double2 *b, int rows, int cols, int64_t rs, int64_t cs,
-                 double *out, hipStream_t s) {
-  hipLaunchKernelGGL(dot2d_kernel, dim3(1), dim3(RT), 0, s, a, b, rows, cols, rs, cs, out);
+                 double *out, hipStream_t s, int count, int64_t ia, int64_t ib, int64_t io) {
+  hipLaunchKernelGGL(dot2d_kernel, dim3(count), dim3(RT), 0, s, a, b, rows, cols, rs, cs, out, ia, ib,
+                     io);
   return hipGetLastError();
 }
 
@@ -151,8 +162,8 @@ hipError_t sum_partials(DType ty, const void *y, int P, int64_t pstride, int64_t
   return hipGetLastError();
 }
 
-hipError_t axpy_scalar(double *dst, const double *src, double c, hipStream_t s) {
-  hipLaunchKernelGGL(axpy_scalar_kernel, dim3(1), dim3(1), 0, s, dst, src, c);
+hipError_t axpy_scalar(double *dst, const double *src, double c, hipStream_t s, int count, int64_t is) {
+  hipLaunchKernelGGL(axpy_scalar_kernel, dim3(1), dim3(count), 0, s, dst, src, c, is);
   return hipGetLastError();
 }
 

@@ -21,7 +21,8 @@ template <> struct Cplx<float> { using type = float2; };
 
 template <typename T>
 __global__ __launch_bounds__(256) void wapply_kernel(WApplyArgs p) {
-  if (p.skip && *p.skip) return;
+  const int ri = blockIdx.z;   // instance
+  if (p.skip && p.skip[(int64_t)ri * p.inst.skip]) return;
   using V = typename Cplx<T>::type;
   __shared__ T cre[MAXNZ], cim[MAXNZ];
   __shared__ int cw[MAXNZ], cs[MAXNZ];
@@ -29,7 +30,7 @@ __global__ __launch_bounds__(256) void wapply_kernel(WApplyArgs p) {
   const int d = p.d;
   const int wo = blockIdx.y / d, so = blockIdx.y % d;
   const int Win = p.w_in_right ? p.Wr : p.Wl;
-  const double2 *W = reinterpret_cast<const double2 *>(p.W);
+  const double2 *W = reinterpret_cast<const double2 *>(p.W) + (int64_t)ri * p.inst.b;
   const int ncand = Win * d;
   // ordered compaction of nonzero coefficients by wave 0
   if (threadIdx.x < 64) {
@@ -65,8 +66,8 @@ __global__ __launch_bounds__(256) void wapply_kernel(WApplyArgs p) {
   }
   __syncthreads();
   const int nnz = nnz_s;
-  const V *in = reinterpret_cast<const V *>(p.in);
-  V *out = reinterpret_cast<V *>(p.out);
+  const V *in = reinterpret_cast<const V *>(p.in) + (int64_t)ri * p.inst.a;
+  V *out = reinterpret_cast<V *>(p.out) + (int64_t)ri * p.inst.c;
   const int64_t total = (int64_t)p.A * p.C;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
@@ -92,10 +93,10 @@ hipError_t wapply(DType t, const WApplyArgs &a, hipStream_t s) {
   const int Win = a.w_in_right ? a.Wr : a.Wl;
   if (Win * a.d > MAXNZ) return hipErrorInvalidValue;
   const int64_t total = (int64_t)a.A * a.C;
-  if (total <= 0 || Wout <= 0) return hipSuccess;
+  if (total <= 0 || Wout <= 0 || a.inst.count <= 0) return hipSuccess;
   int gx = (int)((total + 255) / 256);
   if (gx > 64) gx = 64;
-  dim3 grid(gx, Wout * a.d);
+  dim3 grid(gx, Wout * a.d, a.inst.count);
   if (t == F64)
     hipLaunchKernelGGL(wapply_kernel<double>, grid, dim3(256), 0, s, a);
   else

@@ -66,6 +66,10 @@ EXPORTS = {
                              c_int, c_void_p]),
     "tdvp_set_krylov_log": (c_int, [c_void_p, c_void_p, c_int]),
     "tdvp_set_graph": (c_int, [c_void_p, c_int]),
+    "tdvp_ps_step_batched": (c_int, [c_void_p, c_int, POINTER(_Mps), POINTER(_Mpo), POINTER(_Envs),
+                                     c_double, c_int, c_int, c_double]),
+    "tdvp_observe_batched": (c_int, [c_void_p, c_int, POINTER(_Mps), POINTER(_Mpo), POINTER(_Envs),
+                                     POINTER(c_int32), c_int, c_void_p]),
     "tdvp_profile": (c_int, [c_void_p, c_int]),
     "tdvp_profile_read": (c_int, [c_void_p, POINTER(c_double), POINTER(c_int64), POINTER(c_double),
                                   POINTER(c_double)]),
@@ -391,3 +395,113 @@ class PsRun:
     def mps_numpy(self):
         self.stream.synchronize()
         return self.mps.numpy()
+
+
+# ---------------------------------------------------------------- ensembles
+
+def ps_step_batched(ctx, descs, dt, nsteps=1, kmax=20, tol=0.0):
+    mps_arr, mpo_arr, env_arr = descs
+    _check(lib().tdvp_ps_step_batched(ctx.h, len(mps_arr), mps_arr, mpo_arr, env_arr, float(dt),
+                                      int(nsteps), int(kmax), float(tol)), "tdvp_ps_step_batched")
+
+
+def observe_batched(ctx, descs, el_sites, out):
+    mps_arr, mpo_arr, env_arr = descs
+    arr = _i32(el_sites)
+    _check(lib().tdvp_observe_batched(ctx.h, len(mps_arr), mps_arr, mpo_arr, env_arr, arr,
+                                      len(el_sites), _ptr(out)), "tdvp_observe_batched")
+
+
+class PsEnsemble:
+    """Independent chains of identical shape evolved together (one launch per kernel).
+
+    Each site tensor of the ensemble is one (nb, ...) device array, so every
+    instance sits at a constant stride from instance 0, as the batched entry
+    points require.  ``params_list`` holds one parameter set per instance
+    (e.g. static-disorder realisations); ``raw_list`` the raw initial MPS of
+    each instance.
+    """
+
+    def __init__(self, params_list, sites, raw_list, device=0, precision=FP64, kmax=20, tol=0.0,
+                 graph=True, stream=None):
+        import torch
+        self.torch = torch
+        nb = len(params_list)
+        self.nb = nb
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
+        self.ctx = Context(device, precision, stream=self.stream)
+        dev = self.ctx.device
+        self.sites = sites
+        self.n_e = params_list[0].n_e
+        self.kmax, self.tol = kmax, tol
+        n = len(sites)
+        with torch.cuda.stream(self.stream):
+            models = [fmo_model(p, sites) for p in params_list]
+            wbond = models[0][1]
+            if any(m[1] != wbond for m in models):
+                raise TdvpError("instances have different MPO bond dims")
+            self.shifts = [m[2] for m in models]
+            self.W = [torch.as_tensor(np.stack([m[0][i] for m in models]), dtype=torch.complex128).to(dev)
+                      for i in range(n)]
+            self.A = [torch.as_tensor(np.stack([r[i] for r in raw_list]), dtype=torch.complex128).to(dev)
+                      for i in range(n)]
+            bond = [raw_list[0][0].shape[0]] + [a.shape[2] for a in raw_list[0]]
+            self.bond, self.wbond = bond, wbond
+            et = self.ctx.env_dtype
+            self.L = [torch.zeros((nb, bond[b], wbond[b], bond[b]), dtype=et, device=dev) for b in range(n + 1)]
+            self.R = [torch.zeros((nb, bond[b], wbond[b], bond[b]), dtype=et, device=dev) for b in range(n + 1)]
+            self.obs = torch.zeros((nb, 2 + self.n_e), dtype=torch.float64, device=dev)
+        self.stream.synchronize()
+        phys = [s[3] for s in sites]
+        self._keep = []
+        mps_arr = (_Mps * nb)()
+        mpo_arr = (_Mpo * nb)()
+        env_arr = (_Envs * nb)()
+        self.el_sites = [0] * self.n_e
+        for i, s in enumerate(sites):
+            if s[0] == "el":
+                self.el_sites[s[1]] = i
+        pp, pb, pw = _i32(phys), _i32(bond), _i32(wbond)
+        self._keep += [pp, pb, pw]
+        for r in range(nb):
+            site = (c_void_p * n)(*[t[r].data_ptr() for t in self.A])
+            wsite = (c_void_p * n)(*[t[r].data_ptr() for t in self.W])
+            lft = (c_void_p * (n + 1))(*[t[r].data_ptr() for t in self.L])
+            rgt = (c_void_p * (n + 1))(*[t[r].data_ptr() for t in self.R])
+            self._keep += [site, wsite, lft, rgt]
+            mps_arr[r] = _Mps(n, pp, pb, site)
+            mpo_arr[r] = _Mpo(n, pp, pw, wsite, float(self.shifts[r]))
+            env_arr[r] = _Envs(lft, rgt)
+        self.descs = (mps_arr, mpo_arr, env_arr)
+        one = workspace_bytes(self.ctx, _Wrap(mps_arr[0]), _Wrap(mpo_arr[0]), kmax)
+        self.ctx.reserve(nb * one)
+        set_graph(self.ctx, graph)
+        for r in range(nb):
+            _check(lib().tdvp_right_canonicalize(self.ctx.h, ctypes.byref(mps_arr[r])),
+                   "tdvp_right_canonicalize")
+            _check(lib().tdvp_envs_build(self.ctx.h, ctypes.byref(mps_arr[r]), ctypes.byref(mpo_arr[r]),
+                                         ctypes.byref(env_arr[r])), "tdvp_envs_build")
+
+    def step(self, dt_au, nsteps=1):
+        ps_step_batched(self.ctx, self.descs, dt_au, nsteps, self.kmax, self.tol)
+
+    def observe(self, out=None):
+        out = self.obs if out is None else out
+        observe_batched(self.ctx, self.descs, self.el_sites, out)
+        return out
+
+    def observe_host(self):
+        out = self.observe()
+        self.stream.synchronize()
+        return out.cpu().numpy().copy()
+
+    def mps_numpy(self, r):
+        self.stream.synchronize()
+        return [t[r].cpu().numpy() for t in self.A]
+
+
+class _Wrap:
+    """Adapter so workspace_bytes() can take a raw descriptor."""
+
+    def __init__(self, desc):
+        self.desc = desc

@@ -1,0 +1,55 @@
+"""Batched ensemble (tdvp_ps_step_batched): every kernel covers all
+instances in one launch; each instance must come out exactly as the single
+chain run does (same kernels, same tile shapes, same reduction order)."""
+
+import numpy as np
+import pytest
+
+from inputs import draw_params, chain_sites, initial_mps_raw
+from oracle import model
+
+from gpu_util import require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _instances(nb, M, n_modes=3, levels=4):
+    ps_ = [draw_params(4, n_modes, levels, seed=0, realisation=r) for r in range(nb)]
+    sites = chain_sites(ps_[0])
+    raws = [initial_mps_raw(p, M, 1e-2, 10 + r) for r, p in enumerate(ps_)]
+    return ps_, sites, raws
+
+
+@pytest.mark.parametrize("precision,graph", [(0, True), (0, False), (1, True)])
+def test_batched_equals_single_runs(precision, graph):
+    require_gpu()
+    from paper_1907_12044_amd import tdvp
+    nb = 3
+    ps_, sites, raws = _instances(nb, 12)
+    tau = 2.0 * model.AU_PER_FS
+    ens = tdvp.PsEnsemble(ps_, sites, raws, 0, precision, kmax=20, graph=graph)
+    singles = [tdvp.PsRun(p, sites, raw, 0, precision, kmax=20, graph=graph) for p, raw in zip(ps_, raws)]
+    for step in range(3):
+        ens.step(tau, 1)
+        ob = ens.observe_host()
+        for r, run in enumerate(singles):
+            run.step(tau, 1)
+            o1 = run.observe_host()
+            assert np.array_equal(ob[r], o1), (step, r, ob[r], o1)
+    for r, run in enumerate(singles):
+        a = ens.mps_numpy(r)
+        b = run.mps_numpy()
+        assert all(np.array_equal(x, y) for x, y in zip(a, b)), r
+
+
+def test_batched_rejects_unstrided_layout():
+    require_gpu()
+    from paper_1907_12044_amd import tdvp
+    import ctypes
+    ps_, sites, raws = _instances(3, 8)
+    ens = tdvp.PsEnsemble(ps_, sites, raws, 0, 0, kmax=8)
+    mps_arr, mpo_arr, env_arr = ens.descs
+    # swap two instances: still valid descriptors, but not at constant strides
+    bad = (type(mps_arr))(mps_arr[0], mps_arr[2], mps_arr[1])
+    with pytest.raises(tdvp.TdvpError):
+        tdvp.ps_step_batched(ens.ctx, (bad, mpo_arr, env_arr), 1.0)
