@@ -35,6 +35,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--eager", action="store_true", help="launch kernels one by one (no step graph)")
     ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--realisations", type=int, default=64)
     return ap.parse_args()
 
 
@@ -61,12 +62,75 @@ def cpu_baseline(name, nsteps):
                       f"({os.cpu_count()} host CPUs visible)"}
 
 
+def ensemble_main(args):
+    """64 static-disorder realisations, bond dims from {32, 64, 96, 128}: one
+    PsEnsemble per bond-dimension class (every kernel covers the class in one
+    launch), the classes on separate streams so they run concurrently."""
+    import numpy as np
+    import torch
+    from inputs import draw_params, chain_sites, initial_mps_raw
+    from inputs.fmo import ensemble_bond
+    from paper_1907_12044_amd import tdvp
+
+    nreal = args.realisations
+    prec = tdvp.FP64 if args.precision == "fp64" else tdvp.FP32
+    classes = {}
+    for r in range(nreal):
+        classes.setdefault(ensemble_bond(0, r), []).append(r)
+    ens = []
+    for M, rs in sorted(classes.items()):
+        ps_ = [draw_params(7, 10, 8, seed=0, realisation=r) for r in rs]
+        sites = chain_sites(ps_[0])
+        raws = [initial_mps_raw(p, M, 1e-2, 1) for p in ps_]
+        ens.append((M, rs, tdvp.PsEnsemble(ps_, sites, raws, 0, prec, kmax=args.kmax, tol=args.tol,
+                                           graph=not args.eager)))
+    tau = 2.0 * tdvp.AU_PER_FS
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        for _, _, e in ens:
+            e.step(tau, 1)
+            e.observe()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for _, _, e in ens:
+            e.step(tau, 1)
+            e.observe()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms = 1e3 * elapsed / max(args.steps, 1)
+    flop = 0.0
+    for _, _, e in ens:
+        tdvp.profile(e.ctx, tdvp.PROF_GEMM)
+        e.step(tau, 1)
+        _, _, f, _ = tdvp.profile_read(e.ctx)
+        tdvp.profile(e.ctx, 0)
+        flop += f
+    pops = np.concatenate([e.observe_host()[:, 2:] for _, _, e in ens])
+    line = {
+        "metric": "TDVP-PS ensemble steps/s (all realisations advanced one step)",
+        "value": 1e3 / ms, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128" if prec == tdvp.FP64 else "c64 contractions / c128 Krylov+QR",
+        "data": "synthetic",
+        "config": {"workload": f"fmo7x10x8_ensemble{nreal}", "classes": {str(M): len(rs) for M, rs, _ in ens},
+                   "precision": args.precision, "kmax": args.kmax},
+        "realisation_steps_per_s": nreal * 1e3 / ms,
+        "heff_tflops": flop / (ms * 1e-3) / 1e12,
+        "population_sum_range": [float(pops.sum(1).min()), float(pops.sum(1).max())],
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "the ensemble would shard realisations across GPUs, see DESIGN.md", file=sys.stderr)
         sys.exit(2)
+    if args.workload.startswith("ensemble"):
+        return ensemble_main(args)
     import numpy as np
     import torch
     from inputs import workload
@@ -105,8 +169,7 @@ def main():
     ks = klog.cpu().numpy()
     ks = ks[ks > 0]
     prof = {}
-    for name, cls in (("gemm", tdvp.PROF_GEMM), ("wapply", tdvp.PROF_WAPPLY),
-                      ("lanczos", tdvp.PROF_LANCZOS), ("qr", tdvp.PROF_QR)):
+    for name, cls in tdvp.PROF_CLASSES.items():
         tdvp.profile(run.ctx, cls)
         run.step(tau, 1)
         ms, n, f, b = tdvp.profile_read(run.ctx)

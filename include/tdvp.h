@@ -190,10 +190,12 @@ tdvp_status tdvp_set_krylov_log(tdvp_ctx *ctx, int32_t *dev, int capacity);
  * time (ms), the launch count and the summed FLOP and bytes. */
 enum {
   TDVP_PROF_OFF = 0,
-  TDVP_PROF_GEMM = 1,     /* complex MFMA contractions                    */
-  TDVP_PROF_WAPPLY = 2,   /* MPO channel stage                            */
-  TDVP_PROF_LANCZOS = 3,  /* Lanczos vector kernels and small exponential */
-  TDVP_PROF_QR = 4        /* Householder QR                               */
+  TDVP_PROF_GEMM = 1,       /* complex MFMA contractions (cgemm_kernel)         */
+  TDVP_PROF_WAPPLY = 2,     /* MPO channel stage (wapply_kernel)                */
+  TDVP_PROF_LZ_DOTS = 3,    /* Lanczos projections (lz_dots_kernel)             */
+  TDVP_PROF_LZ_UPDATE = 4,  /* Lanczos orthogonalisation (lz_update_kernel)     */
+  TDVP_PROF_LZ_ENDS = 5,    /* Lanczos start and final combination + exp(zT)e1  */
+  TDVP_PROF_QR = 6          /* Householder QR (qr_* kernels)                    */
 };
 tdvp_status tdvp_profile(tdvp_ctx *ctx, int kernel_class);
 tdvp_status tdvp_profile_read(tdvp_ctx *ctx, double *ms, int64_t *launches, double *flops,

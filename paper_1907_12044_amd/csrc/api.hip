@@ -239,16 +239,16 @@ tdvp_status run_lanczos(tdvp_ctx *c, const Layout &lay, const Op &op, double zr,
   LzInst li;
   li.count = b.R; li.wss = b.ws; li.xs = sx; li.ys = sy;
   const double vb = 16.0 * n * b.R;
-  int id = prof_begin(c, TDVP_PROF_LANCZOS);
+  int id = prof_begin(c, TDVP_PROF_LZ_ENDS);
   CK(lz_start(st, pp, (const double2 *)x, U, n, zr, zi, tol, keff, li, c->stream));
   prof_end(c, id, 4.0 * n * b.R, 2.0 * vb);
   for (int j = 0; j < keff; ++j) {
     CS(apply_op(c, lay, op, U + (int64_t)j * n, b.wsel(16), &st->stop, b));
-    id = prof_begin(c, TDVP_PROF_LANCZOS);
+    id = prof_begin(c, TDVP_PROF_LZ_DOTS);
     CK(lz_dots(st, pp, env_type(c), c->ws + lay.Y, op.parts(), n, U, n, j, n, li, c->stream));
     prof_end(c, id, 8.0 * (j + 1) * n * b.R,
              (double)op.parts() * n * env_bytes(c) * b.R + vb + (j + 1) * vb);
-    id = prof_begin(c, TDVP_PROF_LANCZOS);
+    id = prof_begin(c, TDVP_PROF_LZ_UPDATE);
     CK(lz_update(st, pp, U, n, j, n, li, c->stream));
     prof_end(c, id, 8.0 * (j + 1) * n * b.R, 2.0 * vb + (j + 1) * vb);
   }
@@ -256,7 +256,7 @@ tdvp_status run_lanczos(tdvp_ctx *c, const Layout &lay, const Op &op, double zr,
     kused = c->klog + c->klog_pos;
     c->klog_pos += b.R;
   }
-  id = prof_begin(c, TDVP_PROF_LANCZOS);
+  id = prof_begin(c, TDVP_PROF_LZ_ENDS);
   CK(lz_finish(st, U, n, n, keff, (double2 *)y, kused, li, c->stream));
   prof_end(c, id, 8.0 * keff * n * b.R, keff * vb + vb);
   return TDVP_OK;

@@ -54,9 +54,11 @@ __device__ double block_sum(double v, double *sh) {
 // exp(z T) e_1 for the k x k real symmetric tridiagonal T(alpha, beta),
 // computed by one wave64 (lane i holds component i): T is shifted by the
 // mean of its diagonal (the shift returns as the scalar factor
-// exp(z shift)); the interval is cut into s pieces with |z| |T'| / s <= 2
-// (Gershgorin bound) and on each piece the Taylor series of exp is summed
-// until its terms fall below 1e-17 of the running sum (at most 40 terms).
+// exp(z shift)); the interval is cut into s pieces with
+// theta = |z| |T'| / s <= 2 (Gershgorin bound on |T'|), and on each piece
+// the Taylor series of exp is summed to m terms, m the smallest with
+// theta^(m+1) / (m+1)! <= 1e-17 (a bound on the truncation error of a
+// piece relative to the unit-norm vector it acts on).
 // Writes k complex coefficients to (outr, outi).
 __device__ void exp_tridiag_e1_wave(const double *alpha, const double *beta, int k, double zr,
                                     double zi, double *outr, double *outi) {
@@ -75,10 +77,20 @@ __device__ void exp_tridiag_e1_wave(const double *alpha, const double *beta, int
   // non-finite but the loop stays bounded
   int ns = (pieces >= 1.0 && pieces <= 65536.0) ? (int)pieces : (pieces > 65536.0 ? 65536 : 1);
   const double hr = zr / ns, hi = zi / ns;
+  const double theta = zabs * gersh / ns;
+  int mterms = 1;
+  {
+    double term = theta;   // theta^m / m!
+    while (mterms < 40 && term * theta / (mterms + 1) > 1e-17) {
+      term *= theta / (mterms + 1);
+      ++mterms;
+    }
+    mterms += 1;
+  }
   double vr = (lane == 0) ? 1.0 : 0.0, vi = 0.0;
   for (int s = 0; s < ns; ++s) {
     double tr = vr, ti = vi, sr = vr, si = vi;
-    for (int t = 1; t <= 40; ++t) {
+    for (int t = 1; t <= mterms; ++t) {
       const double tmr = __shfl_up(tr, 1, 64), tmi = __shfl_up(ti, 1, 64);
       const double tpr = __shfl_down(tr, 1, 64), tpi = __shfl_down(ti, 1, 64);
       double xr = a * tr + bdl * tmr + bu * tpr;
@@ -89,9 +101,6 @@ __device__ void exp_tridiag_e1_wave(const double *alpha, const double *beta, int
       ti = (hr * xi + hi * xr) * inv;
       sr += tr;
       si += ti;
-      const double tmag = wave_max(fabs(tr) + fabs(ti));
-      const double smag = wave_max(fabs(sr) + fabs(si));
-      if (tmag <= 1e-17 * smag) break;
     }
     vr = sr;
     vi = si;

@@ -313,7 +313,9 @@ def observe(ctx, mps, mpo, envs, el_sites, out):
                               ctypes.byref(envs.desc), arr, len(el_sites), _ptr(out)), "tdvp_observe")
 
 
-PROF_GEMM, PROF_WAPPLY, PROF_LANCZOS, PROF_QR = 1, 2, 3, 4
+PROF_GEMM, PROF_WAPPLY, PROF_LZ_DOTS, PROF_LZ_UPDATE, PROF_LZ_ENDS, PROF_QR = 1, 2, 3, 4, 5, 6
+PROF_CLASSES = {"gemm": PROF_GEMM, "wapply": PROF_WAPPLY, "lz_dots": PROF_LZ_DOTS,
+                "lz_update": PROF_LZ_UPDATE, "lz_ends": PROF_LZ_ENDS, "qr": PROF_QR}
 
 
 def set_krylov_log(ctx, buf):

@@ -167,3 +167,40 @@ def test_parity_drift_over_steps():
         err = np.abs(obs[2:] - om.site_populations(m, sites, p.n_e)).max()
         print(f"steps {target}: max population difference {err:.3e}")
         assert err < 1e-10
+
+
+def test_fmo77_m64_fp64_one_step_matches_oracle():
+    """Bond dim 64 (multi-work-group QR path): one step against the oracle."""
+    require_gpu()
+    p = draw_params(7, 10, 8, seed=0)
+    sites = chain_sites(p)
+    raw = initial_mps_raw(p, 64, 1e-2, 1)
+    tau = 2.0 * model.AU_PER_FS
+    run = _gpu_run(p, sites, raw)
+    run.step(tau, 1)
+    obs = run.observe_host()
+    Ws, m0 = _oracle_init(p, sites, raw)
+    m, _ = ps.evolve(m0, Ws, tau, 1, kmax=20)
+    pops = om.site_populations(m, sites, p.n_e)
+    assert np.abs(obs[2:] - pops).max() < 1e-10
+    assert abs(obs[0] - om.norm2(m)) < 1e-12
+
+
+def test_fmo77_m128_mixed_vs_fp64_gpu():
+    """Bond dim 128: FP32 contractions against the FP64 GPU path (itself
+    pinned to the oracle above), plus norm and energy conservation."""
+    require_gpu()
+    p, sites, phys, dims, raw, w = workload("fmo7x10x8_M128")
+    tau = w["dt_fs"] * model.AU_PER_FS
+    r64 = _gpu_run(p, sites, raw, precision=0)
+    r32 = _gpu_run(p, sites, raw, precision=1)
+    e0 = r64.observe_host().copy()
+    for s in range(3):
+        r64.step(tau, 1)
+        r32.step(tau, 1)
+        a, b = r64.observe_host(), r32.observe_host()
+        print(f"step {s + 1}: |dP| {np.abs(a[2:] - b[2:]).max():.2e}  |dnorm| {abs(a[0] - b[0]):.2e}")
+        assert np.abs(a[2:] - b[2:]).max() < 1e-5
+    assert abs(a[0] - 1.0) < 1e-11
+    shift = r64.mpo.shift
+    assert abs((a[1] - shift * a[0]) - (e0[1] - shift * e0[0])) < 1e-10
