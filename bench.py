@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--eager", action="store_true", help="launch kernels one by one (no step graph)")
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--realisations", type=int, default=64)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one plain 256 MiB device copy first (reference for HBM counters)")
     return ap.parse_args()
 
 
@@ -136,6 +138,12 @@ def main():
     from inputs import workload
     from paper_1907_12044_amd import tdvp
 
+    if args.copy_calibration:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda:0")   # 256 MiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     p, sites, phys, dims, raw, w = workload(args.workload)
     prec = tdvp.FP64 if args.precision == "fp64" else tdvp.FP32
     run = tdvp.PsRun(p, sites, raw, device=0, precision=prec, kmax=args.kmax, tol=args.tol,

@@ -166,6 +166,16 @@ tdvp_status tdvp_ps_step(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo
  * Steps run eagerly while a Krylov log or kernel timing is active. */
 tdvp_status tdvp_set_graph(tdvp_ctx *ctx, int enable);
 
+/* Kernel path of the local Lanczos solves (eq:tdvp2_C, eq:tdvp2_D).  With
+ * enable != 0 (the default) a solve whose bond dimensions are small enough
+ * for the tiles of one work-group per output column to fit in LDS (e.g.
+ * M <= 32 in FP64, M <= 64 in FP32 for MPO bonds <= 16) runs each Krylov
+ * step as two kernels: the fused H x with its projections, then the
+ * orthogonalisation.  enable = 0 forces the general path (three contraction
+ * kernels, projections, orthogonalisation) for every solve.  Both paths
+ * compute the same quantities; results differ by rounding order only. */
+tdvp_status tdvp_set_fused(tdvp_ctx *ctx, int enable);
+
 /* Observables of a right-canonical MPS (Sec. III.A): out_dev (device double
  * [2 + n_el]) receives <psi|psi>, <psi|H|psi> + energy_shift * <psi|psi>, and
  * the populations <psi|a+_m a_m|psi> of the electronic sites el_sites[m]
@@ -195,7 +205,8 @@ enum {
   TDVP_PROF_LZ_DOTS = 3,    /* Lanczos projections (lz_dots_kernel)             */
   TDVP_PROF_LZ_UPDATE = 4,  /* Lanczos orthogonalisation (lz_update_kernel)     */
   TDVP_PROF_LZ_ENDS = 5,    /* Lanczos start and final combination + exp(zT)e1  */
-  TDVP_PROF_QR = 6          /* Householder QR (qr_* kernels)                    */
+  TDVP_PROF_QR = 6,         /* Householder QR (qr_* kernels)                    */
+  TDVP_PROF_LZ_FUSED = 7    /* fused H x + projections (heff_small_kernel)      */
 };
 tdvp_status tdvp_profile(tdvp_ctx *ctx, int kernel_class);
 tdvp_status tdvp_profile_read(tdvp_ctx *ctx, double *ms, int64_t *launches, double *flops,

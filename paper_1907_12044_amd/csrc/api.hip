@@ -44,6 +44,7 @@ struct tdvp_ctx {
   hipGraph_t graph;
   hipGraphExec_t gexec;
   std::vector<uint64_t> gkey;     // what the captured graph was built for
+  int fused_off;                  // 1: never use the fused small-bond Lanczos step
 };
 
 namespace {
@@ -69,6 +70,7 @@ int env_bytes(const tdvp_ctx *c) { return c->prec == TDVP_FP64 ? 16 : 8; }
 // entries and largest MPO bond is wmax.
 struct Layout {
   size_t st, pp, U, T1, T2, Y, D, tmp, qr, obs, total;
+  size_t ybytes;     // bytes of each of T1, T2, Y
   int64_t n;
 };
 
@@ -76,6 +78,7 @@ Layout layout(int64_t n, int wmax, int kmax, int es) {
   Layout L;
   size_t o = 0;
   L.n = n;
+  L.ybytes = (size_t)wmax * n * es;
   L.st = o; o += al256(sizeof(LzState));
   L.pp = o; o += al256(sizeof(LzPartials));
   L.U = o; o += al256((size_t)(kmax + 1) * n * 16);
@@ -227,6 +230,32 @@ tdvp_status apply_op(tdvp_ctx *c, const Layout &lay, const Op &op, const double2
   return TDVP_OK;
 }
 
+// Fused small-bond step (heff_small) for Op, if its tiles fit in LDS and the
+// nonzero table of W fits in the Y buffer (unused on this path).  Fills the
+// kernel arguments except st, pp, U, j.
+bool fused_args(const tdvp_ctx *c, const Layout &lay, const Op &op, const Bi &b, HeffSmallArgs &a) {
+  if (c->fused_off) return false;
+  a = HeffSmallArgs{};
+  a.L = op.L; a.R = op.R;
+  a.Ml = op.Ml; a.d = op.d; a.Mr = op.Mr; a.Wl = op.Wl; a.Wr = op.Wr;
+  a.n = op.size();
+  a.Gprev = lz_grid(a.n);
+  a.wss = b.ws; a.sL = op.sL; a.sR = op.sR;
+  if (!heff_small_fits(a, env_bytes(c) / 2)) return false;
+  if (op.W) {
+    const size_t rows = (size_t)op.Wl * op.d, cap = (size_t)op.d * op.Wr;
+    const size_t o_col = al256((rows + 1) * 4), o_coef = o_col + al256(rows * cap * 4);
+    if (o_coef + rows * cap * 16 > lay.ybytes) return false;
+    char *base = c->ws + lay.Y;
+    a.row = reinterpret_cast<const int *>(base);
+    a.col = reinterpret_cast<const int *>(base + o_col);
+    a.coef = reinterpret_cast<const double2 *>(base + o_coef);
+  } else if (op.Wl != op.Wr || op.d != 1) {
+    return false;
+  }
+  return true;
+}
+
 // y = exp(z Op) x for every instance; x, y c128 with instance strides sx, sy.
 tdvp_status run_lanczos(tdvp_ctx *c, const Layout &lay, const Op &op, double zr, double zi,
                         int kmax, double tol, const void *x, int64_t sx, void *y, int64_t sy,
@@ -239,17 +268,40 @@ tdvp_status run_lanczos(tdvp_ctx *c, const Layout &lay, const Op &op, double zr,
   LzInst li;
   li.count = b.R; li.wss = b.ws; li.xs = sx; li.ys = sy;
   const double vb = 16.0 * n * b.R;
+  HeffSmallArgs fa;
+  const bool fused = fused_args(c, lay, op, b, fa);
+  const int trows = fused ? op.Ml * op.d : 0;
+  if (fused && op.W)
+    CK(wtable((const double2 *)op.W, op.Wl, op.d, op.Wr, op.sW, const_cast<int *>(fa.row),
+              const_cast<int *>(fa.col), const_cast<double2 *>(fa.coef), b.ws, b.R, c->stream));
   int id = prof_begin(c, TDVP_PROF_LZ_ENDS);
-  CK(lz_start(st, pp, (const double2 *)x, U, n, zr, zi, tol, keff, li, c->stream));
+  CK(lz_start(st, pp, (const double2 *)x, U, n, zr, zi, tol, keff, trows, li, c->stream));
   prof_end(c, id, 4.0 * n * b.R, 2.0 * vb);
+  fa.st = st; fa.pp = pp; fa.U = U;
   for (int j = 0; j < keff; ++j) {
+    if (fused) {
+      // algorithmic work: the three contraction stages and j+1 projections;
+      // bytes: u_j, both environments, W, H u_j, and u_0..u_j once
+      const double Ml = op.Ml, d = op.d, Mr = op.Mr, Wl = op.Wl, Wr = op.Wr;
+      const double fl = 8.0 * (Ml * d * Mr * Wr * Mr + Wl * Ml * Ml * d * Mr) + 8.0 * (j + 1) * n;
+      const double by = (Ml * Wl * Ml + Mr * Wr * Mr) * env_bytes(c) +
+                        (op.W ? Wl * d * d * Wr * 16.0 : 0.0);
+      id = prof_begin(c, TDVP_PROF_LZ_FUSED);
+      fa.j = j;
+      CK(heff_small(env_type(c), fa, b.R, c->stream));
+      prof_end(c, id, fl * b.R, by * b.R + (j + 2) * vb);
+      id = prof_begin(c, TDVP_PROF_LZ_UPDATE);
+      CK(lz_update(st, pp, U, n, j, n, op.Mr, li, c->stream));
+      prof_end(c, id, 8.0 * (j + 1) * n * b.R, 2.0 * vb + (j + 1) * vb);
+      continue;
+    }
     CS(apply_op(c, lay, op, U + (int64_t)j * n, b.wsel(16), &st->stop, b));
     id = prof_begin(c, TDVP_PROF_LZ_DOTS);
     CK(lz_dots(st, pp, env_type(c), c->ws + lay.Y, op.parts(), n, U, n, j, n, li, c->stream));
     prof_end(c, id, 8.0 * (j + 1) * n * b.R,
              (double)op.parts() * n * env_bytes(c) * b.R + vb + (j + 1) * vb);
     id = prof_begin(c, TDVP_PROF_LZ_UPDATE);
-    CK(lz_update(st, pp, U, n, j, n, li, c->stream));
+    CK(lz_update(st, pp, U, n, j, n, 0, li, c->stream));
     prof_end(c, id, 8.0 * (j + 1) * n * b.R, 2.0 * vb + (j + 1) * vb);
   }
   if (!kused && c->klog && c->klog_pos + b.R <= c->klog_cap) {
@@ -257,7 +309,7 @@ tdvp_status run_lanczos(tdvp_ctx *c, const Layout &lay, const Op &op, double zr,
     c->klog_pos += b.R;
   }
   id = prof_begin(c, TDVP_PROF_LZ_ENDS);
-  CK(lz_finish(st, U, n, n, keff, (double2 *)y, kused, li, c->stream));
+  CK(lz_finish(st, U, n, n, keff, (double2 *)y, kused, trows, li, c->stream));
   prof_end(c, id, 8.0 * keff * n * b.R, keff * vb + vb);
   return TDVP_OK;
 }
@@ -461,6 +513,7 @@ tdvp_status tdvp_create(tdvp_ctx **ctx, int device, void *hip_stream, tdvp_preci
   c->klog_cap = 0;
   c->klog_pos = 0;
   c->graph_mode = 0;
+  c->fused_off = 0;
   c->graph = nullptr;
   c->gexec = nullptr;
   if (hipSetDevice(device) != hipSuccess) { delete c; return TDVP_E_DEVICE; }
@@ -496,7 +549,7 @@ tdvp_status tdvp_set_krylov_log(tdvp_ctx *ctx, int32_t *dev, int capacity) {
 }
 
 tdvp_status tdvp_profile(tdvp_ctx *ctx, int kernel_class) {
-  if (!ctx || kernel_class < 0 || kernel_class > TDVP_PROF_QR) return TDVP_E_ARG;
+  if (!ctx || kernel_class < 0 || kernel_class > TDVP_PROF_LZ_FUSED) return TDVP_E_ARG;
   ctx->prof_class = kernel_class;
   ctx->prof.clear();
   ctx->pool_used = 0;
@@ -718,6 +771,12 @@ tdvp_status tdvp_set_graph(tdvp_ctx *ctx, int enable) {
   return TDVP_OK;
 }
 
+tdvp_status tdvp_set_fused(tdvp_ctx *ctx, int enable) {
+  if (!ctx) return TDVP_E_ARG;
+  ctx->fused_off = enable ? 0 : 1;
+  return TDVP_OK;
+}
+
 tdvp_status tdvp_ps_step(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo,
                          const tdvp_envs *envs, double dt, int nsteps, int kmax, double tol) {
   return tdvp_ps_step_batched(ctx, 1, mps, mpo, envs, dt, nsteps, kmax, tol);
@@ -875,6 +934,7 @@ tdvp_status tdvp_ps_step_batched(tdvp_ctx *ctx, int nb, const tdvp_mps *mps, con
   key.push_back((uint64_t)kmax);
   key.push_back((uint64_t)(int)ctx->prec);
   key.push_back((uint64_t)nb);
+  key.push_back((uint64_t)ctx->fused_off);
   put(ctx->ws); put(ctx->stream);
   for (int i = 0; i < ch.n; ++i) {
     put(mps[0].site[i]); put(mpo[0].site[i]);

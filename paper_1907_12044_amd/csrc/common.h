@@ -89,14 +89,43 @@ struct LzInst {
   int count = 1;
   int64_t wss = 0, xs = 0, ys = 0;
 };
+// trows > 0 (lz_start, lz_finish): the basis is stored column-major, index
+// c * trows + r for the element (r, c) of the row-major n / trows-column x, y.
 hipError_t lz_start(LzState *st, LzPartials *pp, const double2 *x, double2 *u0, int64_t n,
-                    double zr, double zi, double tol, int keff, const LzInst &in, hipStream_t s);
+                    double zr, double zi, double tol, int keff, int trows, const LzInst &in,
+                    hipStream_t s);
 hipError_t lz_dots(LzState *st, LzPartials *pp, DType ty, const void *ypart, int P, int64_t pstride,
                    double2 *U, int64_t ldu, int j, int64_t n, const LzInst &in, hipStream_t s);
-hipError_t lz_update(LzState *st, LzPartials *pp, double2 *U, int64_t ldu, int j, int64_t n,
+// Gd: number of per-work-group dot partials written by the kernel before
+// (0 = the lz_dots grid for n).
+hipError_t lz_update(LzState *st, LzPartials *pp, double2 *U, int64_t ldu, int j, int64_t n, int Gd,
                      const LzInst &in, hipStream_t s);
+int lz_grid(int64_t n);   // work-groups of the Lanczos vector kernels for an n-vector
 hipError_t lz_finish(LzState *st, const double2 *U, int64_t ldu, int64_t n, int keff, double2 *y,
-                     int32_t *k_used, const LzInst &in, hipStream_t s);
+                     int32_t *k_used, int trows, const LzInst &in, hipStream_t s);
+
+// Fused small-bond Lanczos step: H u_j and the partial projections in one
+// launch, grid (Mr, instances).  u_j = U + j n, column-major (rows Ml d);
+// H u_j goes to U + (j + 1) n; one dot partial per column r' in pp.  The
+// operator is H[i] with W given by its nonzero table (row, col, coef from
+// wtable) or, with row == NULL, the bond operator (d = 1, Wl == Wr).
+constexpr size_t HEFF_SMALL_LDS = 150 * 1024;
+struct HeffSmallArgs {
+  LzState *st; LzPartials *pp; double2 *U;
+  int64_t n; int j; int Gprev;          // Gprev: norm partials written by the kernel before
+  const void *L, *R;                    // environments (context element type)
+  const int *row, *col; const double2 *coef;   // CSR table of W (wtable), in the workspace
+  int Ml, d, Mr, Wl, Wr;
+  int64_t wss, sL, sR;                  // instance strides: workspace bytes, env elements
+};
+size_t heff_small_lds(const HeffSmallArgs &a, int tm_bytes);
+bool heff_small_fits(const HeffSmallArgs &a, int tm_bytes);
+hipError_t heff_small(DType t, const HeffSmallArgs &a, int count, hipStream_t s);
+// CSR table of W[wl][s'][s][wr] (instance stride sW elements) over rows
+// wl d + s' (Wl d <= 256): row pointers rowp[Wl d + 1], then col (s Wr + wr)
+// and coef of each nonzero in index order.  Outputs at instance stride wss bytes.
+hipError_t wtable(const double2 *W, int Wl, int d, int Wr, int64_t sW, int *rowp, int *col,
+                  double2 *coef, int64_t wss, int count, hipStream_t s);
 
 // Householder QR of an m x n (m >= n) c128 matrix given by strides; writes
 // Q (m x n) and R (n x n) through output strides, with optional conjugation

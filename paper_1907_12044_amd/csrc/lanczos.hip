@@ -16,6 +16,7 @@
 // atomics or fences).  The breakdown test for step j-1 is therefore taken at
 // the start of lz_dots(j); a stopped solve makes every later kernel return
 // at once, so one fixed launch sequence serves every Krylov length.
+#include <algorithm>
 #include <type_traits>
 
 #include "common.h"
@@ -116,10 +117,75 @@ __device__ void exp_tridiag_e1_wave(const double *alpha, const double *beta, int
   }
 }
 
+// Start of Lanczos step j, run by every work-group of the kernel that opens
+// the step: add the Gprev partial norms of the previous kernel (fixed
+// tree), then close step j-1: beta_{j-1} and scale_j, the breakdown test
+// beta_{j-1} <= 1e-12 |H v_{j-1}|, the basis-size limit and, with tol > 0,
+// the a-posteriori estimate |z beta_{j-1} [exp(z T_j) e_1]_{j-1}| < tol.
+// Work-group 0 records the scalars.  Returns true (in every thread) if the
+// basis is final; the caller then returns.
+__device__ bool close_step(LzState *st, LzPartials *pp, int Gprev, int j) {
+  __shared__ int stop_s;
+  __shared__ double nrm_s;
+  __shared__ double coefr[KMAX], coefi[KMAX];
+  double aw = 0.0;
+  int keff = 0;
+  if (threadIdx.x < 64) {
+    if (threadIdx.x == 0 && j > 0) {   // issued with the partial loads
+      aw = st->aw[j - 1];
+      keff = st->keff;
+    }
+    double t = 0.0;
+    for (int b = threadIdx.x; b < Gprev; b += 64) t += pp->nrm[b];
+    t = wave_sum(t);
+    if (threadIdx.x == 0) nrm_s = t;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double nv = sqrt(nrm_s);
+    int stop = 0;
+    if (j == 0) {
+      if (!(nv > 0.0) || !isfinite(nv)) stop = 1;
+      if (blockIdx.x == 0) {
+        st->xnorm = nv;
+        st->scale[0] = stop ? 0.0 : 1.0 / nv;
+      }
+    } else {
+      if (!(nv > 1e-12 * aw) || !isfinite(nv) || j >= keff) stop = 1;
+      if (!stop && blockIdx.x == 0) {
+        st->beta[j - 1] = nv;
+        st->scale[j] = 1.0 / nv;
+      }
+    }
+    stop_s = stop;
+  }
+  __syncthreads();
+  if (!stop_s && j > 0 && st->tol > 0.0) {
+    const double bj = sqrt(nrm_s);
+    if (threadIdx.x < 64) {
+      // T_j needs beta_0 .. beta_{j-2}, all written by earlier kernels
+      exp_tridiag_e1_wave(st->alpha, st->beta, j, st->z_re, st->z_im, coefr, coefi);
+      if (threadIdx.x == 0) {
+        const double zabs = sqrt(st->z_re * st->z_re + st->z_im * st->z_im);
+        const double c = sqrt(coefr[j - 1] * coefr[j - 1] + coefi[j - 1] * coefi[j - 1]);
+        if (zabs * bj * c < st->tol) stop_s = 1;
+      }
+    }
+    __syncthreads();
+  }
+  const bool stop = stop_s != 0;
+  if (stop && blockIdx.x == 0 && threadIdx.x == 0) {
+    st->k = j;
+    st->stop = 1;
+  }
+  return stop;
+}
+
 __global__ __launch_bounds__(LZ_BLOCK) void lz_start_kernel(LzState *st, LzPartials *pp,
                                                             const double2 *x, double2 *u0,
                                                             int64_t n, double zr, double zi,
-                                                            double tol, int keff, LzInst in) {
+                                                            double tol, int keff, int trows,
+                                                            LzInst in) {
   const int64_t wo = (int64_t)blockIdx.y * in.wss;
   st = shift_bytes(st, wo);
   pp = shift_bytes(pp, wo);
@@ -127,9 +193,11 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_start_kernel(LzState *st, LzParti
   x += (int64_t)blockIdx.y * in.xs;
   __shared__ double sh[8];
   double s = 0.0;
+  const int64_t tcols = trows > 0 ? n / trows : 0;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const double2 v = x[e];
+    // column-major basis: u0[c * trows + r] = x[r * tcols + c]
+    const double2 v = trows > 0 ? x[(e % trows) * tcols + e / trows] : x[e];
     u0[e] = v;
     s += v.x * v.x + v.y * v.y;
   }
@@ -164,58 +232,8 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_dots_kernel(LzState *st, LzPartia
     U = shift_bytes(U, wo);
   }
   if (st->stop) return;
-  __shared__ int stop_s;
-  __shared__ double coefr[KMAX], coefi[KMAX];
   const int G = gridDim.x;
-  __shared__ double nrm_s;
-  if (threadIdx.x < 64) {   // fixed-order tree sum of the previous kernel's partial norms
-    double t = 0.0;
-    for (int b = threadIdx.x; b < G; b += 64) t += pp->nrm[b];
-    t = wave_sum(t);
-    if (threadIdx.x == 0) nrm_s = t;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const double t = nrm_s;
-    const double nv = sqrt(t);
-    int stop = 0;
-    if (j == 0) {
-      if (!(nv > 0.0) || !isfinite(nv)) stop = 1;
-      if (blockIdx.x == 0) {
-        st->xnorm = nv;
-        st->scale[0] = stop ? 0.0 : 1.0 / nv;
-      }
-    } else {
-      if (!(nv > 1e-12 * st->aw[j - 1]) || !isfinite(nv) || j >= st->keff) stop = 1;
-      if (!stop && blockIdx.x == 0) {
-        st->beta[j - 1] = nv;
-        st->scale[j] = 1.0 / nv;
-      }
-    }
-    stop_s = stop;
-  }
-  __syncthreads();
-  if (!stop_s && j > 0 && st->tol > 0.0) {
-    // a-posteriori estimate |z beta_{j-1} [exp(z T_j) e_1]_{j-1}| (every block alike)
-    const double bj = sqrt(nrm_s);
-    if (threadIdx.x < 64) {
-      // T_j needs beta_0 .. beta_{j-2}, all written by earlier kernels
-      exp_tridiag_e1_wave(st->alpha, st->beta, j, st->z_re, st->z_im, coefr, coefi);
-      if (threadIdx.x == 0) {
-        const double zabs = sqrt(st->z_re * st->z_re + st->z_im * st->z_im);
-        const double c = sqrt(coefr[j - 1] * coefr[j - 1] + coefi[j - 1] * coefi[j - 1]);
-        if (zabs * bj * c < st->tol) stop_s = 1;
-      }
-    }
-    __syncthreads();
-  }
-  if (stop_s) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      st->k = j;
-      st->stop = 1;
-    }
-    return;
-  }
+  if (close_step(st, pp, G, j)) return;
   // Chunks of 256 elements.  Phase 1: w for the chunk (one element per
   // thread) into LDS and U[j+1].  Phase 2: thread (g, t), g = tid / 32,
   // t = tid % 32, accumulates <u_i, w> over the chunk for i = g, g+8, g+16,
@@ -288,10 +306,12 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_dots_kernel(LzState *st, LzPartia
 }
 
 // u_{j+1} = scale_j w - sum_{i<=j} c_i scale_i u_i ; per-block |u_{j+1}|^2.
+// The loads of w and u_0..u_j for a thread's first element are issued
+// before the reduction of the dot partials, so the two latencies overlap.
 template <int JB>
 __global__ __launch_bounds__(LZ_BLOCK) void lz_update_kernel(LzState *st, LzPartials *pp,
                                                              double2 *U, int64_t ldu, int j,
-                                                             int64_t n, LzInst in) {
+                                                             int64_t n, int Gd, LzInst in) {
   {
     const int64_t wo = (int64_t)blockIdx.y * in.wss;
     st = shift_bytes(st, wo);
@@ -301,32 +321,62 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_update_kernel(LzState *st, LzPart
   if (st->stop) return;
   __shared__ double sh[8];
   __shared__ double cr[JB], ci[JB];
-  const int G = gridDim.x;
-  const double sj = st->scale[j];
-  if (threadIdx.x <= j) {
-    const int i = threadIdx.x;
-    double a = 0.0, b = 0.0;
-    for (int blk = 0; blk < G; ++blk) { a += pp->dre[blk][i]; b += pp->dim[blk][i]; }
-    const double si = st->scale[i];
-    const double sc = si * sj;
-    cr[i] = a * sc * si;      // c_i scale_i
-    ci[i] = b * sc * si;
-    if (i == j && blockIdx.x == 0) st->alpha[j] = a * sc;
+  double2 *w = U + (int64_t)(j + 1) * ldu;
+  const int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t estride = (int64_t)gridDim.x * blockDim.x;
+  constexpr int PF = JB < 16 ? JB : 16;    // basis vectors held in registers
+  double2 wv = make_double2(0.0, 0.0), uv[PF];
+  if (e0 < n) {
+    wv = w[e0];
+#pragma unroll
+    for (int i = 0; i < PF; ++i) uv[i] = i <= j ? U[(int64_t)i * ldu + e0] : make_double2(0.0, 0.0);
   }
-  if (threadIdx.x == 32 && blockIdx.x == 0) {
-    double t = 0.0;
-    for (int blk = 0; blk < G; ++blk) t += pp->w2[blk];
-    st->aw[j] = sqrt(t) * sj;
+  const double sj = st->scale[j];
+  // Reduce the Gd dot partials of the previous kernel: 8 lanes per basis
+  // index i (lane l adds partials l, l+8, ...), then a fixed 3-level tree.
+  {
+    const int i = threadIdx.x >> 3, l8 = threadIdx.x & 7;
+    double a = 0.0, b = 0.0;
+    if (i <= j) {
+      for (int blk = l8; blk < Gd; blk += 8) { a += pp->dre[blk][i]; b += pp->dim[blk][i]; }
+    }
+#pragma unroll
+    for (int o = 4; o > 0; o >>= 1) {
+      a += __shfl_xor(a, o, 8);
+      b += __shfl_xor(b, o, 8);
+    }
+    if (l8 == 0 && i <= j) {
+      const double si = st->scale[i];
+      const double sc = si * sj;
+      cr[i] = a * sc * si;      // c_i scale_i
+      ci[i] = b * sc * si;
+      if (i == j && blockIdx.x == 0) st->alpha[j] = a * sc;
+    }
+    if (blockIdx.x == 0 && threadIdx.x >= 192) {   // last wave: |H v_j|
+      double t = 0.0;
+      for (int blk = threadIdx.x - 192; blk < Gd; blk += 64) t += pp->w2[blk];
+      t = wave_sum(t);
+      if (threadIdx.x == 192) st->aw[j] = sqrt(t) * sj;
+    }
   }
   __syncthreads();
-  double2 *w = U + (int64_t)(j + 1) * ldu;
   double s2 = 0.0;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const double2 wv = w[e];
+  for (int64_t e = e0; e < n; e += estride) {
+    if (e != e0) {
+      wv = w[e];
+#pragma unroll
+      for (int i = 0; i < PF; ++i) uv[i] = i <= j ? U[(int64_t)i * ldu + e] : make_double2(0.0, 0.0);
+    }
     double xr = sj * wv.x, xi = sj * wv.y;
+#pragma unroll
+    for (int i = 0; i < PF; ++i) {
+      if (i <= j) {
+        xr -= cr[i] * uv[i].x - ci[i] * uv[i].y;
+        xi -= cr[i] * uv[i].y + ci[i] * uv[i].x;
+      }
+    }
 #pragma unroll 8
-    for (int i = 0; i <= j; ++i) {
+    for (int i = PF; i <= j; ++i) {
       const double2 u = U[(int64_t)i * ldu + e];
       xr -= cr[i] * u.x - ci[i] * u.y;
       xi -= cr[i] * u.y + ci[i] * u.x;
@@ -344,7 +394,7 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_update_kernel(LzState *st, LzPart
 __global__ __launch_bounds__(LZ_BLOCK) void lz_finish_kernel(LzState *st, const double2 *U,
                                                              int64_t ldu, int64_t n, int keff,
                                                              double2 *y, int32_t *k_used,
-                                                             LzInst in) {
+                                                             int trows, LzInst in) {
   {
     const int64_t wo = (int64_t)blockIdx.y * in.wss;
     st = shift_bytes(st, wo);
@@ -375,9 +425,352 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_finish_kernel(LzState *st, const 
         yi += cr[i] * u.y + ci[i] * u.x;
       }
     }
-    y[e] = make_double2(yr, yi);
+    if (trows > 0) {
+      const int64_t tcols = n / trows;
+      y[(e % trows) * tcols + e / trows] = make_double2(yr, yi);
+    } else {
+      y[e] = make_double2(yr, yi);
+    }
   }
   if (k_used && blockIdx.x == 0 && threadIdx.x == 0) *k_used = zero ? 0 : k;
+}
+
+// ---------------------------------------------------------------------------
+// Fused Lanczos step for small bonds: H[i] u_j (all three contraction
+// stages) plus the projections <u_i, H u_j> in ONE launch.  Work-group r'
+// owns output column r' of y[l', s', r'] and needs no other work-group:
+//   T1[(l, s)][wr] = sum_r u[(l, s)][r] R[r'][wr][r]        (MFMA, N = Wr <= 16)
+//   T2[(wl, l)][s'] = sum_{nonzero W} W[wl][s'][s][wr] T1[(l, s)][wr]   (LDS)
+//   y[l'][s']      = sum_{(wl, l)} L[l'][wl][l] T2[(wl, l)][s']  (MFMA, K split over waves)
+// then y -> U[j+1], per-work-group partial dots <u_i, y> and |y|^2 (the
+// partial layout lz_dots writes, one partial per r'), read by lz_update.
+// On this path the basis vectors are stored column-major (index r' * Ml d +
+// (l', s')), so that a work-group's column is contiguous; lz_start and
+// lz_finish convert from and to the row-major site tensor.  With rows ==
+// NULL the operator is the bond operator of eq:tdvp2_D (d = 1, T2 = T1^T).
+// The nonzeros of W come as a padded table, rows (wl, s'), each holding at
+// most d Wr entries (column s Wr + wr, coefficient).
+
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+template <typename T> struct Mf;
+template <> struct Mf<double> {
+  using acc = f64x4_t;
+  using c2 = double2;
+  static __device__ __forceinline__ acc mfma(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // row of a 16x16 result block held by (lane, register r)
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * r + (lane >> 4); }
+};
+template <> struct Mf<float> {
+  using acc = f32x4_t;
+  using c2 = float2;
+  static __device__ __forceinline__ acc mfma(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+constexpr int HS_WAVES = 8;            // waves per work-group of the fused step
+constexpr int HS_NZ = 512;             // W nonzeros staged in LDS (more: read from global)
+
+// Stage 2 over the (K3 x d) block of T2: T2[(wl, l)][s'] from T1 and the
+// nonzero table: row pointers rp, columns cl, coefficients (cr, ci) staged
+// in LDS, or the c128 table gc in global memory (GL).
+template <typename T, bool GL, typename PI>
+__device__ __forceinline__ void hs_stage2(T *t2_re, T *t2_im, const T *t1_re, const T *t1_im,
+                                          int K3, int Ml, int d, int cap, PI rp, PI cl,
+                                          const T *cr, const T *ci, const double2 *gc) {
+  for (int e = threadIdx.x; e < K3 * d; e += HS_WAVES * 64) {
+    const int k = e / d, sp = e - k * d;
+    const int wl = k / Ml, l = k - wl * Ml;
+    const int rw = wl * d + sp, q1 = rp[rw + 1];
+    const T *tr_ = t1_re + l * cap, *ti_ = t1_im + l * cap;
+    T re = 0, im = 0;
+    for (int q = rp[rw]; q < q1; ++q) {
+      const int cc = cl[q];
+      T wre, wim;
+      if (GL) {
+        const double2 w = gc[q];
+        wre = (T)w.x;
+        wim = (T)w.y;
+      } else {
+        wre = cr[q];
+        wim = ci[q];
+      }
+      const T tr = tr_[cc], ti = ti_[cc];
+      re += wre * tr - wim * ti;
+      im += wre * ti + wim * tr;
+    }
+    t2_re[k * 16 + sp] = re;
+    t2_im[k * 16 + sp] = im;
+  }
+}
+
+template <typename T, int JB>
+__global__ __launch_bounds__(HS_WAVES * 64) void heff_small_kernel(HeffSmallArgs a) {
+  using AccT = typename Mf<T>::acc;
+  using VE = typename Mf<T>::c2;
+  constexpr int NT = HS_WAVES * 64;
+  extern __shared__ char smem[];
+  const int rp = blockIdx.x;                      // output column r'
+  const int inst = blockIdx.y;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  LzState *st = shift_bytes(a.st, (int64_t)inst * a.wss);
+  LzPartials *pp = shift_bytes(a.pp, (int64_t)inst * a.wss);
+  double2 *U = shift_bytes(a.U, (int64_t)inst * a.wss);
+  const VE *L = reinterpret_cast<const VE *>(a.L) + (int64_t)inst * a.sL;
+  const VE *R = reinterpret_cast<const VE *>(a.R) + (int64_t)inst * a.sR;
+  const int j = a.j;
+  const int Ml = a.Ml, d = a.d, Mr = a.Mr, Wl = a.Wl, Wr = a.Wr;
+  const int ML1 = Ml * d;                  // rows of T1 and of y
+  const int K3 = Wl * Ml;                  // inner dimension of stage 3
+  const int Mr4 = (Mr + 3) & ~3, K34 = (K3 + 3) & ~3;
+  const int T1P = (ML1 * Wr + 3) & ~3;     // plane sizes keep every region 16-byte aligned
+  const int AP = max(2 * Mr4 * 16 + 2 * T1P, HS_WAVES * 2 * 256);
+  T *rr_re = reinterpret_cast<T *>(smem);  // stage 1 B operand [Mr4][16]
+  T *rr_im = rr_re + Mr4 * 16;
+  T *t1_re = rr_im + Mr4 * 16;             // [ML1][Wr]
+  T *t1_im = t1_re + T1P;
+  T *red = rr_re;                          // stage 3 partial results, over rr and T1
+  T *t2_re = rr_re + AP;                   // [K34][16]
+  T *t2_im = t2_re + K34 * 16;
+  double2 *ycol = reinterpret_cast<double2 *>(t2_im + K34 * 16);   // [ML1]
+  T *nz_re = reinterpret_cast<T *>(ycol + ML1);                   // staged W table
+  T *nz_im = nz_re + HS_NZ;
+  int *nz_col = reinterpret_cast<int *>(nz_im + HS_NZ);
+  int *nz_row = nz_col + HS_NZ;
+
+  const int stopped = st->stop;
+  // stage the R slice and the W table (loads issued before the step test)
+  for (int e = threadIdx.x; e < Mr4 * 16; e += NT) {
+    const int k = e >> 4, c = e & 15;
+    T re = 0, im = 0;
+    if (k < Mr && c < Wr) {
+      const VE v = R[((int64_t)rp * Wr + c) * Mr + k];
+      re = v.x;
+      im = v.y;
+    }
+    rr_re[e] = re;
+    rr_im[e] = im;
+  }
+  const int rows = Wl * d;
+  const int *g_row = a.row ? shift_bytes(a.row, (int64_t)inst * a.wss) : nullptr;
+  const int *g_col = a.row ? shift_bytes(a.col, (int64_t)inst * a.wss) : nullptr;
+  const double2 *g_coef = a.row ? shift_bytes(a.coef, (int64_t)inst * a.wss) : nullptr;
+  int nnz = 0;
+  if (g_row) {
+    nnz = g_row[rows];
+    for (int e = threadIdx.x; e <= rows; e += NT) nz_row[e] = g_row[e];
+    if (nnz <= HS_NZ) {
+      for (int e = threadIdx.x; e < nnz; e += NT) {
+        const double2 w = g_coef[e];
+        nz_re[e] = (T)w.x;
+        nz_im[e] = (T)w.y;
+        nz_col[e] = g_col[e];
+      }
+    }
+  }
+  if (stopped) return;
+  if (close_step(st, pp, a.Gprev, j)) return;   // (synchronises the work-group)
+
+  const double2 *x = U + (int64_t)j * a.n; // u_j, column-major
+  // stage 1: T1 (ML1 x Wr) = X (ML1 x Mr) Rr (Mr x Wr), 16-row tiles over the waves
+  for (int rt = wave; rt * 16 < ML1; rt += HS_WAVES) {
+    AccT cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+    const int row = rt * 16 + (lane & 15);
+#pragma unroll 8
+    for (int k0 = 0; k0 < Mr; k0 += 4) {
+      const int k = k0 + (lane >> 4);
+      T ar = 0, ai = 0;
+      if (row < ML1 && k < Mr) {
+        const double2 v = x[(int64_t)k * ML1 + row];
+        ar = (T)v.x;
+        ai = (T)v.y;
+      }
+      const T br = rr_re[k * 16 + (lane & 15)], bi = rr_im[k * 16 + (lane & 15)];
+      cr = Mf<T>::mfma(ar, br, cr);
+      cr = Mf<T>::mfma(-ai, bi, cr);
+      ci = Mf<T>::mfma(ar, bi, ci);
+      ci = Mf<T>::mfma(ai, br, ci);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int orow = rt * 16 + Mf<T>::row(lane, r);
+      const int ocol = lane & 15;
+      if (orow < ML1 && ocol < Wr) {
+        t1_re[orow * Wr + ocol] = cr[r];
+        t1_im[orow * Wr + ocol] = ci[r];
+      }
+    }
+  }
+  __syncthreads();
+  // stage 2: T2[(wl, l)][s'] for s' < d (padding columns only feed discarded
+  // outputs), padding rows K3..K34 zero
+  for (int e = K3 * 16 + threadIdx.x; e < K34 * 16; e += NT) {
+    t2_re[e] = 0;
+    t2_im[e] = 0;
+  }
+  if (!g_row) {                            // bond operator: T2[(w, l)][0] = T1[l][w]
+    for (int k = threadIdx.x; k < K3; k += NT) {
+      const int w = k / Ml, l = k - w * Ml;
+      t2_re[k * 16] = t1_re[l * Wr + w];
+      t2_im[k * 16] = t1_im[l * Wr + w];
+    }
+  } else if (nnz <= HS_NZ) {
+    hs_stage2<T, false>(t2_re, t2_im, t1_re, t1_im, K3, Ml, d, d * Wr, (const int *)nz_row,
+                        (const int *)nz_col, nz_re, nz_im, nullptr);
+  } else {
+    hs_stage2<T, true>(t2_re, t2_im, t1_re, t1_im, K3, Ml, d, d * Wr, g_row, g_col, nullptr,
+                       nullptr, g_coef);
+  }
+  __syncthreads();
+  // stage 3: y (Ml x d) = L (Ml x K3) T2 (K3 x d).  A round covers TPR row
+  // tiles; the K dimension of each tile is split over `parts` waves.
+  const int RT = (Ml + 15) / 16;
+  const int TPR = min(RT, HS_WAVES), parts = HS_WAVES / TPR;
+  const int kchunk = ((K34 / 4 + parts - 1) / parts) * 4;
+  for (int rt0 = 0; rt0 < RT; rt0 += TPR) {
+    AccT cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+    const int rt = rt0 + wave % TPR, part = wave / TPR;
+    if (rt < RT && part < parts) {
+      const int kb = part * kchunk, ke = min(K34, kb + kchunk);
+      const int row = rt * 16 + (lane & 15);
+      const VE *Lrow = L + (int64_t)row * K3;
+#pragma unroll 8
+      for (int k0 = kb; k0 < ke; k0 += 4) {
+        const int k = k0 + (lane >> 4);
+        T ar = 0, ai = 0;
+        if (row < Ml && k < K3) {
+          const VE v = Lrow[k];
+          ar = v.x;
+          ai = v.y;
+        }
+        const T br = t2_re[k * 16 + (lane & 15)], bi = t2_im[k * 16 + (lane & 15)];
+        cr = Mf<T>::mfma(ar, br, cr);
+        cr = Mf<T>::mfma(-ai, bi, cr);
+        ci = Mf<T>::mfma(ar, bi, ci);
+        ci = Mf<T>::mfma(ai, br, ci);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      red[(wave * 2 + 0) * 256 + r * 64 + lane] = cr[r];
+      red[(wave * 2 + 1) * 256 + r * 64 + lane] = ci[r];
+    }
+    __syncthreads();
+    // add the K parts in order, scatter into ycol[(l', s')]
+    for (int e = threadIdx.x; e < min(RT - rt0, TPR) * 256; e += NT) {
+      const int tt = e >> 8, rem = e & 255, r = rem >> 6, ln = rem & 63;
+      T sr = 0, si = 0;
+      for (int p = 0; p < parts; ++p) {
+        const int w = p * TPR + tt;
+        sr += red[(w * 2 + 0) * 256 + r * 64 + ln];
+        si += red[(w * 2 + 1) * 256 + r * 64 + ln];
+      }
+      const int orow = (rt0 + tt) * 16 + Mf<T>::row(ln, r);
+      const int ocol = ln & 15;
+      if (orow < Ml && ocol < d) ycol[orow * d + ocol] = make_double2((double)sr, (double)si);
+    }
+    __syncthreads();
+  }
+  // y -> U[j+1] (column r'), |y|^2 and <u_i, y> partials for this column:
+  // thread group g (32 threads) takes i = g, g + 16, ...
+  double2 *wdst = U + (int64_t)(j + 1) * a.n + (int64_t)rp * ML1;
+  double w2 = 0.0;
+  for (int e = threadIdx.x; e < ML1; e += NT) {
+    const double2 y = ycol[e];
+    wdst[e] = y;
+    w2 += y.x * y.x + y.y * y.y;
+  }
+  constexpr int NG = NT / 32;
+  constexpr int NQ = (JB + NG - 1) / NG;
+  const int g = threadIdx.x >> 5, t32 = threadIdx.x & 31;
+  double dr[NQ], di[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    dr[q] = 0.0;
+    di[q] = 0.0;
+    const int i = g + NG * q;
+    if (i <= j) {
+      const double2 *ui = U + (int64_t)i * a.n + (int64_t)rp * ML1;
+#pragma unroll 8
+      for (int el = t32; el < ML1; el += 32) {
+        const double2 u = ui[el];
+        const double2 y = ycol[el];
+        dr[q] += u.x * y.x + u.y * y.y;
+        di[q] += u.x * y.y - u.y * y.x;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+#pragma unroll
+    for (int o = 16; o > 0; o >>= 1) {
+      dr[q] += __shfl_xor(dr[q], o, 32);
+      di[q] += __shfl_xor(di[q], o, 32);
+    }
+    const int i = g + NG * q;
+    if (t32 == 0 && i <= j) {
+      pp->dre[rp][i] = dr[q];
+      pp->dim[rp][i] = di[q];
+    }
+  }
+  __shared__ double w2s[HS_WAVES];
+  w2 = wave_sum(w2);
+  if (lane == 0) w2s[wave] = w2;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < HS_WAVES; ++w) t += w2s[w];
+    pp->w2[rp] = t;
+  }
+}
+
+// Nonzero table (CSR over rows (wl, s')) of an MPO site tensor
+// W[wl][s'][s][wr]; one work-group per instance, thread r scans row r.
+__global__ __launch_bounds__(256) void wtable_kernel(const double2 *W, int rows, int d, int Wr,
+                                                     int64_t sW, int *rowp, int *col,
+                                                     double2 *coef, int64_t wss) {
+  const int inst = blockIdx.x, r = threadIdx.x;
+  W += (int64_t)inst * sW;
+  rowp = shift_bytes(rowp, (int64_t)inst * wss);
+  col = shift_bytes(col, (int64_t)inst * wss);
+  coef = shift_bytes(coef, (int64_t)inst * wss);
+  __shared__ int cnt[257];
+  const int cap = d * Wr;
+  int c = 0;
+  if (r < rows)
+    for (int q = 0; q < cap; ++q) {
+      const double2 v = W[(int64_t)r * cap + q];
+      c += (v.x != 0.0 || v.y != 0.0) ? 1 : 0;
+    }
+  cnt[r] = c;
+  __syncthreads();
+  if (r == 0) {
+    int s = 0;
+    for (int t = 0; t < rows; ++t) {
+      const int ct = cnt[t];
+      cnt[t] = s;
+      s += ct;
+    }
+    cnt[rows] = s;
+  }
+  __syncthreads();
+  if (r < rows) rowp[r] = cnt[r];
+  if (r == 0) rowp[rows] = cnt[rows];
+  if (r < rows) {
+    int pos = cnt[r];
+    for (int q = 0; q < cap; ++q) {
+      const double2 v = W[(int64_t)r * cap + q];
+      if (v.x != 0.0 || v.y != 0.0) {
+        col[pos] = q;
+        coef[pos] = v;
+        ++pos;
+      }
+    }
+  }
 }
 
 // Work-groups for an n-element vector pass: one element per thread, at most
@@ -392,9 +785,10 @@ int grid_for(int64_t n) {
 }  // namespace
 
 hipError_t lz_start(LzState *st, LzPartials *pp, const double2 *x, double2 *u0, int64_t n,
-                    double zr, double zi, double tol, int keff, const LzInst &in, hipStream_t s) {
+                    double zr, double zi, double tol, int keff, int trows, const LzInst &in,
+                    hipStream_t s) {
   hipLaunchKernelGGL(lz_start_kernel, dim3(grid_for(n), in.count), dim3(LZ_BLOCK), 0, s, st, pp, x,
-                     u0, n, zr, zi, tol, keff, in);
+                     u0, n, zr, zi, tol, keff, trows, in);
   return hipGetLastError();
 }
 
@@ -419,20 +813,75 @@ hipError_t lz_dots(LzState *st, LzPartials *pp, DType ty, const void *ypart, int
   return hipGetLastError();
 }
 
-hipError_t lz_update(LzState *st, LzPartials *pp, double2 *U, int64_t ldu, int j, int64_t n,
+hipError_t lz_update(LzState *st, LzPartials *pp, double2 *U, int64_t ldu, int j, int64_t n, int Gd,
                      const LzInst &in, hipStream_t s) {
   const dim3 g(grid_for(n), in.count), b(LZ_BLOCK);
-  if (j < 4) hipLaunchKernelGGL((lz_update_kernel<4>), g, b, 0, s, st, pp, U, ldu, j, n, in);
-  else if (j < 8) hipLaunchKernelGGL((lz_update_kernel<8>), g, b, 0, s, st, pp, U, ldu, j, n, in);
-  else if (j < 16) hipLaunchKernelGGL((lz_update_kernel<16>), g, b, 0, s, st, pp, U, ldu, j, n, in);
-  else hipLaunchKernelGGL((lz_update_kernel<32>), g, b, 0, s, st, pp, U, ldu, j, n, in);
+  if (Gd <= 0) Gd = grid_for(n);
+  if (j < 4) hipLaunchKernelGGL((lz_update_kernel<4>), g, b, 0, s, st, pp, U, ldu, j, n, Gd, in);
+  else if (j < 8) hipLaunchKernelGGL((lz_update_kernel<8>), g, b, 0, s, st, pp, U, ldu, j, n, Gd, in);
+  else if (j < 16) hipLaunchKernelGGL((lz_update_kernel<16>), g, b, 0, s, st, pp, U, ldu, j, n, Gd, in);
+  else hipLaunchKernelGGL((lz_update_kernel<32>), g, b, 0, s, st, pp, U, ldu, j, n, Gd, in);
+  return hipGetLastError();
+}
+
+int lz_grid(int64_t n) { return grid_for(n); }
+
+size_t heff_small_lds(const HeffSmallArgs &a, int tm_bytes) {
+  const size_t Mr4 = (a.Mr + 3) & ~3;
+  const size_t K34 = ((size_t)a.Wl * a.Ml + 3) & ~(size_t)3;
+  const size_t t1p = ((size_t)a.Ml * a.d * a.Wr + 3) & ~(size_t)3;
+  const size_t ap = std::max<size_t>(2 * Mr4 * 16 + 2 * t1p, HS_WAVES * 2 * 256);
+  return (ap + 2 * K34 * 16 + 2 * HS_NZ) * tm_bytes + (size_t)a.Ml * a.d * sizeof(double2) +
+         (HS_NZ + (size_t)a.Wl * a.d + 1) * sizeof(int);
+}
+
+bool heff_small_fits(const HeffSmallArgs &a, int tm_bytes) {
+  return a.Mr >= 1 && a.Mr <= LZ_GRID && a.Wr <= 16 && a.d <= 16 && a.Ml >= 1 &&
+         a.Wl * a.d <= 256 && heff_small_lds(a, tm_bytes) <= HEFF_SMALL_LDS;
+}
+
+hipError_t heff_small(DType t, const HeffSmallArgs &a, int count, hipStream_t s) {
+  static bool attr = false;
+  if (!attr) {
+    attr = true;
+#define HS_ATTR(T, JB)                                                                  \
+  (void)hipFuncSetAttribute((const void *)heff_small_kernel<T, JB>,                     \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, HEFF_SMALL_LDS)
+    HS_ATTR(double, 4); HS_ATTR(double, 8); HS_ATTR(double, 16); HS_ATTR(double, 32);
+    HS_ATTR(float, 4); HS_ATTR(float, 8); HS_ATTR(float, 16); HS_ATTR(float, 32);
+#undef HS_ATTR
+    (void)hipGetLastError();
+  }
+  const dim3 g(a.Mr, count), b(HS_WAVES * 64);
+  const size_t lds = heff_small_lds(a, t == F64 ? 8 : 4);
+#define HS(T, JB) hipLaunchKernelGGL((heff_small_kernel<T, JB>), g, b, lds, s, a)
+  if (t == F64) {
+    if (a.j < 4) HS(double, 4);
+    else if (a.j < 8) HS(double, 8);
+    else if (a.j < 16) HS(double, 16);
+    else HS(double, 32);
+  } else {
+    if (a.j < 4) HS(float, 4);
+    else if (a.j < 8) HS(float, 8);
+    else if (a.j < 16) HS(float, 16);
+    else HS(float, 32);
+  }
+#undef HS
+  return hipGetLastError();
+}
+
+hipError_t wtable(const double2 *W, int Wl, int d, int Wr, int64_t sW, int *rowp, int *col,
+                  double2 *coef, int64_t wss, int count, hipStream_t s) {
+  if (Wl * d > 256) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(wtable_kernel, dim3(count), dim3(256), 0, s, W, Wl * d, d, Wr, sW, rowp, col,
+                     coef, wss);
   return hipGetLastError();
 }
 
 hipError_t lz_finish(LzState *st, const double2 *U, int64_t ldu, int64_t n, int keff, double2 *y,
-                     int32_t *k_used, const LzInst &in, hipStream_t s) {
+                     int32_t *k_used, int trows, const LzInst &in, hipStream_t s) {
   hipLaunchKernelGGL(lz_finish_kernel, dim3(grid_for(n), in.count), dim3(LZ_BLOCK), 0, s, st, U,
-                     ldu, n, keff, y, k_used, in);
+                     ldu, n, keff, y, k_used, trows, in);
   return hipGetLastError();
 }
 

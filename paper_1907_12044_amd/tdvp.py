@@ -66,6 +66,7 @@ EXPORTS = {
                              c_int, c_void_p]),
     "tdvp_set_krylov_log": (c_int, [c_void_p, c_void_p, c_int]),
     "tdvp_set_graph": (c_int, [c_void_p, c_int]),
+    "tdvp_set_fused": (c_int, [c_void_p, c_int]),
     "tdvp_ps_step_batched": (c_int, [c_void_p, c_int, POINTER(_Mps), POINTER(_Mpo), POINTER(_Envs),
                                      c_double, c_int, c_int, c_double]),
     "tdvp_observe_batched": (c_int, [c_void_p, c_int, POINTER(_Mps), POINTER(_Mpo), POINTER(_Envs),
@@ -301,6 +302,10 @@ def set_graph(ctx, enable):
     _check(lib().tdvp_set_graph(ctx.h, 1 if enable else 0), "tdvp_set_graph")
 
 
+def set_fused(ctx, enable):
+    _check(lib().tdvp_set_fused(ctx.h, 1 if enable else 0), "tdvp_set_fused")
+
+
 def ps_step(ctx, mps, mpo, envs, dt, nsteps=1, kmax=20, tol=0.0):
     _check(lib().tdvp_ps_step(ctx.h, ctypes.byref(mps.desc), ctypes.byref(mpo.desc),
                               ctypes.byref(envs.desc), float(dt), int(nsteps), int(kmax), float(tol)),
@@ -314,8 +319,10 @@ def observe(ctx, mps, mpo, envs, el_sites, out):
 
 
 PROF_GEMM, PROF_WAPPLY, PROF_LZ_DOTS, PROF_LZ_UPDATE, PROF_LZ_ENDS, PROF_QR = 1, 2, 3, 4, 5, 6
+PROF_LZ_FUSED = 7
 PROF_CLASSES = {"gemm": PROF_GEMM, "wapply": PROF_WAPPLY, "lz_dots": PROF_LZ_DOTS,
-                "lz_update": PROF_LZ_UPDATE, "lz_ends": PROF_LZ_ENDS, "qr": PROF_QR}
+                "lz_update": PROF_LZ_UPDATE, "lz_ends": PROF_LZ_ENDS, "qr": PROF_QR,
+                "lz_fused": PROF_LZ_FUSED}
 
 
 def set_krylov_log(ctx, buf):
@@ -351,7 +358,7 @@ class PsRun:
     """
 
     def __init__(self, params, sites, raw_mps, device=0, precision=FP64, kmax=20, tol=0.0,
-                 graph=True):
+                 graph=True, fused=True):
         import torch
         self.torch = torch
         self.stream = torch.cuda.Stream(device=device)
@@ -374,6 +381,7 @@ class PsRun:
             self.obs = torch.zeros(2 + params.n_e, dtype=torch.float64, device=dev)
         self.stream.synchronize()
         set_graph(self.ctx, graph)
+        set_fused(self.ctx, fused)
         right_canonicalize(self.ctx, self.mps)
         envs_build(self.ctx, self.mps, self.mpo, self.envs)
 
@@ -425,7 +433,7 @@ class PsEnsemble:
     """
 
     def __init__(self, params_list, sites, raw_list, device=0, precision=FP64, kmax=20, tol=0.0,
-                 graph=True, stream=None):
+                 graph=True, stream=None, fused=True):
         import torch
         self.torch = torch
         nb = len(params_list)
@@ -478,6 +486,7 @@ class PsEnsemble:
         one = workspace_bytes(self.ctx, _Wrap(mps_arr[0]), _Wrap(mpo_arr[0]), kmax)
         self.ctx.reserve(nb * one)
         set_graph(self.ctx, graph)
+        set_fused(self.ctx, fused)
         for r in range(nb):
             _check(lib().tdvp_right_canonicalize(self.ctx.h, ctypes.byref(mps_arr[r])),
                    "tdvp_right_canonicalize")

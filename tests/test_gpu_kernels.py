@@ -110,14 +110,27 @@ def test_env_update_both_directions_match_oracle(ctxs, prec, shape):
     assert relerr(host(out), om.env_right(Rin, A, W)) < _tol(prec)
 
 
+@pytest.fixture(params=["fused", "general"])
+def path(request, ctxs):
+    """Kernel path of the Lanczos solves: fused small-bond step where it
+    applies (the default), or the general multi-kernel step everywhere."""
+    from paper_1907_12044_amd import tdvp
+    for c in ctxs.values():
+        tdvp.set_fused(c, request.param == "fused")
+    yield request.param
+    for c in ctxs.values():
+        tdvp.set_fused(c, True)
+
+
 @pytest.mark.parametrize("shape,z,kmax", [
     ((1, 2, 2, 1, 5), -0.9j, 20),
     ((7, 2, 13, 3, 4), -2.5j, 20),
     ((32, 8, 32, 7, 9), -1.0j, 20),
     ((40, 8, 33, 9, 5), 0.7j, 12),
     ((65, 2, 70, 9, 9), -3.0j, 32),
+    ((17, 3, 128, 4, 16), -1.3j, 16),
 ])
-def test_lanczos_expm_matches_oracle(ctxs, shape, z, kmax):
+def test_lanczos_expm_matches_oracle(ctxs, path, shape, z, kmax):
     import torch
     from paper_1907_12044_amd import tdvp
     ctx = ctxs["fp64"]
@@ -142,7 +155,7 @@ def test_lanczos_expm_matches_oracle(ctxs, shape, z, kmax):
     assert relerr(host(xd), ref) < 1e-11
 
 
-def test_lanczos_full_space_is_exact_and_zero_vector(ctxs):
+def test_lanczos_full_space_is_exact_and_zero_vector(ctxs, path):
     import scipy.linalg
     import torch
     from paper_1907_12044_amd import tdvp
@@ -171,7 +184,7 @@ def test_lanczos_full_space_is_exact_and_zero_vector(ctxs):
     assert np.all(host(yd) == 0) and int(host(kd)[0]) == 0
 
 
-def test_lanczos_tolerance_stop(ctxs):
+def test_lanczos_tolerance_stop(ctxs, path):
     import torch
     from paper_1907_12044_amd import tdvp
     ctx = ctxs["fp64"]
@@ -190,6 +203,75 @@ def test_lanczos_tolerance_stop(ctxs):
     ref = expm_lanczos(lambda v: om.heff(L, W, R, v), x, -1j, kmax=32, tol=1e-10, info=info)
     assert int(host(kd)[0]) == info["k"] and info["k"] < 32
     assert relerr(host(xd), ref) < 1e-11
+
+
+@pytest.mark.parametrize("Ml,Mr,W,kmax", [(5, 7, 3, 20), (32, 32, 9, 20), (33, 64, 9, 12), (64, 128, 5, 32)])
+def test_lanczos_bond_operator_matches_oracle(ctxs, path, Ml, Mr, W, kmax):
+    """exp(z K) D for the bond operator of eq:tdvp2_D, both kernel paths."""
+    import torch
+    from paper_1907_12044_amd import tdvp
+    ctx = ctxs["fp64"]
+    seed = 3 * (Ml + Mr + W)
+    L = random_hermitian_env(Ml, W, seed)
+    R = random_hermitian_env(Mr, W, seed + 1)
+    D = random_complex((Ml, Mr), seed + 2)
+    KD = om.bond_op(L, R, D)
+    s = 1.0 / (np.linalg.norm(KD) / np.linalg.norm(D))
+    L = L * s
+    xd = dev(D)
+    kd = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+    tdvp.lanczos_expm(ctx, dev(L), None, dev(R), Ml, 1, Mr, W, W, 1.1j, kmax, 0.0, xd, xd, kd)
+    info = {}
+    ref = expm_lanczos(lambda v: om.bond_op(L, R, v), D, 1.1j, kmax=kmax, info=info)
+    assert int(host(kd)[0]) == info["k"]
+    assert relerr(host(xd), ref) < 1e-11
+
+
+@pytest.mark.parametrize("shape", [(32, 8, 32, 7, 9), (64, 2, 64, 9, 9), (40, 8, 33, 9, 5)])
+def test_lanczos_fp32_contractions_match_oracle(ctxs, path, shape):
+    """FP32 environments and contractions, FP64 Krylov basis: 2e-5 relative."""
+    import torch
+    from paper_1907_12044_amd import tdvp
+    ctx = ctxs["fp32"]
+    Ml, d, Mr, Wl, Wr = shape
+    seed = 7 * sum(shape)
+    L = random_hermitian_env(Ml, Wl, seed)
+    R = random_hermitian_env(Mr, Wr, seed + 1)
+    W0 = random_mpo_like(Wl, d, Wr, seed + 2, density=0.4)
+    W = 0.5 * (W0 + np.conj(np.transpose(W0, (0, 2, 1, 3))))
+    x = random_complex((Ml, d, Mr), seed + 3)
+    Hx = om.heff(L, W, R, x)
+    W = W / (np.linalg.norm(Hx) / np.linalg.norm(x))
+    xd = dev(x)
+    tdvp.lanczos_expm(ctx, dev(L, torch.complex64), dev(W), dev(R, torch.complex64), Ml, d, Mr, Wl, Wr,
+                      -1.0j, 20, 0.0, xd, xd, None)
+    ref = expm_lanczos(lambda v: om.heff(L, W, R, v), x, -1.0j, kmax=20)
+    assert relerr(host(xd), ref) < 2e-5
+
+
+def test_fused_and_general_paths_agree(ctxs):
+    """The two kernel paths compute the same Krylov solve: equal Krylov
+    dimension and results equal to rounding (1e-13 relative)."""
+    import torch
+    from paper_1907_12044_amd import tdvp
+    ctx = ctxs["fp64"]
+    Ml, d, Mr, Wl, Wr = 32, 8, 32, 9, 9
+    L = random_hermitian_env(Ml, Wl, 41)
+    R = random_hermitian_env(Mr, Wr, 42)
+    W0 = random_mpo_like(Wl, d, Wr, 43, density=0.3)
+    W = 0.5 * (W0 + np.conj(np.transpose(W0, (0, 2, 1, 3))))
+    x = random_complex((Ml, d, Mr), 44)
+    W = W / (np.linalg.norm(om.heff(L, W, R, x)) / np.linalg.norm(x))
+    out = {}
+    for fused in (True, False):
+        tdvp.set_fused(ctx, fused)
+        yd = dev(np.zeros_like(x))
+        kd = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+        tdvp.lanczos_expm(ctx, dev(L), dev(W), dev(R), Ml, d, Mr, Wl, Wr, -0.8j, 24, 0.0, dev(x), yd, kd)
+        out[fused] = (host(yd), int(host(kd)[0]))
+    tdvp.set_fused(ctx, True)
+    assert out[True][1] == out[False][1]
+    assert relerr(out[True][0], out[False][0]) < 1e-13
 
 
 @pytest.mark.parametrize("m,n", [(1, 1), (4, 2), (16, 16), (256, 32), (257, 33), (700, 45), (1024, 128), (1500, 100), (2560, 256)])
