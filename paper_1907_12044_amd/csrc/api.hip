@@ -230,18 +230,30 @@ tdvp_status apply_op(tdvp_ctx *c, const Layout &lay, const Op &op, const double2
   return TDVP_OK;
 }
 
-// Fused small-bond step (heff_small) for Op, if its tiles fit in LDS and the
-// nonzero table of W fits in the Y buffer (unused on this path).  Fills the
-// kernel arguments except st, pp, U, j.
+// Arguments of the fused Lanczos step (heff_small) for Op, if it applies:
+// its tiles fit in LDS, the nonzero table of W fits in the Y buffer and the
+// P partial vectors in the T1 buffer (both unused on this path).  The sum
+// over the bra index l is split into P parts so that Mr P work-groups per
+// instance cover the chip.  Fills everything except st, pp, U, j.
 bool fused_args(const tdvp_ctx *c, const Layout &lay, const Op &op, const Bi &b, HeffSmallArgs &a) {
   if (c->fused_off) return false;
+  if (!op.W && (op.Wl != op.Wr || op.d != 1)) return false;
   a = HeffSmallArgs{};
   a.L = op.L; a.R = op.R;
   a.Ml = op.Ml; a.d = op.d; a.Mr = op.Mr; a.Wl = op.Wl; a.Wr = op.Wr;
   a.n = op.size();
   a.Gprev = lz_grid(a.n);
+  a.Gw = lz_grid(a.n);
   a.wss = b.ws; a.sL = op.sL; a.sR = op.sR;
+  const int64_t cols = (int64_t)op.Mr * b.R;
+  int P = (int)std::min<int64_t>(HS_PMAX, std::max<int64_t>(1, (256 + cols - 1) / cols));
+  P = std::min(P, std::max(1, op.Ml / 4));
+  while (P > 1 && ((int64_t)P * op.Mr > LZ_PARTS || (size_t)P * a.n * 16 > lay.ybytes)) --P;
+  a.nl = (op.Ml + P - 1) / P;
+  a.P = (op.Ml + a.nl - 1) / a.nl;
+  if ((size_t)a.P * a.n * 16 > lay.ybytes) return false;
   if (!heff_small_fits(a, env_bytes(c) / 2)) return false;
+  a.Yp = reinterpret_cast<double2 *>(c->ws + lay.T1);
   if (op.W) {
     const size_t rows = (size_t)op.Wl * op.d, cap = (size_t)op.d * op.Wr;
     const size_t o_col = al256((rows + 1) * 4), o_coef = o_col + al256(rows * cap * 4);
@@ -250,8 +262,6 @@ bool fused_args(const tdvp_ctx *c, const Layout &lay, const Op &op, const Bi &b,
     a.row = reinterpret_cast<const int *>(base);
     a.col = reinterpret_cast<const int *>(base + o_col);
     a.coef = reinterpret_cast<const double2 *>(base + o_coef);
-  } else if (op.Wl != op.Wr || op.d != 1) {
-    return false;
   }
   return true;
 }
@@ -291,7 +301,7 @@ tdvp_status run_lanczos(tdvp_ctx *c, const Layout &lay, const Op &op, double zr,
       CK(heff_small(env_type(c), fa, b.R, c->stream));
       prof_end(c, id, fl * b.R, by * b.R + (j + 2) * vb);
       id = prof_begin(c, TDVP_PROF_LZ_UPDATE);
-      CK(lz_update(st, pp, U, n, j, n, op.Mr, li, c->stream));
+      CK(lz_update(st, pp, U, n, j, n, op.Mr * fa.P, fa.Yp, fa.P, li, c->stream));
       prof_end(c, id, 8.0 * (j + 1) * n * b.R, 2.0 * vb + (j + 1) * vb);
       continue;
     }
@@ -301,7 +311,7 @@ tdvp_status run_lanczos(tdvp_ctx *c, const Layout &lay, const Op &op, double zr,
     prof_end(c, id, 8.0 * (j + 1) * n * b.R,
              (double)op.parts() * n * env_bytes(c) * b.R + vb + (j + 1) * vb);
     id = prof_begin(c, TDVP_PROF_LZ_UPDATE);
-    CK(lz_update(st, pp, U, n, j, n, 0, li, c->stream));
+    CK(lz_update(st, pp, U, n, j, n, 0, nullptr, 0, li, c->stream));
     prof_end(c, id, 8.0 * (j + 1) * n * b.R, 2.0 * vb + (j + 1) * vb);
   }
   if (!kused && c->klog && c->klog_pos + b.R <= c->klog_cap) {

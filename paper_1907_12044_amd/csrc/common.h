@@ -11,6 +11,7 @@ namespace tdvp {
 
 constexpr int KMAX = 32;          // largest Krylov dimension compiled in
 constexpr int LZ_GRID = 128;      // work-groups of the Lanczos vector kernels
+constexpr int LZ_PARTS = 512;     // most per-work-group partials of one reduction
 constexpr int LZ_BLOCK = 256;
 
 enum DType { F64 = 0, F32 = 1 };
@@ -77,9 +78,8 @@ struct LzState {
 // array it writes.
 struct LzPartials {
   double nrm[LZ_GRID];
-  double dre[LZ_GRID][KMAX + 1];
-  double dim[LZ_GRID][KMAX + 1];
-  double w2[LZ_GRID];
+  double2 dot[KMAX + 1][LZ_PARTS];   // <u_i, H u_j> partials, [i][work-group]
+  double w2[LZ_PARTS];          // |H u_j|^2 partials (lz_dots, or lz_update on the fused path)
 };
 
 // Lanczos kernels over `inst.count` instances: instance r uses the state,
@@ -97,22 +97,30 @@ hipError_t lz_start(LzState *st, LzPartials *pp, const double2 *x, double2 *u0, 
 hipError_t lz_dots(LzState *st, LzPartials *pp, DType ty, const void *ypart, int P, int64_t pstride,
                    double2 *U, int64_t ldu, int j, int64_t n, const LzInst &in, hipStream_t s);
 // Gd: number of per-work-group dot partials written by the kernel before
-// (0 = the lz_dots grid for n).
+// (0 = the lz_dots grid for n).  Yp != NULL (fused path): H u_j is the sum
+// of the P partial vectors Yp + p n (instance stride in.wss bytes), and the
+// kernel also writes the |H u_j|^2 partials.
 hipError_t lz_update(LzState *st, LzPartials *pp, double2 *U, int64_t ldu, int j, int64_t n, int Gd,
-                     const LzInst &in, hipStream_t s);
+                     const double2 *Yp, int P, const LzInst &in, hipStream_t s);
 int lz_grid(int64_t n);   // work-groups of the Lanczos vector kernels for an n-vector
 hipError_t lz_finish(LzState *st, const double2 *U, int64_t ldu, int64_t n, int keff, double2 *y,
                      int32_t *k_used, int trows, const LzInst &in, hipStream_t s);
 
-// Fused small-bond Lanczos step: H u_j and the partial projections in one
-// launch, grid (Mr, instances).  u_j = U + j n, column-major (rows Ml d);
-// H u_j goes to U + (j + 1) n; one dot partial per column r' in pp.  The
+// Fused Lanczos step: H u_j and its partial projections in one launch,
+// grid (Mr P, instances).  u_j = U + j n, column-major (rows Ml d).  Work-group
+// (p, r') forms the part of column r' of H u_j that comes from the bra-side
+// indices l in [p nl, (p + 1) nl) (the sum over l split P ways) and writes it
+// to Yp + p n; its dots with u_0..u_j go to partial slot p Mr + r'.  The
 // operator is H[i] with W given by its nonzero table (row, col, coef from
 // wtable) or, with row == NULL, the bond operator (d = 1, Wl == Wr).
 constexpr size_t HEFF_SMALL_LDS = 150 * 1024;
+constexpr int HS_PMAX = 8;              // most parts P
 struct HeffSmallArgs {
   LzState *st; LzPartials *pp; double2 *U;
-  int64_t n; int j; int Gprev;          // Gprev: norm partials written by the kernel before
+  double2 *Yp;                          // P partial vectors of n (workspace)
+  int64_t n; int j;
+  int Gprev, Gw;                        // norm and |H u|^2 partials written by the kernel before
+  int P, nl;                            // parts, bra indices per part
   const void *L, *R;                    // environments (context element type)
   const int *row, *col; const double2 *coef;   // CSR table of W (wtable), in the workspace
   int Ml, d, Mr, Wl, Wr;
@@ -122,8 +130,10 @@ size_t heff_small_lds(const HeffSmallArgs &a, int tm_bytes);
 bool heff_small_fits(const HeffSmallArgs &a, int tm_bytes);
 hipError_t heff_small(DType t, const HeffSmallArgs &a, int count, hipStream_t s);
 // CSR table of W[wl][s'][s][wr] (instance stride sW elements) over rows
-// wl d + s' (Wl d <= 256): row pointers rowp[Wl d + 1], then col (s Wr + wr)
-// and coef of each nonzero in index order.  Outputs at instance stride wss bytes.
+// wl d + s' (Wl d <= 256, Wl d d Wr <= WT_MAX): row pointers rowp[Wl d + 1],
+// then col (s Wr + wr) and coef of each nonzero in index order.  Outputs at
+// instance stride wss bytes.
+constexpr int WT_MAX = 8192;
 hipError_t wtable(const double2 *W, int Wl, int d, int Wr, int64_t sW, int *rowp, int *col,
                   double2 *coef, int64_t wss, int count, hipStream_t s);
 

@@ -88,6 +88,7 @@ __device__ void exp_tridiag_e1_wave(const double *alpha, const double *beta, int
     }
     mterms += 1;
   }
+  const double inv_lane = 1.0 / (double)(lane + 1);   // 1/t for term t = lane + 1
   double vr = (lane == 0) ? 1.0 : 0.0, vi = 0.0;
   for (int s = 0; s < ns; ++s) {
     double tr = vr, ti = vi, sr = vr, si = vi;
@@ -97,7 +98,7 @@ __device__ void exp_tridiag_e1_wave(const double *alpha, const double *beta, int
       double xr = a * tr + bdl * tmr + bu * tpr;
       double xi = a * ti + bdl * tmi + bu * tpi;
       if (!act) { xr = 0.0; xi = 0.0; }
-      const double inv = 1.0 / (double)t;
+      const double inv = __shfl(inv_lane, t - 1, 64);
       tr = (hr * xr - hi * xi) * inv;
       ti = (hr * xi + hi * xr) * inv;
       sr += tr;
@@ -122,23 +123,31 @@ __device__ void exp_tridiag_e1_wave(const double *alpha, const double *beta, int
 // tree), then close step j-1: beta_{j-1} and scale_j, the breakdown test
 // beta_{j-1} <= 1e-12 |H v_{j-1}|, the basis-size limit and, with tol > 0,
 // the a-posteriori estimate |z beta_{j-1} [exp(z T_j) e_1]_{j-1}| < tol.
-// Work-group 0 records the scalars.  Returns true (in every thread) if the
-// basis is final; the caller then returns.
-__device__ bool close_step(LzState *st, LzPartials *pp, int Gprev, int j) {
+// |H v_{j-1}| is st->aw[j-1] (Gw == 0) or comes from the Gw partials
+// pp->w2 of |H u_{j-1}|^2.  Work-group 0 records the scalars.  Returns true
+// (in every thread) if the basis is final; the caller then returns.
+__device__ bool close_step(LzState *st, LzPartials *pp, int Gprev, int j, int Gw) {
   __shared__ int stop_s;
-  __shared__ double nrm_s;
+  __shared__ double nrm_s, aw_s;
   __shared__ double coefr[KMAX], coefi[KMAX];
-  double aw = 0.0;
+  double aw = 0.0, sprev = 0.0;
   int keff = 0;
   if (threadIdx.x < 64) {
     if (threadIdx.x == 0 && j > 0) {   // issued with the partial loads
-      aw = st->aw[j - 1];
       keff = st->keff;
+      if (Gw > 0) sprev = st->scale[j - 1];
+      else aw = st->aw[j - 1];
     }
-    double t = 0.0;
+    double t = 0.0, t2 = 0.0;
     for (int b = threadIdx.x; b < Gprev; b += 64) t += pp->nrm[b];
+    if (j > 0)
+      for (int b = threadIdx.x; b < Gw; b += 64) t2 += pp->w2[b];
     t = wave_sum(t);
-    if (threadIdx.x == 0) nrm_s = t;
+    t2 = wave_sum(t2);
+    if (threadIdx.x == 0) {
+      nrm_s = t;
+      aw_s = Gw > 0 ? sqrt(t2) * sprev : aw;
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -151,7 +160,7 @@ __device__ bool close_step(LzState *st, LzPartials *pp, int Gprev, int j) {
         st->scale[0] = stop ? 0.0 : 1.0 / nv;
       }
     } else {
-      if (!(nv > 1e-12 * aw) || !isfinite(nv) || j >= keff) stop = 1;
+      if (!(nv > 1e-12 * aw_s) || !isfinite(nv) || j >= keff) stop = 1;
       if (!stop && blockIdx.x == 0) {
         st->beta[j - 1] = nv;
         st->scale[j] = 1.0 / nv;
@@ -233,7 +242,7 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_dots_kernel(LzState *st, LzPartia
   }
   if (st->stop) return;
   const int G = gridDim.x;
-  if (close_step(st, pp, G, j)) return;
+  if (close_step(st, pp, G, j, 0)) return;
   // Chunks of 256 elements.  Phase 1: w for the chunk (one element per
   // thread) into LDS and U[j+1].  Phase 2: thread (g, t), g = tid / 32,
   // t = tid % 32, accumulates <u_i, w> over the chunk for i = g, g+8, g+16,
@@ -291,8 +300,7 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_dots_kernel(LzState *st, LzPartia
     }
     const int i = g8 + 8 * q;
     if (t32 == 0 && i <= j) {
-      pp->dre[blockIdx.x][i] = ar[q];
-      pp->dim[blockIdx.x][i] = ai[q];
+      pp->dot[i][blockIdx.x] = make_double2(ar[q], ai[q]);
     }
   }
   w2 = wave_sum(w2);
@@ -306,17 +314,22 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_dots_kernel(LzState *st, LzPartia
 }
 
 // u_{j+1} = scale_j w - sum_{i<=j} c_i scale_i u_i ; per-block |u_{j+1}|^2.
-// The loads of w and u_0..u_j for a thread's first element are issued
-// before the reduction of the dot partials, so the two latencies overlap.
+// w is U[j+1] (written by lz_dots), or on the fused path the sum of the P
+// partial vectors Yp[p] (then the per-block |w|^2 partials are written too).
+// The loads of a thread's first element are issued before the reduction of
+// the dot partials, so the two latencies overlap.
 template <int JB>
 __global__ __launch_bounds__(LZ_BLOCK) void lz_update_kernel(LzState *st, LzPartials *pp,
                                                              double2 *U, int64_t ldu, int j,
-                                                             int64_t n, int Gd, LzInst in) {
+                                                             int64_t n, int Gd,
+                                                             const double2 *Yp, int P,
+                                                             LzInst in) {
   {
     const int64_t wo = (int64_t)blockIdx.y * in.wss;
     st = shift_bytes(st, wo);
     pp = shift_bytes(pp, wo);
     U = shift_bytes(U, wo);
+    if (Yp) Yp = shift_bytes(Yp, wo);
   }
   if (st->stop) return;
   __shared__ double sh[8];
@@ -324,26 +337,41 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_update_kernel(LzState *st, LzPart
   double2 *w = U + (int64_t)(j + 1) * ldu;
   const int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t estride = (int64_t)gridDim.x * blockDim.x;
-  constexpr int PF = JB < 16 ? JB : 16;    // basis vectors held in registers
-  double2 wv = make_double2(0.0, 0.0), uv[PF];
-  if (e0 < n) {
-    wv = w[e0];
-#pragma unroll
-    for (int i = 0; i < PF; ++i) uv[i] = i <= j ? U[(int64_t)i * ldu + e0] : make_double2(0.0, 0.0);
-  }
+  constexpr int PF = JB < 8 ? JB : 8;      // basis vectors held in registers
+  double2 uv[PF], yv[HS_PMAX];
+#define LZ_UPDATE_LOAD(e)                                                                  \
+  do {                                                                                     \
+    if (Yp) {                                                                              \
+      _Pragma("unroll") for (int p = 0; p < HS_PMAX; ++p)                                  \
+        yv[p] = p < P ? Yp[(int64_t)p * n + (e)] : make_double2(0.0, 0.0);                 \
+    } else {                                                                               \
+      yv[0] = w[e];                                                                        \
+    }                                                                                      \
+    _Pragma("unroll") for (int i = 0; i < PF; ++i)                                         \
+      uv[i] = i <= j ? U[(int64_t)i * ldu + (e)] : make_double2(0.0, 0.0);                 \
+  } while (0)
+  if (e0 < n) LZ_UPDATE_LOAD(e0);
   const double sj = st->scale[j];
-  // Reduce the Gd dot partials of the previous kernel: 8 lanes per basis
-  // index i (lane l adds partials l, l+8, ...), then a fixed 3-level tree.
+  // Reduce the Gd dot partials of the previous kernel: LPI = 256 / JB lanes
+  // per basis index i (lane l adds partials l, l + LPI, ...), then a fixed
+  // tree over the LPI lanes.
   {
-    const int i = threadIdx.x >> 3, l8 = threadIdx.x & 7;
+    constexpr int LPI = LZ_BLOCK / JB;
+    const int i = threadIdx.x / LPI, l8 = threadIdx.x % LPI;
     double a = 0.0, b = 0.0;
     if (i <= j) {
-      for (int blk = l8; blk < Gd; blk += 8) { a += pp->dre[blk][i]; b += pp->dim[blk][i]; }
+      const double2 *dp = pp->dot[i];
+#pragma unroll 8
+      for (int blk = l8; blk < Gd; blk += LPI) {
+        const double2 v = dp[blk];
+        a += v.x;
+        b += v.y;
+      }
     }
 #pragma unroll
-    for (int o = 4; o > 0; o >>= 1) {
-      a += __shfl_xor(a, o, 8);
-      b += __shfl_xor(b, o, 8);
+    for (int o = LPI / 2; o > 0; o >>= 1) {
+      a += __shfl_xor(a, o, LPI);
+      b += __shfl_xor(b, o, LPI);
     }
     if (l8 == 0 && i <= j) {
       const double si = st->scale[i];
@@ -352,7 +380,7 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_update_kernel(LzState *st, LzPart
       ci[i] = b * sc * si;
       if (i == j && blockIdx.x == 0) st->alpha[j] = a * sc;
     }
-    if (blockIdx.x == 0 && threadIdx.x >= 192) {   // last wave: |H v_j|
+    if (!Yp && blockIdx.x == 0 && threadIdx.x >= 192) {   // last wave: |H v_j|
       double t = 0.0;
       for (int blk = threadIdx.x - 192; blk < Gd; blk += 64) t += pp->w2[blk];
       t = wave_sum(t);
@@ -360,12 +388,19 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_update_kernel(LzState *st, LzPart
     }
   }
   __syncthreads();
-  double s2 = 0.0;
+  double s2 = 0.0, sw = 0.0;
   for (int64_t e = e0; e < n; e += estride) {
-    if (e != e0) {
-      wv = w[e];
+    if (e != e0) LZ_UPDATE_LOAD(e);
+    double2 wv = yv[0];
+    if (Yp) {
 #pragma unroll
-      for (int i = 0; i < PF; ++i) uv[i] = i <= j ? U[(int64_t)i * ldu + e] : make_double2(0.0, 0.0);
+      for (int p = 1; p < HS_PMAX; ++p) {
+        if (p < P) {
+          wv.x += yv[p].x;
+          wv.y += yv[p].y;
+        }
+      }
+      sw += wv.x * wv.x + wv.y * wv.y;
     }
     double xr = sj * wv.x, xi = sj * wv.y;
 #pragma unroll
@@ -384,13 +419,20 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_update_kernel(LzState *st, LzPart
     w[e] = make_double2(xr, xi);
     s2 += xr * xr + xi * xi;
   }
+#undef LZ_UPDATE_LOAD
   s2 = block_sum(s2, sh);
-  if (threadIdx.x == 0) pp->nrm[blockIdx.x] = s2;
+  if (Yp) sw = block_sum(sw, sh + 4);
+  if (threadIdx.x == 0) {
+    pp->nrm[blockIdx.x] = s2;
+    if (Yp) pp->w2[blockIdx.x] = sw;
+  }
 }
 
 // y = |x| sum_i [exp(z T_k) e_1]_i v_i with k = the final basis size (keff
 // unless the solve stopped early).  Every block evaluates the small
-// exponential redundantly (wave 0), then combines its slice of the basis.
+// exponential redundantly (wave 0), then combines its slice of the basis;
+// the basis loads of a thread's first element are issued first.
+template <int KB>
 __global__ __launch_bounds__(LZ_BLOCK) void lz_finish_kernel(LzState *st, const double2 *U,
                                                              int64_t ldu, int64_t n, int keff,
                                                              double2 *y, int32_t *k_used,
@@ -403,6 +445,15 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_finish_kernel(LzState *st, const 
     if (k_used) k_used += blockIdx.y;
   }
   __shared__ double cr[KMAX], ci[KMAX];
+  constexpr int PF = KB < 8 ? KB : 8;
+  const int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double2 uv[PF];
+#define LZ_FINISH_LOAD(e)                                                                  \
+  do {                                                                                     \
+    _Pragma("unroll") for (int i = 0; i < PF; ++i)                                         \
+      uv[i] = i < keff ? U[(int64_t)i * ldu + (e)] : make_double2(0.0, 0.0);               \
+  } while (0)
+  if (e0 < n) LZ_FINISH_LOAD(e0);
   const int k = st->stop ? st->k : keff;
   const double xn = st->xnorm;
   const bool zero = !(xn > 0.0) || k <= 0;
@@ -415,11 +466,19 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_finish_kernel(LzState *st, const 
     ci[threadIdx.x] *= sc;
   }
   __syncthreads();
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t e = e0; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    if (e != e0) LZ_FINISH_LOAD(e);
     double yr = 0.0, yi = 0.0;
     if (!zero) {
-      for (int i = 0; i < k; ++i) {
+#pragma unroll
+      for (int i = 0; i < PF; ++i) {
+        if (i < k) {
+          yr += cr[i] * uv[i].x - ci[i] * uv[i].y;
+          yi += cr[i] * uv[i].y + ci[i] * uv[i].x;
+        }
+      }
+#pragma unroll 8
+      for (int i = PF; i < k; ++i) {
         const double2 u = U[(int64_t)i * ldu + e];
         yr += cr[i] * u.x - ci[i] * u.y;
         yi += cr[i] * u.y + ci[i] * u.x;
@@ -432,24 +491,26 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_finish_kernel(LzState *st, const 
       y[e] = make_double2(yr, yi);
     }
   }
+#undef LZ_FINISH_LOAD
   if (k_used && blockIdx.x == 0 && threadIdx.x == 0) *k_used = zero ? 0 : k;
 }
 
 // ---------------------------------------------------------------------------
-// Fused Lanczos step for small bonds: H[i] u_j (all three contraction
-// stages) plus the projections <u_i, H u_j> in ONE launch.  Work-group r'
-// owns output column r' of y[l', s', r'] and needs no other work-group:
+// Fused Lanczos step: H[i] u_j (all three contraction stages) plus the
+// projections <u_i, H u_j> in ONE launch.  Work-group (p, r') forms the part
+// of output column r' of y[l', s', r'] that comes from the bra-side indices
+// l in [l0, l0 + nl), l0 = p nl:
 //   T1[(l, s)][wr] = sum_r u[(l, s)][r] R[r'][wr][r]        (MFMA, N = Wr <= 16)
 //   T2[(wl, l)][s'] = sum_{nonzero W} W[wl][s'][s][wr] T1[(l, s)][wr]   (LDS)
-//   y[l'][s']      = sum_{(wl, l)} L[l'][wl][l] T2[(wl, l)][s']  (MFMA, K split over waves)
-// then y -> U[j+1], per-work-group partial dots <u_i, y> and |y|^2 (the
-// partial layout lz_dots writes, one partial per r'), read by lz_update.
-// On this path the basis vectors are stored column-major (index r' * Ml d +
-// (l', s')), so that a work-group's column is contiguous; lz_start and
-// lz_finish convert from and to the row-major site tensor.  With rows ==
-// NULL the operator is the bond operator of eq:tdvp2_D (d = 1, T2 = T1^T).
-// The nonzeros of W come as a padded table, rows (wl, s'), each holding at
-// most d Wr entries (column s Wr + wr, coefficient).
+//   y_p[l'][s']    = sum_{(wl, l)} L[l'][wl][l] T2[(wl, l)][s']  (MFMA)
+// writes y_p to Yp[p] and the dots <u_i, y_p> to partial slot p Mr + r';
+// lz_update adds the P parts (H u_j = sum_p y_p, dots likewise).  Splitting
+// the sum over l spreads one column over P work-groups, so a small bond
+// still fills the chip.  On this path the basis vectors are stored
+// column-major (index r' Ml d + (l', s')), so a column is contiguous;
+// lz_start and lz_finish convert from and to the row-major site tensor.
+// With row == NULL the operator is the bond operator of eq:tdvp2_D (d = 1,
+// T2 = T1^T).  The nonzeros of W come as a CSR table over rows (wl, s').
 
 typedef double f64x4_t __attribute__((ext_vector_type(4)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
@@ -475,18 +536,73 @@ template <> struct Mf<float> {
 constexpr int HS_WAVES = 8;            // waves per work-group of the fused step
 constexpr int HS_NZ = 512;             // W nonzeros staged in LDS (more: read from global)
 
-// Stage 2 over the (K3 x d) block of T2: T2[(wl, l)][s'] from T1 and the
+// Complex C (Mrows x 16) = A (Mrows x K) B (K x 16) on the MFMA units of one
+// work-group: 16-row tiles; when there are fewer tiles than waves the K
+// range of a tile is split over several waves and the parts are added in
+// order through `red` (HS_WAVES x 2 x 256 values).  A comes from
+// loadA(row, k, re, im) (row < Mrows, k < K); B from LDS planes [K4][16]
+// whose rows K..K4-1 are zero.  store(row, col, re, im) receives every
+// result with row < Mrows.
+template <typename T, typename LoadA, typename Store>
+__device__ __forceinline__ void hs_mm16(int Mrows, int K, const T *b_re, const T *b_im, T *red,
+                                        LoadA loadA, Store store) {
+  using AccT = typename Mf<T>::acc;
+  constexpr int NT = HS_WAVES * 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int RT = (Mrows + 15) / 16, K4 = (K + 3) & ~3;
+  const int TPR = min(RT, HS_WAVES), parts = HS_WAVES / TPR;
+  const int kchunk = ((K4 / 4 + parts - 1) / parts) * 4;
+  for (int rt0 = 0; rt0 < RT; rt0 += TPR) {
+    AccT cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+    const int rt = rt0 + wave % TPR, pt = wave / TPR;
+    if (rt < RT && pt < parts) {
+      const int kb = pt * kchunk, ke = min(K4, kb + kchunk);
+      const int row = rt * 16 + (lane & 15);
+#pragma unroll 8
+      for (int k0 = kb; k0 < ke; k0 += 4) {
+        const int k = k0 + (lane >> 4);
+        T ar = 0, ai = 0;
+        if (row < Mrows && k < K) loadA(row, k, ar, ai);
+        const T br = b_re[k * 16 + (lane & 15)], bi = b_im[k * 16 + (lane & 15)];
+        cr = Mf<T>::mfma(ar, br, cr);
+        cr = Mf<T>::mfma(-ai, bi, cr);
+        ci = Mf<T>::mfma(ar, bi, ci);
+        ci = Mf<T>::mfma(ai, br, ci);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      red[(wave * 2 + 0) * 256 + r * 64 + lane] = cr[r];
+      red[(wave * 2 + 1) * 256 + r * 64 + lane] = ci[r];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < min(RT - rt0, TPR) * 256; e += NT) {
+      const int tt = e >> 8, rem = e & 255, r = rem >> 6, ln = rem & 63;
+      T sr = 0, si = 0;
+      for (int p = 0; p < parts; ++p) {
+        const int w = p * TPR + tt;
+        sr += red[(w * 2 + 0) * 256 + r * 64 + ln];
+        si += red[(w * 2 + 1) * 256 + r * 64 + ln];
+      }
+      const int orow = (rt0 + tt) * 16 + Mf<T>::row(ln, r);
+      if (orow < Mrows) store(orow, ln & 15, sr, si);
+    }
+    __syncthreads();
+  }
+}
+
+// Stage 2 over the (K3 x d) block of T2: T2[(wl, ll)][s'] from T1 and the
 // nonzero table: row pointers rp, columns cl, coefficients (cr, ci) staged
 // in LDS, or the c128 table gc in global memory (GL).
 template <typename T, bool GL, typename PI>
 __device__ __forceinline__ void hs_stage2(T *t2_re, T *t2_im, const T *t1_re, const T *t1_im,
-                                          int K3, int Ml, int d, int cap, PI rp, PI cl,
+                                          int K3, int nl, int d, int cap, PI rp, PI cl,
                                           const T *cr, const T *ci, const double2 *gc) {
   for (int e = threadIdx.x; e < K3 * d; e += HS_WAVES * 64) {
     const int k = e / d, sp = e - k * d;
-    const int wl = k / Ml, l = k - wl * Ml;
+    const int wl = k / nl, ll = k - wl * nl;
     const int rw = wl * d + sp, q1 = rp[rw + 1];
-    const T *tr_ = t1_re + l * cap, *ti_ = t1_im + l * cap;
+    const T *tr_ = t1_re + ll * cap, *ti_ = t1_im + ll * cap;
     T re = 0, im = 0;
     for (int q = rp[rw]; q < q1; ++q) {
       const int cc = cl[q];
@@ -510,34 +626,35 @@ __device__ __forceinline__ void hs_stage2(T *t2_re, T *t2_im, const T *t1_re, co
 
 template <typename T, int JB>
 __global__ __launch_bounds__(HS_WAVES * 64) void heff_small_kernel(HeffSmallArgs a) {
-  using AccT = typename Mf<T>::acc;
   using VE = typename Mf<T>::c2;
   constexpr int NT = HS_WAVES * 64;
   extern __shared__ char smem[];
-  const int rp = blockIdx.x;                      // output column r'
+  const int Ml = a.Ml, d = a.d, Mr = a.Mr, Wl = a.Wl, Wr = a.Wr;
+  const int rp = blockIdx.x % Mr, part = blockIdx.x / Mr;   // output column r', part p
   const int inst = blockIdx.y;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   LzState *st = shift_bytes(a.st, (int64_t)inst * a.wss);
   LzPartials *pp = shift_bytes(a.pp, (int64_t)inst * a.wss);
   double2 *U = shift_bytes(a.U, (int64_t)inst * a.wss);
+  double2 *Yp = shift_bytes(a.Yp, (int64_t)inst * a.wss);
   const VE *L = reinterpret_cast<const VE *>(a.L) + (int64_t)inst * a.sL;
   const VE *R = reinterpret_cast<const VE *>(a.R) + (int64_t)inst * a.sR;
   const int j = a.j;
-  const int Ml = a.Ml, d = a.d, Mr = a.Mr, Wl = a.Wl, Wr = a.Wr;
-  const int ML1 = Ml * d;                  // rows of T1 and of y
-  const int K3 = Wl * Ml;                  // inner dimension of stage 3
+  const int l0 = part * a.nl, nl = min(a.nl, Ml - l0);
+  const int ML1 = Ml * d;                  // rows of y
+  const int MP = nl * d;                   // rows of T1: x rows l0 d .. (l0 + nl) d
+  const int K3 = Wl * nl;                  // inner dimension of stage 3
   const int Mr4 = (Mr + 3) & ~3, K34 = (K3 + 3) & ~3;
-  const int T1P = (ML1 * Wr + 3) & ~3;     // plane sizes keep every region 16-byte aligned
-  const int AP = max(2 * Mr4 * 16 + 2 * T1P, HS_WAVES * 2 * 256);
+  const int T1P = (MP * Wr + 3) & ~3;      // plane sizes keep every region 16-byte aligned
   T *rr_re = reinterpret_cast<T *>(smem);  // stage 1 B operand [Mr4][16]
   T *rr_im = rr_re + Mr4 * 16;
-  T *t1_re = rr_im + Mr4 * 16;             // [ML1][Wr]
+  T *t1_re = rr_im + Mr4 * 16;             // [MP][Wr]
   T *t1_im = t1_re + T1P;
-  T *red = rr_re;                          // stage 3 partial results, over rr and T1
-  T *t2_re = rr_re + AP;                   // [K34][16]
+  T *t2_re = t1_im + T1P;                  // [K34][16]
   T *t2_im = t2_re + K34 * 16;
-  double2 *ycol = reinterpret_cast<double2 *>(t2_im + K34 * 16);   // [ML1]
-  T *nz_re = reinterpret_cast<T *>(ycol + ML1);                   // staged W table
+  T *red = t2_im + K34 * 16;               // [HS_WAVES][2][256]
+  double2 *ycol = reinterpret_cast<double2 *>(red + HS_WAVES * 2 * 256);   // [ML1]
+  T *nz_re = reinterpret_cast<T *>(ycol + ML1);                          // staged W table
   T *nz_im = nz_re + HS_NZ;
   int *nz_col = reinterpret_cast<int *>(nz_im + HS_NZ);
   int *nz_row = nz_col + HS_NZ;
@@ -572,121 +689,63 @@ __global__ __launch_bounds__(HS_WAVES * 64) void heff_small_kernel(HeffSmallArgs
       }
     }
   }
-  if (stopped) return;
-  if (close_step(st, pp, a.Gprev, j)) return;   // (synchronises the work-group)
-
-  const double2 *x = U + (int64_t)j * a.n; // u_j, column-major
-  // stage 1: T1 (ML1 x Wr) = X (ML1 x Mr) Rr (Mr x Wr), 16-row tiles over the waves
-  for (int rt = wave; rt * 16 < ML1; rt += HS_WAVES) {
-    AccT cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
-    const int row = rt * 16 + (lane & 15);
-#pragma unroll 8
-    for (int k0 = 0; k0 < Mr; k0 += 4) {
-      const int k = k0 + (lane >> 4);
-      T ar = 0, ai = 0;
-      if (row < ML1 && k < Mr) {
-        const double2 v = x[(int64_t)k * ML1 + row];
-        ar = (T)v.x;
-        ai = (T)v.y;
-      }
-      const T br = rr_re[k * 16 + (lane & 15)], bi = rr_im[k * 16 + (lane & 15)];
-      cr = Mf<T>::mfma(ar, br, cr);
-      cr = Mf<T>::mfma(-ai, bi, cr);
-      ci = Mf<T>::mfma(ar, bi, ci);
-      ci = Mf<T>::mfma(ai, br, ci);
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int orow = rt * 16 + Mf<T>::row(lane, r);
-      const int ocol = lane & 15;
-      if (orow < ML1 && ocol < Wr) {
-        t1_re[orow * Wr + ocol] = cr[r];
-        t1_im[orow * Wr + ocol] = ci[r];
-      }
-    }
-  }
-  __syncthreads();
-  // stage 2: T2[(wl, l)][s'] for s' < d (padding columns only feed discarded
-  // outputs), padding rows K3..K34 zero
-  for (int e = K3 * 16 + threadIdx.x; e < K34 * 16; e += NT) {
+  for (int e = K3 * 16 + threadIdx.x; e < K34 * 16; e += NT) {   // zero padding rows of T2
     t2_re[e] = 0;
     t2_im[e] = 0;
   }
-  if (!g_row) {                            // bond operator: T2[(w, l)][0] = T1[l][w]
+  if (stopped) return;
+  if (close_step(st, pp, a.Gprev, j, j > 0 ? a.Gw : 0)) return;   // (synchronises the work-group)
+
+  // stage 1: T1 (MP x Wr) = X[l0 d .., :] (MP x Mr) Rr (Mr x Wr)
+  const double2 *x = U + (int64_t)j * a.n + (int64_t)l0 * d;   // u_j, column-major
+  hs_mm16<T>(MP, Mr, rr_re, rr_im, red,
+             [&](int row, int k, T &re, T &im) {
+               const double2 v = x[(int64_t)k * ML1 + row];
+               re = (T)v.x;
+               im = (T)v.y;
+             },
+             [&](int row, int col, T re, T im) {
+               if (col < Wr) {
+                 t1_re[row * Wr + col] = re;
+                 t1_im[row * Wr + col] = im;
+               }
+             });
+  // stage 2: T2[(wl, ll)][s'] for s' < d (padding columns only feed
+  // discarded outputs); hs_mm16 ended with a barrier
+  if (!g_row) {                            // bond operator: T2[(w, ll)][0] = T1[ll][w]
     for (int k = threadIdx.x; k < K3; k += NT) {
-      const int w = k / Ml, l = k - w * Ml;
-      t2_re[k * 16] = t1_re[l * Wr + w];
-      t2_im[k * 16] = t1_im[l * Wr + w];
+      const int w = k / nl, ll = k - w * nl;
+      t2_re[k * 16] = t1_re[ll * Wr + w];
+      t2_im[k * 16] = t1_im[ll * Wr + w];
     }
   } else if (nnz <= HS_NZ) {
-    hs_stage2<T, false>(t2_re, t2_im, t1_re, t1_im, K3, Ml, d, d * Wr, (const int *)nz_row,
+    hs_stage2<T, false>(t2_re, t2_im, t1_re, t1_im, K3, nl, d, d * Wr, (const int *)nz_row,
                         (const int *)nz_col, nz_re, nz_im, nullptr);
   } else {
-    hs_stage2<T, true>(t2_re, t2_im, t1_re, t1_im, K3, Ml, d, d * Wr, g_row, g_col, nullptr,
+    hs_stage2<T, true>(t2_re, t2_im, t1_re, t1_im, K3, nl, d, d * Wr, g_row, g_col, nullptr,
                        nullptr, g_coef);
   }
   __syncthreads();
-  // stage 3: y (Ml x d) = L (Ml x K3) T2 (K3 x d).  A round covers TPR row
-  // tiles; the K dimension of each tile is split over `parts` waves.
-  const int RT = (Ml + 15) / 16;
-  const int TPR = min(RT, HS_WAVES), parts = HS_WAVES / TPR;
-  const int kchunk = ((K34 / 4 + parts - 1) / parts) * 4;
-  for (int rt0 = 0; rt0 < RT; rt0 += TPR) {
-    AccT cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
-    const int rt = rt0 + wave % TPR, part = wave / TPR;
-    if (rt < RT && part < parts) {
-      const int kb = part * kchunk, ke = min(K34, kb + kchunk);
-      const int row = rt * 16 + (lane & 15);
-      const VE *Lrow = L + (int64_t)row * K3;
-#pragma unroll 8
-      for (int k0 = kb; k0 < ke; k0 += 4) {
-        const int k = k0 + (lane >> 4);
-        T ar = 0, ai = 0;
-        if (row < Ml && k < K3) {
-          const VE v = Lrow[k];
-          ar = v.x;
-          ai = v.y;
-        }
-        const T br = t2_re[k * 16 + (lane & 15)], bi = t2_im[k * 16 + (lane & 15)];
-        cr = Mf<T>::mfma(ar, br, cr);
-        cr = Mf<T>::mfma(-ai, bi, cr);
-        ci = Mf<T>::mfma(ar, bi, ci);
-        ci = Mf<T>::mfma(ai, br, ci);
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      red[(wave * 2 + 0) * 256 + r * 64 + lane] = cr[r];
-      red[(wave * 2 + 1) * 256 + r * 64 + lane] = ci[r];
-    }
-    __syncthreads();
-    // add the K parts in order, scatter into ycol[(l', s')]
-    for (int e = threadIdx.x; e < min(RT - rt0, TPR) * 256; e += NT) {
-      const int tt = e >> 8, rem = e & 255, r = rem >> 6, ln = rem & 63;
-      T sr = 0, si = 0;
-      for (int p = 0; p < parts; ++p) {
-        const int w = p * TPR + tt;
-        sr += red[(w * 2 + 0) * 256 + r * 64 + ln];
-        si += red[(w * 2 + 1) * 256 + r * 64 + ln];
-      }
-      const int orow = (rt0 + tt) * 16 + Mf<T>::row(ln, r);
-      const int ocol = ln & 15;
-      if (orow < Ml && ocol < d) ycol[orow * d + ocol] = make_double2((double)sr, (double)si);
-    }
-    __syncthreads();
-  }
-  // y -> U[j+1] (column r'), |y|^2 and <u_i, y> partials for this column:
-  // thread group g (32 threads) takes i = g, g + 16, ...
-  double2 *wdst = U + (int64_t)(j + 1) * a.n + (int64_t)rp * ML1;
-  double w2 = 0.0;
-  for (int e = threadIdx.x; e < ML1; e += NT) {
-    const double2 y = ycol[e];
-    wdst[e] = y;
-    w2 += y.x * y.x + y.y * y.y;
-  }
+  // stage 3: y_p (Ml x d) = L[:, :, l0 ..] (Ml x K3) T2 (K3 x d)
+  const int64_t lrow = (int64_t)Wl * Ml;
+  hs_mm16<T>(Ml, K3, t2_re, t2_im, red,
+             [&](int row, int k, T &re, T &im) {
+               const int wl = k / nl, ll = k - wl * nl;
+               const VE v = L[(int64_t)row * lrow + wl * Ml + l0 + ll];
+               re = v.x;
+               im = v.y;
+             },
+             [&](int row, int col, T re, T im) {
+               if (col < d) ycol[row * d + col] = make_double2((double)re, (double)im);
+             });
+  // y_p -> Yp[p] (column r'); <u_i, y_p> partials: thread group g (32
+  // threads) takes i = g, g + 16, ...
+  double2 *wdst = Yp + (int64_t)part * a.n + (int64_t)rp * ML1;
+  for (int e = threadIdx.x; e < ML1; e += NT) wdst[e] = ycol[e];
   constexpr int NG = NT / 32;
   constexpr int NQ = (JB + NG - 1) / NG;
   const int g = threadIdx.x >> 5, t32 = threadIdx.x & 31;
+  const int slot = blockIdx.x;
   double dr[NQ], di[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
@@ -713,64 +772,65 @@ __global__ __launch_bounds__(HS_WAVES * 64) void heff_small_kernel(HeffSmallArgs
     }
     const int i = g + NG * q;
     if (t32 == 0 && i <= j) {
-      pp->dre[rp][i] = dr[q];
-      pp->dim[rp][i] = di[q];
+      pp->dot[i][slot] = make_double2(dr[q], di[q]);
     }
   }
-  __shared__ double w2s[HS_WAVES];
-  w2 = wave_sum(w2);
-  if (lane == 0) w2s[wave] = w2;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int w = 0; w < HS_WAVES; ++w) t += w2s[w];
-    pp->w2[rp] = t;
-  }
+  (void)lane;
+  (void)wave;
 }
 
-// Nonzero table (CSR over rows (wl, s')) of an MPO site tensor
-// W[wl][s'][s][wr]; one work-group per instance, thread r scans row r.
-__global__ __launch_bounds__(256) void wtable_kernel(const double2 *W, int rows, int d, int Wr,
-                                                     int64_t sW, int *rowp, int *col,
-                                                     double2 *coef, int64_t wss) {
-  const int inst = blockIdx.x, r = threadIdx.x;
+// CSR table of an MPO site tensor W[wl][s'][s][wr] over rows (wl, s'): one
+// work-group per instance.  Every thread loads its candidates (index
+// e = t + 1024 q) at once; a work-group scan over the nonzero flags, chunk
+// by chunk in index order, gives each nonzero its position.
+constexpr int WT_THREADS = 1024;
+__global__ __launch_bounds__(WT_THREADS) void wtable_kernel(const double2 *W, int rows, int cap,
+                                                            int64_t sW, int *rowp, int *col,
+                                                            double2 *coef, int64_t wss) {
+  constexpr int QN = WT_MAX / WT_THREADS;
+  const int inst = blockIdx.x, t = threadIdx.x, lane = t & 63, wave = t >> 6;
   W += (int64_t)inst * sW;
   rowp = shift_bytes(rowp, (int64_t)inst * wss);
   col = shift_bytes(col, (int64_t)inst * wss);
   coef = shift_bytes(coef, (int64_t)inst * wss);
-  __shared__ int cnt[257];
-  const int cap = d * Wr;
-  int c = 0;
-  if (r < rows)
-    for (int q = 0; q < cap; ++q) {
-      const double2 v = W[(int64_t)r * cap + q];
-      c += (v.x != 0.0 || v.y != 0.0) ? 1 : 0;
-    }
-  cnt[r] = c;
-  __syncthreads();
-  if (r == 0) {
-    int s = 0;
-    for (int t = 0; t < rows; ++t) {
-      const int ct = cnt[t];
-      cnt[t] = s;
-      s += ct;
-    }
-    cnt[rows] = s;
+  const int total = rows * cap;
+  double2 v[QN];
+#pragma unroll
+  for (int q = 0; q < QN; ++q) {
+    const int e = t + WT_THREADS * q;
+    v[q] = e < total ? W[e] : make_double2(0.0, 0.0);
   }
+  __shared__ int wcount[WT_THREADS / 64];
+  __shared__ int base_s;
+  if (t == 0) base_s = 0;
   __syncthreads();
-  if (r < rows) rowp[r] = cnt[r];
-  if (r == 0) rowp[rows] = cnt[rows];
-  if (r < rows) {
-    int pos = cnt[r];
-    for (int q = 0; q < cap; ++q) {
-      const double2 v = W[(int64_t)r * cap + q];
-      if (v.x != 0.0 || v.y != 0.0) {
-        col[pos] = q;
-        coef[pos] = v;
-        ++pos;
-      }
+#pragma unroll
+  for (int q = 0; q < QN; ++q) {
+    const int e = t + WT_THREADS * q;
+    if (WT_THREADS * q >= total) break;
+    const bool nz = e < total && (v[q].x != 0.0 || v[q].y != 0.0);
+    const unsigned long long m = __ballot(nz);
+    const int below = __popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) wcount[wave] = __popcll(m);
+    __syncthreads();
+    int off = base_s;
+    for (int w = 0; w < wave; ++w) off += wcount[w];
+    const int pos = off + below;
+    if (nz) {
+      col[pos] = e % cap;
+      coef[pos] = v[q];
     }
+    // rowp[r] = nonzeros before index r cap
+    if (e < total && e % cap == 0) rowp[e / cap] = pos;
+    __syncthreads();
+    if (t == 0) {
+      int s = base_s;
+      for (int w = 0; w < WT_THREADS / 64; ++w) s += wcount[w];
+      base_s = s;
+    }
+    __syncthreads();
   }
+  if (t == 0) rowp[rows] = base_s;
 }
 
 // Work-groups for an n-element vector pass: one element per thread, at most
@@ -814,13 +874,17 @@ hipError_t lz_dots(LzState *st, LzPartials *pp, DType ty, const void *ypart, int
 }
 
 hipError_t lz_update(LzState *st, LzPartials *pp, double2 *U, int64_t ldu, int j, int64_t n, int Gd,
-                     const LzInst &in, hipStream_t s) {
+                     const double2 *Yp, int P, const LzInst &in, hipStream_t s) {
   const dim3 g(grid_for(n), in.count), b(LZ_BLOCK);
   if (Gd <= 0) Gd = grid_for(n);
-  if (j < 4) hipLaunchKernelGGL((lz_update_kernel<4>), g, b, 0, s, st, pp, U, ldu, j, n, Gd, in);
-  else if (j < 8) hipLaunchKernelGGL((lz_update_kernel<8>), g, b, 0, s, st, pp, U, ldu, j, n, Gd, in);
-  else if (j < 16) hipLaunchKernelGGL((lz_update_kernel<16>), g, b, 0, s, st, pp, U, ldu, j, n, Gd, in);
-  else hipLaunchKernelGGL((lz_update_kernel<32>), g, b, 0, s, st, pp, U, ldu, j, n, Gd, in);
+  if (Yp && (P < 1 || P > HS_PMAX)) return hipErrorInvalidValue;
+#define LZ_UPD(JB) \
+  hipLaunchKernelGGL((lz_update_kernel<JB>), g, b, 0, s, st, pp, U, ldu, j, n, Gd, Yp, P, in)
+  if (j < 4) LZ_UPD(4);
+  else if (j < 8) LZ_UPD(8);
+  else if (j < 16) LZ_UPD(16);
+  else LZ_UPD(32);
+#undef LZ_UPD
   return hipGetLastError();
 }
 
@@ -828,16 +892,18 @@ int lz_grid(int64_t n) { return grid_for(n); }
 
 size_t heff_small_lds(const HeffSmallArgs &a, int tm_bytes) {
   const size_t Mr4 = (a.Mr + 3) & ~3;
-  const size_t K34 = ((size_t)a.Wl * a.Ml + 3) & ~(size_t)3;
-  const size_t t1p = ((size_t)a.Ml * a.d * a.Wr + 3) & ~(size_t)3;
-  const size_t ap = std::max<size_t>(2 * Mr4 * 16 + 2 * t1p, HS_WAVES * 2 * 256);
-  return (ap + 2 * K34 * 16 + 2 * HS_NZ) * tm_bytes + (size_t)a.Ml * a.d * sizeof(double2) +
+  const size_t K34 = ((size_t)a.Wl * a.nl + 3) & ~(size_t)3;
+  const size_t t1p = ((size_t)a.nl * a.d * a.Wr + 3) & ~(size_t)3;
+  const size_t planes = 2 * Mr4 * 16 + 2 * t1p + 2 * K34 * 16 + HS_WAVES * 2 * 256 + 2 * HS_NZ;
+  return planes * tm_bytes + (size_t)a.Ml * a.d * sizeof(double2) +
          (HS_NZ + (size_t)a.Wl * a.d + 1) * sizeof(int);
 }
 
 bool heff_small_fits(const HeffSmallArgs &a, int tm_bytes) {
-  return a.Mr >= 1 && a.Mr <= LZ_GRID && a.Wr <= 16 && a.d <= 16 && a.Ml >= 1 &&
-         a.Wl * a.d <= 256 && heff_small_lds(a, tm_bytes) <= HEFF_SMALL_LDS;
+  return a.Mr >= 1 && a.Ml >= 1 && a.Wr <= 16 && a.d <= 16 && a.Wl * a.d <= 256 &&
+         (int64_t)a.Wl * a.d * a.d * a.Wr <= WT_MAX && a.nl >= 1 && a.P >= 1 &&
+         a.P <= HS_PMAX && (int64_t)a.P * a.nl >= a.Ml && (int64_t)(a.P - 1) * a.nl < a.Ml &&
+         (int64_t)a.P * a.Mr <= LZ_PARTS && heff_small_lds(a, tm_bytes) <= HEFF_SMALL_LDS;
 }
 
 hipError_t heff_small(DType t, const HeffSmallArgs &a, int count, hipStream_t s) {
@@ -852,7 +918,7 @@ hipError_t heff_small(DType t, const HeffSmallArgs &a, int count, hipStream_t s)
 #undef HS_ATTR
     (void)hipGetLastError();
   }
-  const dim3 g(a.Mr, count), b(HS_WAVES * 64);
+  const dim3 g(a.Mr * a.P, count), b(HS_WAVES * 64);
   const size_t lds = heff_small_lds(a, t == F64 ? 8 : 4);
 #define HS(T, JB) hipLaunchKernelGGL((heff_small_kernel<T, JB>), g, b, lds, s, a)
   if (t == F64) {
@@ -872,16 +938,21 @@ hipError_t heff_small(DType t, const HeffSmallArgs &a, int count, hipStream_t s)
 
 hipError_t wtable(const double2 *W, int Wl, int d, int Wr, int64_t sW, int *rowp, int *col,
                   double2 *coef, int64_t wss, int count, hipStream_t s) {
-  if (Wl * d > 256) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(wtable_kernel, dim3(count), dim3(256), 0, s, W, Wl * d, d, Wr, sW, rowp, col,
-                     coef, wss);
+  if (Wl * d > 256 || (int64_t)Wl * d * d * Wr > WT_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(wtable_kernel, dim3(count), dim3(WT_THREADS), 0, s, W, Wl * d, d * Wr, sW,
+                     rowp, col, coef, wss);
   return hipGetLastError();
 }
 
 hipError_t lz_finish(LzState *st, const double2 *U, int64_t ldu, int64_t n, int keff, double2 *y,
                      int32_t *k_used, int trows, const LzInst &in, hipStream_t s) {
-  hipLaunchKernelGGL(lz_finish_kernel, dim3(grid_for(n), in.count), dim3(LZ_BLOCK), 0, s, st, U,
-                     ldu, n, keff, y, k_used, trows, in);
+  const dim3 g(grid_for(n), in.count), b(LZ_BLOCK);
+#define LZ_FIN(KB) \
+  hipLaunchKernelGGL((lz_finish_kernel<KB>), g, b, 0, s, st, U, ldu, n, keff, y, k_used, trows, in)
+  if (keff <= 4) LZ_FIN(4);
+  else if (keff <= 8) LZ_FIN(8);
+  else LZ_FIN(16);
+#undef LZ_FIN
   return hipGetLastError();
 }
 
