@@ -52,6 +52,26 @@ __device__ double block_sum(double v, double *sh) {
   return t;
 }
 
+// Neighbour exchange across the whole wave through DPP wave shifts (no LDS
+// round trip): shr1 gives lane i the value of lane i-1 (lane 0: 0), shl1
+// the value of lane i+1 (lane 63: 0).
+__device__ __forceinline__ double wave_shr1(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wave_shl1(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+// value of v in lane l (l uniform across the wave)
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
 // exp(z T) e_1 for the k x k real symmetric tridiagonal T(alpha, beta),
 // computed by one wave64 (lane i holds component i): T is shifted by the
 // mean of its diagonal (the shift returns as the scalar factor
@@ -93,12 +113,12 @@ __device__ void exp_tridiag_e1_wave(const double *alpha, const double *beta, int
   for (int s = 0; s < ns; ++s) {
     double tr = vr, ti = vi, sr = vr, si = vi;
     for (int t = 1; t <= mterms; ++t) {
-      const double tmr = __shfl_up(tr, 1, 64), tmi = __shfl_up(ti, 1, 64);
-      const double tpr = __shfl_down(tr, 1, 64), tpi = __shfl_down(ti, 1, 64);
+      const double tmr = wave_shr1(tr), tmi = wave_shr1(ti);
+      const double tpr = wave_shl1(tr), tpi = wave_shl1(ti);
       double xr = a * tr + bdl * tmr + bu * tpr;
       double xi = a * ti + bdl * tmi + bu * tpi;
       if (!act) { xr = 0.0; xi = 0.0; }
-      const double inv = __shfl(inv_lane, t - 1, 64);
+      const double inv = lane_value(inv_lane, t - 1);
       tr = (hr * xr - hi * xi) * inv;
       ti = (hr * xi + hi * xr) * inv;
       sr += tr;
