@@ -252,7 +252,11 @@ bool fused_args(const tdvp_ctx *c, const Layout &lay, const Op &op, const Bi &b,
   a.nl = (op.Ml + P - 1) / P;
   a.P = (op.Ml + a.nl - 1) / a.nl;
   if ((size_t)a.P * a.n * 16 > lay.ybytes) return false;
-  if (!heff_small_fits(a, env_bytes(c) / 2)) return false;
+  a.staged = 1;
+  if (!heff_small_fits(a, env_bytes(c) / 2)) {
+    a.staged = 0;
+    if (!heff_small_fits(a, env_bytes(c) / 2)) return false;
+  }
   a.Yp = reinterpret_cast<double2 *>(c->ws + lay.T1);
   if (op.W) {
     const size_t rows = (size_t)op.Wl * op.d, cap = (size_t)op.d * op.Wr;

@@ -121,6 +121,7 @@ struct HeffSmallArgs {
   int64_t n; int j;
   int Gprev, Gw;                        // norm and |H u|^2 partials written by the kernel before
   int P, nl;                            // parts, bra indices per part
+  int staged;                           // 1: x and L slices staged through LDS
   const void *L, *R;                    // environments (context element type)
   const int *row, *col; const double2 *coef;   // CSR table of W (wtable), in the workspace
   int Ml, d, Mr, Wl, Wr;

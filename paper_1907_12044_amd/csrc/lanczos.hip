@@ -146,27 +146,47 @@ __device__ void exp_tridiag_e1_wave(const double *alpha, const double *beta, int
 // |H v_{j-1}| is st->aw[j-1] (Gw == 0) or comes from the Gw partials
 // pp->w2 of |H u_{j-1}|^2.  Work-group 0 records the scalars.  Returns true
 // (in every thread) if the basis is final; the caller then returns.
-__device__ bool close_step(LzState *st, LzPartials *pp, int Gprev, int j, int Gw) {
-  __shared__ int stop_s;
-  __shared__ double nrm_s, aw_s;
-  __shared__ double coefr[KMAX], coefi[KMAX];
-  double aw = 0.0, sprev = 0.0;
-  int keff = 0;
+// The loads of close_step, issued by wave 0 (Gprev, Gw <= LZ_GRID) so that a
+// kernel can request them together with its other inputs.
+struct StepPre {
+  double nr[2], w2[2];
+  double aw, sprev, tol;
+  int keff;
+};
+__device__ __forceinline__ void close_step_load(const LzState *st, const LzPartials *pp, int Gprev,
+                                                int j, int Gw, StepPre &p) {
+  p.nr[0] = p.nr[1] = p.w2[0] = p.w2[1] = 0.0;
+  p.aw = p.sprev = p.tol = 0.0;
+  p.keff = 0;
   if (threadIdx.x < 64) {
-    if (threadIdx.x == 0 && j > 0) {   // issued with the partial loads
-      keff = st->keff;
-      if (Gw > 0) sprev = st->scale[j - 1];
-      else aw = st->aw[j - 1];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int b = threadIdx.x + 64 * q;
+      if (b < Gprev) p.nr[q] = pp->nrm[b];
+      if (j > 0 && b < Gw) p.w2[q] = pp->w2[b];
     }
-    double t = 0.0, t2 = 0.0;
-    for (int b = threadIdx.x; b < Gprev; b += 64) t += pp->nrm[b];
-    if (j > 0)
-      for (int b = threadIdx.x; b < Gw; b += 64) t2 += pp->w2[b];
-    t = wave_sum(t);
-    t2 = wave_sum(t2);
+    if (threadIdx.x == 0) {
+      p.tol = st->tol;
+      if (j > 0) {
+        p.keff = st->keff;
+        if (Gw > 0) p.sprev = st->scale[j - 1];
+        else p.aw = st->aw[j - 1];
+      }
+    }
+  }
+}
+
+__device__ bool close_step_finish(LzState *st, const StepPre &p, int j, int Gw) {
+  __shared__ int stop_s;
+  __shared__ double nrm_s, aw_s, tol_s;
+  __shared__ double coefr[KMAX], coefi[KMAX];
+  if (threadIdx.x < 64) {
+    double t = wave_sum(p.nr[0] + p.nr[1]);
+    double t2 = wave_sum(p.w2[0] + p.w2[1]);
     if (threadIdx.x == 0) {
       nrm_s = t;
-      aw_s = Gw > 0 ? sqrt(t2) * sprev : aw;
+      aw_s = Gw > 0 ? sqrt(t2) * p.sprev : p.aw;
+      tol_s = p.tol;
     }
   }
   __syncthreads();
@@ -180,7 +200,7 @@ __device__ bool close_step(LzState *st, LzPartials *pp, int Gprev, int j, int Gw
         st->scale[0] = stop ? 0.0 : 1.0 / nv;
       }
     } else {
-      if (!(nv > 1e-12 * aw_s) || !isfinite(nv) || j >= keff) stop = 1;
+      if (!(nv > 1e-12 * aw_s) || !isfinite(nv) || j >= p.keff) stop = 1;
       if (!stop && blockIdx.x == 0) {
         st->beta[j - 1] = nv;
         st->scale[j] = 1.0 / nv;
@@ -189,7 +209,7 @@ __device__ bool close_step(LzState *st, LzPartials *pp, int Gprev, int j, int Gw
     stop_s = stop;
   }
   __syncthreads();
-  if (!stop_s && j > 0 && st->tol > 0.0) {
+  if (!stop_s && j > 0 && tol_s > 0.0) {
     const double bj = sqrt(nrm_s);
     if (threadIdx.x < 64) {
       // T_j needs beta_0 .. beta_{j-2}, all written by earlier kernels
@@ -197,7 +217,7 @@ __device__ bool close_step(LzState *st, LzPartials *pp, int Gprev, int j, int Gw
       if (threadIdx.x == 0) {
         const double zabs = sqrt(st->z_re * st->z_re + st->z_im * st->z_im);
         const double c = sqrt(coefr[j - 1] * coefr[j - 1] + coefi[j - 1] * coefi[j - 1]);
-        if (zabs * bj * c < st->tol) stop_s = 1;
+        if (zabs * bj * c < tol_s) stop_s = 1;
       }
     }
     __syncthreads();
@@ -208,6 +228,22 @@ __device__ bool close_step(LzState *st, LzPartials *pp, int Gprev, int j, int Gw
     st->stop = 1;
   }
   return stop;
+}
+
+__device__ bool close_step(LzState *st, LzPartials *pp, int Gprev, int j, int Gw) {
+  StepPre p;
+  close_step_load(st, pp, Gprev, j, Gw, p);
+  return close_step_finish(st, p, j, Gw);
+}
+
+constexpr int LU_E = 64;
+// Work-groups of lz_start and lz_update (one norm partial each): LU_E
+// elements per work-group and pass.
+__host__ __device__ inline int upd_grid(int64_t n) {
+  int64_t g = (n + LU_E - 1) / LU_E;
+  if (g > LZ_GRID) g = LZ_GRID;
+  if (g < 1) g = 1;
+  return (int)g;
 }
 
 __global__ __launch_bounds__(LZ_BLOCK) void lz_start_kernel(LzState *st, LzPartials *pp,
@@ -262,7 +298,7 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_dots_kernel(LzState *st, LzPartia
   }
   if (st->stop) return;
   const int G = gridDim.x;
-  if (close_step(st, pp, G, j, 0)) return;
+  if (close_step(st, pp, upd_grid(n), j, 0)) return;
   // Chunks of 256 elements.  Phase 1: w for the chunk (one element per
   // thread) into LDS and U[j+1].  Phase 2: thread (g, t), g = tid / 32,
   // t = tid % 32, accumulates <u_i, w> over the chunk for i = g, g+8, g+16,
@@ -336,8 +372,11 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_dots_kernel(LzState *st, LzPartia
 // u_{j+1} = scale_j w - sum_{i<=j} c_i scale_i u_i ; per-block |u_{j+1}|^2.
 // w is U[j+1] (written by lz_dots), or on the fused path the sum of the P
 // partial vectors Yp[p] (then the per-block |w|^2 partials are written too).
-// The loads of a thread's first element are issued before the reduction of
-// the dot partials, so the two latencies overlap.
+// A work-group takes LU_E elements per pass; wave q adds the basis vectors
+// i = q, q + 4, ... and the partial vectors p = q, q + 4, ..., and wave 0
+// combines the four wave sums in order.  A thread's loads for its first
+// pass are issued before the reduction of the dot partials, so the two
+// latencies overlap.
 template <int JB>
 __global__ __launch_bounds__(LZ_BLOCK) void lz_update_kernel(LzState *st, LzPartials *pp,
                                                              double2 *U, int64_t ldu, int j,
@@ -354,23 +393,32 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_update_kernel(LzState *st, LzPart
   if (st->stop) return;
   __shared__ double sh[8];
   __shared__ double cr[JB], ci[JB];
+  __shared__ double2 pw[4][LU_E], ps[4][LU_E];
+  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
   double2 *w = U + (int64_t)(j + 1) * ldu;
-  const int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t estride = (int64_t)gridDim.x * blockDim.x;
-  constexpr int PF = JB < 8 ? JB : 8;      // basis vectors held in registers
-  double2 uv[PF], yv[HS_PMAX];
+  const int64_t b0 = (int64_t)blockIdx.x * LU_E, bstride = (int64_t)gridDim.x * LU_E;
+  constexpr int NI = (JB + 3) / 4;         // basis vectors per wave
+  constexpr int NP = (HS_PMAX + 3) / 4;    // partial vectors per wave
+  double2 uv[NI], yv[NP];
 #define LZ_UPDATE_LOAD(e)                                                                  \
   do {                                                                                     \
-    if (Yp) {                                                                              \
-      _Pragma("unroll") for (int p = 0; p < HS_PMAX; ++p)                                  \
-        yv[p] = p < P ? Yp[(int64_t)p * n + (e)] : make_double2(0.0, 0.0);                 \
-    } else {                                                                               \
-      yv[0] = w[e];                                                                        \
+    _Pragma("unroll") for (int t = 0; t < NP; ++t) {                                       \
+      const int p = q + 4 * t;                                                             \
+      yv[t] = make_double2(0.0, 0.0);                                                      \
+      if ((e) < n) {                                                                       \
+        if (Yp) {                                                                          \
+          if (p < P) yv[t] = Yp[(int64_t)p * n + (e)];                                     \
+        } else if (p == 0) {                                                               \
+          yv[t] = w[e];                                                                    \
+        }                                                                                  \
+      }                                                                                    \
     }                                                                                      \
-    _Pragma("unroll") for (int i = 0; i < PF; ++i)                                         \
-      uv[i] = i <= j ? U[(int64_t)i * ldu + (e)] : make_double2(0.0, 0.0);                 \
+    _Pragma("unroll") for (int t = 0; t < NI; ++t) {                                       \
+      const int i = q + 4 * t;                                                             \
+      uv[t] = (i <= j && (e) < n) ? U[(int64_t)i * ldu + (e)] : make_double2(0.0, 0.0);   \
+    }                                                                                      \
   } while (0)
-  if (e0 < n) LZ_UPDATE_LOAD(e0);
+  if (b0 < n) LZ_UPDATE_LOAD(b0 + lane);
   const double sj = st->scale[j];
   // Reduce the Gd dot partials of the previous kernel: LPI = 256 / JB lanes
   // per basis index i (lane l adds partials l, l + LPI, ...), then a fixed
@@ -409,35 +457,42 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_update_kernel(LzState *st, LzPart
   }
   __syncthreads();
   double s2 = 0.0, sw = 0.0;
-  for (int64_t e = e0; e < n; e += estride) {
-    if (e != e0) LZ_UPDATE_LOAD(e);
-    double2 wv = yv[0];
-    if (Yp) {
+  for (int64_t base = b0; base < n; base += bstride) {
+    const int64_t e = base + lane;
+    if (base != b0) LZ_UPDATE_LOAD(e);
+    double2 acc = yv[0];
 #pragma unroll
-      for (int p = 1; p < HS_PMAX; ++p) {
-        if (p < P) {
-          wv.x += yv[p].x;
-          wv.y += yv[p].y;
-        }
+    for (int t = 1; t < NP; ++t) {
+      acc.x += yv[t].x;
+      acc.y += yv[t].y;
+    }
+    double sr = 0.0, si = 0.0;
+#pragma unroll
+    for (int t = 0; t < NI; ++t) {
+      const int i = q + 4 * t;
+      if (i <= j) {
+        sr += cr[i] * uv[t].x - ci[i] * uv[t].y;
+        si += cr[i] * uv[t].y + ci[i] * uv[t].x;
       }
+    }
+    pw[q][lane] = acc;
+    ps[q][lane] = make_double2(sr, si);
+    __syncthreads();
+    if (q == 0 && e < n) {
+      double2 wv = pw[0][lane], sv = ps[0][lane];
+#pragma unroll
+      for (int t = 1; t < 4; ++t) {
+        wv.x += pw[t][lane].x;
+        wv.y += pw[t][lane].y;
+        sv.x += ps[t][lane].x;
+        sv.y += ps[t][lane].y;
+      }
+      const double xr = sj * wv.x - sv.x, xi = sj * wv.y - sv.y;
+      w[e] = make_double2(xr, xi);
+      s2 += xr * xr + xi * xi;
       sw += wv.x * wv.x + wv.y * wv.y;
     }
-    double xr = sj * wv.x, xi = sj * wv.y;
-#pragma unroll
-    for (int i = 0; i < PF; ++i) {
-      if (i <= j) {
-        xr -= cr[i] * uv[i].x - ci[i] * uv[i].y;
-        xi -= cr[i] * uv[i].y + ci[i] * uv[i].x;
-      }
-    }
-#pragma unroll 8
-    for (int i = PF; i <= j; ++i) {
-      const double2 u = U[(int64_t)i * ldu + e];
-      xr -= cr[i] * u.x - ci[i] * u.y;
-      xi -= cr[i] * u.y + ci[i] * u.x;
-    }
-    w[e] = make_double2(xr, xi);
-    s2 += xr * xr + xi * xi;
+    __syncthreads();
   }
 #undef LZ_UPDATE_LOAD
   s2 = block_sum(s2, sh);
@@ -555,6 +610,9 @@ template <> struct Mf<float> {
 
 constexpr int HS_WAVES = 8;            // waves per work-group of the fused step
 constexpr int HS_NZ = 512;             // W nonzeros staged in LDS (more: read from global)
+constexpr int HS_RV = 4;               // R-slice elements per thread: Mr <= 128
+constexpr int HS_XV = 4;               // staged x-slice elements per thread
+constexpr int HS_LV = 8;               // staged L-slice elements per thread
 
 // Complex C (Mrows x 16) = A (Mrows x K) B (K x 16) on the MFMA units of one
 // work-group: 16-row tiles; when there are fewer tiles than waves the K
@@ -644,7 +702,33 @@ __device__ __forceinline__ void hs_stage2(T *t2_re, T *t2_im, const T *t1_re, co
   }
 }
 
-template <typename T, int JB>
+// LDS layout of the fused step (elements of T unless noted); `stg` adds
+// the staged x and L slices.
+struct HsLayout {
+  int Mr4, MP, MP16, K3, K34, Ml16, T1P;
+  int rr, t1, t2, red, xs, ls, ycol_b, nz_b, total_b;   // offsets (T elements; _b: bytes)
+  __host__ __device__ HsLayout(int Ml, int d, int Mr, int Wl, int Wr, int nl, bool stg, int tb) {
+    Mr4 = (Mr + 3) & ~3;
+    MP = nl * d;
+    MP16 = (MP + 15) & ~15;
+    K3 = Wl * nl;
+    K34 = (K3 + 3) & ~3;
+    Ml16 = (Ml + 15) & ~15;
+    T1P = (MP * Wr + 3) & ~3;
+    rr = 0;
+    t1 = rr + 2 * Mr4 * 16;
+    t2 = t1 + 2 * T1P;
+    red = t2 + 2 * K34 * 16;
+    xs = red + HS_WAVES * 2 * 256;
+    ls = xs + (stg ? 2 * Mr4 * MP16 : 0);
+    const int tend = ls + (stg ? 2 * K34 * Ml16 : 0);
+    ycol_b = tend * tb;
+    nz_b = ycol_b + Ml * d * 16;
+    total_b = nz_b + HS_NZ * (2 * tb + 4) + (Wl * d + 1) * 4;
+  }
+};
+
+template <typename T, int JB, bool STG>
 __global__ __launch_bounds__(HS_WAVES * 64) void heff_small_kernel(HeffSmallArgs a) {
   using VE = typename Mf<T>::c2;
   constexpr int NT = HS_WAVES * 64;
@@ -652,7 +736,6 @@ __global__ __launch_bounds__(HS_WAVES * 64) void heff_small_kernel(HeffSmallArgs
   const int Ml = a.Ml, d = a.d, Mr = a.Mr, Wl = a.Wl, Wr = a.Wr;
   const int rp = blockIdx.x % Mr, part = blockIdx.x / Mr;   // output column r', part p
   const int inst = blockIdx.y;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   LzState *st = shift_bytes(a.st, (int64_t)inst * a.wss);
   LzPartials *pp = shift_bytes(a.pp, (int64_t)inst * a.wss);
   double2 *U = shift_bytes(a.U, (int64_t)inst * a.wss);
@@ -662,74 +745,154 @@ __global__ __launch_bounds__(HS_WAVES * 64) void heff_small_kernel(HeffSmallArgs
   const int j = a.j;
   const int l0 = part * a.nl, nl = min(a.nl, Ml - l0);
   const int ML1 = Ml * d;                  // rows of y
+  // this part's shapes (a ragged last part is smaller than the layout's)
   const int MP = nl * d;                   // rows of T1: x rows l0 d .. (l0 + nl) d
   const int K3 = Wl * nl;                  // inner dimension of stage 3
-  const int Mr4 = (Mr + 3) & ~3, K34 = (K3 + 3) & ~3;
-  const int T1P = (MP * Wr + 3) & ~3;      // plane sizes keep every region 16-byte aligned
-  T *rr_re = reinterpret_cast<T *>(smem);  // stage 1 B operand [Mr4][16]
-  T *rr_im = rr_re + Mr4 * 16;
-  T *t1_re = rr_im + Mr4 * 16;             // [MP][Wr]
-  T *t1_im = t1_re + T1P;
-  T *t2_re = t1_im + T1P;                  // [K34][16]
-  T *t2_im = t2_re + K34 * 16;
-  T *red = t2_im + K34 * 16;               // [HS_WAVES][2][256]
-  double2 *ycol = reinterpret_cast<double2 *>(red + HS_WAVES * 2 * 256);   // [ML1]
-  T *nz_re = reinterpret_cast<T *>(ycol + ML1);                          // staged W table
+  const int K34 = (K3 + 3) & ~3;
+  const HsLayout lay(Ml, d, Mr, Wl, Wr, a.nl, STG, (int)sizeof(T));
+  T *base = reinterpret_cast<T *>(smem);
+  T *rr_re = base + lay.rr, *rr_im = rr_re + lay.Mr4 * 16;          // stage 1 B [Mr4][16]
+  T *t1_re = base + lay.t1, *t1_im = t1_re + lay.T1P;                // [MP][Wr]
+  T *t2_re = base + lay.t2, *t2_im = t2_re + lay.K34 * 16;           // [K34][16]
+  T *red = base + lay.red;                                           // [HS_WAVES][2][256]
+  T *xs_re = base + lay.xs, *xs_im = xs_re + lay.Mr4 * lay.MP16;     // staged x [Mr][MP16]
+  T *ls_re = base + lay.ls, *ls_im = ls_re + lay.K34 * lay.Ml16;     // staged L [K34][Ml16]
+  double2 *ycol = reinterpret_cast<double2 *>(smem + lay.ycol_b);   // [ML1]
+  T *nz_re = reinterpret_cast<T *>(smem + lay.nz_b);                 // staged W table
   T *nz_im = nz_re + HS_NZ;
   int *nz_col = reinterpret_cast<int *>(nz_im + HS_NZ);
   int *nz_row = nz_col + HS_NZ;
 
-  const int stopped = st->stop;
-  // stage the R slice and the W table (loads issued before the step test)
-  for (int e = threadIdx.x; e < Mr4 * 16; e += NT) {
-    const int k = e >> 4, c = e & 15;
-    T re = 0, im = 0;
-    if (k < Mr && c < Wr) {
-      const VE v = R[((int64_t)rp * Wr + c) * Mr + k];
-      re = v.x;
-      im = v.y;
-    }
-    rr_re[e] = re;
-    rr_im[e] = im;
-  }
+  const double2 *x = U + (int64_t)j * a.n + (int64_t)l0 * d;   // u_j, column-major
   const int rows = Wl * d;
   const int *g_row = a.row ? shift_bytes(a.row, (int64_t)inst * a.wss) : nullptr;
   const int *g_col = a.row ? shift_bytes(a.col, (int64_t)inst * a.wss) : nullptr;
   const double2 *g_coef = a.row ? shift_bytes(a.coef, (int64_t)inst * a.wss) : nullptr;
-  int nnz = 0;
+  const int tid = threadIdx.x;
+  // One round of global loads: every input of the step is requested before
+  // any of them is used (the step state, the close_step partials, the R
+  // slice, the W table, the x and L slices of the staged variant and the
+  // basis columns of the projections).
+  const int stopped = st->stop;
+  StepPre pre;
+  close_step_load(st, pp, a.Gprev, j, j > 0 ? a.Gw : 0, pre);
+  VE rv[HS_RV];
+#pragma unroll
+  for (int q = 0; q < HS_RV; ++q) {
+    const int e = tid + NT * q, k = e >> 4, c = e & 15;
+    rv[q].x = 0;
+    rv[q].y = 0;
+    if (e < lay.Mr4 * 16 && k < Mr && c < Wr) rv[q] = R[((int64_t)rp * Wr + c) * Mr + k];
+  }
+  const int tcap = min(HS_NZ, rows * d * Wr);
+  int nnz = 0, trow = 0, tcol = 0;
+  double2 tco = make_double2(0.0, 0.0);
   if (g_row) {
     nnz = g_row[rows];
-    for (int e = threadIdx.x; e <= rows; e += NT) nz_row[e] = g_row[e];
-    if (nnz <= HS_NZ) {
-      for (int e = threadIdx.x; e < nnz; e += NT) {
-        const double2 w = g_coef[e];
-        nz_re[e] = (T)w.x;
-        nz_im[e] = (T)w.y;
-        nz_col[e] = g_col[e];
+    if (tid <= rows) trow = g_row[tid];
+    if (tid < tcap) {
+      tcol = g_col[tid];
+      tco = g_coef[tid];
+    }
+  }
+  double2 xv[HS_XV];
+  VE lv[HS_LV];
+  if (STG) {
+#pragma unroll
+    for (int q = 0; q < HS_XV; ++q) {
+      const int e = tid + NT * q, k = e / lay.MP16, row = e - k * lay.MP16;
+      xv[q] = make_double2(0.0, 0.0);
+      if (e < lay.Mr4 * lay.MP16 && k < Mr && row < MP) xv[q] = x[(int64_t)k * ML1 + row];
+    }
+#pragma unroll
+    for (int q = 0; q < HS_LV; ++q) {
+      const int e = tid + NT * q, row = e / K34, k = e - row * K34;   // k fastest: runs of L
+      lv[q].x = 0;
+      lv[q].y = 0;
+      if (e < K34 * lay.Ml16 && k < K3 && row < Ml) {
+        const int wl = k / nl, ll = k - wl * nl;
+        lv[q] = L[(int64_t)row * Wl * Ml + wl * Ml + l0 + ll];
       }
     }
   }
-  for (int e = K3 * 16 + threadIdx.x; e < K34 * 16; e += NT) {   // zero padding rows of T2
+  constexpr int NG = NT / 32;              // thread groups of 32 for the projections
+  constexpr int NQ = (JB + NG - 1) / NG;
+  constexpr int UE = 8;                    // basis elements per (group, q) held in registers
+  const int g = tid >> 5, t32 = tid & 31;
+  double2 ur[NQ][UE];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int i = g + NG * q;
+    const double2 *ui = U + (int64_t)i * a.n + (int64_t)rp * ML1;
+#pragma unroll
+    for (int t = 0; t < UE; ++t) {
+      const int el = t32 + 32 * t;
+      ur[q][t] = (i <= j && el < ML1) ? ui[el] : make_double2(0.0, 0.0);
+    }
+  }
+  // stores to LDS
+#pragma unroll
+  for (int q = 0; q < HS_RV; ++q) {
+    const int e = tid + NT * q;
+    if (e < lay.Mr4 * 16) {
+      rr_re[e] = rv[q].x;
+      rr_im[e] = rv[q].y;
+    }
+  }
+  if (g_row) {
+    if (tid <= rows) nz_row[tid] = trow;
+    if (tid < tcap) {
+      nz_re[tid] = (T)tco.x;
+      nz_im[tid] = (T)tco.y;
+      nz_col[tid] = tcol;
+    }
+  }
+  if (STG) {
+#pragma unroll
+    for (int q = 0; q < HS_XV; ++q) {
+      const int e = tid + NT * q;
+      if (e < lay.Mr4 * lay.MP16) {
+        xs_re[e] = (T)xv[q].x;
+        xs_im[e] = (T)xv[q].y;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < HS_LV; ++q) {
+      const int e = tid + NT * q, row = e / K34, k = e - row * K34;
+      if (e < K34 * lay.Ml16) {
+        ls_re[k * lay.Ml16 + row] = lv[q].x;
+        ls_im[k * lay.Ml16 + row] = lv[q].y;
+      }
+    }
+  }
+  for (int e = K3 * 16 + tid; e < K34 * 16; e += NT) {   // zero padding rows of T2
     t2_re[e] = 0;
     t2_im[e] = 0;
   }
   if (stopped) return;
-  if (close_step(st, pp, a.Gprev, j, j > 0 ? a.Gw : 0)) return;   // (synchronises the work-group)
+  if (close_step_finish(st, pre, j, j > 0 ? a.Gw : 0)) return;   // (synchronises the work-group)
 
   // stage 1: T1 (MP x Wr) = X[l0 d .., :] (MP x Mr) Rr (Mr x Wr)
-  const double2 *x = U + (int64_t)j * a.n + (int64_t)l0 * d;   // u_j, column-major
-  hs_mm16<T>(MP, Mr, rr_re, rr_im, red,
-             [&](int row, int k, T &re, T &im) {
-               const double2 v = x[(int64_t)k * ML1 + row];
-               re = (T)v.x;
-               im = (T)v.y;
-             },
-             [&](int row, int col, T re, T im) {
-               if (col < Wr) {
-                 t1_re[row * Wr + col] = re;
-                 t1_im[row * Wr + col] = im;
-               }
-             });
+  auto st1 = [&](int row, int col, T re, T im) {
+    if (col < Wr) {
+      t1_re[row * Wr + col] = re;
+      t1_im[row * Wr + col] = im;
+    }
+  };
+  if (STG) {
+    hs_mm16<T>(MP, Mr, rr_re, rr_im, red,
+               [&](int row, int k, T &re, T &im) {
+                 re = xs_re[k * lay.MP16 + row];
+                 im = xs_im[k * lay.MP16 + row];
+               }, st1);
+  } else {
+    hs_mm16<T>(MP, Mr, rr_re, rr_im, red,
+               [&](int row, int k, T &re, T &im) {
+                 const double2 v = x[(int64_t)k * ML1 + row];
+                 re = (T)v.x;
+                 im = (T)v.y;
+               }, st1);
+  }
   // stage 2: T2[(wl, ll)][s'] for s' < d (padding columns only feed
   // discarded outputs); hs_mm16 ended with a barrier
   if (!g_row) {                            // bond operator: T2[(w, ll)][0] = T1[ll][w]
@@ -747,24 +910,28 @@ __global__ __launch_bounds__(HS_WAVES * 64) void heff_small_kernel(HeffSmallArgs
   }
   __syncthreads();
   // stage 3: y_p (Ml x d) = L[:, :, l0 ..] (Ml x K3) T2 (K3 x d)
-  const int64_t lrow = (int64_t)Wl * Ml;
-  hs_mm16<T>(Ml, K3, t2_re, t2_im, red,
-             [&](int row, int k, T &re, T &im) {
-               const int wl = k / nl, ll = k - wl * nl;
-               const VE v = L[(int64_t)row * lrow + wl * Ml + l0 + ll];
-               re = v.x;
-               im = v.y;
-             },
-             [&](int row, int col, T re, T im) {
-               if (col < d) ycol[row * d + col] = make_double2((double)re, (double)im);
-             });
-  // y_p -> Yp[p] (column r'); <u_i, y_p> partials: thread group g (32
-  // threads) takes i = g, g + 16, ...
+  auto st3 = [&](int row, int col, T re, T im) {
+    if (col < d) ycol[row * d + col] = make_double2((double)re, (double)im);
+  };
+  if (STG) {
+    hs_mm16<T>(Ml, K3, t2_re, t2_im, red,
+               [&](int row, int k, T &re, T &im) {
+                 re = ls_re[k * lay.Ml16 + row];
+                 im = ls_im[k * lay.Ml16 + row];
+               }, st3);
+  } else {
+    const int64_t lrow = (int64_t)Wl * Ml;
+    hs_mm16<T>(Ml, K3, t2_re, t2_im, red,
+               [&](int row, int k, T &re, T &im) {
+                 const int wl = k / nl, ll = k - wl * nl;
+                 const VE v = L[(int64_t)row * lrow + wl * Ml + l0 + ll];
+                 re = v.x;
+                 im = v.y;
+               }, st3);
+  }
+  // y_p -> Yp[p] (column r'); <u_i, y_p> partials: group g takes i = g, g + NG, ...
   double2 *wdst = Yp + (int64_t)part * a.n + (int64_t)rp * ML1;
   for (int e = threadIdx.x; e < ML1; e += NT) wdst[e] = ycol[e];
-  constexpr int NG = NT / 32;
-  constexpr int NQ = (JB + NG - 1) / NG;
-  const int g = threadIdx.x >> 5, t32 = threadIdx.x & 31;
   const int slot = blockIdx.x;
   double dr[NQ], di[NQ];
 #pragma unroll
@@ -773,9 +940,19 @@ __global__ __launch_bounds__(HS_WAVES * 64) void heff_small_kernel(HeffSmallArgs
     di[q] = 0.0;
     const int i = g + NG * q;
     if (i <= j) {
+#pragma unroll
+      for (int t = 0; t < UE; ++t) {
+        const int el = t32 + 32 * t;
+        if (el < ML1) {
+          const double2 u = ur[q][t];
+          const double2 y = ycol[el];
+          dr[q] += u.x * y.x + u.y * y.y;
+          di[q] += u.x * y.y - u.y * y.x;
+        }
+      }
       const double2 *ui = U + (int64_t)i * a.n + (int64_t)rp * ML1;
 #pragma unroll 8
-      for (int el = t32; el < ML1; el += 32) {
+      for (int el = t32 + 32 * UE; el < ML1; el += 32) {
         const double2 u = ui[el];
         const double2 y = ycol[el];
         dr[q] += u.x * y.x + u.y * y.y;
@@ -791,12 +968,8 @@ __global__ __launch_bounds__(HS_WAVES * 64) void heff_small_kernel(HeffSmallArgs
       di[q] += __shfl_xor(di[q], o, 32);
     }
     const int i = g + NG * q;
-    if (t32 == 0 && i <= j) {
-      pp->dot[i][slot] = make_double2(dr[q], di[q]);
-    }
+    if (t32 == 0 && i <= j) pp->dot[i][slot] = make_double2(dr[q], di[q]);
   }
-  (void)lane;
-  (void)wave;
 }
 
 // CSR table of an MPO site tensor W[wl][s'][s][wr] over rows (wl, s'): one
@@ -867,7 +1040,7 @@ int grid_for(int64_t n) {
 hipError_t lz_start(LzState *st, LzPartials *pp, const double2 *x, double2 *u0, int64_t n,
                     double zr, double zi, double tol, int keff, int trows, const LzInst &in,
                     hipStream_t s) {
-  hipLaunchKernelGGL(lz_start_kernel, dim3(grid_for(n), in.count), dim3(LZ_BLOCK), 0, s, st, pp, x,
+  hipLaunchKernelGGL(lz_start_kernel, dim3(upd_grid(n), in.count), dim3(LZ_BLOCK), 0, s, st, pp, x,
                      u0, n, zr, zi, tol, keff, trows, in);
   return hipGetLastError();
 }
@@ -895,7 +1068,7 @@ hipError_t lz_dots(LzState *st, LzPartials *pp, DType ty, const void *ypart, int
 
 hipError_t lz_update(LzState *st, LzPartials *pp, double2 *U, int64_t ldu, int j, int64_t n, int Gd,
                      const double2 *Yp, int P, const LzInst &in, hipStream_t s) {
-  const dim3 g(grid_for(n), in.count), b(LZ_BLOCK);
+  const dim3 g(upd_grid(n), in.count), b(LZ_BLOCK);
   if (Gd <= 0) Gd = grid_for(n);
   if (Yp && (P < 1 || P > HS_PMAX)) return hipErrorInvalidValue;
 #define LZ_UPD(JB) \
@@ -908,19 +1081,19 @@ hipError_t lz_update(LzState *st, LzPartials *pp, double2 *U, int64_t ldu, int j
   return hipGetLastError();
 }
 
-int lz_grid(int64_t n) { return grid_for(n); }
+int lz_grid(int64_t n) { return upd_grid(n); }
 
 size_t heff_small_lds(const HeffSmallArgs &a, int tm_bytes) {
-  const size_t Mr4 = (a.Mr + 3) & ~3;
-  const size_t K34 = ((size_t)a.Wl * a.nl + 3) & ~(size_t)3;
-  const size_t t1p = ((size_t)a.nl * a.d * a.Wr + 3) & ~(size_t)3;
-  const size_t planes = 2 * Mr4 * 16 + 2 * t1p + 2 * K34 * 16 + HS_WAVES * 2 * 256 + 2 * HS_NZ;
-  return planes * tm_bytes + (size_t)a.Ml * a.d * sizeof(double2) +
-         (HS_NZ + (size_t)a.Wl * a.d + 1) * sizeof(int);
+  return HsLayout(a.Ml, a.d, a.Mr, a.Wl, a.Wr, a.nl, a.staged != 0, tm_bytes).total_b;
 }
 
 bool heff_small_fits(const HeffSmallArgs &a, int tm_bytes) {
-  return a.Mr >= 1 && a.Ml >= 1 && a.Wr <= 16 && a.d <= 16 && a.Wl * a.d <= 256 &&
+  if (a.staged) {
+    const HsLayout l(a.Ml, a.d, a.Mr, a.Wl, a.Wr, a.nl, true, tm_bytes);
+    if (l.Mr4 * l.MP16 > HS_XV * HS_WAVES * 64 || l.K34 * l.Ml16 > HS_LV * HS_WAVES * 64)
+      return false;
+  }
+  return a.Mr >= 1 && a.Mr <= 128 && a.Ml >= 1 && a.Wr <= 16 && a.d <= 16 && a.Wl * a.d <= 256 &&
          (int64_t)a.Wl * a.d * a.d * a.Wr <= WT_MAX && a.nl >= 1 && a.P >= 1 &&
          a.P <= HS_PMAX && (int64_t)a.P * a.nl >= a.Ml && (int64_t)(a.P - 1) * a.nl < a.Ml &&
          (int64_t)a.P * a.Mr <= LZ_PARTS && heff_small_lds(a, tm_bytes) <= HEFF_SMALL_LDS;
@@ -930,28 +1103,33 @@ hipError_t heff_small(DType t, const HeffSmallArgs &a, int count, hipStream_t s)
   static bool attr = false;
   if (!attr) {
     attr = true;
-#define HS_ATTR(T, JB)                                                                  \
-  (void)hipFuncSetAttribute((const void *)heff_small_kernel<T, JB>,                     \
+#define HS_ATTR(T, JB, S)                                                               \
+  (void)hipFuncSetAttribute((const void *)heff_small_kernel<T, JB, S>,                  \
                             hipFuncAttributeMaxDynamicSharedMemorySize, HEFF_SMALL_LDS)
-    HS_ATTR(double, 4); HS_ATTR(double, 8); HS_ATTR(double, 16); HS_ATTR(double, 32);
-    HS_ATTR(float, 4); HS_ATTR(float, 8); HS_ATTR(float, 16); HS_ATTR(float, 32);
+#define HS_ATTR2(T, S) HS_ATTR(T, 4, S); HS_ATTR(T, 8, S); HS_ATTR(T, 16, S); HS_ATTR(T, 32, S)
+    HS_ATTR2(double, false); HS_ATTR2(double, true); HS_ATTR2(float, false); HS_ATTR2(float, true);
+#undef HS_ATTR2
 #undef HS_ATTR
     (void)hipGetLastError();
   }
   const dim3 g(a.Mr * a.P, count), b(HS_WAVES * 64);
   const size_t lds = heff_small_lds(a, t == F64 ? 8 : 4);
-#define HS(T, JB) hipLaunchKernelGGL((heff_small_kernel<T, JB>), g, b, lds, s, a)
+#define HS(T, JB, S) hipLaunchKernelGGL((heff_small_kernel<T, JB, S>), g, b, lds, s, a)
+#define HS_J(T, S)                 \
+  do {                             \
+    if (a.j < 4) HS(T, 4, S);      \
+    else if (a.j < 8) HS(T, 8, S); \
+    else if (a.j < 16) HS(T, 16, S); \
+    else HS(T, 32, S);             \
+  } while (0)
   if (t == F64) {
-    if (a.j < 4) HS(double, 4);
-    else if (a.j < 8) HS(double, 8);
-    else if (a.j < 16) HS(double, 16);
-    else HS(double, 32);
+    if (a.staged) HS_J(double, true);
+    else HS_J(double, false);
   } else {
-    if (a.j < 4) HS(float, 4);
-    else if (a.j < 8) HS(float, 8);
-    else if (a.j < 16) HS(float, 16);
-    else HS(float, 32);
+    if (a.staged) HS_J(float, true);
+    else HS_J(float, false);
   }
+#undef HS_J
 #undef HS
   return hipGetLastError();
 }
