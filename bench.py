@@ -34,8 +34,12 @@ def parse():
     ap.add_argument("--tol", type=float, default=0.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--eager", action="store_true", help="launch kernels one by one (no step graph)")
-    ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--no-class-timing", action="store_true",
+                    help="skip the per-kernel-class timing steps (for counter runs)")
     ap.add_argument("--realisations", type=int, default=64)
+    ap.add_argument("--no-fused", action="store_true",
+                    help="general multi-kernel Lanczos step everywhere (tdvp_set_fused(ctx, 0))")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 256 MiB device copy first (reference for HBM counters)")
     return ap.parse_args()
@@ -64,6 +68,64 @@ def cpu_baseline(name, nsteps):
                       f"({os.cpu_count()} host CPUs visible)"}
 
 
+# Kernel classes that are dense complex contractions (MFMA roof); the others
+# are priced against HBM bandwidth.
+MFMA_CLASSES = ("gemm", "lz_fused")
+KERNEL_OF_CLASS = {"gemm": "cgemm_kernel", "lz_fused": "heff_small_kernel", "lz_update": "lz_update_kernel",
+                   "lz_dots": "lz_dots_kernel", "lz_ends": "lz_finish_kernel", "qr": "qr_reg_kernel",
+                   "wapply": "wapply_kernel"}
+
+
+def measured_traffic(kernel, workload, precision):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size), or None
+    when there is none for this workload or the kernel sources changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    src = os.path.join(ROOT, "paper_1907_12044_amd", "csrc", rec.get("source", ""))
+    try:
+        with open(src, "rb") as f:
+            digest = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    if digest != rec.get("source_sha256"):
+        return None
+    ent = rec.get("kernels", {}).get(f"{workload}/{precision}/{kernel}")
+    return None if ent is None else ent.get("bytes_per_launch")
+
+
+def roofline(prof, prec, ms_per_step, workload=None, precision=None):
+    """Roofline entry for the kernel class with the largest time per step,
+    from the event-timed class step: algorithmic FLOP (contractions) or bytes
+    (the rest) per launch over the average launch time."""
+    from paper_1907_12044_amd import tdvp
+    if not prof:
+        return None, None
+    heff_flop = sum(prof[k]["flop"] for k in MFMA_CLASSES if k in prof)
+    heff_tflops = heff_flop / (ms_per_step * 1e-3) / 1e12
+    dom = max(prof, key=lambda k: prof[k]["ms_per_step"])
+    d = prof[dom]
+    t = d["ms_per_step"] * 1e-3
+    if dom in MFMA_CLASSES:
+        peak = PEAK["fp64_mfma_tflops"] if prec == tdvp.FP64 else PEAK["fp32_mfma_tflops"]
+        roof = {"bound": "mfma", "achieved": d["flop"] / t / 1e12, "peak": peak, "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": d["bytes"] / t / 1e9, "peak": PEAK["hbm_gbs"], "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = measured_traffic(KERNEL_OF_CLASS.get(dom, dom), workload, precision)
+    roof["kernel"] = KERNEL_OF_CLASS.get(dom, dom)
+    roof["launches_per_step"] = d["launches"]
+    roof["avg_launch_us"] = 1e6 * t / max(d["launches"], 1)
+    roof["per_launch"] = {"flop": d["flop"] / max(d["launches"], 1),
+                          "bytes": d["bytes"] / max(d["launches"], 1)}
+    return roof, heff_tflops
+
+
 def ensemble_main(args):
     """64 static-disorder realisations, bond dims from {32, 64, 96, 128}: one
     PsEnsemble per bond-dimension class (every kernel covers the class in one
@@ -85,7 +147,7 @@ def ensemble_main(args):
         sites = chain_sites(ps_[0])
         raws = [initial_mps_raw(p, M, 1e-2, 1) for p in ps_]
         ens.append((M, rs, tdvp.PsEnsemble(ps_, sites, raws, 0, prec, kmax=args.kmax, tol=args.tol,
-                                           graph=not args.eager)))
+                                           graph=not args.eager, fused=not args.no_fused)))
     tau = 2.0 * tdvp.AU_PER_FS
     torch.cuda.synchronize()
     for _ in range(args.warmup):
@@ -101,13 +163,21 @@ def ensemble_main(args):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms = 1e3 * elapsed / max(args.steps, 1)
-    flop = 0.0
-    for _, _, e in ens:
-        tdvp.profile(e.ctx, tdvp.PROF_GEMM)
-        e.step(tau, 1)
-        _, _, f, _ = tdvp.profile_read(e.ctx)
-        tdvp.profile(e.ctx, 0)
-        flop += f
+    prof = {}
+    if not args.no_class_timing:
+        for name, cls in tdvp.PROF_CLASSES.items():
+            acc = {"ms_per_step": 0.0, "launches": 0, "flop": 0.0, "bytes": 0.0}
+            for _, _, e in ens:
+                tdvp.profile(e.ctx, cls)
+                e.step(tau, 1)
+                ms_, n_, f_, b_ = tdvp.profile_read(e.ctx)
+                tdvp.profile(e.ctx, 0)
+                acc["ms_per_step"] += ms_
+                acc["launches"] += n_
+                acc["flop"] += f_
+                acc["bytes"] += b_
+            prof[name] = acc
+    roof, heff_tflops = roofline(prof, prec, ms, f"ensemble{nreal}", args.precision)
     pops = np.concatenate([e.observe_host()[:, 2:] for _, _, e in ens])
     line = {
         "metric": "TDVP-PS ensemble steps/s (all realisations advanced one step)",
@@ -119,7 +189,9 @@ def ensemble_main(args):
         "config": {"workload": f"fmo7x10x8_ensemble{nreal}", "classes": {str(M): len(rs) for M, rs, _ in ens},
                    "precision": args.precision, "kmax": args.kmax},
         "realisation_steps_per_s": nreal * 1e3 / ms,
-        "heff_tflops": flop / (ms * 1e-3) / 1e12,
+        "heff_tflops": heff_tflops,
+        "class_ms_per_step": {k: round(v["ms_per_step"], 3) for k, v in prof.items()},
+        "roofline": roof,
         "population_sum_range": [float(pops.sum(1).min()), float(pops.sum(1).max())],
     }
     print(json.dumps(line), flush=True)
@@ -147,7 +219,7 @@ def main():
     p, sites, phys, dims, raw, w = workload(args.workload)
     prec = tdvp.FP64 if args.precision == "fp64" else tdvp.FP32
     run = tdvp.PsRun(p, sites, raw, device=0, precision=prec, kmax=args.kmax, tol=args.tol,
-                     graph=not args.eager)
+                     graph=not args.eager, fused=not args.no_fused)
     tau = w["dt_fs"] * tdvp.AU_PER_FS
     nsolve = 4 * len(sites)
     with torch.cuda.stream(run.stream):
@@ -177,28 +249,14 @@ def main():
     ks = klog.cpu().numpy()
     ks = ks[ks > 0]
     prof = {}
-    for name, cls in tdvp.PROF_CLASSES.items():
-        tdvp.profile(run.ctx, cls)
-        run.step(tau, 1)
-        ms, n, f, b = tdvp.profile_read(run.ctx)
-        tdvp.profile(run.ctx, 0)
-        prof[name] = {"ms_per_step": ms, "launches": n, "flop": f, "bytes": b}
-
-    g = prof["gemm"]
-    heff_tflops = g["flop"] / (ms_per_step * 1e-3) / 1e12
-    dom = max(prof, key=lambda k: prof[k]["ms_per_step"])
-    d = prof[dom]
-    if dom == "gemm":
-        peak = PEAK["fp64_mfma_tflops"] if prec == tdvp.FP64 else PEAK["fp32_mfma_tflops"]
-        ach = d["flop"] / (d["ms_per_step"] * 1e-3) / 1e12
-        roof = {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s"}
-    else:
-        ach = d["bytes"] / (d["ms_per_step"] * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": ach, "peak": PEAK["hbm_gbs"], "unit": "GB/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
-    roof["kernel"] = dom
-    roof["avg_launch_us"] = 1e3 * d["ms_per_step"] / max(d["launches"], 1)
+    if not args.no_class_timing:
+        for name, cls in tdvp.PROF_CLASSES.items():
+            tdvp.profile(run.ctx, cls)
+            run.step(tau, 1)
+            ms, n, f, b = tdvp.profile_read(run.ctx)
+            tdvp.profile(run.ctx, 0)
+            prof[name] = {"ms_per_step": ms, "launches": n, "flop": f, "bytes": b}
+    roof, heff_tflops = roofline(prof, prec, ms_per_step, args.workload, args.precision)
 
     line = {
         "metric": "TDVP-PS steps/s (H_eff TFLOP/s alongside)",
@@ -215,10 +273,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "sites": len(sites), "bond_dim": w["M"],
                    "mpo_bond_max": max(run.mpo.bond), "dt_fs": w["dt_fs"], "kmax": args.kmax,
-                   "tol": args.tol, "precision": args.precision, "graph": not args.eager},
+                   "tol": args.tol, "precision": args.precision, "graph": not args.eager,
+                   "fused": not args.no_fused},
         "heff_tflops": heff_tflops,
         "krylov_mean": float(ks.mean()) if ks.size else None,
-        "profile_ms_per_step": {k: round(v["ms_per_step"], 3) for k, v in prof.items()},
+        "class_ms_per_step": {k: round(v["ms_per_step"], 3) for k, v in prof.items()},
         "roofline": roof,
         "final_populations": [float(x) for x in host_obs[-1, 2:]],
         "final_norm": float(host_obs[-1, 0]),

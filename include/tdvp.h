@@ -168,9 +168,9 @@ tdvp_status tdvp_set_graph(tdvp_ctx *ctx, int enable);
 
 /* Kernel path of the local Lanczos solves (eq:tdvp2_C, eq:tdvp2_D).  With
  * enable != 0 (the default) a solve whose bond dimensions are small enough
- * for the tiles of one work-group per output column to fit in LDS (e.g.
- * M <= 32 in FP64, M <= 64 in FP32 for MPO bonds <= 16) runs each Krylov
- * step as two kernels: the fused H x with its projections, then the
+ * (right bond dimension <= 64, MPO bonds <= 16, and the tiles of the
+ * work-groups that share an output column fit in LDS) runs each Krylov step
+ * as two kernels: the fused H x with its projections, then the
  * orthogonalisation.  enable = 0 forces the general path (three contraction
  * kernels, projections, orthogonalisation) for every solve.  Both paths
  * compute the same quantities; results differ by rounding order only. */

@@ -225,6 +225,11 @@ WORKLOADS = {
     # 7 electronic sites x 10 modes x 8 levels, M = 32, FP64
     "fmo7x10x8_M32": dict(n_e=7, n_modes=10, levels=8, M=32, dt_fs=2.0, steps=500,
                           seed=0, eta=1e-2, phi_seed=1),
+    # the same chain at the other bond dimensions of the disorder ensemble
+    "fmo7x10x8_M64": dict(n_e=7, n_modes=10, levels=8, M=64, dt_fs=2.0, steps=500,
+                          seed=0, eta=1e-2, phi_seed=1),
+    "fmo7x10x8_M96": dict(n_e=7, n_modes=10, levels=8, M=96, dt_fs=2.0, steps=500,
+                          seed=0, eta=1e-2, phi_seed=1),
     # same chain at M = 128, mixed precision, Krylov dim 20
     "fmo7x10x8_M128": dict(n_e=7, n_modes=10, levels=8, M=128, dt_fs=2.0, steps=1000,
                            seed=0, eta=1e-2, phi_seed=1, kdim=20),
