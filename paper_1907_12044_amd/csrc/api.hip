@@ -87,7 +87,7 @@ Layout layout(int64_t n, int wmax, int kmax, int es) {
   L.Y = o; o += al256((size_t)wmax * n * es);
   L.D = o; o += al256((size_t)n * 16);
   L.tmp = o; o += al256((size_t)n * 16);
-  L.qr = o; o += al256((size_t)2 * n * 16 + 16 * 1024);   // QR: 2 m n + 2 n complex (n <= 256)
+  L.qr = o; o += al256((size_t)8 * n * 16 + 16 * 1024);   // QR: panel path 2 m n + 2 n, Cholesky QR 3 m n + 5 n^2 complex
   L.obs = o; o += al256((size_t)3 * n * 16 + 4096);
   L.total = o;
   return L;
@@ -236,11 +236,13 @@ tdvp_status apply_op(tdvp_ctx *c, const Layout &lay, const Op &op, const double2
 // over the bra index l is split into P parts so that Mr P work-groups per
 // instance cover the chip.  Fills everything except st, pp, U, j.
 // Measured on the 77-site chain: the fused step wins up to bond dimension
-// 64 (FP64 and FP32); at 128 the tiled GEMM path is faster.
+// 64 (FP64 and FP32); at 128 the tiled GEMM path is faster, for H[i] and for
+// the bond operator alike.
 constexpr int FUSED_MAX_MR = 64;
+constexpr int FUSED_MAX_MR_BOND = 64;
 
 bool fused_args(const tdvp_ctx *c, const Layout &lay, const Op &op, const Bi &b, HeffSmallArgs &a) {
-  if (c->fused_off || op.Mr > FUSED_MAX_MR) return false;
+  if (c->fused_off || op.Mr > (op.W ? FUSED_MAX_MR : FUSED_MAX_MR_BOND)) return false;
   if (!op.W && (op.Wl != op.Wr || op.d != 1)) return false;
   a = HeffSmallArgs{};
   a.L = op.L; a.R = op.R;
@@ -249,7 +251,9 @@ bool fused_args(const tdvp_ctx *c, const Layout &lay, const Op &op, const Bi &b,
   a.Gprev = lz_grid(a.n);
   a.Gw = lz_grid(a.n);
   a.wss = b.ws; a.sL = op.sL; a.sR = op.sR;
-  const int64_t cols = (int64_t)op.Mr * b.R;
+  // P depends on the shape only (not on the instance count), so an instance
+  // of a batch computes exactly what the same chain computes alone
+  const int64_t cols = op.Mr;
   int P = (int)std::min<int64_t>(HS_PMAX, std::max<int64_t>(1, (256 + cols - 1) / cols));
   P = std::min(P, std::max(1, op.Ml / 4));
   while (P > 1 && ((int64_t)P * op.Mr > LZ_PARTS || (size_t)P * a.n * 16 > lay.ybytes)) --P;

@@ -1,0 +1,418 @@
+// QR of a tall complex matrix by shifted Cholesky QR in three passes, for
+// the gauge shifts of the sweep at larger bond dimension (eq:QR), where one
+// work-group's Householder QR runs out of LDS and parallelism.
+//
+// Pass p (W_0 = A):  G = W_p^H W_p  (MFMA);  R_p = chol(G [+ s I])  with
+// G = R_p^H R_p, diag(R_p) > 0;  W_{p+1} = W_p R_p^{-1}  (GEMM).
+// The first pass adds the shift s = 11 (m n + n (n + 1)) u tr(G) (u the
+// unit round-off), which keeps the Cholesky factorisation defined up to a
+// condition number ~1/u; the next two passes restore orthogonality to
+// round-off.  Q = W_3, R = R_3 R_2 R_1: upper triangular with real positive
+// diagonal, i.e. the same factorisation (C = L D with diag(D) real >= 0) that
+// the Householder paths produce, unique for full-rank input.
+//
+// Kernels: cq_prep (A through strides / conjugation into W_0), per pass
+// cq_gram (upper 16x16 tiles of G, K split over the 16 waves of a
+// work-group), cq_chol (one work-group: blocked Cholesky and block-triangular
+// inverse on the matrix cores) and cgemm for W R^{-1} and
+// the running product of the R factors (the last ones write Q and R through
+// the caller's strides).
+// n <= 128.
+#include "common.h"
+#include "mfma.h"
+
+namespace tdvp {
+
+namespace {
+
+constexpr int CQ_THREADS = 1024;
+constexpr int CQ_NMAX = 128;
+
+__global__ __launch_bounds__(256) void cq_prep_kernel(QrArgs p, double2 *W0, int64_t ws) {
+  const int64_t inst = blockIdx.y;
+  const double2 *A = p.A + inst * p.inst.a;
+  W0 += inst * ws;
+  const int64_t total = (int64_t)p.m * p.n;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / p.n, c = e - r * p.n;
+    double2 v = A[r * p.a_rs + c * p.a_cs];
+    if (p.conjA) v.y = -v.y;
+    W0[e] = v;
+  }
+}
+
+// G[i][j] = sum_k conj(W[k][i]) W[k][j] on the upper 16x16 tiles (tj >= ti);
+// the 16 waves of a work-group take interleaved 4-row slices of k, and the
+// wave results are added in order through LDS.
+__global__ __launch_bounds__(CQ_THREADS) void cq_gram_kernel(const double2 *W, int m, int n,
+                                                             double2 *G, int64_t ws) {
+  const int64_t inst = blockIdx.y;
+  W += inst * ws;
+  G += inst * ws;
+  const int nt = (n + 15) / 16;
+  int t = blockIdx.x, ti = 0;
+  while (t >= nt - ti) {
+    t -= nt - ti;
+    ++ti;
+  }
+  const int tj = ti + t;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = ti * 16 + (lane & 15), j = tj * 16 + (lane & 15);
+  f64x4_t cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+  for (int k0 = 4 * wave; k0 < m; k0 += 4 * (CQ_THREADS / 64)) {
+    const int k = k0 + (lane >> 4);
+    double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
+    if (k < m) {
+      if (i < n) a = W[(int64_t)k * n + i];
+      if (j < n) b = W[(int64_t)k * n + j];
+    }
+    // conj(a) * b
+    cr = Mf<double>::mfma(a.x, b.x, cr);
+    cr = Mf<double>::mfma(a.y, b.y, cr);
+    ci = Mf<double>::mfma(a.x, b.y, ci);
+    ci = Mf<double>::mfma(-a.y, b.x, ci);
+  }
+  // waves 8..15 park their results, waves 0..7 add them to their own, then
+  // 8 partial tiles are added in order (32 KiB of LDS)
+  __shared__ double red[8][2][256];
+  if (wave >= 8) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      red[wave - 8][0][r * 64 + lane] = cr[r];
+      red[wave - 8][1][r * 64 + lane] = ci[r];
+    }
+  }
+  __syncthreads();
+  if (wave < 8) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      red[wave][0][r * 64 + lane] += cr[r];
+      red[wave][1][r * 64 + lane] += ci[r];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 256) {
+    const int r = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    double sr = 0.0, si = 0.0;
+    for (int w = 0; w < 8; ++w) {
+      sr += red[w][0][r * 64 + ln];
+      si += red[w][1][r * 64 + ln];
+    }
+    const int gi = ti * 16 + Mf<double>::row(ln, r), gj = tj * 16 + (ln & 15);
+    if (gi < n && gj < n) G[(int64_t)gi * n + gj] = make_double2(sr, si);
+  }
+}
+
+// 16x16 complex blocks in LDS, row-major.  acc (re, im) += op(A) B on the
+// matrix cores of one wave; op(A) = A^H when adj.
+__device__ __forceinline__ void blk_mma(const double2 *A, bool adj, const double2 *B, f64x4_t &cr,
+                                        f64x4_t &ci) {
+  const int lane = threadIdx.x & 63, i = lane & 15, kk = lane >> 4;
+#pragma unroll
+  for (int k0 = 0; k0 < 16; k0 += 4) {
+    const int k = k0 + kk;
+    double2 av = adj ? A[k * 16 + i] : A[i * 16 + k];
+    if (adj) av.y = -av.y;
+    const double2 bv = B[k * 16 + i];
+    cr = Mf<double>::mfma(av.x, bv.x, cr);
+    cr = Mf<double>::mfma(-av.y, bv.y, cr);
+    ci = Mf<double>::mfma(av.x, bv.y, ci);
+    ci = Mf<double>::mfma(av.y, bv.x, ci);
+  }
+}
+
+// One work-group per instance: blocked right-looking Cholesky G = R^H R in
+// 16x16 blocks (n padded to a multiple of 16 with an identity block), then
+// R^{-1} by block back substitution.  Per block column K: wave 0 factors
+// the diagonal block (row k in lane k) and inverts it (column c in lane c);
+// the waves form the block row R_KJ = R_KK^{-H} G_KJ and the trailing
+// update G_IJ -= R_KI^H R_KJ on the matrix cores.  The upper blocks live in
+// LDS (packed by block row); R and R^{-1} are written as full n x n
+// matrices (zeros below the diagonal).
+struct CholArgs {
+  const double2 *G; double2 *R; double2 *Rinv;
+  int m, n, shift;
+  int64_t ws;                      // instance stride of the work area (elements)
+};
+
+constexpr int CQ_NB = CQ_NMAX / 16;   // block rows / columns at most
+constexpr int CQ_CHOL_THREADS = 512;  // 8 waves (>= CQ_NB - 1 for the back substitution)
+
+__device__ __forceinline__ int bidx(int I, int J, int nb) { return I * nb - (I * (I - 1)) / 2 + (J - I); }
+
+__global__ __launch_bounds__(CQ_CHOL_THREADS) void cq_chol_kernel(CholArgs a) {
+  extern __shared__ double2 Bk[];   // packed upper blocks, then one scratch block Dv
+  __shared__ double trace_s[CQ_CHOL_THREADS / 64];
+  const int64_t inst = blockIdx.x;
+  const double2 *G = a.G + inst * a.ws;
+  double2 *Rout = a.R + inst * a.ws;
+  double2 *Rinv = a.Rinv + inst * a.ws;
+  const int n = a.n, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nb = (n + 15) / 16;
+  const int nblk = nb * (nb + 1) / 2;
+  double2 *Dv = Bk + nblk * 256;     // inverse of the current diagonal block
+  // diagonal shift from the trace (first pass)
+  double shift = 0.0;
+  if (a.shift) {
+    double tr = 0.0;
+    for (int i = tid; i < n; i += CQ_CHOL_THREADS) tr += G[(int64_t)i * n + i].x;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) tr += __shfl_xor(tr, o, 64);
+    if (lane == 0) trace_s[wave] = tr;
+    __syncthreads();
+    tr = 0.0;
+    for (int w = 0; w < CQ_CHOL_THREADS / 64; ++w) tr += trace_s[w];
+    shift = 11.0 * ((double)a.m * n + (double)n * (n + 1)) * 1.1102230246251565e-16 * tr;
+  }
+  // load the upper blocks (identity padding beyond n)
+  for (int e = tid; e < nblk * 256; e += CQ_CHOL_THREADS) {
+    const int b = e >> 8, w = e & 255;
+    int I = 0, t = b;
+    while (t >= nb - I) { t -= nb - I; ++I; }
+    const int J = I + t;
+    const int i = 16 * I + (w >> 4), j = 16 * J + (w & 15);
+    double2 v = make_double2(0.0, 0.0);
+    if (i < n && j < n) {
+      if (j >= i) v = G[(int64_t)i * n + j];
+      if (i == j) v = make_double2(v.x + shift, 0.0);
+    } else if (i == j) {
+      v = make_double2(1.0, 0.0);
+    }
+    Bk[e] = v;
+  }
+  __syncthreads();
+  for (int K = 0; K < nb; ++K) {
+    double2 *D = Bk + bidx(K, K, nb) * 256;
+    if (wave == 0) {
+      // factor D = R^H R in place: lane i holds row i
+      double2 r[16];
+      if (lane < 16) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) r[j] = D[lane * 16 + j];
+      }
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        if (lane == k) {
+          double p = r[k].x;
+          if (!(p > 1e-300)) p = 1e-300;       // not positive definite: keep the values finite
+          const double y = rsqrt_nr(p);
+#pragma unroll
+          for (int j = 0; j < 16; ++j) {
+            if (j > k) r[j] = make_double2(r[j].x * y, r[j].y * y);
+            else if (j == k) r[j] = make_double2(p * y, 0.0);
+            else r[j] = make_double2(0.0, 0.0);
+            D[k * 16 + j] = r[j];
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (lane > k && lane < 16) {
+          double2 rk[16];
+#pragma unroll
+          for (int j = 0; j < 16; ++j) rk[j] = D[k * 16 + j];
+          double2 cik = make_double2(0.0, 0.0);
+#pragma unroll
+          for (int j = 0; j < 16; ++j)
+            if (j == lane) cik = rk[j];     // R[k][i]
+#pragma unroll
+          for (int j = 0; j < 16; ++j) {
+            if (j >= lane) {               // r[j] -= conj(R[k][i]) R[k][j]
+              r[j].x -= cik.x * rk[j].x + cik.y * rk[j].y;
+              r[j].y -= cik.x * rk[j].y - cik.y * rk[j].x;
+            }
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+      // Dv = R_KK^{-1}: lane c solves R x = e_c from row c down (x in registers)
+      if (lane < 16) {
+        double2 x[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) x[q] = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int i = 15; i >= 0; --i) {
+          if (i <= lane) {
+            double sr = (i == lane) ? 1.0 : 0.0, si = 0.0;
+#pragma unroll
+            for (int k = i + 1; k < 16; ++k) {
+              if (k <= lane) {
+                const double2 rv = D[i * 16 + k];
+                sr -= rv.x * x[k].x - rv.y * x[k].y;
+                si -= rv.x * x[k].y + rv.y * x[k].x;
+              }
+            }
+            const double inv = rcp_nr(D[i * 16 + i].x);
+            x[i] = make_double2(sr * inv, si * inv);
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) Dv[i * 16 + lane] = x[i];
+      }
+    }
+    __syncthreads();
+    // block row: R_KJ = Dv^H G_KJ, one wave per block
+    for (int J = K + 1 + wave; J < nb; J += CQ_CHOL_THREADS / 64) {
+      double2 *Bj = Bk + bidx(K, J, nb) * 256;
+      f64x4_t cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+      blk_mma(Dv, true, Bj, cr, ci);
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr)
+        Bj[Mf<double>::row(lane, rr) * 16 + (lane & 15)] = make_double2(cr[rr], ci[rr]);
+    }
+    __syncthreads();
+    // trailing update G_IJ -= R_KI^H R_KJ, K < I <= J
+    {
+      const int nt = nb - K - 1;
+      for (int t = wave; t < nt * (nt + 1) / 2; t += CQ_CHOL_THREADS / 64) {
+        int I = 0, u = t;
+        while (u >= nt - I) { u -= nt - I; ++I; }
+        I += K + 1;
+        const int J = I + u;
+        double2 *Cij = Bk + bidx(I, J, nb) * 256;
+        f64x4_t cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+        blk_mma(Bk + bidx(K, I, nb) * 256, true, Bk + bidx(K, J, nb) * 256, cr, ci);
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          double2 &c = Cij[Mf<double>::row(lane, rr) * 16 + (lane & 15)];
+          c.x -= cr[rr];
+          c.y -= ci[rr];
+        }
+      }
+    }
+    // keep the diagonal block's inverse for the back substitution
+    for (int e = tid; e < 256; e += CQ_CHOL_THREADS) {
+      const int i = 16 * K + (e >> 4), j = 16 * K + (e & 15);
+      if (i < n && j < n) Rinv[(int64_t)i * n + j] = Dv[e];
+    }
+    __syncthreads();
+  }
+  // R, full
+  for (int e = tid; e < n * n; e += CQ_CHOL_THREADS) {
+    const int i = e / n, j = e - i * n;
+    double2 v = make_double2(0.0, 0.0);
+    if (j >= i) v = Bk[bidx(i >> 4, j >> 4, nb) * 256 + (i & 15) * 16 + (j & 15)];
+    Rout[e] = v;
+  }
+  __syncthreads();
+  // R^{-1} by block rows from the bottom: X_II = R_II^{-1} (kept above),
+  // X_IJ = -X_II sum_{K=I+1..J} R_IK X_KJ; block row I of R is overwritten by
+  // X once formed (rows below I already hold X)
+  for (int I = nb - 1; I >= 0; --I) {
+    for (int e = tid; e < 256; e += CQ_CHOL_THREADS) {
+      const int i = 16 * I + (e >> 4), j = 16 * I + (e & 15);
+      Dv[e] = (i < n && j < n) ? Rinv[(int64_t)i * n + j] : make_double2(i == j ? 1.0 : 0.0, 0.0);
+    }
+    __syncthreads();
+    // S_J = sum_K R_IK X_KJ (one wave per J), then X_IJ = -X_II S_J
+    const int J = I + 1 + wave;         // nb - 1 <= 7 < 8 waves
+    f64x4_t sr = {0, 0, 0, 0}, si = {0, 0, 0, 0};
+    if (J < nb)
+      for (int K = I + 1; K <= J; ++K)
+        blk_mma(Bk + bidx(I, K, nb) * 256, false, Bk + bidx(K, J, nb) * 256, sr, si);
+    __syncthreads();   // every R_IK has been read
+    if (J < nb) {
+      double2 *Xj = Bk + bidx(I, J, nb) * 256;
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr)
+        Xj[Mf<double>::row(lane, rr) * 16 + (lane & 15)] = make_double2(sr[rr], si[rr]);
+      __builtin_amdgcn_wave_barrier();
+      f64x4_t cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+      blk_mma(Dv, false, Xj, cr, ci);
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr)
+        Xj[Mf<double>::row(lane, rr) * 16 + (lane & 15)] = make_double2(-cr[rr], -ci[rr]);
+    }
+    for (int e = tid; e < 256; e += CQ_CHOL_THREADS) Bk[bidx(I, I, nb) * 256 + e] = Dv[e];
+    __syncthreads();
+  }
+  for (int e = tid; e < n * n; e += CQ_CHOL_THREADS) {
+    const int i = e / n, j = e - i * n;
+    double2 v = make_double2(0.0, 0.0);
+    if (j >= i) v = Bk[bidx(i >> 4, j >> 4, nb) * 256 + (i & 15) * 16 + (j & 15)];
+    Rinv[e] = v;
+  }
+}
+
+}  // namespace
+
+bool cholqr_ok(int m, int n) { return n >= 1 && n <= CQ_NMAX && m >= n; }
+
+int64_t cholqr_work_elems(int m, int n) {
+  return 3 * (int64_t)m * n + 5 * (int64_t)n * n;   // W_0..W_2, G, R_p, Rinv, two running products
+}
+
+hipError_t cholqr(const QrArgs &p, hipStream_t s) {
+  const int m = p.m, n = p.n, R = p.inst.count;
+  if (!cholqr_ok(m, n)) return hipErrorInvalidValue;
+  static bool attr = false;
+  if (!attr) {
+    attr = true;
+    (void)hipFuncSetAttribute((const void *)cq_chol_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (CQ_NB * (CQ_NB + 1) / 2 + 1) * 256 * (int)sizeof(double2));
+    (void)hipGetLastError();
+  }
+  const int64_t mn = (int64_t)m * n, nn = (int64_t)n * n, ws = p.inst.skip;
+  double2 *Wb[3] = {p.work, p.work + mn, p.work + 2 * mn};
+  double2 *G = p.work + 3 * mn;
+  double2 *Rk = G + nn, *Rinv = Rk + nn;
+  double2 *Racc[2] = {Rinv + nn, Rinv + 2 * nn};
+  {
+    int64_t gx = (mn + 255) / 256;
+    if (gx > 1024) gx = 1024;
+    hipLaunchKernelGGL(cq_prep_kernel, dim3((unsigned)gx, R), dim3(256), 0, s, p, Wb[0], ws);
+  }
+  const int nt = (n + 15) / 16;
+  const int nbk = (n + 15) / 16;
+  const size_t lds = (size_t)(nbk * (nbk + 1) / 2 + 1) * 256 * sizeof(double2);
+  // n x n product X Y (row-major operands in the work area) into Z with
+  // strides (zr, zc) and instance stride zs; conj: conjugated result
+  auto nn_gemm = [&](const double2 *X, const double2 *Y, double2 *Z, int64_t zr, int64_t zc,
+                     int64_t zs, int conj) {
+    GemmArgs g{};
+    g.A = X; g.B = Y; g.C = Z;
+    g.M = n; g.N = n; g.K = n; g.batch = 1;
+    g.sam = n; g.sak = 1; g.sbk = n; g.sbn = 1; g.scm = zr; g.scn = zc;
+    g.conjA = conj; g.conjB = conj;
+    g.inst.count = R; g.inst.a = ws; g.inst.b = ws; g.inst.c = zs;
+    return cgemm(F64, F64, F64, g, s);
+  };
+  for (int pass = 0; pass < 3; ++pass) {
+    const bool last = pass == 2;
+    hipLaunchKernelGGL(cq_gram_kernel, dim3(nt * (nt + 1) / 2, R), dim3(CQ_THREADS), 0, s, Wb[pass],
+                       m, n, G, ws);
+    CholArgs ca{};
+    ca.G = G; ca.R = pass == 0 ? Racc[0] : Rk; ca.Rinv = Rinv;
+    ca.m = m; ca.n = n; ca.ws = ws;
+    ca.shift = pass == 0;
+    hipLaunchKernelGGL(cq_chol_kernel, dim3(R), dim3(CQ_CHOL_THREADS), lds, s, ca);
+    // R = R_3 R_2 R_1, accumulated from the left; the last product goes to
+    // the caller's R through its strides
+    hipError_t e = hipSuccess;
+    if (pass == 1) e = nn_gemm(Rk, Racc[0], Racc[1], n, 1, ws, 0);
+    if (last) e = nn_gemm(Rk, Racc[1], p.R, p.r_rs, p.r_cs, p.inst.c, p.conjR);
+    if (e != hipSuccess) return e;
+    // W_{p+1} = W_p Rinv; the last one is Q, written through the caller's
+    // strides (conjugated output = product of conjugated operands)
+    GemmArgs g{};
+    g.A = Wb[pass]; g.B = Rinv;
+    g.M = m; g.N = n; g.K = n; g.batch = 1;
+    g.sam = n; g.sak = 1; g.sbk = n; g.sbn = 1;
+    g.inst.count = R;
+    g.inst.a = ws; g.inst.b = ws;
+    if (last) {
+      g.C = p.Q; g.scm = p.q_rs; g.scn = p.q_cs;
+      g.conjA = p.conjQ; g.conjB = p.conjQ;
+      g.inst.c = p.inst.b;
+    } else {
+      g.C = Wb[pass + 1]; g.scm = n; g.scn = 1;
+      g.inst.c = ws;
+    }
+    e = cgemm(F64, F64, F64, g, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace tdvp

@@ -150,6 +150,11 @@ struct QrArgs {
   Inst inst;      // a = A, b = Q, c = R strides; skip = work stride (elements)
 };
 hipError_t qr(const QrArgs &a, hipStream_t s);
+// Shifted Cholesky QR (three passes) for m >= n, n <= 128; the work area
+// (QrArgs::work, instance stride inst.skip) must hold cholqr_work_elems c128.
+bool cholqr_ok(int m, int n);
+int64_t cholqr_work_elems(int m, int n);
+hipError_t cholqr(const QrArgs &a, hipStream_t s);
 void qr_init();   // once per process, outside stream capture
 
 }  // namespace tdvp

@@ -20,6 +20,7 @@
 #include <type_traits>
 
 #include "common.h"
+#include "mfma.h"
 
 namespace tdvp {
 
@@ -586,27 +587,6 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_finish_kernel(LzState *st, const 
 // lz_start and lz_finish convert from and to the row-major site tensor.
 // With row == NULL the operator is the bond operator of eq:tdvp2_D (d = 1,
 // T2 = T1^T).  The nonzeros of W come as a CSR table over rows (wl, s').
-
-typedef double f64x4_t __attribute__((ext_vector_type(4)));
-typedef float f32x4_t __attribute__((ext_vector_type(4)));
-template <typename T> struct Mf;
-template <> struct Mf<double> {
-  using acc = f64x4_t;
-  using c2 = double2;
-  static __device__ __forceinline__ acc mfma(double a, double b, acc c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  // row of a 16x16 result block held by (lane, register r)
-  static __device__ __forceinline__ int row(int lane, int r) { return 4 * r + (lane >> 4); }
-};
-template <> struct Mf<float> {
-  using acc = f32x4_t;
-  using c2 = float2;
-  static __device__ __forceinline__ acc mfma(float a, float b, acc c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
-};
 
 constexpr int HS_WAVES = 8;            // waves per work-group of the fused step
 constexpr int HS_NZ = 512;             // W nonzeros staged in LDS (more: read from global)

@@ -888,6 +888,7 @@ hipError_t qr(const QrArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(qr_lds_kernel, dim3(R), dim3(QR_THREADS), elems * sizeof(double2), s, a);
     return hipGetLastError();
   }
+  if (cholqr_ok(a.m, a.n)) return cholqr(a, s);
   int nb = PANEL_LDS_ELEMS / a.m;
   if (nb > 8) nb = 8;
   if (!panel_ok || a.m > 64 * RPL || nb < 1) {

@@ -20,12 +20,15 @@ def _instances(nb, M, n_modes=3, levels=4):
     return ps_, sites, raws
 
 
-@pytest.mark.parametrize("precision,graph", [(0, True), (0, False), (1, True)])
-def test_batched_equals_single_runs(precision, graph):
+@pytest.mark.parametrize("precision,graph,M", [(0, True, 12), (0, False, 12), (1, True, 12), (0, True, 48)],
+                         ids=["fp64-graph", "fp64-eager", "fp32-graph", "fp64-graph-M48"])
+def test_batched_equals_single_runs(precision, graph, M):
+    """M = 12: register QR and fused Lanczos step; M = 48 (4 modes x 8
+    levels): also the Cholesky QR path (384 x 48 gauge shifts)."""
     require_gpu()
     from paper_1907_12044_amd import tdvp
     nb = 3
-    ps_, sites, raws = _instances(nb, 12)
+    ps_, sites, raws = (_instances(nb, M) if M == 12 else _instances(nb, M, n_modes=4, levels=8))
     tau = 2.0 * model.AU_PER_FS
     ens = tdvp.PsEnsemble(ps_, sites, raws, 0, precision, kmax=20, graph=graph)
     singles = [tdvp.PsRun(p, sites, raw, 0, precision, kmax=20, graph=graph) for p, raw in zip(ps_, raws)]

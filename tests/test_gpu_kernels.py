@@ -306,6 +306,38 @@ def test_qr_rank_deficient_is_still_orthonormal(ctxs):
     assert relerr(Qh @ Rh, A) < 1e-13
 
 
+@pytest.mark.parametrize("m,n,kind", [(700, 96, "graded"), (600, 64, "rank-deficient"),
+                                      (1024, 128, "graded"), (300, 33, "rank-deficient")])
+def test_qr_cholesky_path_hard_cases(ctxs, m, n, kind):
+    """Shapes of the shifted Cholesky QR path: singular values graded down to
+    1e-12, or exactly repeated columns; Q orthonormal and QR = A to round-off,
+    R upper triangular with real non-negative diagonal."""
+    from paper_1907_12044_amd import tdvp
+    ctx = ctxs["fp64"]
+    if kind == "graded":
+        U, _ = np.linalg.qr(random_complex((m, n), m))
+        V, _ = np.linalg.qr(random_complex((n, n), n))
+        A = (U * np.logspace(0, -12, n)) @ V.conj().T
+    else:
+        A = random_complex((m, n), m + 1)
+        k = n // 4
+        A[:, n - k:] = A[:, :k] * (1.0 + 2.0j)
+    Q = dev(np.zeros((m, n), complex))
+    R = dev(np.zeros((n, n), complex))
+    tdvp.qr(ctx, dev(A), m, n, Q, R)
+    Qh, Rh = host(Q), host(R)
+    assert np.abs(Qh.conj().T @ Qh - np.eye(n)).max() < 1e-12
+    assert relerr(Qh @ Rh, A) < 1e-13
+    assert np.abs(np.tril(Rh, -1)).max() == 0.0
+    assert np.all(np.diag(Rh).real >= 0) and np.abs(np.diag(Rh).imag).max() == 0.0
+    if kind == "graded":
+        # unique factorisation: compare the well-determined leading columns with the oracle
+        Qo, Ro = om.qr_pos(A)
+        lead = n // 4
+        assert relerr(Rh[:lead, :lead], Ro[:lead, :lead]) < 1e-10
+        assert relerr(Qh[:, :lead], Qo[:, :lead]) < 1e-9
+
+
 def test_bad_arguments_are_rejected(ctxs):
     from paper_1907_12044_amd import tdvp
     ctx = ctxs["fp64"]
