@@ -104,6 +104,10 @@ __global__ __launch_bounds__(CQ_THREADS) void cq_gram_kernel(const double2 *W, i
   }
 }
 
+__device__ __forceinline__ double2 shfl_c(double2 v, int src) {
+  return make_double2(__shfl(v.x, src, 64), __shfl(v.y, src, 64));
+}
+
 // 16x16 complex blocks in LDS, row-major.  acc (re, im) += op(A) B on the
 // matrix cores of one wave; op(A) = A^H when adj.
 __device__ __forceinline__ void blk_mma(const double2 *A, bool adj, const double2 *B, f64x4_t &cr,
@@ -125,7 +129,7 @@ __device__ __forceinline__ void blk_mma(const double2 *A, bool adj, const double
 // One work-group per instance: blocked right-looking Cholesky G = R^H R in
 // 16x16 blocks (n padded to a multiple of 16 with an identity block), then
 // R^{-1} by block back substitution.  Per block column K: wave 0 factors
-// the diagonal block (row k in lane k) and inverts it (column c in lane c);
+// the diagonal block and inverts it (4 lanes per column, shuffles);
 // the waves form the block row R_KJ = R_KK^{-H} G_KJ and the trailing
 // update G_IJ -= R_KI^H R_KJ on the matrix cores.  The upper blocks live in
 // LDS (packed by block row); R and R^{-1} are written as full n x n
@@ -144,6 +148,7 @@ __device__ __forceinline__ int bidx(int I, int J, int nb) { return I * nb - (I *
 __global__ __launch_bounds__(CQ_CHOL_THREADS) void cq_chol_kernel(CholArgs a) {
   extern __shared__ double2 Bk[];   // packed upper blocks, then one scratch block Dv
   __shared__ double trace_s[CQ_CHOL_THREADS / 64];
+  __shared__ double invd[16];        // 1 / R_KK[c][c] of the current diagonal block
   const int64_t inst = blockIdx.x;
   const double2 *G = a.G + inst * a.ws;
   double2 *Rout = a.R + inst * a.ws;
@@ -185,69 +190,68 @@ __global__ __launch_bounds__(CQ_CHOL_THREADS) void cq_chol_kernel(CholArgs a) {
   for (int K = 0; K < nb; ++K) {
     double2 *D = Bk + bidx(K, K, nb) * 256;
     if (wave == 0) {
-      // factor D = R^H R in place: lane i holds row i
-      double2 r[16];
-      if (lane < 16) {
+      // factor D = R^H R in place on one wave: lane (g, c) = (lane / 16,
+      // lane % 16) holds column c of rows g, g + 4, g + 8, g + 12
+      const int c = lane & 15, g = lane >> 4;
+      double2 d[4];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) r[j] = D[lane * 16 + j];
-      }
+      for (int q = 0; q < 4; ++q) d[q] = D[(g + 4 * q) * 16 + c];
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
-        if (lane == k) {
-          double p = r[k].x;
-          if (!(p > 1e-300)) p = 1e-300;       // not positive definite: keep the values finite
-          const double y = rsqrt_nr(p);
+        const int qk = k >> 2, src = (k & 3) << 4;     // row k is held by lanes src .. src + 15
+        const double2 rkc = shfl_c(d[qk], src + c);     // D[k][c]
+        double p = __shfl(d[qk].x, src + k, 64);        // D[k][k], the same in every lane
+        if (!(p > 1e-300)) p = 1e-300;                  // not positive definite: keep the values finite
+        const double y = rsqrt_nr(p);
+        const double2 rk = c > k ? make_double2(rkc.x * y, rkc.y * y)
+                                 : (c == k ? make_double2(p * y, 0.0) : make_double2(0.0, 0.0));
 #pragma unroll
-          for (int j = 0; j < 16; ++j) {
-            if (j > k) r[j] = make_double2(r[j].x * y, r[j].y * y);
-            else if (j == k) r[j] = make_double2(p * y, 0.0);
-            else r[j] = make_double2(0.0, 0.0);
-            D[k * 16 + j] = r[j];
+        for (int q = 0; q < 4; ++q) {
+          const int i = g + 4 * q;
+          const double2 rki = shfl_c(rk, i);            // R[k][i] (column i, any row group)
+          if (i > k && c >= i) {                         // d -= conj(R[k][i]) R[k][c]
+            d[q].x -= rki.x * rk.x + rki.y * rk.y;
+            d[q].y -= rki.x * rk.y - rki.y * rk.x;
           }
+          if (i == k) d[q] = rk;
         }
-        __builtin_amdgcn_wave_barrier();
-        if (lane > k && lane < 16) {
-          double2 rk[16];
-#pragma unroll
-          for (int j = 0; j < 16; ++j) rk[j] = D[k * 16 + j];
-          double2 cik = make_double2(0.0, 0.0);
-#pragma unroll
-          for (int j = 0; j < 16; ++j)
-            if (j == lane) cik = rk[j];     // R[k][i]
-#pragma unroll
-          for (int j = 0; j < 16; ++j) {
-            if (j >= lane) {               // r[j] -= conj(R[k][i]) R[k][j]
-              r[j].x -= cik.x * rk[j].x + cik.y * rk[j].y;
-              r[j].y -= cik.x * rk[j].y - cik.y * rk[j].x;
-            }
-          }
-        }
-        __builtin_amdgcn_wave_barrier();
       }
-      // Dv = R_KK^{-1}: lane c solves R x = e_c from row c down (x in registers)
-      if (lane < 16) {
-        double2 x[16];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) x[q] = make_double2(0.0, 0.0);
+      for (int q = 0; q < 4; ++q) D[(g + 4 * q) * 16 + c] = d[q];
+      __builtin_amdgcn_wave_barrier();
+      if (g == 0) invd[c] = rcp_nr(D[c * 16 + c].x);
+      __builtin_amdgcn_wave_barrier();
+      // Dv = R^{-1}: lane (g, c) computes rows g + 4 q of column c, from row 15 up;
+      // the four row groups of a column add their partial sums in order
+      double2 x[4];
 #pragma unroll
-        for (int i = 15; i >= 0; --i) {
-          if (i <= lane) {
-            double sr = (i == lane) ? 1.0 : 0.0, si = 0.0;
+      for (int q = 0; q < 4; ++q) x[q] = make_double2(0.0, 0.0);
 #pragma unroll
-            for (int k = i + 1; k < 16; ++k) {
-              if (k <= lane) {
-                const double2 rv = D[i * 16 + k];
-                sr -= rv.x * x[k].x - rv.y * x[k].y;
-                si -= rv.x * x[k].y + rv.y * x[k].x;
-              }
-            }
-            const double inv = rcp_nr(D[i * 16 + i].x);
-            x[i] = make_double2(sr * inv, si * inv);
+      for (int i = 15; i >= 0; --i) {
+        double sr = 0.0, si = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int k = g + 4 * q;
+          if (k > i) {
+            const double2 rv = D[i * 16 + k];
+            sr += rv.x * x[q].x - rv.y * x[q].y;
+            si += rv.x * x[q].y + rv.y * x[q].x;
           }
         }
+        sr += __shfl_xor(sr, 16, 64);
+        si += __shfl_xor(si, 16, 64);
+        sr += __shfl_xor(sr, 32, 64);
+        si += __shfl_xor(si, 32, 64);
+        if ((i & 3) == g && i <= c) {
+          const double inv = invd[i];
+          const double br = (i == c ? 1.0 : 0.0) - sr, bi = -si;
 #pragma unroll
-        for (int i = 0; i < 16; ++i) Dv[i * 16 + lane] = x[i];
+          for (int q = 0; q < 4; ++q)
+            if (q == (i >> 2)) x[q] = make_double2(br * inv, bi * inv);
+        }
       }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Dv[(g + 4 * q) * 16 + c] = x[q];
     }
     __syncthreads();
     // block row: R_KJ = Dv^H G_KJ, one wave per block
