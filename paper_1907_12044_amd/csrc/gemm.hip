@@ -77,34 +77,53 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs g) {
       ci[i][j] = AccT{0, 0, 0, 0};
     }
 
-  for (int k0 = 0; k0 < K; k0 += BK) {
-    for (int e = tid; e < BM * BK; e += 256) {
+  // Register-staged tiles: the global loads of tile k0 + BK are issued
+  // before the MFMAs of tile k0, so their latency overlaps the arithmetic.
+  constexpr int NA = BM * BK / 256, NB = BK * BN / 256;
+  VA ra[NA];
+  VB rb[NB];
+  auto load_tiles = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int e = tid + 256 * q;
       int mm, kk;
       if (a_kfast) { kk = e % BK; mm = e / BK; } else { mm = e % BM; kk = e / BM; }
       const int gm = bm0 + mm, gk = k0 + kk;
-      TM re = 0, im = 0;
-      if (gm < M && gk < K) {
-        const VA v = A[(int64_t)gm * g.sam + (int64_t)gk * g.sak];
-        re = (TM)v.x;
-        im = sa * (TM)v.y;
-      }
-      As[0][kk][mm] = re;
-      As[1][kk][mm] = im;
+      ra[q].x = 0;
+      ra[q].y = 0;
+      if (gm < M && gk < K) ra[q] = A[(int64_t)gm * g.sam + (int64_t)gk * g.sak];
     }
-    for (int e = tid; e < BK * BN; e += 256) {
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int e = tid + 256 * q;
       int kk, nn;
       if (b_nfast) { nn = e % BN; kk = e / BN; } else { kk = e % BK; nn = e / BK; }
       const int gn = bn0 + nn, gk = k0 + kk;
-      TM re = 0, im = 0;
-      if (gn < N && gk < K) {
-        const VB v = B[(int64_t)gk * g.sbk + (int64_t)gn * g.sbn];
-        re = (TM)v.x;
-        im = sb * (TM)v.y;
-      }
-      Bs[0][kk][nn] = re;
-      Bs[1][kk][nn] = im;
+      rb[q].x = 0;
+      rb[q].y = 0;
+      if (gn < N && gk < K) rb[q] = B[(int64_t)gk * g.sbk + (int64_t)gn * g.sbn];
+    }
+  };
+  load_tiles(0);
+  for (int k0 = 0; k0 < K; k0 += BK) {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int e = tid + 256 * q;
+      int mm, kk;
+      if (a_kfast) { kk = e % BK; mm = e / BK; } else { mm = e % BM; kk = e / BM; }
+      As[0][kk][mm] = (TM)ra[q].x;
+      As[1][kk][mm] = sa * (TM)ra[q].y;
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int e = tid + 256 * q;
+      int kk, nn;
+      if (b_nfast) { nn = e % BN; kk = e / BN; } else { kk = e % BK; nn = e / BK; }
+      Bs[0][kk][nn] = (TM)rb[q].x;
+      Bs[1][kk][nn] = sb * (TM)rb[q].y;
     }
     __syncthreads();
+    if (k0 + BK < K) load_tiles(k0 + BK);
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       const int kr = ks + (lane >> 4);
