@@ -149,19 +149,21 @@ __device__ void exp_tridiag_e1_wave(const double *alpha, const double *beta, int
 // (in every thread) if the basis is final; the caller then returns.
 // The loads of close_step, issued by wave 0 (Gprev, Gw <= LZ_GRID) so that a
 // kernel can request them together with its other inputs.
+constexpr int SP_Q = LZ_GRID / 64;   // partials per lane of wave 0
 struct StepPre {
-  double nr[2], w2[2];
+  double nr[SP_Q], w2[SP_Q];
   double aw, sprev, tol;
   int keff;
 };
 __device__ __forceinline__ void close_step_load(const LzState *st, const LzPartials *pp, int Gprev,
                                                 int j, int Gw, StepPre &p) {
-  p.nr[0] = p.nr[1] = p.w2[0] = p.w2[1] = 0.0;
+#pragma unroll
+  for (int q = 0; q < SP_Q; ++q) p.nr[q] = p.w2[q] = 0.0;
   p.aw = p.sprev = p.tol = 0.0;
   p.keff = 0;
   if (threadIdx.x < 64) {
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
+    for (int q = 0; q < SP_Q; ++q) {
       const int b = threadIdx.x + 64 * q;
       if (b < Gprev) p.nr[q] = pp->nrm[b];
       if (j > 0 && b < Gw) p.w2[q] = pp->w2[b];
@@ -182,8 +184,14 @@ __device__ bool close_step_finish(LzState *st, const StepPre &p, int j, int Gw) 
   __shared__ double nrm_s, aw_s, tol_s;
   __shared__ double coefr[KMAX], coefi[KMAX];
   if (threadIdx.x < 64) {
-    double t = wave_sum(p.nr[0] + p.nr[1]);
-    double t2 = wave_sum(p.w2[0] + p.w2[1]);
+    double a = 0.0, b = 0.0;
+#pragma unroll
+    for (int q = 0; q < SP_Q; ++q) {
+      a += p.nr[q];
+      b += p.w2[q];
+    }
+    double t = wave_sum(a);
+    double t2 = wave_sum(b);
     if (threadIdx.x == 0) {
       nrm_s = t;
       aw_s = Gw > 0 ? sqrt(t2) * p.sprev : p.aw;
@@ -460,20 +468,26 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_update_kernel(LzState *st, LzPart
   double s2 = 0.0, sw = 0.0;
   for (int64_t base = b0; base < n; base += bstride) {
     const int64_t e = base + lane;
-    if (base != b0) LZ_UPDATE_LOAD(e);
-    double2 acc = yv[0];
+    // this pass's inputs, then the next pass's loads (issued before the arithmetic)
+    double2 ucur[NI], ycur[NP];
+#pragma unroll
+    for (int t = 0; t < NI; ++t) ucur[t] = uv[t];
+#pragma unroll
+    for (int t = 0; t < NP; ++t) ycur[t] = yv[t];
+    if (base + bstride < n) LZ_UPDATE_LOAD(base + bstride + lane);
+    double2 acc = ycur[0];
 #pragma unroll
     for (int t = 1; t < NP; ++t) {
-      acc.x += yv[t].x;
-      acc.y += yv[t].y;
+      acc.x += ycur[t].x;
+      acc.y += ycur[t].y;
     }
     double sr = 0.0, si = 0.0;
 #pragma unroll
     for (int t = 0; t < NI; ++t) {
       const int i = q + 4 * t;
       if (i <= j) {
-        sr += cr[i] * uv[t].x - ci[i] * uv[t].y;
-        si += cr[i] * uv[t].y + ci[i] * uv[t].x;
+        sr += cr[i] * ucur[t].x - ci[i] * ucur[t].y;
+        si += cr[i] * ucur[t].y + ci[i] * ucur[t].x;
       }
     }
     pw[q][lane] = acc;
@@ -1010,7 +1024,7 @@ __global__ __launch_bounds__(WT_THREADS) void wtable_kernel(const double2 *W, in
 // LZ_GRID groups (so the partial sums stay short).
 int grid_for(int64_t n) {
   int64_t g = (n + LZ_BLOCK - 1) / LZ_BLOCK;
-  if (g > LZ_GRID) g = LZ_GRID;
+  if (g > LZ_DOTS_GRID) g = LZ_DOTS_GRID;
   if (g < 1) g = 1;
   return (int)g;
 }
