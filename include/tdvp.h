@@ -222,7 +222,10 @@ tdvp_status tdvp_profile_read(tdvp_ctx *ctx, double *ms, int64_t *launches, doub
  * ensemble is one (nb, ...) array; TDVP_E_ARG otherwise.  The workspace
  * must hold nb times tdvp_workspace_bytes of one chain.  Observables go to
  * out_dev[r * (2 + n_el) + ...] per instance.  Results per instance are
- * identical to the single-chain calls. */
+ * the single-chain results: bit for bit where the fused Lanczos step splits
+ * a column the same way for nb chains as for one (always on the general
+ * path; on the fused path the split count falls as nb grows, and results
+ * then differ from a single run only in the order of one summation). */
 tdvp_status tdvp_ps_step_batched(tdvp_ctx *ctx, int nb, const tdvp_mps *mps, const tdvp_mpo *mpo,
                                  const tdvp_envs *envs, double dt, int nsteps, int kmax, double tol);
 tdvp_status tdvp_observe_batched(tdvp_ctx *ctx, int nb, const tdvp_mps *mps, const tdvp_mpo *mpo,

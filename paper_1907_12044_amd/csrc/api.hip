@@ -251,9 +251,11 @@ bool fused_args(const tdvp_ctx *c, const Layout &lay, const Op &op, const Bi &b,
   a.Gprev = lz_grid(a.n);
   a.Gw = lz_grid(a.n);
   a.wss = b.ws; a.sL = op.sL; a.sR = op.sR;
-  // P depends on the shape only (not on the instance count), so an instance
-  // of a batch computes exactly what the same chain computes alone
-  const int64_t cols = op.Mr;
+  // P is chosen so that all instances together cover the chip: one chain
+  // gets up to 8 parts per column, a large batch 1 (each part adds
+  // redundant reads of the basis columns, so a batch that already fills
+  // the chip runs faster unsplit)
+  const int64_t cols = (int64_t)op.Mr * b.R;
   int P = (int)std::min<int64_t>(HS_PMAX, std::max<int64_t>(1, (256 + cols - 1) / cols));
   P = std::min(P, std::max(1, op.Ml / 4));
   while (P > 1 && ((int64_t)P * op.Mr > LZ_PARTS || (size_t)P * a.n * 16 > lay.ybytes)) --P;

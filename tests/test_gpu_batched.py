@@ -23,8 +23,11 @@ def _instances(nb, M, n_modes=3, levels=4):
 @pytest.mark.parametrize("precision,graph,M", [(0, True, 12), (0, False, 12), (1, True, 12), (0, True, 48)],
                          ids=["fp64-graph", "fp64-eager", "fp32-graph", "fp64-graph-M48"])
 def test_batched_equals_single_runs(precision, graph, M):
-    """M = 12: register QR and fused Lanczos step; M = 48 (4 modes x 8
-    levels): also the Cholesky QR path (384 x 48 gauge shifts)."""
+    """M = 12: register QR and fused Lanczos step, split the same way for one
+    or three chains, so batched == single bit for bit.  M = 48 (4 modes x 8
+    levels): also the Cholesky QR path (384 x 48 gauge shifts); the fused
+    step splits a column over fewer work-groups for three chains than for
+    one, so the results agree to round-off (1e-12) instead of bitwise."""
     require_gpu()
     from paper_1907_12044_amd import tdvp
     nb = 3
@@ -32,17 +35,33 @@ def test_batched_equals_single_runs(precision, graph, M):
     tau = 2.0 * model.AU_PER_FS
     ens = tdvp.PsEnsemble(ps_, sites, raws, 0, precision, kmax=20, graph=graph)
     singles = [tdvp.PsRun(p, sites, raw, 0, precision, kmax=20, graph=graph) for p, raw in zip(ps_, raws)]
+    exact = M == 12
     for step in range(3):
         ens.step(tau, 1)
         ob = ens.observe_host()
         for r, run in enumerate(singles):
             run.step(tau, 1)
             o1 = run.observe_host()
-            assert np.array_equal(ob[r], o1), (step, r, ob[r], o1)
+            if exact:
+                assert np.array_equal(ob[r], o1), (step, r, ob[r], o1)
+            else:
+                assert np.abs(ob[r] - o1).max() < 1e-12, (step, r, ob[r], o1)
     for r, run in enumerate(singles):
         a = ens.mps_numpy(r)
         b = run.mps_numpy()
-        assert all(np.array_equal(x, y) for x, y in zip(a, b)), r
+        if exact:
+            assert all(np.array_equal(x, y) for x, y in zip(a, b)), r
+        else:
+            # the tensors carry gauge freedom in weakly occupied directions:
+            # compare the states through their overlap.  The Krylov solves
+            # are not converged in the high-energy directions of the bond
+            # bases (|z| |H| >> 1 there), so a change of summation order moves
+            # those small components by more than round-off: 1e-9 infidelity
+            # (the observables above agree to 1e-12)
+            ov = np.ones((1, 1), complex)
+            for x, y in zip(a, b):
+                ov = np.tensordot(np.tensordot(ov, x, axes=([1], [0])), y.conj(), axes=([0, 1], [0, 1]))
+            assert 1.0 - abs(ov[0, 0]) < 1e-9, r
 
 
 def test_batched_rejects_unstrided_layout():
