@@ -18,6 +18,8 @@
 // the running product of the R factors (the last ones write Q and R through
 // the caller's strides).
 // n <= 128.
+#include <utility>
+
 #include "common.h"
 #include "mfma.h"
 
@@ -108,22 +110,118 @@ __device__ __forceinline__ double2 shfl_c(double2 v, int src) {
   return make_double2(__shfl(v.x, src, 64), __shfl(v.y, src, 64));
 }
 
-// 16x16 complex blocks in LDS, row-major.  acc (re, im) += op(A) B on the
-// matrix cores of one wave; op(A) = A^H when adj.
+// 16x16 complex blocks in LDS: element (i, j) at i * 16 + (j ^ i), so that
+// sixteen lanes reading a row or a column touch sixteen different banks.
+__device__ __forceinline__ int bo(int i, int j) { return (i << 4) | (j ^ i); }
+
+// acc (re, im) += op(A) B on the matrix cores of one wave; op(A) = A^H when adj.
 __device__ __forceinline__ void blk_mma(const double2 *A, bool adj, const double2 *B, f64x4_t &cr,
                                         f64x4_t &ci) {
   const int lane = threadIdx.x & 63, i = lane & 15, kk = lane >> 4;
 #pragma unroll
   for (int k0 = 0; k0 < 16; k0 += 4) {
     const int k = k0 + kk;
-    double2 av = adj ? A[k * 16 + i] : A[i * 16 + k];
+    double2 av = adj ? A[bo(k, i)] : A[bo(i, k)];
     if (adj) av.y = -av.y;
-    const double2 bv = B[k * 16 + i];
+    const double2 bv = B[bo(k, i)];
     cr = Mf<double>::mfma(av.x, bv.x, cr);
     cr = Mf<double>::mfma(-av.y, bv.y, cr);
     ci = Mf<double>::mfma(av.x, bv.y, ci);
     ci = Mf<double>::mfma(av.y, bv.x, ci);
   }
+}
+
+// Cross-lane moves of one wave for the 16x16 diagonal block held as lane
+// (g, c) = (lane / 16, lane % 16) <- rows g + 4 q of column c.
+// value of lane l (l uniform), as a wave-uniform scalar
+__device__ __forceinline__ double rd_lane(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readlane((int)b, l);
+  const unsigned hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+// lane (g, c) <- lane (g, K): DPP row_newbcast
+template <int K> __device__ __forceinline__ double nbc(double v) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x150 + K, 0xF, 0xF, false);
+  const unsigned hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x150 + K, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+template <int K> __device__ __forceinline__ double2 nbc(double2 v) { return make_double2(nbc<K>(v.x), nbc<K>(v.y)); }
+// lane (g, c) <- lane (gk, c): the 32-lane swap pairs rows (0, 1) with
+// (2, 3), the 16-lane swap then row 0 with 1 and 2 with 3
+__device__ __forceinline__ unsigned grp32(unsigned v, int gk) {
+  const auto s = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+  const unsigned a = gk < 2 ? s[0] : s[1];
+  const auto t = __builtin_amdgcn_permlane16_swap(a, a, false, false);
+  return (gk & 1) ? t[1] : t[0];
+}
+__device__ __forceinline__ double grp(double v, int gk) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = grp32((unsigned)b, gk), hi = grp32((unsigned)(b >> 32), gk);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ double2 grp(double2 v, int gk) { return make_double2(grp(v.x, gk), grp(v.y, gk)); }
+
+// Step k of the one-wave factorisation of a 16x16 diagonal block (lane
+// (g, c) holds column c of rows g + 4 q of the full Hermitian block): pivot
+// p = D[k][k]; row k of R is D[k][c] / sqrt(p) (c > k), sqrt(p) (c == k),
+// 0 (c < k); Schur complement D[i][c] -= D[i][k] D[k][c] / p for i, c > k.
+// yk[k] = 1 / R[k][k].  k is a template argument so every lane move is an
+// immediate-controlled DPP / swap and the registers are indexed statically.
+template <int k> __device__ __forceinline__ void chol_step(double2 (&d)[4], double (&yk)[16], int g, int c) {
+  constexpr int qk = k >> 2, gk = k & 3;
+  double p = rd_lane(d[qk].x, 16 * gk + k);
+  if (!(p > 1e-300)) p = 1e-300;                    // not positive definite: keep the values finite
+  const double y = rsqrt_nr(p), ip = y * y;
+  yk[k] = y;
+  const double2 dkc = grp(d[qk], gk);               // D[k][c] in every row group
+  const double2 rk = c > k ? make_double2(dkc.x * y, dkc.y * y)
+                           : (c == k ? make_double2(p * y, 0.0) : make_double2(0.0, 0.0));
+  const double2 t = make_double2(dkc.x * ip, dkc.y * ip);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (4 * q + 3 > k) {                            // some row g + 4 q is below row k
+      const int i = g + 4 * q;
+      const double2 dik = nbc<k>(d[q]);             // D[i][k]
+      if (i > k && c > k) {
+        d[q].x -= dik.x * t.x - dik.y * t.y;
+        d[q].y -= dik.x * t.y + dik.y * t.x;
+      }
+    }
+    if (q == qk && g == gk) d[q] = rk;
+  }
+}
+// Step k of X = R^{-1} by back substitution on B = I (x holds B, rows g + 4 q
+// of column c; r holds R): X[k][c] = B[k][c] / R[k][k], then
+// B[i][c] -= R[i][k] X[k][c] for the rows i < k.
+template <int k> __device__ __forceinline__ void inv_step(double2 (&x)[4], const double2 (&r)[4],
+                                                          const double (&yk)[16], int g) {
+  constexpr int qk = k >> 2, gk = k & 3;
+  const double2 bk = grp(x[qk], gk);
+  const double2 xk = make_double2(bk.x * yk[k], bk.y * yk[k]);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (4 * q < k) {                                // some row g + 4 q is above row k
+      const int i = g + 4 * q;
+      const double2 rik = nbc<k>(r[q]);             // R[i][k]
+      if (i < k) {
+        x[q].x -= rik.x * xk.x - rik.y * xk.y;
+        x[q].y -= rik.x * xk.y + rik.y * xk.x;
+      }
+    }
+    if (q == qk && g == gk) x[q] = xk;
+  }
+}
+template <int... ks>
+__device__ __forceinline__ void chol_block(double2 (&d)[4], double (&yk)[16], int g, int c,
+                                           std::integer_sequence<int, ks...>) {
+  (chol_step<ks>(d, yk, g, c), ...);
+}
+template <int... ks>
+__device__ __forceinline__ void inv_block(double2 (&x)[4], const double2 (&r)[4], const double (&yk)[16], int g,
+                                          std::integer_sequence<int, ks...>) {
+  (inv_step<15 - ks>(x, r, yk, g), ...);            // k = 15 down to 0
 }
 
 // One work-group per instance: blocked right-looking Cholesky G = R^H R in
@@ -148,7 +246,6 @@ __device__ __forceinline__ int bidx(int I, int J, int nb) { return I * nb - (I *
 __global__ __launch_bounds__(CQ_CHOL_THREADS) void cq_chol_kernel(CholArgs a) {
   extern __shared__ double2 Bk[];   // packed upper blocks, then one scratch block Dv
   __shared__ double trace_s[CQ_CHOL_THREADS / 64];
-  __shared__ double invd[16];        // 1 / R_KK[c][c] of the current diagonal block
   const int64_t inst = blockIdx.x;
   const double2 *G = a.G + inst * a.ws;
   double2 *Rout = a.R + inst * a.ws;
@@ -184,74 +281,34 @@ __global__ __launch_bounds__(CQ_CHOL_THREADS) void cq_chol_kernel(CholArgs a) {
     } else if (i == j) {
       v = make_double2(1.0, 0.0);
     }
-    Bk[e] = v;
+    Bk[(b << 8) + bo(w >> 4, w & 15)] = v;
   }
   __syncthreads();
   for (int K = 0; K < nb; ++K) {
     double2 *D = Bk + bidx(K, K, nb) * 256;
     if (wave == 0) {
-      // factor D = R^H R in place on one wave: lane (g, c) = (lane / 16,
-      // lane % 16) holds column c of rows g, g + 4, g + 8, g + 12
+      // factor D = R^H R on one wave in registers (chol_step), the lower
+      // half of the block mirrored from the upper one
       const int c = lane & 15, g = lane >> 4;
       double2 d[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) d[q] = D[(g + 4 * q) * 16 + c];
-#pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        const int qk = k >> 2, src = (k & 3) << 4;     // row k is held by lanes src .. src + 15
-        const double2 rkc = shfl_c(d[qk], src + c);     // D[k][c]
-        double p = __shfl(d[qk].x, src + k, 64);        // D[k][k], the same in every lane
-        if (!(p > 1e-300)) p = 1e-300;                  // not positive definite: keep the values finite
-        const double y = rsqrt_nr(p);
-        const double2 rk = c > k ? make_double2(rkc.x * y, rkc.y * y)
-                                 : (c == k ? make_double2(p * y, 0.0) : make_double2(0.0, 0.0));
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int i = g + 4 * q;
-          const double2 rki = shfl_c(rk, i);            // R[k][i] (column i, any row group)
-          if (i > k && c >= i) {                         // d -= conj(R[k][i]) R[k][c]
-            d[q].x -= rki.x * rk.x + rki.y * rk.y;
-            d[q].y -= rki.x * rk.y - rki.y * rk.x;
-          }
-          if (i == k) d[q] = rk;
-        }
+      for (int q = 0; q < 4; ++q) {
+        const int i = g + 4 * q;
+        const double2 v = c >= i ? D[bo(i, c)] : D[bo(c, i)];
+        d[q] = c >= i ? v : make_double2(v.x, -v.y);
       }
+      double yk[16];
+      chol_block(d, yk, g, c, std::make_integer_sequence<int, 16>{});
+      // (d now holds R: rows g + 4 q, zeros below the diagonal)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) D[(g + 4 * q) * 16 + c] = d[q];
-      __builtin_amdgcn_wave_barrier();
-      if (g == 0) invd[c] = rcp_nr(D[c * 16 + c].x);
-      __builtin_amdgcn_wave_barrier();
-      // Dv = R^{-1}: lane (g, c) computes rows g + 4 q of column c, from row 15 up;
-      // the four row groups of a column add their partial sums in order
+      for (int q = 0; q < 4; ++q) D[bo(g + 4 * q, c)] = d[q];
+      // Dv = R^{-1} (inv_step)
       double2 x[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) x[q] = make_double2(0.0, 0.0);
+      for (int q = 0; q < 4; ++q) x[q] = make_double2(g + 4 * q == c ? 1.0 : 0.0, 0.0);
+      inv_block(x, d, yk, g, std::make_integer_sequence<int, 16>{});
 #pragma unroll
-      for (int i = 15; i >= 0; --i) {
-        double sr = 0.0, si = 0.0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int k = g + 4 * q;
-          if (k > i) {
-            const double2 rv = D[i * 16 + k];
-            sr += rv.x * x[q].x - rv.y * x[q].y;
-            si += rv.x * x[q].y + rv.y * x[q].x;
-          }
-        }
-        sr += __shfl_xor(sr, 16, 64);
-        si += __shfl_xor(si, 16, 64);
-        sr += __shfl_xor(sr, 32, 64);
-        si += __shfl_xor(si, 32, 64);
-        if ((i & 3) == g && i <= c) {
-          const double inv = invd[i];
-          const double br = (i == c ? 1.0 : 0.0) - sr, bi = -si;
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-            if (q == (i >> 2)) x[q] = make_double2(br * inv, bi * inv);
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) Dv[(g + 4 * q) * 16 + c] = x[q];
+      for (int q = 0; q < 4; ++q) Dv[bo(g + 4 * q, c)] = x[q];
     }
     __syncthreads();
     // block row: R_KJ = Dv^H G_KJ, one wave per block
@@ -262,7 +319,7 @@ __global__ __launch_bounds__(CQ_CHOL_THREADS) void cq_chol_kernel(CholArgs a) {
       __builtin_amdgcn_wave_barrier();
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr)
-        Bj[Mf<double>::row(lane, rr) * 16 + (lane & 15)] = make_double2(cr[rr], ci[rr]);
+        Bj[bo(Mf<double>::row(lane, rr), lane & 15)] = make_double2(cr[rr], ci[rr]);
     }
     __syncthreads();
     // trailing update G_IJ -= R_KI^H R_KJ, K < I <= J
@@ -278,7 +335,7 @@ __global__ __launch_bounds__(CQ_CHOL_THREADS) void cq_chol_kernel(CholArgs a) {
         blk_mma(Bk + bidx(K, I, nb) * 256, true, Bk + bidx(K, J, nb) * 256, cr, ci);
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
-          double2 &c = Cij[Mf<double>::row(lane, rr) * 16 + (lane & 15)];
+          double2 &c = Cij[bo(Mf<double>::row(lane, rr), lane & 15)];
           c.x -= cr[rr];
           c.y -= ci[rr];
         }
@@ -287,7 +344,7 @@ __global__ __launch_bounds__(CQ_CHOL_THREADS) void cq_chol_kernel(CholArgs a) {
     // keep the diagonal block's inverse for the back substitution
     for (int e = tid; e < 256; e += CQ_CHOL_THREADS) {
       const int i = 16 * K + (e >> 4), j = 16 * K + (e & 15);
-      if (i < n && j < n) Rinv[(int64_t)i * n + j] = Dv[e];
+      if (i < n && j < n) Rinv[(int64_t)i * n + j] = Dv[bo(e >> 4, e & 15)];
     }
     __syncthreads();
   }
@@ -295,7 +352,7 @@ __global__ __launch_bounds__(CQ_CHOL_THREADS) void cq_chol_kernel(CholArgs a) {
   for (int e = tid; e < n * n; e += CQ_CHOL_THREADS) {
     const int i = e / n, j = e - i * n;
     double2 v = make_double2(0.0, 0.0);
-    if (j >= i) v = Bk[bidx(i >> 4, j >> 4, nb) * 256 + (i & 15) * 16 + (j & 15)];
+    if (j >= i) v = Bk[bidx(i >> 4, j >> 4, nb) * 256 + bo(i & 15, j & 15)];
     Rout[e] = v;
   }
   __syncthreads();
@@ -305,7 +362,7 @@ __global__ __launch_bounds__(CQ_CHOL_THREADS) void cq_chol_kernel(CholArgs a) {
   for (int I = nb - 1; I >= 0; --I) {
     for (int e = tid; e < 256; e += CQ_CHOL_THREADS) {
       const int i = 16 * I + (e >> 4), j = 16 * I + (e & 15);
-      Dv[e] = (i < n && j < n) ? Rinv[(int64_t)i * n + j] : make_double2(i == j ? 1.0 : 0.0, 0.0);
+      Dv[bo(e >> 4, e & 15)] = (i < n && j < n) ? Rinv[(int64_t)i * n + j] : make_double2(i == j ? 1.0 : 0.0, 0.0);
     }
     __syncthreads();
     // S_J = sum_K R_IK X_KJ (one wave per J), then X_IJ = -X_II S_J
@@ -319,14 +376,14 @@ __global__ __launch_bounds__(CQ_CHOL_THREADS) void cq_chol_kernel(CholArgs a) {
       double2 *Xj = Bk + bidx(I, J, nb) * 256;
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr)
-        Xj[Mf<double>::row(lane, rr) * 16 + (lane & 15)] = make_double2(sr[rr], si[rr]);
+        Xj[bo(Mf<double>::row(lane, rr), lane & 15)] = make_double2(sr[rr], si[rr]);
       __builtin_amdgcn_wave_barrier();
       f64x4_t cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
       blk_mma(Dv, false, Xj, cr, ci);
       __builtin_amdgcn_wave_barrier();
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr)
-        Xj[Mf<double>::row(lane, rr) * 16 + (lane & 15)] = make_double2(-cr[rr], -ci[rr]);
+        Xj[bo(Mf<double>::row(lane, rr), lane & 15)] = make_double2(-cr[rr], -ci[rr]);
     }
     for (int e = tid; e < 256; e += CQ_CHOL_THREADS) Bk[bidx(I, I, nb) * 256 + e] = Dv[e];
     __syncthreads();
@@ -334,7 +391,7 @@ __global__ __launch_bounds__(CQ_CHOL_THREADS) void cq_chol_kernel(CholArgs a) {
   for (int e = tid; e < n * n; e += CQ_CHOL_THREADS) {
     const int i = e / n, j = e - i * n;
     double2 v = make_double2(0.0, 0.0);
-    if (j >= i) v = Bk[bidx(i >> 4, j >> 4, nb) * 256 + (i & 15) * 16 + (j & 15)];
+    if (j >= i) v = Bk[bidx(i >> 4, j >> 4, nb) * 256 + bo(i & 15, j & 15)];
     Rinv[e] = v;
   }
 }
