@@ -163,75 +163,73 @@ __device__ __forceinline__ double grp(double v, int gk) {
 }
 __device__ __forceinline__ double2 grp(double2 v, int gk) { return make_double2(grp(v.x, gk), grp(v.y, gk)); }
 
-// Step k of the one-wave factorisation of a 16x16 diagonal block (lane
-// (g, c) holds column c of rows g + 4 q of the full Hermitian block): pivot
-// p = D[k][k]; row k of R is D[k][c] / sqrt(p) (c > k), sqrt(p) (c == k),
-// 0 (c < k); Schur complement D[i][c] -= D[i][k] D[k][c] / p for i, c > k.
-// yk[k] = 1 / R[k][k].  k is a template argument so every lane move is an
-// immediate-controlled DPP / swap and the registers are indexed statically.
-template <int k> __device__ __forceinline__ void chol_step(double2 (&d)[4], double (&yk)[16], int g, int c) {
+// Step k of the one-wave factorisation of a 16x16 diagonal block.  Lane
+// (g, c) holds column c of rows g + 4 q: d the Hermitian block being
+// reduced, r the rows of R found so far.  Pivot p = D[k][k]; row k of R is
+// D[k][c] / sqrt(p) (c > k), sqrt(p) (c == k), 0 (c < k); Schur complement
+// D[i][c] -= D[i][k] D[k][c] / p.  The update runs unmasked: rows and
+// columns <= k of d are never read again.  yk[k] = 1 / R[k][k].  k is a
+// template argument so every lane move is an immediate-controlled DPP /
+// swap and all registers are indexed statically.
+template <int k> __device__ __forceinline__ void chol_step(double2 (&d)[4], double2 (&r)[4], double (&yk)[16],
+                                                           int g, int c) {
   constexpr int qk = k >> 2, gk = k & 3;
   double p = rd_lane(d[qk].x, 16 * gk + k);
   if (!(p > 1e-300)) p = 1e-300;                    // not positive definite: keep the values finite
   const double y = rsqrt_nr(p), ip = y * y;
   yk[k] = y;
   const double2 dkc = grp(d[qk], gk);               // D[k][c] in every row group
-  const double2 rk = c > k ? make_double2(dkc.x * y, dkc.y * y)
-                           : (c == k ? make_double2(p * y, 0.0) : make_double2(0.0, 0.0));
+  if (g == gk)
+    r[qk] = c > k ? make_double2(dkc.x * y, dkc.y * y)
+                  : (c == k ? make_double2(p * y, 0.0) : make_double2(0.0, 0.0));
   const double2 t = make_double2(dkc.x * ip, dkc.y * ip);
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     if (4 * q + 3 > k) {                            // some row g + 4 q is below row k
-      const int i = g + 4 * q;
-      const double2 dik = nbc<k>(d[q]);             // D[i][k]
-      if (i > k && c > k) {
-        d[q].x -= dik.x * t.x - dik.y * t.y;
-        d[q].y -= dik.x * t.y + dik.y * t.x;
-      }
+      const double2 dik = nbc<k>(d[q]);             // D[i][k], i = g + 4 q
+      d[q].x -= dik.x * t.x - dik.y * t.y;
+      d[q].y -= dik.x * t.y + dik.y * t.x;
     }
-    if (q == qk && g == gk) d[q] = rk;
   }
 }
-// Step k of X = R^{-1} by back substitution on B = I (x holds B, rows g + 4 q
-// of column c; r holds R): X[k][c] = B[k][c] / R[k][k], then
-// B[i][c] -= R[i][k] X[k][c] for the rows i < k.
-template <int k> __device__ __forceinline__ void inv_step(double2 (&x)[4], const double2 (&r)[4],
+// Step k of X = R^{-1} by back substitution on B = I (b holds B, rows
+// g + 4 q of column c; r holds R, zero below the diagonal):
+// X[k][c] = B[k][c] / R[k][k] goes to x, then B[i][c] -= R[i][k] X[k][c]
+// (a no-op for the rows i > k, where R[i][k] = 0).
+template <int k> __device__ __forceinline__ void inv_step(double2 (&b)[4], double2 (&x)[4], const double2 (&r)[4],
                                                           const double (&yk)[16], int g) {
   constexpr int qk = k >> 2, gk = k & 3;
-  const double2 bk = grp(x[qk], gk);
+  const double2 bk = grp(b[qk], gk);
   const double2 xk = make_double2(bk.x * yk[k], bk.y * yk[k]);
+  if (g == gk) x[qk] = xk;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     if (4 * q < k) {                                // some row g + 4 q is above row k
-      const int i = g + 4 * q;
       const double2 rik = nbc<k>(r[q]);             // R[i][k]
-      if (i < k) {
-        x[q].x -= rik.x * xk.x - rik.y * xk.y;
-        x[q].y -= rik.x * xk.y + rik.y * xk.x;
-      }
+      b[q].x -= rik.x * xk.x - rik.y * xk.y;
+      b[q].y -= rik.x * xk.y + rik.y * xk.x;
     }
-    if (q == qk && g == gk) x[q] = xk;
   }
 }
 template <int... ks>
-__device__ __forceinline__ void chol_block(double2 (&d)[4], double (&yk)[16], int g, int c,
+__device__ __forceinline__ void chol_block(double2 (&d)[4], double2 (&r)[4], double (&yk)[16], int g, int c,
                                            std::integer_sequence<int, ks...>) {
-  (chol_step<ks>(d, yk, g, c), ...);
+  (chol_step<ks>(d, r, yk, g, c), ...);
 }
 template <int... ks>
-__device__ __forceinline__ void inv_block(double2 (&x)[4], const double2 (&r)[4], const double (&yk)[16], int g,
-                                          std::integer_sequence<int, ks...>) {
-  (inv_step<15 - ks>(x, r, yk, g), ...);            // k = 15 down to 0
+__device__ __forceinline__ void inv_block(double2 (&b)[4], double2 (&x)[4], const double2 (&r)[4],
+                                          const double (&yk)[16], int g, std::integer_sequence<int, ks...>) {
+  (inv_step<15 - ks>(b, x, r, yk, g), ...);         // k = 15 down to 0
 }
 
 // One work-group per instance: blocked right-looking Cholesky G = R^H R in
 // 16x16 blocks (n padded to a multiple of 16 with an identity block), then
 // R^{-1} by block back substitution.  Per block column K: wave 0 factors
-// the diagonal block and inverts it (4 lanes per column, shuffles);
-// the waves form the block row R_KJ = R_KK^{-H} G_KJ and the trailing
-// update G_IJ -= R_KI^H R_KJ on the matrix cores.  The upper blocks live in
-// LDS (packed by block row); R and R^{-1} are written as full n x n
-// matrices (zeros below the diagonal).
+// the diagonal block in registers, writes R_KK to the output and keeps
+// X_KK = R_KK^{-1} in the block's place; the waves form the block row
+// R_KJ = X_KK^H G_KJ and the trailing update G_IJ -= R_KI^H R_KJ on the
+// matrix cores.  The upper blocks live in LDS (packed by block row); R and
+// R^{-1} are written as full n x n matrices (zeros below the diagonal).
 struct CholArgs {
   const double2 *G; double2 *R; double2 *Rinv;
   int m, n, shift;
@@ -240,82 +238,78 @@ struct CholArgs {
 
 constexpr int CQ_NB = CQ_NMAX / 16;   // block rows / columns at most
 constexpr int CQ_CHOL_THREADS = 512;  // 8 waves (>= CQ_NB - 1 for the back substitution)
+constexpr int CQ_RSTEP = CQ_CHOL_THREADS / CQ_NMAX;   // rows per pass of the row-major copies
+constexpr int CQ_U = 8;                                // copies in flight per thread
 
 __device__ __forceinline__ int bidx(int I, int J, int nb) { return I * nb - (I * (I - 1)) / 2 + (J - I); }
 
 __global__ __launch_bounds__(CQ_CHOL_THREADS) void cq_chol_kernel(CholArgs a) {
-  extern __shared__ double2 Bk[];   // packed upper blocks, then one scratch block Dv
-  __shared__ double trace_s[CQ_CHOL_THREADS / 64];
+  extern __shared__ double2 Bk[];   // packed upper blocks
   const int64_t inst = blockIdx.x;
   const double2 *G = a.G + inst * a.ws;
   double2 *Rout = a.R + inst * a.ws;
   double2 *Rinv = a.Rinv + inst * a.ws;
   const int n = a.n, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int nb = (n + 15) / 16;
-  const int nblk = nb * (nb + 1) / 2;
-  double2 *Dv = Bk + nblk * 256;     // inverse of the current diagonal block
+  const int nb = (n + 15) / 16, np = 16 * nb;
+  // row-major copies: thread (i0, j) takes column j, rows i0 + CQ_RSTEP u
+  const int cj = tid & (CQ_NMAX - 1), ci0 = tid / CQ_NMAX;
+  // load the upper blocks (identity padding beyond n)
+  for (int s0 = 0; s0 < np; s0 += CQ_U * CQ_RSTEP) {
+    double2 v[CQ_U];
+#pragma unroll
+    for (int u = 0; u < CQ_U; ++u) {
+      const int i = s0 + ci0 + CQ_RSTEP * u;
+      v[u] = make_double2(0.0, 0.0);
+      if (i < n && cj < n && (cj >> 4) >= (i >> 4)) v[u] = G[(int64_t)i * n + cj];
+      else if (i == cj) v[u] = make_double2(1.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < CQ_U; ++u) {
+      const int i = s0 + ci0 + CQ_RSTEP * u;
+      if (i < np && cj < np && (cj >> 4) >= (i >> 4)) Bk[bidx(i >> 4, cj >> 4, nb) * 256 + bo(i & 15, cj & 15)] = v[u];
+    }
+  }
+  __syncthreads();
   // diagonal shift from the trace (first pass)
-  double shift = 0.0;
-  if (a.shift) {
+  if (a.shift && wave == 0) {
     double tr = 0.0;
-    for (int i = tid; i < n; i += CQ_CHOL_THREADS) tr += G[(int64_t)i * n + i].x;
+    for (int i = lane; i < n; i += 64) tr += Bk[bidx(i >> 4, i >> 4, nb) * 256 + bo(i & 15, i & 15)].x;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) tr += __shfl_xor(tr, o, 64);
-    if (lane == 0) trace_s[wave] = tr;
-    __syncthreads();
-    tr = 0.0;
-    for (int w = 0; w < CQ_CHOL_THREADS / 64; ++w) tr += trace_s[w];
-    shift = 11.0 * ((double)a.m * n + (double)n * (n + 1)) * 1.1102230246251565e-16 * tr;
-  }
-  // load the upper blocks (identity padding beyond n)
-  for (int e = tid; e < nblk * 256; e += CQ_CHOL_THREADS) {
-    const int b = e >> 8, w = e & 255;
-    int I = 0, t = b;
-    while (t >= nb - I) { t -= nb - I; ++I; }
-    const int J = I + t;
-    const int i = 16 * I + (w >> 4), j = 16 * J + (w & 15);
-    double2 v = make_double2(0.0, 0.0);
-    if (i < n && j < n) {
-      if (j >= i) v = G[(int64_t)i * n + j];
-      if (i == j) v = make_double2(v.x + shift, 0.0);
-    } else if (i == j) {
-      v = make_double2(1.0, 0.0);
-    }
-    Bk[(b << 8) + bo(w >> 4, w & 15)] = v;
+    const double shift = 11.0 * ((double)a.m * n + (double)n * (n + 1)) * 1.1102230246251565e-16 * tr;
+    for (int i = lane; i < n; i += 64) Bk[bidx(i >> 4, i >> 4, nb) * 256 + bo(i & 15, i & 15)].x += shift;
   }
   __syncthreads();
   for (int K = 0; K < nb; ++K) {
-    double2 *D = Bk + bidx(K, K, nb) * 256;
+    double2 *D = Bk + bidx(K, K, nb) * 256;     // G_KK, then X_KK
     if (wave == 0) {
-      // factor D = R^H R on one wave in registers (chol_step), the lower
-      // half of the block mirrored from the upper one
       const int c = lane & 15, g = lane >> 4;
-      double2 d[4];
+      double2 d[4], r[4], b[4], x[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < 4; ++q) {             // the full Hermitian block from its upper half
         const int i = g + 4 * q;
         const double2 v = c >= i ? D[bo(i, c)] : D[bo(c, i)];
         d[q] = c >= i ? v : make_double2(v.x, -v.y);
+        r[q] = x[q] = make_double2(0.0, 0.0);
+        b[q] = make_double2(i == c ? 1.0 : 0.0, 0.0);
       }
       double yk[16];
-      chol_block(d, yk, g, c, std::make_integer_sequence<int, 16>{});
-      // (d now holds R: rows g + 4 q, zeros below the diagonal)
+      chol_block(d, r, yk, g, c, std::make_integer_sequence<int, 16>{});
 #pragma unroll
-      for (int q = 0; q < 4; ++q) D[bo(g + 4 * q, c)] = d[q];
-      // Dv = R^{-1} (inv_step)
-      double2 x[4];
+      for (int q = 0; q < 4; ++q) {
+        const int i = 16 * K + g + 4 * q, jj = 16 * K + c;
+        if (i < n && jj < n) Rout[(int64_t)i * n + jj] = r[q];
+      }
+      inv_block(b, x, r, yk, g, std::make_integer_sequence<int, 16>{});
 #pragma unroll
-      for (int q = 0; q < 4; ++q) x[q] = make_double2(g + 4 * q == c ? 1.0 : 0.0, 0.0);
-      inv_block(x, d, yk, g, std::make_integer_sequence<int, 16>{});
-#pragma unroll
-      for (int q = 0; q < 4; ++q) Dv[bo(g + 4 * q, c)] = x[q];
+      for (int q = 0; q < 4; ++q) D[bo(g + 4 * q, c)] = x[q];
     }
     __syncthreads();
-    // block row: R_KJ = Dv^H G_KJ, one wave per block
+    // block row: R_KJ = X_KK^H G_KJ, one wave per block
     for (int J = K + 1 + wave; J < nb; J += CQ_CHOL_THREADS / 64) {
       double2 *Bj = Bk + bidx(K, J, nb) * 256;
       f64x4_t cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
-      blk_mma(Dv, true, Bj, cr, ci);
+      blk_mma(D, true, Bj, cr, ci);
       __builtin_amdgcn_wave_barrier();
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr)
@@ -341,30 +335,28 @@ __global__ __launch_bounds__(CQ_CHOL_THREADS) void cq_chol_kernel(CholArgs a) {
         }
       }
     }
-    // keep the diagonal block's inverse for the back substitution
-    for (int e = tid; e < 256; e += CQ_CHOL_THREADS) {
-      const int i = 16 * K + (e >> 4), j = 16 * K + (e & 15);
-      if (i < n && j < n) Rinv[(int64_t)i * n + j] = Dv[bo(e >> 4, e & 15)];
-    }
     __syncthreads();
   }
-  // R, full
-  for (int e = tid; e < n * n; e += CQ_CHOL_THREADS) {
-    const int i = e / n, j = e - i * n;
-    double2 v = make_double2(0.0, 0.0);
-    if (j >= i) v = Bk[bidx(i >> 4, j >> 4, nb) * 256 + bo(i & 15, j & 15)];
-    Rout[e] = v;
+  // R: the blocks above the diagonal blocks (written above) and zeros below
+  for (int s0 = 0; s0 < n; s0 += CQ_U * CQ_RSTEP) {
+    double2 v[CQ_U];
+#pragma unroll
+    for (int u = 0; u < CQ_U; ++u) {
+      const int i = s0 + ci0 + CQ_RSTEP * u;
+      v[u] = make_double2(0.0, 0.0);
+      if (i < n && cj < n && (cj >> 4) > (i >> 4)) v[u] = Bk[bidx(i >> 4, cj >> 4, nb) * 256 + bo(i & 15, cj & 15)];
+    }
+#pragma unroll
+    for (int u = 0; u < CQ_U; ++u) {
+      const int i = s0 + ci0 + CQ_RSTEP * u;
+      if (i < n && cj < n && (cj >> 4) != (i >> 4)) Rout[(int64_t)i * n + cj] = v[u];
+    }
   }
   __syncthreads();
-  // R^{-1} by block rows from the bottom: X_II = R_II^{-1} (kept above),
-  // X_IJ = -X_II sum_{K=I+1..J} R_IK X_KJ; block row I of R is overwritten by
-  // X once formed (rows below I already hold X)
-  for (int I = nb - 1; I >= 0; --I) {
-    for (int e = tid; e < 256; e += CQ_CHOL_THREADS) {
-      const int i = 16 * I + (e >> 4), j = 16 * I + (e & 15);
-      Dv[bo(e >> 4, e & 15)] = (i < n && j < n) ? Rinv[(int64_t)i * n + j] : make_double2(i == j ? 1.0 : 0.0, 0.0);
-    }
-    __syncthreads();
+  // R^{-1} by block rows from the bottom: X_IJ = -X_II sum_{K=I+1..J} R_IK X_KJ;
+  // block row I of R is overwritten by X once formed (rows below I already
+  // hold X, the diagonal blocks hold X_II since the factorisation)
+  for (int I = nb - 2; I >= 0; --I) {
     // S_J = sum_K R_IK X_KJ (one wave per J), then X_IJ = -X_II S_J
     const int J = I + 1 + wave;         // nb - 1 <= 7 < 8 waves
     f64x4_t sr = {0, 0, 0, 0}, si = {0, 0, 0, 0};
@@ -379,20 +371,27 @@ __global__ __launch_bounds__(CQ_CHOL_THREADS) void cq_chol_kernel(CholArgs a) {
         Xj[bo(Mf<double>::row(lane, rr), lane & 15)] = make_double2(sr[rr], si[rr]);
       __builtin_amdgcn_wave_barrier();
       f64x4_t cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
-      blk_mma(Dv, false, Xj, cr, ci);
+      blk_mma(Bk + bidx(I, I, nb) * 256, false, Xj, cr, ci);
       __builtin_amdgcn_wave_barrier();
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr)
         Xj[bo(Mf<double>::row(lane, rr), lane & 15)] = make_double2(-cr[rr], -ci[rr]);
     }
-    for (int e = tid; e < 256; e += CQ_CHOL_THREADS) Bk[bidx(I, I, nb) * 256 + e] = Dv[e];
     __syncthreads();
   }
-  for (int e = tid; e < n * n; e += CQ_CHOL_THREADS) {
-    const int i = e / n, j = e - i * n;
-    double2 v = make_double2(0.0, 0.0);
-    if (j >= i) v = Bk[bidx(i >> 4, j >> 4, nb) * 256 + bo(i & 15, j & 15)];
-    Rinv[e] = v;
+  for (int s0 = 0; s0 < n; s0 += CQ_U * CQ_RSTEP) {
+    double2 v[CQ_U];
+#pragma unroll
+    for (int u = 0; u < CQ_U; ++u) {
+      const int i = s0 + ci0 + CQ_RSTEP * u;
+      v[u] = make_double2(0.0, 0.0);
+      if (i < n && cj < n && (cj >> 4) >= (i >> 4)) v[u] = Bk[bidx(i >> 4, cj >> 4, nb) * 256 + bo(i & 15, cj & 15)];
+    }
+#pragma unroll
+    for (int u = 0; u < CQ_U; ++u) {
+      const int i = s0 + ci0 + CQ_RSTEP * u;
+      if (i < n && cj < n) Rinv[(int64_t)i * n + cj] = v[u];
+    }
   }
 }
 
@@ -411,7 +410,7 @@ hipError_t cholqr(const QrArgs &p, hipStream_t s) {
   if (!attr) {
     attr = true;
     (void)hipFuncSetAttribute((const void *)cq_chol_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (CQ_NB * (CQ_NB + 1) / 2 + 1) * 256 * (int)sizeof(double2));
+                              CQ_NB * (CQ_NB + 1) / 2 * 256 * (int)sizeof(double2));
     (void)hipGetLastError();
   }
   const int64_t mn = (int64_t)m * n, nn = (int64_t)n * n, ws = p.inst.skip;
@@ -426,7 +425,7 @@ hipError_t cholqr(const QrArgs &p, hipStream_t s) {
   }
   const int nt = (n + 15) / 16;
   const int nbk = (n + 15) / 16;
-  const size_t lds = (size_t)(nbk * (nbk + 1) / 2 + 1) * 256 * sizeof(double2);
+  const size_t lds = (size_t)(nbk * (nbk + 1) / 2) * 256 * sizeof(double2);
   // n x n product X Y (row-major operands in the work area) into Z with
   // strides (zr, zc) and instance stride zs; conj: conjugated result
   auto nn_gemm = [&](const double2 *X, const double2 *Y, double2 *Z, int64_t zr, int64_t zc,
