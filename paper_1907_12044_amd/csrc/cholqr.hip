@@ -114,9 +114,15 @@ __device__ __forceinline__ double2 shfl_c(double2 v, int src) {
 // sixteen lanes reading a row or a column touch sixteen different banks.
 __device__ __forceinline__ int bo(int i, int j) { return (i << 4) | (j ^ i); }
 
-// acc (re, im) += op(A) B on the matrix cores of one wave; op(A) = A^H when adj.
-__device__ __forceinline__ void blk_mma(const double2 *A, bool adj, const double2 *B, f64x4_t &cr,
-                                        f64x4_t &ci) {
+// acc += op(A) B on the matrix cores of one wave, op(A) = A^H when adj, with
+// three real products per complex one: P1 = Ar Br, P2 = Ai Bi,
+// P3 = (Ar + Ai)(Br + Bi); Re = P1 - P2, Im = P3 - P1 - P2.
+struct CAcc {
+  f64x4_t p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0}, p3 = {0, 0, 0, 0};
+  __device__ double re(int r) const { return p1[r] - p2[r]; }
+  __device__ double im(int r) const { return p3[r] - p1[r] - p2[r]; }
+};
+__device__ __forceinline__ void blk_mma(const double2 *A, bool adj, const double2 *B, CAcc &acc) {
   const int lane = threadIdx.x & 63, i = lane & 15, kk = lane >> 4;
 #pragma unroll
   for (int k0 = 0; k0 < 16; k0 += 4) {
@@ -124,10 +130,9 @@ __device__ __forceinline__ void blk_mma(const double2 *A, bool adj, const double
     double2 av = adj ? A[bo(k, i)] : A[bo(i, k)];
     if (adj) av.y = -av.y;
     const double2 bv = B[bo(k, i)];
-    cr = Mf<double>::mfma(av.x, bv.x, cr);
-    cr = Mf<double>::mfma(-av.y, bv.y, cr);
-    ci = Mf<double>::mfma(av.x, bv.y, ci);
-    ci = Mf<double>::mfma(av.y, bv.x, ci);
+    acc.p1 = Mf<double>::mfma(av.x, bv.x, acc.p1);
+    acc.p2 = Mf<double>::mfma(av.y, bv.y, acc.p2);
+    acc.p3 = Mf<double>::mfma(av.x + av.y, bv.x + bv.y, acc.p3);
   }
 }
 
@@ -239,7 +244,8 @@ struct CholArgs {
 constexpr int CQ_NB = CQ_NMAX / 16;   // block rows / columns at most
 constexpr int CQ_CHOL_THREADS = 512;  // 8 waves (>= CQ_NB - 1 for the back substitution)
 constexpr int CQ_RSTEP = CQ_CHOL_THREADS / CQ_NMAX;   // rows per pass of the row-major copies
-constexpr int CQ_U = 8;                                // copies in flight per thread
+constexpr int CQ_U = 8;                                // copies in flight per thread (LDS to global)
+constexpr int CQ_UL = CQ_NMAX / CQ_RSTEP;              // global loads in flight per thread: all rows
 
 __device__ __forceinline__ int bidx(int I, int J, int nb) { return I * nb - (I * (I - 1)) / 2 + (J - I); }
 
@@ -254,18 +260,18 @@ __global__ __launch_bounds__(CQ_CHOL_THREADS) void cq_chol_kernel(CholArgs a) {
   // row-major copies: thread (i0, j) takes column j, rows i0 + CQ_RSTEP u
   const int cj = tid & (CQ_NMAX - 1), ci0 = tid / CQ_NMAX;
   // load the upper blocks (identity padding beyond n)
-  for (int s0 = 0; s0 < np; s0 += CQ_U * CQ_RSTEP) {
-    double2 v[CQ_U];
+  {
+    double2 v[CQ_UL];
 #pragma unroll
-    for (int u = 0; u < CQ_U; ++u) {
-      const int i = s0 + ci0 + CQ_RSTEP * u;
+    for (int u = 0; u < CQ_UL; ++u) {
+      const int i = ci0 + CQ_RSTEP * u;
       v[u] = make_double2(0.0, 0.0);
       if (i < n && cj < n && (cj >> 4) >= (i >> 4)) v[u] = G[(int64_t)i * n + cj];
       else if (i == cj) v[u] = make_double2(1.0, 0.0);
     }
 #pragma unroll
-    for (int u = 0; u < CQ_U; ++u) {
-      const int i = s0 + ci0 + CQ_RSTEP * u;
+    for (int u = 0; u < CQ_UL; ++u) {
+      const int i = ci0 + CQ_RSTEP * u;
       if (i < np && cj < np && (cj >> 4) >= (i >> 4)) Bk[bidx(i >> 4, cj >> 4, nb) * 256 + bo(i & 15, cj & 15)] = v[u];
     }
   }
@@ -308,12 +314,12 @@ __global__ __launch_bounds__(CQ_CHOL_THREADS) void cq_chol_kernel(CholArgs a) {
     // block row: R_KJ = X_KK^H G_KJ, one wave per block
     for (int J = K + 1 + wave; J < nb; J += CQ_CHOL_THREADS / 64) {
       double2 *Bj = Bk + bidx(K, J, nb) * 256;
-      f64x4_t cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
-      blk_mma(D, true, Bj, cr, ci);
+      CAcc acc;
+      blk_mma(D, true, Bj, acc);
       __builtin_amdgcn_wave_barrier();
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr)
-        Bj[bo(Mf<double>::row(lane, rr), lane & 15)] = make_double2(cr[rr], ci[rr]);
+        Bj[bo(Mf<double>::row(lane, rr), lane & 15)] = make_double2(acc.re(rr), acc.im(rr));
     }
     __syncthreads();
     // trailing update G_IJ -= R_KI^H R_KJ, K < I <= J
@@ -325,13 +331,13 @@ __global__ __launch_bounds__(CQ_CHOL_THREADS) void cq_chol_kernel(CholArgs a) {
         I += K + 1;
         const int J = I + u;
         double2 *Cij = Bk + bidx(I, J, nb) * 256;
-        f64x4_t cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
-        blk_mma(Bk + bidx(K, I, nb) * 256, true, Bk + bidx(K, J, nb) * 256, cr, ci);
+        CAcc acc;
+        blk_mma(Bk + bidx(K, I, nb) * 256, true, Bk + bidx(K, J, nb) * 256, acc);
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
           double2 &c = Cij[bo(Mf<double>::row(lane, rr), lane & 15)];
-          c.x -= cr[rr];
-          c.y -= ci[rr];
+          c.x -= acc.re(rr);
+          c.y -= acc.im(rr);
         }
       }
     }
@@ -359,23 +365,22 @@ __global__ __launch_bounds__(CQ_CHOL_THREADS) void cq_chol_kernel(CholArgs a) {
   for (int I = nb - 2; I >= 0; --I) {
     // S_J = sum_K R_IK X_KJ (one wave per J), then X_IJ = -X_II S_J
     const int J = I + 1 + wave;         // nb - 1 <= 7 < 8 waves
-    f64x4_t sr = {0, 0, 0, 0}, si = {0, 0, 0, 0};
+    CAcc sa;
     if (J < nb)
-      for (int K = I + 1; K <= J; ++K)
-        blk_mma(Bk + bidx(I, K, nb) * 256, false, Bk + bidx(K, J, nb) * 256, sr, si);
+      for (int K = I + 1; K <= J; ++K) blk_mma(Bk + bidx(I, K, nb) * 256, false, Bk + bidx(K, J, nb) * 256, sa);
     __syncthreads();   // every R_IK has been read
     if (J < nb) {
       double2 *Xj = Bk + bidx(I, J, nb) * 256;
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr)
-        Xj[bo(Mf<double>::row(lane, rr), lane & 15)] = make_double2(sr[rr], si[rr]);
+        Xj[bo(Mf<double>::row(lane, rr), lane & 15)] = make_double2(sa.re(rr), sa.im(rr));
       __builtin_amdgcn_wave_barrier();
-      f64x4_t cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
-      blk_mma(Bk + bidx(I, I, nb) * 256, false, Xj, cr, ci);
+      CAcc acc;
+      blk_mma(Bk + bidx(I, I, nb) * 256, false, Xj, acc);
       __builtin_amdgcn_wave_barrier();
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr)
-        Xj[bo(Mf<double>::row(lane, rr), lane & 15)] = make_double2(-cr[rr], -ci[rr]);
+        Xj[bo(Mf<double>::row(lane, rr), lane & 15)] = make_double2(-acc.re(rr), -acc.im(rr));
     }
     __syncthreads();
   }
