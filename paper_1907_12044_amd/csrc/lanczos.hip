@@ -307,12 +307,16 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_dots_kernel(LzState *st, LzPartia
   }
   if (st->stop) return;
   const int G = gridDim.x;
-  if (close_step(st, pp, upd_grid(n), j, 0)) return;
-  // Chunks of 256 elements.  Phase 1: w for the chunk (one element per
-  // thread) into LDS and U[j+1].  Phase 2: thread (g, t), g = tid / 32,
-  // t = tid % 32, accumulates <u_i, w> over the chunk for i = g, g+8, g+16,
-  // g+24: 32 independent loads per thread per chunk.
+  StepPre pre;
+  close_step_load(st, pp, upd_grid(n), j, 0, pre);
+  // Chunks of 256 elements (one chunk per work-group while n <= 256 LZ_PARTS).
+  // Thread (g, t), g = tid / 32, t = tid % 32, projects onto u_i for
+  // i = g, g+8, g+16, g+24 over the elements t + 32 v of the chunk; its
+  // basis elements and the parts of its own w element are all requested
+  // before any is used (one memory round trip per chunk).  w for the chunk
+  // goes through LDS.
   constexpr int NQ = (JB + 7) / 8;
+  constexpr int PR = 8;                 // parts of w held in registers (more: loaded after)
   __shared__ double2 wl[LZ_BLOCK];
   __shared__ double w2s[LZ_BLOCK / 64];
   const int g8 = threadIdx.x >> 5, t32 = threadIdx.x & 31;
@@ -321,12 +325,39 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_dots_kernel(LzState *st, LzPartia
   for (int q = 0; q < NQ; ++q) { ar[q] = 0.0; ai[q] = 0.0; }
   double w2 = 0.0;
   double2 *wdst = U + (int64_t)(j + 1) * ldu;
+  bool first = true;
   for (int64_t c0 = (int64_t)blockIdx.x * LZ_BLOCK; c0 < n; c0 += (int64_t)G * LZ_BLOCK) {
     const int64_t e = c0 + threadIdx.x;
+    double2 ur[NQ][LZ_BLOCK / 32];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int i = g8 + 8 * q;
+      const double2 *ui = U + (int64_t)i * ldu + c0;
+#pragma unroll
+      for (int t = 0; t < LZ_BLOCK / 32; ++t) {
+        const int el = t32 + 32 * t;
+        ur[q][t] = (i <= j && c0 + el < n) ? ui[el] : make_double2(0.0, 0.0);
+      }
+    }
+    TY yv[PR];
+#pragma unroll
+    for (int p = 0; p < PR; ++p) {
+      yv[p].x = 0;
+      yv[p].y = 0;
+      if (p < P && e < n) yv[p] = ypart[(int64_t)p * pstride + e];
+    }
+    if (first) {
+      first = false;
+      if (close_step_finish(st, pre, j, 0)) return;   // (synchronises the work-group)
+    }
     double wr = 0.0, wi = 0.0;
     if (e < n) {
-#pragma unroll 4
-      for (int p = 0; p < P; ++p) {
+#pragma unroll
+      for (int p = 0; p < PR; ++p) {
+        wr += (double)yv[p].x;
+        wi += (double)yv[p].y;
+      }
+      for (int p = PR; p < P; ++p) {
         const TY v = ypart[(int64_t)p * pstride + e];
         wr += (double)v.x;
         wi += (double)v.y;
@@ -340,16 +371,12 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_dots_kernel(LzState *st, LzPartia
     for (int q = 0; q < NQ; ++q) {
       const int i = g8 + 8 * q;
       if (i <= j) {
-        const double2 *ui = U + (int64_t)i * ldu + c0;
 #pragma unroll
         for (int t = 0; t < LZ_BLOCK / 32; ++t) {
-          const int el = t32 + 32 * t;
-          if (c0 + el < n) {
-            const double2 u = ui[el];
-            const double2 w = wl[el];
-            ar[q] += u.x * w.x + u.y * w.y;
-            ai[q] += u.x * w.y - u.y * w.x;
-          }
+          const double2 u = ur[q][t];
+          const double2 w = wl[t32 + 32 * t];
+          ar[q] += u.x * w.x + u.y * w.y;
+          ai[q] += u.x * w.y - u.y * w.x;
         }
       }
     }
@@ -1029,6 +1056,14 @@ int grid_for(int64_t n) {
   return (int)g;
 }
 
+// Work-groups of lz_dots: one 256-element chunk each, at most LZ_PARTS.
+int dots_grid(int64_t n) {
+  int64_t g = (n + LZ_BLOCK - 1) / LZ_BLOCK;
+  if (g > LZ_PARTS) g = LZ_PARTS;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
 }  // namespace
 
 hipError_t lz_start(LzState *st, LzPartials *pp, const double2 *x, double2 *u0, int64_t n,
@@ -1041,7 +1076,7 @@ hipError_t lz_start(LzState *st, LzPartials *pp, const double2 *x, double2 *u0, 
 
 hipError_t lz_dots(LzState *st, LzPartials *pp, DType ty, const void *ypart, int P, int64_t pstride,
                    double2 *U, int64_t ldu, int j, int64_t n, const LzInst &in, hipStream_t s) {
-  const dim3 g(grid_for(n), in.count), b(LZ_BLOCK);
+  const dim3 g(dots_grid(n), in.count), b(LZ_BLOCK);
 #define LZ_DOTS(T, JB)                                                                         \
   hipLaunchKernelGGL((lz_dots_kernel<T, JB>), g, b, 0, s, st, pp, (const T *)ypart, P, pstride, \
                      U, ldu, j, n, in)
@@ -1063,7 +1098,7 @@ hipError_t lz_dots(LzState *st, LzPartials *pp, DType ty, const void *ypart, int
 hipError_t lz_update(LzState *st, LzPartials *pp, double2 *U, int64_t ldu, int j, int64_t n, int Gd,
                      const double2 *Yp, int P, const LzInst &in, hipStream_t s) {
   const dim3 g(upd_grid(n), in.count), b(LZ_BLOCK);
-  if (Gd <= 0) Gd = grid_for(n);
+  if (Gd <= 0) Gd = dots_grid(n);
   if (Yp && (P < 1 || P > HS_PMAX)) return hipErrorInvalidValue;
 #define LZ_UPD(JB) \
   hipLaunchKernelGGL((lz_update_kernel<JB>), g, b, 0, s, st, pp, U, ldu, j, n, Gd, Yp, P, in)
