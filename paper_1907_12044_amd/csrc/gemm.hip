@@ -3,9 +3,10 @@
 // Every dense contraction of the TDVP-PS step (stages 1 and 3 of H[i] x,
 // the bond operator of eq:tdvp2_D, the environment update eq:tdvp1_h and the
 // centre move C_{i+1} = D R_{i+1}) is a (batched) complex GEMM with
-// arbitrary strides.  A complex product is four real MFMAs on split
-// real/imaginary planes held in LDS:
-//   Cr += Ar Br - Ai Bi,   Ci += Ar Bi + Ai Br.
+// arbitrary strides.  A complex product is three real MFMAs on split
+// real/imaginary planes held in LDS (the three-multiplication form):
+//   P1 += Ar Br,  P2 += Ai Bi,  P3 += (Ar + Ai)(Br + Bi);
+//   Cr = P1 - P2,  Ci = P3 - P1 - P2.
 // Tiles: a 256-thread work-group (4 wave64) owns a BM x BN output tile, each
 // wave a (BM/2) x (BN/2) quarter built from 16x16 MFMA blocks
 // (v_mfma_f64_16x16x4_f64 / v_mfma_f32_16x16x4_f32).  Operand lane layout of
@@ -68,13 +69,14 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs g) {
   const int wm0 = (wave >> 1) * WM;
   const int wn0 = (wave & 1) * WN;
 
-  AccT cr[TI][TJ], ci[TI][TJ];
+  AccT p1[TI][TJ], p2[TI][TJ], p3[TI][TJ];
 #pragma unroll
   for (int i = 0; i < TI; ++i)
 #pragma unroll
     for (int j = 0; j < TJ; ++j) {
-      cr[i][j] = AccT{0, 0, 0, 0};
-      ci[i][j] = AccT{0, 0, 0, 0};
+      p1[i][j] = AccT{0, 0, 0, 0};
+      p2[i][j] = AccT{0, 0, 0, 0};
+      p3[i][j] = AccT{0, 0, 0, 0};
     }
 
   // Register-staged tiles: the global loads of tile k0 + BK are issued
@@ -127,26 +129,26 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs g) {
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       const int kr = ks + (lane >> 4);
-      TM ar[TI], ai[TI], an[TI], br[TJ], bi[TJ];
+      TM ar[TI], ai[TI], as[TI], br[TJ], bi[TJ], bs[TJ];
 #pragma unroll
       for (int i = 0; i < TI; ++i) {
         ar[i] = As[0][kr][wm0 + i * 16 + (lane & 15)];
         ai[i] = As[1][kr][wm0 + i * 16 + (lane & 15)];
-        an[i] = -ai[i];
+        as[i] = ar[i] + ai[i];
       }
 #pragma unroll
       for (int j = 0; j < TJ; ++j) {
         br[j] = Bs[0][kr][wn0 + j * 16 + (lane & 15)];
         bi[j] = Bs[1][kr][wn0 + j * 16 + (lane & 15)];
+        bs[j] = br[j] + bi[j];
       }
 #pragma unroll
       for (int i = 0; i < TI; ++i)
 #pragma unroll
         for (int j = 0; j < TJ; ++j) {
-          cr[i][j] = mfma16(ar[i], br[j], cr[i][j]);
-          cr[i][j] = mfma16(an[i], bi[j], cr[i][j]);
-          ci[i][j] = mfma16(ar[i], bi[j], ci[i][j]);
-          ci[i][j] = mfma16(ai[i], br[j], ci[i][j]);
+          p1[i][j] = mfma16(ar[i], br[j], p1[i][j]);
+          p2[i][j] = mfma16(ai[i], bi[j], p2[i][j]);
+          p3[i][j] = mfma16(as[i], bs[j], p3[i][j]);
         }
     }
     __syncthreads();
@@ -165,8 +167,8 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs g) {
         const int col = bn0 + wn0 + j * 16 + (lane & 15);
         if (row < M && col < N) {
           VC v;
-          v.x = (TC)cr[i][j][r];
-          v.y = (TC)ci[i][j][r];
+          v.x = (TC)(p1[i][j][r] - p2[i][j][r]);
+          v.y = (TC)(p3[i][j][r] - p1[i][j][r] - p2[i][j][r]);
           C[(int64_t)row * g.scm + (int64_t)col * g.scn] = v;
         }
       }
