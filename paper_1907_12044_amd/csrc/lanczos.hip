@@ -636,7 +636,7 @@ constexpr int HS_XV = 4;               // staged x-slice elements per thread
 constexpr int HS_LV = 8;               // staged L-slice elements per thread
 
 // Complex C (Mrows x 16) = A (Mrows x K) B (K x 16) on the MFMA units of one
-// work-group: 16-row tiles; when there are fewer tiles than waves the K
+// work-group (three real products per complex one): 16-row tiles; when there are fewer tiles than waves the K
 // range of a tile is split over several waves and the parts are added in
 // order through `red` (HS_WAVES x 2 x 256 values).  A comes from
 // loadA(row, k, re, im) (row < Mrows, k < K); B from LDS planes [K4][16]
@@ -652,7 +652,7 @@ __device__ __forceinline__ void hs_mm16(int Mrows, int K, const T *b_re, const T
   const int TPR = min(RT, HS_WAVES), parts = HS_WAVES / TPR;
   const int kchunk = ((K4 / 4 + parts - 1) / parts) * 4;
   for (int rt0 = 0; rt0 < RT; rt0 += TPR) {
-    AccT cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+    AccT p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0}, p3 = {0, 0, 0, 0};   // Ar Br, Ai Bi, (Ar+Ai)(Br+Bi)
     const int rt = rt0 + wave % TPR, pt = wave / TPR;
     if (rt < RT && pt < parts) {
       const int kb = pt * kchunk, ke = min(K4, kb + kchunk);
@@ -663,16 +663,15 @@ __device__ __forceinline__ void hs_mm16(int Mrows, int K, const T *b_re, const T
         T ar = 0, ai = 0;
         if (row < Mrows && k < K) loadA(row, k, ar, ai);
         const T br = b_re[k * 16 + (lane & 15)], bi = b_im[k * 16 + (lane & 15)];
-        cr = Mf<T>::mfma(ar, br, cr);
-        cr = Mf<T>::mfma(-ai, bi, cr);
-        ci = Mf<T>::mfma(ar, bi, ci);
-        ci = Mf<T>::mfma(ai, br, ci);
+        p1 = Mf<T>::mfma(ar, br, p1);
+        p2 = Mf<T>::mfma(ai, bi, p2);
+        p3 = Mf<T>::mfma(ar + ai, br + bi, p3);
       }
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      red[(wave * 2 + 0) * 256 + r * 64 + lane] = cr[r];
-      red[(wave * 2 + 1) * 256 + r * 64 + lane] = ci[r];
+      red[(wave * 2 + 0) * 256 + r * 64 + lane] = p1[r] - p2[r];
+      red[(wave * 2 + 1) * 256 + r * 64 + lane] = p3[r] - p1[r] - p2[r];
     }
     __syncthreads();
     for (int e = threadIdx.x; e < min(RT - rt0, TPR) * 256; e += NT) {
