@@ -72,6 +72,25 @@ def heff(L, W, R, x):
     return np.tensordot(L, T, axes=([1, 2], [0, 2]))        # b s q
 
 
+def heff_element(L, W, R, x, b, s, q):
+    """One element (b, s, q) of H[i] x (eq:tdvp1_H): the sum over w, k, t, v,
+    r of L[b, w, k] W[w, s, t, v] R[q, v, r] x[k, t, r], evaluated on its own
+    so that single outputs of a large application can be checked.
+    """
+    T = np.tensordot(x, R[q], axes=([2], [1]))              # k t v
+    T = np.tensordot(W[:, s], T, axes=([1, 2], [1, 2]))     # w k
+    return complex(np.sum(L[b] * T))
+
+
+def env_left_element(L, A, W, q, y, r):
+    """One element (q, y, r) of the left environment update (eq:tdvp1_h1i):
+    the sum over b, w, k, t, s of L[b, w, k] A[k, t, r] W[w, s, t, y] conj(A[b, s, q]).
+    """
+    T = np.tensordot(L, A[:, :, r], axes=([2], [0]))        # b w t
+    T = np.tensordot(T, W[:, :, :, y], axes=([1, 2], [0, 2]))   # b s
+    return complex(np.sum(np.conj(A[:, :, q]) * T))
+
+
 def bond_op(L, R, D):
     """Zero-site operator of eq:tdvp2_D: sum_w h[1:i]_{l' w l} h[i+1:N]_{r' w r} D_{l r}.
 

@@ -116,3 +116,36 @@ def test_populations_equal_dense(small_chain):
         if s[0] == "el":
             ref = P.take(1, axis=pos).sum()
             assert pops[s[1]] == pytest.approx(ref, abs=1e-15)
+
+
+def test_single_elements_match_brute_force_sums():
+    """heff_element / env_left_element against the defining sums written
+    out as loops over every index (tiny shapes), and against the full
+    applications at a few points."""
+    Ml, d, Mr, Wl, Wr = 3, 2, 2, 2, 3
+    L = random_complex((Ml, Wl, Ml), 1)
+    W = random_complex((Wl, d, d, Wr), 2)
+    R = random_complex((Mr, Wr, Mr), 3)
+    x = random_complex((Ml, d, Mr), 4)
+    for (b, s, q) in [(0, 0, 0), (2, 1, 1), (1, 0, 1)]:
+        ref = 0j
+        for w in range(Wl):
+            for k in range(Ml):
+                for t in range(d):
+                    for v in range(Wr):
+                        for r in range(Mr):
+                            ref += L[b, w, k] * W[w, s, t, v] * R[q, v, r] * x[k, t, r]
+        assert abs(om.heff_element(L, W, R, x, b, s, q) - ref) < 1e-13
+        assert abs(om.heff(L, W, R, x)[b, s, q] - ref) < 1e-13
+    A = random_complex((Ml, d, Mr), 5)
+    Wa = random_complex((Wl, d, d, Wr), 6)
+    for (q, y, r) in [(0, 0, 0), (1, 2, 1), (0, 1, 1)]:
+        ref = 0j
+        for b in range(Ml):
+            for w in range(Wl):
+                for k in range(Ml):
+                    for t in range(d):
+                        for s in range(d):
+                            ref += L[b, w, k] * A[k, t, r] * Wa[w, s, t, y] * np.conj(A[b, s, q])
+        assert abs(om.env_left_element(L, A, Wa, q, y, r) - ref) < 1e-13
+        assert abs(om.env_left(L, A, Wa)[q, y, r] - ref) < 1e-13
