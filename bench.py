@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--realisations", type=int, default=64)
     ap.add_argument("--no-fused", action="store_true",
                     help="general multi-kernel Lanczos step everywhere (tdvp_set_fused(ctx, 0))")
+    ap.add_argument("--autotune", choices=["on", "off"], default=None,
+                    help="time candidate launch shapes of new problem keys in the first step "
+                         "(tdvp_set_autotune); default: on for the ensemble, off otherwise")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 256 MiB device copy first (reference for HBM counters)")
     return ap.parse_args()
@@ -74,6 +77,10 @@ MFMA_CLASSES = ("gemm", "lz_fused")
 KERNEL_OF_CLASS = {"gemm": "cgemm_kernel", "lz_fused": "heff_small_kernel", "lz_update": "lz_update_kernel",
                    "lz_dots": "lz_dots_kernel", "lz_ends": "lz_finish_kernel", "qr": "qr_reg_kernel",
                    "wapply": "wapply_kernel"}
+
+
+def autotune_on(args):
+    return args.autotune == "on" or (args.autotune is None and args.workload == "ensemble")
 
 
 def measured_traffic(kernel, workload, precision):
@@ -147,7 +154,8 @@ def ensemble_main(args):
         sites = chain_sites(ps_[0])
         raws = [initial_mps_raw(p, M, 1e-2, 1) for p in ps_]
         ens.append((M, rs, tdvp.PsEnsemble(ps_, sites, raws, 0, prec, kmax=args.kmax, tol=args.tol,
-                                           graph=not args.eager, fused=not args.no_fused)))
+                                           graph=not args.eager, fused=not args.no_fused,
+                                           autotune=autotune_on(args))))
     tau = 2.0 * tdvp.AU_PER_FS
     torch.cuda.synchronize()
     for _ in range(args.warmup):
@@ -187,7 +195,7 @@ def ensemble_main(args):
         "dtype": "c128" if prec == tdvp.FP64 else "c64 contractions / c128 Krylov+QR",
         "data": "synthetic",
         "config": {"workload": f"fmo7x10x8_ensemble{nreal}", "classes": {str(M): len(rs) for M, rs, _ in ens},
-                   "precision": args.precision, "kmax": args.kmax},
+                   "precision": args.precision, "kmax": args.kmax, "autotune": autotune_on(args)},
         "realisation_steps_per_s": nreal * 1e3 / ms,
         "heff_tflops": heff_tflops,
         "class_ms_per_step": {k: round(v["ms_per_step"], 3) for k, v in prof.items()},
@@ -219,7 +227,7 @@ def main():
     p, sites, phys, dims, raw, w = workload(args.workload)
     prec = tdvp.FP64 if args.precision == "fp64" else tdvp.FP32
     run = tdvp.PsRun(p, sites, raw, device=0, precision=prec, kmax=args.kmax, tol=args.tol,
-                     graph=not args.eager, fused=not args.no_fused)
+                     graph=not args.eager, fused=not args.no_fused, autotune=autotune_on(args))
     tau = w["dt_fs"] * tdvp.AU_PER_FS
     nsolve = 4 * len(sites)
     with torch.cuda.stream(run.stream):
@@ -274,7 +282,7 @@ def main():
         "config": {"workload": args.workload, "sites": len(sites), "bond_dim": w["M"],
                    "mpo_bond_max": max(run.mpo.bond), "dt_fs": w["dt_fs"], "kmax": args.kmax,
                    "tol": args.tol, "precision": args.precision, "graph": not args.eager,
-                   "fused": not args.no_fused},
+                   "fused": not args.no_fused, "autotune": autotune_on(args)},
         "heff_tflops": heff_tflops,
         "krylov_mean": float(ks.mean()) if ks.size else None,
         "class_ms_per_step": {k: round(v["ms_per_step"], 3) for k, v in prof.items()},

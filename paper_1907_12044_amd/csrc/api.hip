@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <new>
 #include <vector>
 
@@ -45,6 +46,13 @@ struct tdvp_ctx {
   hipGraphExec_t gexec;
   std::vector<uint64_t> gkey;     // what the captured graph was built for
   int fused_off;                  // 1: never use the fused small-bond Lanczos step
+  // autotuner: per problem key (kind, shapes, instance count, types) the
+  // candidate that ran fastest when the key was first met outside a graph
+  // capture; later launches (and captured graphs) reuse it
+  int autotune;
+  int tune_now;                   // predicated launches may be timed (a step that cannot be stopped)
+  std::map<std::vector<int64_t>, int> tuned;
+  hipEvent_t tune_ev[2];
 };
 
 namespace {
@@ -122,8 +130,55 @@ void prof_end(tdvp_ctx *c, int idx, double flops, double bytes) {
 
 int esz(DType t) { return t == F64 ? 16 : 8; }
 
+// Autotuning: may the launch about to be issued be timed now?  Only outside
+// a graph capture, and for a launch predicated on the Lanczos stop flag only
+// where the caller has marked the step as one that cannot be stopped.
+bool can_tune(tdvp_ctx *c, const void *skip) {
+  if (!c->autotune || (skip && !c->tune_now)) return false;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(c->stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return false;
+  for (hipEvent_t &e : c->tune_ev)
+    if (!e && hipEventCreate(&e) != hipSuccess) return false;
+  return true;
+}
+// Average time of `launch` (one warm-up call, then reps timed calls) in ms;
+// a failed launch returns a huge time so it is never chosen.
+template <typename F> double time_launch(tdvp_ctx *c, F launch, int reps = 3) {
+  if (launch() != hipSuccess) return 1e30;
+  hipEventRecord(c->tune_ev[0], c->stream);
+  for (int r = 0; r < reps; ++r)
+    if (launch() != hipSuccess) return 1e30;
+  hipEventRecord(c->tune_ev[1], c->stream);
+  float ms = 0.f;
+  if (hipEventSynchronize(c->tune_ev[1]) != hipSuccess ||
+      hipEventElapsedTime(&ms, c->tune_ev[0], c->tune_ev[1]) != hipSuccess)
+    return 1e30;
+  return ms / reps;
+}
+
 // cgemm with timing: algorithmic FLOP 8 M N K per batch; bytes = operands once + output once.
-hipError_t gemm_t(tdvp_ctx *c, DType ta, DType tb, DType tc, const GemmArgs &g) {
+// With the autotuner on, the tile shape (32x32 or 64x64) of a new problem
+// key is chosen by timing both (a GEMM overwrites C, so repeats are harmless).
+hipError_t gemm_t(tdvp_ctx *c, DType ta, DType tb, DType tc, const GemmArgs &g0) {
+  GemmArgs g = g0;
+  if (c->autotune) {
+    const std::vector<int64_t> key = {0, ta, tb, tc, g.M, g.N, g.K, g.batch, g.inst.count,
+                                      g.sak == 1, g.sbn == 1, g.scn == 1};
+    auto it = c->tuned.find(key);
+    if (it != c->tuned.end()) {
+      g.tile = it->second;
+    } else if (can_tune(c, g.skip)) {
+      int best = 32;
+      double tbest = 1e300;
+      for (int cand : {32, 64}) {
+        g.tile = cand;
+        const double t = time_launch(c, [&] { return cgemm(ta, tb, tc, g, c->stream); });
+        if (t < tbest) { tbest = t; best = cand; }
+      }
+      c->tuned[key] = best;
+      g.tile = best;
+    }
+  }
   const int id = prof_begin(c, TDVP_PROF_GEMM);
   const hipError_t e = cgemm(ta, tb, tc, g, c->stream);
   const double M = g.M, N = g.N, K = g.K, B = g.batch;
@@ -241,7 +296,8 @@ tdvp_status apply_op(tdvp_ctx *c, const Layout &lay, const Op &op, const double2
 constexpr int FUSED_MAX_MR = 64;
 constexpr int FUSED_MAX_MR_BOND = 64;
 
-bool fused_args(const tdvp_ctx *c, const Layout &lay, const Op &op, const Bi &b, HeffSmallArgs &a) {
+bool fused_args(const tdvp_ctx *c, const Layout &lay, const Op &op, const Bi &b, HeffSmallArgs &a,
+                int force_P = 0) {
   if (c->fused_off || op.Mr > (op.W ? FUSED_MAX_MR : FUSED_MAX_MR_BOND)) return false;
   if (!op.W && (op.Wl != op.Wr || op.d != 1)) return false;
   a = HeffSmallArgs{};
@@ -258,6 +314,7 @@ bool fused_args(const tdvp_ctx *c, const Layout &lay, const Op &op, const Bi &b,
   const int64_t cols = (int64_t)op.Mr * b.R;
   int P = (int)std::min<int64_t>(HS_PMAX, std::max<int64_t>(1, (256 + cols - 1) / cols));
   P = std::min(P, std::max(1, op.Ml / 4));
+  if (force_P > 0) P = std::min(force_P, op.Ml);   // autotuner candidate
   while (P > 1 && ((int64_t)P * op.Mr > LZ_PARTS || (size_t)P * a.n * 16 > lay.ybytes)) --P;
   a.nl = (op.Ml + P - 1) / P;
   a.P = (op.Ml + a.nl - 1) / a.nl;
@@ -293,7 +350,13 @@ tdvp_status run_lanczos(tdvp_ctx *c, const Layout &lay, const Op &op, double zr,
   li.count = b.R; li.wss = b.ws; li.xs = sx; li.ys = sy;
   const double vb = 16.0 * n * b.R;
   HeffSmallArgs fa;
-  const bool fused = fused_args(c, lay, op, b, fa);
+  bool fused = fused_args(c, lay, op, b, fa);
+  std::vector<int64_t> fkey;
+  if (fused && c->autotune) {
+    fkey = {1, op.Ml, op.d, op.Mr, op.Wl, op.Wr, b.R, (int64_t)c->prec, op.W ? 1 : 0};
+    auto it = c->tuned.find(fkey);
+    if (it != c->tuned.end()) fused = fused_args(c, lay, op, b, fa, it->second);
+  }
   const int trows = fused ? op.Ml * op.d : 0;
   if (fused && op.W)
     CK(wtable((const double2 *)op.W, op.Wl, op.d, op.Wr, op.sW, const_cast<int *>(fa.row),
@@ -302,6 +365,26 @@ tdvp_status run_lanczos(tdvp_ctx *c, const Layout &lay, const Op &op, double zr,
   CK(lz_start(st, pp, (const double2 *)x, U, n, zr, zi, tol, keff, trows, li, c->stream));
   prof_end(c, id, 4.0 * n * b.R, 2.0 * vb);
   fa.st = st; fa.pp = pp; fa.U = U;
+  if (fused && c->autotune && !c->tuned.count(fkey) && can_tune(c, nullptr)) {
+    // time the split of the sum over l (P parts) on the first Krylov step
+    // (never stopped: it only normalises x); the step itself then runs with
+    // the chosen split, overwriting what the candidates wrote
+    int best = fa.P;
+    double tbest = 1e300;
+    for (int cand : {1, 2, 4, 8}) {
+      HeffSmallArgs ca;
+      if (!fused_args(c, lay, op, b, ca, cand) || ca.P != cand) continue;
+      ca.st = st; ca.pp = pp; ca.U = U; ca.j = 0;
+      const double t = time_launch(c, [&] { return heff_small(env_type(c), ca, b.R, c->stream); });
+      if (t < tbest) { tbest = t; best = cand; }
+    }
+    c->tuned[fkey] = best;
+    HeffSmallArgs ba;
+    if (fused_args(c, lay, op, b, ba, best)) {
+      ba.st = st; ba.pp = pp; ba.U = U;
+      fa = ba;
+    }
+  }
   for (int j = 0; j < keff; ++j) {
     if (fused) {
       // algorithmic work: the three contraction stages and j+1 projections;
@@ -319,7 +402,10 @@ tdvp_status run_lanczos(tdvp_ctx *c, const Layout &lay, const Op &op, double zr,
       prof_end(c, id, 8.0 * (j + 1) * n * b.R, 2.0 * vb + (j + 1) * vb);
       continue;
     }
-    CS(apply_op(c, lay, op, U + (int64_t)j * n, b.wsel(16), &st->stop, b));
+    c->tune_now = j == 0;   // the first Krylov step is never stopped
+    const tdvp_status so = apply_op(c, lay, op, U + (int64_t)j * n, b.wsel(16), &st->stop, b);
+    c->tune_now = 0;
+    CS(so);
     id = prof_begin(c, TDVP_PROF_LZ_DOTS);
     CK(lz_dots(st, pp, env_type(c), c->ws + lay.Y, op.parts(), n, U, n, j, n, li, c->stream));
     prof_end(c, id, 8.0 * (j + 1) * n * b.R,
@@ -538,6 +624,9 @@ tdvp_status tdvp_create(tdvp_ctx **ctx, int device, void *hip_stream, tdvp_preci
   c->klog_pos = 0;
   c->graph_mode = 0;
   c->fused_off = 0;
+  c->autotune = 0;
+  c->tune_now = 0;
+  c->tune_ev[0] = c->tune_ev[1] = nullptr;
   c->graph = nullptr;
   c->gexec = nullptr;
   if (hipSetDevice(device) != hipSuccess) { delete c; return TDVP_E_DEVICE; }
@@ -550,6 +639,8 @@ tdvp_status tdvp_create(tdvp_ctx **ctx, int device, void *hip_stream, tdvp_preci
 tdvp_status tdvp_destroy(tdvp_ctx *ctx) {
   if (!ctx) return TDVP_E_ARG;
   for (hipEvent_t e : ctx->pool) hipEventDestroy(e);
+  for (hipEvent_t e : ctx->tune_ev)
+    if (e) hipEventDestroy(e);
   if (ctx->gexec) hipGraphExecDestroy(ctx->gexec);
   if (ctx->graph) hipGraphDestroy(ctx->graph);
   delete ctx;
@@ -801,6 +892,18 @@ tdvp_status tdvp_set_fused(tdvp_ctx *ctx, int enable) {
   return TDVP_OK;
 }
 
+tdvp_status tdvp_set_autotune(tdvp_ctx *ctx, int enable) {
+  if (!ctx) return TDVP_E_ARG;
+  ctx->autotune = enable ? 1 : 0;
+  return TDVP_OK;
+}
+
+tdvp_status tdvp_autotune_count(const tdvp_ctx *ctx, int32_t *count) {
+  if (!ctx || !count) return TDVP_E_ARG;
+  *count = (int32_t)ctx->tuned.size();
+  return TDVP_OK;
+}
+
 tdvp_status tdvp_ps_step(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo,
                          const tdvp_envs *envs, double dt, int nsteps, int kmax, double tol) {
   return tdvp_ps_step_batched(ctx, 1, mps, mpo, envs, dt, nsteps, kmax, tol);
@@ -959,6 +1062,7 @@ tdvp_status tdvp_ps_step_batched(tdvp_ctx *ctx, int nb, const tdvp_mps *mps, con
   key.push_back((uint64_t)(int)ctx->prec);
   key.push_back((uint64_t)nb);
   key.push_back((uint64_t)ctx->fused_off);
+  key.push_back((uint64_t)ctx->autotune);
   put(ctx->ws); put(ctx->stream);
   for (int i = 0; i < ch.n; ++i) {
     put(mps[0].site[i]); put(mpo[0].site[i]);
@@ -971,6 +1075,12 @@ tdvp_status tdvp_ps_step_batched(tdvp_ctx *ctx, int nb, const tdvp_mps *mps, con
     key.push_back((uint64_t)ch.bond[bb] << 32 | (uint32_t)ch.wbond[bb]);
   }
   if (!ctx->gexec || key != ctx->gkey) {
+    if (ctx->autotune) {
+      // one eager step first, so that the tuner can time the shapes it has
+      // not met yet; the graph captured next uses its choices
+      CS(enqueue_steps(ctx, lay, ch, &mps[0], &mpo[0], &envs[0], dt, 1, kmax, tol, b, s));
+      --nsteps;
+    }
     if (ctx->gexec) { hipGraphExecDestroy(ctx->gexec); ctx->gexec = nullptr; }
     if (ctx->graph) { hipGraphDestroy(ctx->graph); ctx->graph = nullptr; }
     ctx->gkey.clear();

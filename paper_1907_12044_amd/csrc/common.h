@@ -38,6 +38,7 @@ struct GemmArgs {
   int conjA, conjB;
   const int *skip;
   Inst inst;                 // a = A, b = B, c = C strides
+  int tile;                  // 0: by problem size; 32: 32x32 tiles; 64: 64x64 tiles
 };
 
 hipError_t cgemm(DType ta, DType tb, DType tc, const GemmArgs &g, hipStream_t s);

@@ -181,7 +181,7 @@ hipError_t launch(const GemmArgs &g, hipStream_t s) {
   // the tile shape depends on one instance's problem only, so a batched
   // launch computes every instance exactly as a single launch would
   const int64_t tiles64 = (int64_t)((g.M + 63) / 64) * ((g.N + 63) / 64) * g.batch;
-  if (tiles64 >= 240) {
+  if (g.tile == 64 || (g.tile == 0 && tiles64 >= 240)) {
     dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, nz);
     hipLaunchKernelGGL((cgemm_kernel<TA, TB, TC, TM, 64, 64, 16>), grid, dim3(256), 0, s, g);
   } else {

@@ -67,6 +67,8 @@ EXPORTS = {
     "tdvp_set_krylov_log": (c_int, [c_void_p, c_void_p, c_int]),
     "tdvp_set_graph": (c_int, [c_void_p, c_int]),
     "tdvp_set_fused": (c_int, [c_void_p, c_int]),
+    "tdvp_set_autotune": (c_int, [c_void_p, c_int]),
+    "tdvp_autotune_count": (c_int, [c_void_p, c_void_p]),
     "tdvp_ps_step_batched": (c_int, [c_void_p, c_int, POINTER(_Mps), POINTER(_Mpo), POINTER(_Envs),
                                      c_double, c_int, c_int, c_double]),
     "tdvp_observe_batched": (c_int, [c_void_p, c_int, POINTER(_Mps), POINTER(_Mpo), POINTER(_Envs),
@@ -306,6 +308,16 @@ def set_fused(ctx, enable):
     _check(lib().tdvp_set_fused(ctx.h, 1 if enable else 0), "tdvp_set_fused")
 
 
+def set_autotune(ctx, enable):
+    _check(lib().tdvp_set_autotune(ctx.h, 1 if enable else 0), "tdvp_set_autotune")
+
+
+def autotune_count(ctx):
+    n = ctypes.c_int32(0)
+    _check(lib().tdvp_autotune_count(ctx.h, ctypes.byref(n)), "tdvp_autotune_count")
+    return int(n.value)
+
+
 def ps_step(ctx, mps, mpo, envs, dt, nsteps=1, kmax=20, tol=0.0):
     _check(lib().tdvp_ps_step(ctx.h, ctypes.byref(mps.desc), ctypes.byref(mpo.desc),
                               ctypes.byref(envs.desc), float(dt), int(nsteps), int(kmax), float(tol)),
@@ -358,7 +370,7 @@ class PsRun:
     """
 
     def __init__(self, params, sites, raw_mps, device=0, precision=FP64, kmax=20, tol=0.0,
-                 graph=True, fused=True):
+                 graph=True, fused=True, autotune=False):
         import torch
         self.torch = torch
         self.stream = torch.cuda.Stream(device=device)
@@ -382,6 +394,7 @@ class PsRun:
         self.stream.synchronize()
         set_graph(self.ctx, graph)
         set_fused(self.ctx, fused)
+        set_autotune(self.ctx, autotune)
         right_canonicalize(self.ctx, self.mps)
         envs_build(self.ctx, self.mps, self.mpo, self.envs)
 
@@ -433,7 +446,7 @@ class PsEnsemble:
     """
 
     def __init__(self, params_list, sites, raw_list, device=0, precision=FP64, kmax=20, tol=0.0,
-                 graph=True, stream=None, fused=True):
+                 graph=True, stream=None, fused=True, autotune=False):
         import torch
         self.torch = torch
         nb = len(params_list)
@@ -487,6 +500,7 @@ class PsEnsemble:
         self.ctx.reserve(nb * one)
         set_graph(self.ctx, graph)
         set_fused(self.ctx, fused)
+        set_autotune(self.ctx, autotune)
         for r in range(nb):
             _check(lib().tdvp_right_canonicalize(self.ctx.h, ctypes.byref(mps_arr[r])),
                    "tdvp_right_canonicalize")
