@@ -20,7 +20,10 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"fp64_mfma_tflops": 78.6, "fp32_mfma_tflops": 157.3, "hbm_gbs": 8000.0}
+# MI355X dense peaks; split-BF16 GEMMs do three bf16 products per real
+# product, so their effective peak is the bf16 one over three
+PEAK = {"fp64_mfma_tflops": 78.6, "fp32_mfma_tflops": 157.3, "bf16x3_eff_tflops": 2500.0 / 3,
+        "hbm_gbs": 8000.0}
 
 
 def parse():
@@ -29,7 +32,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="fmo7x10x8_M32")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--kmax", type=int, default=20)
     ap.add_argument("--tol", type=float, default=0.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -40,9 +43,9 @@ def parse():
     ap.add_argument("--realisations", type=int, default=64)
     ap.add_argument("--no-fused", action="store_true",
                     help="general multi-kernel Lanczos step everywhere (tdvp_set_fused(ctx, 0))")
-    ap.add_argument("--autotune", choices=["on", "off"], default=None,
-                    help="time candidate launch shapes of new problem keys in the first step "
-                         "(tdvp_set_autotune); default: on for the ensemble, off otherwise")
+    ap.add_argument("--autotune", choices=["on", "off"], default="on",
+                    help="time candidate launch shapes of new problem keys in the first (warm-up) "
+                         "step (tdvp_set_autotune)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 256 MiB device copy first (reference for HBM counters)")
     return ap.parse_args()
@@ -79,8 +82,12 @@ KERNEL_OF_CLASS = {"gemm": "cgemm_kernel", "lz_fused": "heff_small_kernel", "lz_
                    "wapply": "wapply_kernel"}
 
 
+DTYPE_OF = {0: "c128", 1: "c64 contractions / c128 Krylov+QR",
+            2: "c64 (split-bf16 MFMA GEMMs) contractions / c128 Krylov+QR"}
+
+
 def autotune_on(args):
-    return args.autotune == "on" or (args.autotune is None and args.workload == "ensemble")
+    return args.autotune == "on"
 
 
 def measured_traffic(kernel, workload, precision):
@@ -119,7 +126,12 @@ def roofline(prof, prec, ms_per_step, workload=None, precision=None):
     d = prof[dom]
     t = d["ms_per_step"] * 1e-3
     if dom in MFMA_CLASSES:
-        peak = PEAK["fp64_mfma_tflops"] if prec == tdvp.FP64 else PEAK["fp32_mfma_tflops"]
+        if prec == tdvp.FP64:
+            peak = PEAK["fp64_mfma_tflops"]
+        elif prec == tdvp.BF16X3 and dom == "gemm":
+            peak = PEAK["bf16x3_eff_tflops"]
+        else:
+            peak = PEAK["fp32_mfma_tflops"]
         roof = {"bound": "mfma", "achieved": d["flop"] / t / 1e12, "peak": peak, "unit": "TFLOP/s"}
     else:
         roof = {"bound": "hbm", "achieved": d["bytes"] / t / 1e9, "peak": PEAK["hbm_gbs"], "unit": "GB/s"}
@@ -144,7 +156,7 @@ def ensemble_main(args):
     from paper_1907_12044_amd import tdvp
 
     nreal = args.realisations
-    prec = tdvp.FP64 if args.precision == "fp64" else tdvp.FP32
+    prec = {"fp64": tdvp.FP64, "fp32": tdvp.FP32, "bf16x3": tdvp.BF16X3}[args.precision]
     classes = {}
     for r in range(nreal):
         classes.setdefault(ensemble_bond(0, r), []).append(r)
@@ -192,7 +204,7 @@ def ensemble_main(args):
         "value": 1e3 / ms, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c128" if prec == tdvp.FP64 else "c64 contractions / c128 Krylov+QR",
+        "dtype": DTYPE_OF[prec],
         "data": "synthetic",
         "config": {"workload": f"fmo7x10x8_ensemble{nreal}", "classes": {str(M): len(rs) for M, rs, _ in ens},
                    "precision": args.precision, "kmax": args.kmax, "autotune": autotune_on(args)},
@@ -225,7 +237,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     p, sites, phys, dims, raw, w = workload(args.workload)
-    prec = tdvp.FP64 if args.precision == "fp64" else tdvp.FP32
+    prec = {"fp64": tdvp.FP64, "fp32": tdvp.FP32, "bf16x3": tdvp.BF16X3}[args.precision]
     run = tdvp.PsRun(p, sites, raw, device=0, precision=prec, kmax=args.kmax, tol=args.tol,
                      graph=not args.eager, fused=not args.no_fused, autotune=autotune_on(args))
     tau = w["dt_fs"] * tdvp.AU_PER_FS
@@ -277,7 +289,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c128" if prec == tdvp.FP64 else "c64 contractions / c128 Krylov+QR",
+        "dtype": DTYPE_OF[prec],
         "data": "synthetic",
         "config": {"workload": args.workload, "sites": len(sites), "bond_dim": w["M"],
                    "mpo_bond_max": max(run.mpo.bond), "dt_fs": w["dt_fs"], "kmax": args.kmax,

@@ -56,9 +56,14 @@ typedef enum {
 
 typedef enum {
   TDVP_FP64 = 0,  /* every contraction in FP64 (complex128)                   */
-  TDVP_FP32 = 1   /* contractions and environments in FP32 (complex64) with
+  TDVP_FP32 = 1,  /* contractions and environments in FP32 (complex64) with
                      FP32 accumulation; Lanczos orthogonalisation, norms,
                      the small exponential, QR and the MPS stay FP64          */
+  TDVP_BF16X3 = 2 /* as TDVP_FP32, but the tiled GEMMs of the contractions run
+                     on the bf16 matrix cores with each FP32 operand split
+                     into two bf16 parts and three products per real product
+                     (FP32 accumulation, ~17 significant bits per operand);
+                     the fused small-bond Lanczos step stays FP32             */
 } tdvp_precision;
 
 typedef struct tdvp_ctx tdvp_ctx;

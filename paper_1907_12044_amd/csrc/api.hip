@@ -130,6 +130,13 @@ void prof_end(tdvp_ctx *c, int idx, double flops, double bytes) {
 
 int esz(DType t) { return t == F64 ? 16 : 8; }
 
+// The contraction GEMMs (FP32 output) of the split-BF16 mode run on the bf16
+// matrix cores; every other GEMM as requested.
+hipError_t gemm_any(tdvp_ctx *c, DType ta, DType tb, DType tc, const GemmArgs &g) {
+  if (c->prec == TDVP_BF16X3 && tc == F32) return cgemm_bf3(ta, tb, tc, g, c->stream);
+  return cgemm(ta, tb, tc, g, c->stream);
+}
+
 // Autotuning: may the launch about to be issued be timed now?  Only outside
 // a graph capture, and for a launch predicated on the Lanczos stop flag only
 // where the caller has marked the step as one that cannot be stopped.
@@ -157,22 +164,24 @@ template <typename F> double time_launch(tdvp_ctx *c, F launch, int reps = 3) {
 }
 
 // cgemm with timing: algorithmic FLOP 8 M N K per batch; bytes = operands once + output once.
-// With the autotuner on, the tile shape (32x32 or 64x64) of a new problem
-// key is chosen by timing both (a GEMM overwrites C, so repeats are harmless).
+// With the autotuner on, the tile shape (32x32, or 64x64 with K steps of 16,
+// 32 or 64 in FP32) of a new problem key is chosen by timing each (a GEMM
+// overwrites C, so repeats are harmless).
 hipError_t gemm_t(tdvp_ctx *c, DType ta, DType tb, DType tc, const GemmArgs &g0) {
   GemmArgs g = g0;
   if (c->autotune) {
     const std::vector<int64_t> key = {0, ta, tb, tc, g.M, g.N, g.K, g.batch, g.inst.count,
-                                      g.sak == 1, g.sbn == 1, g.scn == 1};
+                                      g.sak == 1, g.sbn == 1, g.scn == 1, (int64_t)c->prec};
     auto it = c->tuned.find(key);
     if (it != c->tuned.end()) {
       g.tile = it->second;
     } else if (can_tune(c, g.skip)) {
       int best = 32;
       double tbest = 1e300;
-      for (int cand : {32, 64}) {
+      for (int cand : {32, 64, 96, 128}) {
+        if (cand > 64 && (tc != F32 || c->prec == TDVP_BF16X3)) continue;   // FP32 arithmetic only
         g.tile = cand;
-        const double t = time_launch(c, [&] { return cgemm(ta, tb, tc, g, c->stream); });
+        const double t = time_launch(c, [&] { return gemm_any(c, ta, tb, tc, g); });
         if (t < tbest) { tbest = t; best = cand; }
       }
       c->tuned[key] = best;
@@ -180,7 +189,7 @@ hipError_t gemm_t(tdvp_ctx *c, DType ta, DType tb, DType tc, const GemmArgs &g0)
     }
   }
   const int id = prof_begin(c, TDVP_PROF_GEMM);
-  const hipError_t e = cgemm(ta, tb, tc, g, c->stream);
+  const hipError_t e = gemm_any(c, ta, tb, tc, g);
   const double M = g.M, N = g.N, K = g.K, B = g.batch;
   prof_end(c, id, 8.0 * M * N * K * B,
            (g.bsa ? B : 1.0) * M * K * esz(ta) + (g.bsb ? B : 1.0) * K * N * esz(tb) + B * M * N * esz(tc));
@@ -607,7 +616,7 @@ const char *tdvp_status_string(tdvp_status s) {
 
 tdvp_status tdvp_create(tdvp_ctx **ctx, int device, void *hip_stream, tdvp_precision prec) {
   if (!ctx) return TDVP_E_ARG;
-  if (prec != TDVP_FP64 && prec != TDVP_FP32) return TDVP_E_ARG;
+  if (prec != TDVP_FP64 && prec != TDVP_FP32 && prec != TDVP_BF16X3) return TDVP_E_ARG;
   int count = 0;
   if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return TDVP_E_DEVICE;
   tdvp_ctx *c = new (std::nothrow) tdvp_ctx;

@@ -38,10 +38,14 @@ struct GemmArgs {
   int conjA, conjB;
   const int *skip;
   Inst inst;                 // a = A, b = B, c = C strides
-  int tile;                  // 0: by problem size; 32: 32x32 tiles; 64: 64x64 tiles
+  int tile;                  // 0: by problem size; 32: 32x32 tiles; 64, 96, 128: 64x64 tiles with
+                             // K steps of 16, 32, 64 (the last two in FP32 arithmetic only)
 };
 
 hipError_t cgemm(DType ta, DType tb, DType tc, const GemmArgs &g, hipStream_t s);
+// Same product with split-BF16 matrix-core arithmetic and FP32 accumulation
+// (about 17 significant bits per operand); FP32 output only.
+hipError_t cgemm_bf3(DType ta, DType tb, DType tc, const GemmArgs &g, hipStream_t s);
 
 // Sparse MPO-channel contraction (stage 2 of H_eff / environment update):
 //   out[wo][so][a][c] = sum_{wi, si} Wt(wo, so, si, wi) * in[wi][si][a][c]

@@ -174,14 +174,195 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs g) {
       }
 }
 
+// Split-BF16 variant (FP32 accumulation): every real operand x is stored as
+// x_hi = bf16(x) and x_lo = bf16(x - x_hi), so x = x_hi + x_lo to about
+// 2^-17 |x|, and a real product is x_hi y_hi + x_hi y_lo + x_lo y_hi (the
+// x_lo y_lo term, ~2^-18 |x y|, is dropped).  The complex product uses the
+// same three real products as above; each is three bf16 MFMAs
+// (v_mfma_f32_16x16x32_bf16, 32 terms of k per instruction), nine per complex
+// 16x16x32 block.  The planes in LDS are [row][k] with k fastest (a lane's
+// eight k values are one 16-byte read) and a row pitch of 40 so that the
+// sixteen rows of a fragment fall in distinct banks.
+// Operand lane layout (checked on the device): A[i][k] in lane i + 16 (k / 8),
+// element k % 8; B[k][j] in lane j + 16 (k / 8), element k % 8; the result as
+// for v_mfma_f32_16x16x4_f32.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ void split_bf16(float x, __bf16 &hi, __bf16 &lo) {
+  hi = (__bf16)x;
+  lo = (__bf16)(x - (float)hi);
+}
+
+template <typename TA, typename TB, typename TC, int BM, int BN>
+__global__ __launch_bounds__(256) void cgemm_bf3_kernel(GemmArgs g) {
+  const int bz = blockIdx.z % g.batch;
+  const int ri = blockIdx.z / g.batch;
+  if (g.skip && g.skip[(int64_t)ri * g.inst.skip]) return;
+  using VA = typename Cplx<TA>::type;
+  using VB = typename Cplx<TB>::type;
+  using VC = typename Cplx<TC>::type;
+  constexpr int BK = 32, KP = 40;
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int TI = WM / 16, TJ = WN / 16;
+  // planes: re hi, re lo, im hi, im lo, (re + im) hi, (re + im) lo
+  __shared__ __attribute__((aligned(16))) __bf16 As[6][BM][KP];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[6][BN][KP];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int bm0 = blockIdx.y * BM;
+  const int bn0 = blockIdx.x * BN;
+  const VA *A = reinterpret_cast<const VA *>(g.A) + (int64_t)bz * g.bsa + (int64_t)ri * g.inst.a;
+  const VB *B = reinterpret_cast<const VB *>(g.B) + (int64_t)bz * g.bsb + (int64_t)ri * g.inst.b;
+  VC *C = reinterpret_cast<VC *>(g.C) + (int64_t)bz * g.bsc + (int64_t)ri * g.inst.c;
+  const int M = g.M, N = g.N, K = g.K;
+  const bool a_kfast = (g.sak == 1);
+  const bool b_nfast = (g.sbn == 1) || (g.sbk != 1);
+  const float sa = g.conjA ? -1.f : 1.f;
+  const float sb = g.conjB ? -1.f : 1.f;
+  const int wm0 = (wave >> 1) * WM;
+  const int wn0 = (wave & 1) * WN;
+
+  f32x4 p1[TI][TJ], p2[TI][TJ], p3[TI][TJ];
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) {
+      p1[i][j] = f32x4{0, 0, 0, 0};
+      p2[i][j] = f32x4{0, 0, 0, 0};
+      p3[i][j] = f32x4{0, 0, 0, 0};
+    }
+
+  constexpr int NA = BM * BK / 256, NB = BK * BN / 256;
+  VA ra[NA];
+  VB rb[NB];
+  auto load_tiles = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int e = tid + 256 * q;
+      int mm, kk;
+      if (a_kfast) { kk = e % BK; mm = e / BK; } else { mm = e % BM; kk = e / BM; }
+      const int gm = bm0 + mm, gk = k0 + kk;
+      ra[q].x = 0;
+      ra[q].y = 0;
+      if (gm < M && gk < K) ra[q] = A[(int64_t)gm * g.sam + (int64_t)gk * g.sak];
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int e = tid + 256 * q;
+      int nn, kk;
+      if (b_nfast) { nn = e % BN; kk = e / BN; } else { kk = e % BK; nn = e / BK; }
+      const int gn = bn0 + nn, gk = k0 + kk;
+      rb[q].x = 0;
+      rb[q].y = 0;
+      if (gn < N && gk < K) rb[q] = B[(int64_t)gk * g.sbk + (int64_t)gn * g.sbn];
+    }
+  };
+  load_tiles(0);
+  const int fr = lane & 15, fk = 8 * (lane >> 4);
+  for (int k0 = 0; k0 < K; k0 += BK) {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int e = tid + 256 * q;
+      int mm, kk;
+      if (a_kfast) { kk = e % BK; mm = e / BK; } else { mm = e % BM; kk = e / BM; }
+      const float xr = (float)ra[q].x, xi = sa * (float)ra[q].y;
+      split_bf16(xr, As[0][mm][kk], As[1][mm][kk]);
+      split_bf16(xi, As[2][mm][kk], As[3][mm][kk]);
+      split_bf16(xr + xi, As[4][mm][kk], As[5][mm][kk]);
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int e = tid + 256 * q;
+      int nn, kk;
+      if (b_nfast) { nn = e % BN; kk = e / BN; } else { kk = e % BK; nn = e / BK; }
+      const float yr = (float)rb[q].x, yi = sb * (float)rb[q].y;
+      split_bf16(yr, Bs[0][nn][kk], Bs[1][nn][kk]);
+      split_bf16(yi, Bs[2][nn][kk], Bs[3][nn][kk]);
+      split_bf16(yr + yi, Bs[4][nn][kk], Bs[5][nn][kk]);
+    }
+    __syncthreads();
+    if (k0 + BK < K) load_tiles(k0 + BK);
+    bf16x8 a[TI][6], b[TJ][6];
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+      for (int pl = 0; pl < 6; ++pl) a[i][pl] = *reinterpret_cast<const bf16x8 *>(&As[pl][wm0 + 16 * i + fr][fk]);
+#pragma unroll
+    for (int j = 0; j < TJ; ++j)
+#pragma unroll
+      for (int pl = 0; pl < 6; ++pl) b[j][pl] = *reinterpret_cast<const bf16x8 *>(&Bs[pl][wn0 + 16 * j + fr][fk]);
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+      for (int j = 0; j < TJ; ++j) {
+        p1[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][1], b[j][0], p1[i][j], 0, 0, 0);
+        p1[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0], b[j][1], p1[i][j], 0, 0, 0);
+        p1[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0], b[j][0], p1[i][j], 0, 0, 0);
+        p2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][3], b[j][2], p2[i][j], 0, 0, 0);
+        p2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][2], b[j][3], p2[i][j], 0, 0, 0);
+        p2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][2], b[j][2], p2[i][j], 0, 0, 0);
+        p3[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][5], b[j][4], p3[i][j], 0, 0, 0);
+        p3[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][4], b[j][5], p3[i][j], 0, 0, 0);
+        p3[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][4], b[j][4], p3[i][j], 0, 0, 0);
+      }
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = bm0 + wm0 + i * 16 + 4 * (lane >> 4) + r;
+        const int col = bn0 + wn0 + j * 16 + (lane & 15);
+        if (row < M && col < N) {
+          VC v;
+          v.x = (TC)(p1[i][j][r] - p2[i][j][r]);
+          v.y = (TC)(p3[i][j][r] - p1[i][j][r] - p2[i][j][r]);
+          C[(int64_t)row * g.scm + (int64_t)col * g.scn] = v;
+        }
+      }
+}
+
+template <typename TA, typename TB, typename TC>
+hipError_t launch_bf3(const GemmArgs &g, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.inst.count <= 0) return hipSuccess;
+  const int nz = g.batch * g.inst.count;
+  const int64_t tiles64 = (int64_t)((g.M + 63) / 64) * ((g.N + 63) / 64) * g.batch;
+  if (g.tile == 64 || (g.tile == 0 && tiles64 >= 240)) {
+    dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, nz);
+    hipLaunchKernelGGL((cgemm_bf3_kernel<TA, TB, TC, 64, 64>), grid, dim3(256), 0, s, g);
+  } else {
+    dim3 grid((g.N + 31) / 32, (g.M + 31) / 32, nz);
+    hipLaunchKernelGGL((cgemm_bf3_kernel<TA, TB, TC, 32, 32>), grid, dim3(256), 0, s, g);
+  }
+  return hipGetLastError();
+}
+
 template <typename TA, typename TB, typename TC, typename TM>
 hipError_t launch(const GemmArgs &g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.inst.count <= 0) return hipSuccess;
   const int nz = g.batch * g.inst.count;
   // the tile shape depends on one instance's problem only, so a batched
-  // launch computes every instance exactly as a single launch would
+  // launch computes every instance exactly as a single launch would.
+  // tile 64: 64x64 with K steps of 16; 96 / 128: 64x64 with K steps of 32 /
+  // 64 (FP32 arithmetic only: fewer, longer steps hide more load latency
+  // when K is short); 32: 32x32 with K steps of 32.
   const int64_t tiles64 = (int64_t)((g.M + 63) / 64) * ((g.N + 63) / 64) * g.batch;
-  if (g.tile == 64 || (g.tile == 0 && tiles64 >= 240)) {
+  constexpr bool F32M = sizeof(TM) == 4;
+  int tile = g.tile;
+  if (tile == 0) tile = tiles64 >= 240 ? 64 : 32;
+  if (!F32M && tile > 64) tile = 64;
+  if (F32M && tile == 96) {
+    dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, nz);
+    hipLaunchKernelGGL((cgemm_kernel<TA, TB, TC, TM, 64, 64, F32M ? 32 : 16>), grid, dim3(256), 0, s, g);
+  } else if (F32M && tile == 128) {
+    dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, nz);
+    hipLaunchKernelGGL((cgemm_kernel<TA, TB, TC, TM, 64, 64, F32M ? 64 : 16>), grid, dim3(256), 0, s, g);
+  } else if (tile == 64) {
     dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, nz);
     hipLaunchKernelGGL((cgemm_kernel<TA, TB, TC, TM, 64, 64, 16>), grid, dim3(256), 0, s, g);
   } else {
@@ -193,6 +374,15 @@ hipError_t launch(const GemmArgs &g, hipStream_t s) {
 }
 
 }  // namespace
+
+hipError_t cgemm_bf3(DType ta, DType tb, DType tc, const GemmArgs &g, hipStream_t s) {
+  if (tc != F32) return hipErrorInvalidValue;
+  if (ta == F64 && tb == F32) return launch_bf3<double, float, float>(g, s);
+  if (ta == F32 && tb == F64) return launch_bf3<float, double, float>(g, s);
+  if (ta == F32 && tb == F32) return launch_bf3<float, float, float>(g, s);
+  if (ta == F64 && tb == F64) return launch_bf3<double, double, float>(g, s);
+  return hipErrorInvalidValue;
+}
 
 hipError_t cgemm(DType ta, DType tb, DType tc, const GemmArgs &g, hipStream_t s) {
   if (ta == F64 && tb == F64 && tc == F64) return launch<double, double, double, double>(g, s);

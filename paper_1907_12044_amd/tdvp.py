@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libtdvp.so")
 
 FP64 = 0
 FP32 = 1
+BF16X3 = 2
 
 HARTREE_PER_CM = 4.556335252767e-6   # 1 cm^-1 in hartree
 AU_PER_FS = 41.341373335             # 1 fs in atomic units of time
