@@ -43,9 +43,11 @@ def parse():
     ap.add_argument("--realisations", type=int, default=64)
     ap.add_argument("--no-fused", action="store_true",
                     help="general multi-kernel Lanczos step everywhere (tdvp_set_fused(ctx, 0))")
-    ap.add_argument("--autotune", choices=["on", "off"], default="on",
-                    help="time candidate launch shapes of new problem keys in the first (warm-up) "
-                         "step (tdvp_set_autotune)")
+    ap.add_argument("--autotune", choices=["auto", "on", "off"], default="auto",
+                    help="time candidate GEMM tile shapes of new problem keys in the first (warm-up) "
+                         "step (tdvp_set_autotune); auto: on where the tiled GEMMs carry the "
+                         "contractions (bond dimension > 64, the ensemble), off where the fused "
+                         "small-bond step does (measured: no gain there)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 256 MiB device copy first (reference for HBM counters)")
     return ap.parse_args()
@@ -87,7 +89,12 @@ DTYPE_OF = {0: "c128", 1: "c64 contractions / c128 Krylov+QR",
 
 
 def autotune_on(args):
-    return args.autotune == "on"
+    if args.autotune != "auto":
+        return args.autotune == "on"
+    if args.workload == "ensemble":
+        return True
+    from inputs import WORKLOADS
+    return WORKLOADS[args.workload]["M"] > 64
 
 
 def measured_traffic(kernel, workload, precision):

@@ -181,20 +181,21 @@ tdvp_status tdvp_set_graph(tdvp_ctx *ctx, int enable);
  * compute the same quantities; results differ by rounding order only. */
 tdvp_status tdvp_set_fused(tdvp_ctx *ctx, int enable);
 
-/* Autotuner for the launch shapes of the contractions (a production
+/* Autotuner for the tile shapes of the contraction GEMMs (a production
  * pattern, not part of the paper's method).  With enable != 0, the first
- * time a problem key is met outside a graph capture -- a GEMM (types,
- * M, N, K, batch, instance count, operand layout) or a fused Lanczos solve
- * (M_l, d, M_r, W_l, W_r, instance count, precision) -- the candidate
- * launch shapes (GEMM tiles 32x32 / 64x64; the number P in {1, 2, 4, 8} of
- * work-groups that share an output column of the fused step) are each run
- * four times on the context stream and timed with HIP events (the host
- * waits for them), and the fastest is kept in the context for every later
- * launch of that key, captured graphs included.  The candidates compute the
- * same quantities; results differ by rounding order only, so a tuned run
- * agrees with an untuned one to round-off, not bit for bit.  With a step
- * graph enabled, the step that meets new keys runs eagerly and the graph is
- * captured after it.  Default: off. */
+ * time a GEMM problem key (types, M, N, K, batch, instance count, operand
+ * layout, precision) is met outside a graph capture, the candidate tile
+ * shapes (32x32 with K steps of 32; 64x64 with K steps of 16, and in FP32
+ * arithmetic also 32 and 64) are each run six times on the context stream
+ * and timed with HIP events (the host waits for them); the built-in choice
+ * is kept unless another shape is at least 3 % faster, and the choice is
+ * kept in the context for every later launch of that key, captured graphs
+ * included.  The candidates compute the same products; results differ by
+ * rounding order only, so a tuned run agrees with an untuned one to
+ * round-off, not bit for bit.  With a step graph enabled, the step that
+ * meets new keys runs eagerly and the graph is captured after it.  The
+ * fused small-bond Lanczos step keeps its built-in split (its cost depends
+ * on the Krylov index, which a one-shot timing cannot see).  Default: off. */
 tdvp_status tdvp_set_autotune(tdvp_ctx *ctx, int enable);
 /* Number of problem keys the autotuner has decided so far (host int). */
 tdvp_status tdvp_autotune_count(const tdvp_ctx *ctx, int32_t *count);

@@ -3,9 +3,9 @@ quantities, so a tuned run agrees with an untuned one to round-off; the
 step that meets new problem keys runs eagerly, later steps replay a graph
 built with the chosen shapes.
 
-* 77-site chain, M = 32, FP64 (fused Lanczos step, split P tuned): three
-  steps, populations / norm / energy within 1e-10 of the untuned run and of
-  the oracle's first step;
+* 77-site chain, M = 32, FP64 (fused Lanczos step; the environment-update
+  and centre-move GEMMs tuned): three steps, populations / norm / energy
+  within 1e-10 of the untuned run and of the oracle's first step;
 * same chain at M = 96, FP32 contractions (GEMM tiles tuned on the general
   path): populations within 1e-6 of the untuned run after two steps.
 """
