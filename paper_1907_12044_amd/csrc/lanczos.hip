@@ -305,7 +305,8 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_dots_kernel(LzState *st, LzPartia
     ypart = shift_bytes(ypart, wo);
     U = shift_bytes(U, wo);
   }
-  if (st->stop) return;
+  // the stop flag is loaded with the other inputs and tested before any write
+  const int stopped = st->stop;
   const int G = gridDim.x;
   StepPre pre;
   close_step_load(st, pp, upd_grid(n), j, 0, pre);
@@ -348,7 +349,7 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_dots_kernel(LzState *st, LzPartia
     }
     if (first) {
       first = false;
-      if (close_step_finish(st, pre, j, 0)) return;   // (synchronises the work-group)
+      if (stopped || close_step_finish(st, pre, j, 0)) return;   // (synchronises the work-group)
     }
     double wr = 0.0, wi = 0.0;
     if (e < n) {
@@ -382,6 +383,7 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_dots_kernel(LzState *st, LzPartia
     }
     __syncthreads();
   }
+  if (stopped) return;
   // reduce over the 32 threads of each group (half a wave), fixed tree
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
@@ -426,7 +428,10 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_update_kernel(LzState *st, LzPart
     U = shift_bytes(U, wo);
     if (Yp) Yp = shift_bytes(Yp, wo);
   }
-  if (st->stop) return;
+  // the stop flag was written by the previous kernel: its load is issued
+  // together with this kernel's other loads (all of them read memory that
+  // exists whether or not the solve has stopped) and tested before any write
+  const int stopped = st->stop;
   __shared__ double sh[8];
   __shared__ double cr[JB], ci[JB];
   __shared__ double2 pw[4][LU_E], ps[4][LU_E];
@@ -477,6 +482,7 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_update_kernel(LzState *st, LzPart
       a += __shfl_xor(a, o, LPI);
       b += __shfl_xor(b, o, LPI);
     }
+    if (stopped) return;   // (the same value in every thread)
     if (l8 == 0 && i <= j) {
       const double si = st->scale[i];
       const double sc = si * sj;
