@@ -233,6 +233,14 @@ enum {
   TDVP_PROF_LZ_FUSED = 7    /* fused H x + projections (heff_small_kernel)      */
 };
 tdvp_status tdvp_profile(tdvp_ctx *ctx, int kernel_class);
+/* Repeat count for timed launches of the classes whose launches overwrite
+ * outputs they do not read (TDVP_PROF_GEMM, TDVP_PROF_WAPPLY,
+ * TDVP_PROF_LZ_FUSED): each timed launch runs `reps` times back to back
+ * between its two events and tdvp_profile_read divides by reps, so the time
+ * per launch is the kernel's duration plus the gap between two queued
+ * kernels rather than one whole dispatch.  1 <= reps <= 64 (default 1);
+ * the results are those of one launch. */
+tdvp_status tdvp_profile_reps(tdvp_ctx *ctx, int reps);
 tdvp_status tdvp_profile_read(tdvp_ctx *ctx, double *ms, int64_t *launches, double *flops,
                               double *bytes);
 

@@ -26,6 +26,7 @@ namespace {
 struct ProfRec {
   hipEvent_t a, b;
   double flops, bytes;
+  int reps;                       // launches between the two events (same work each)
 };
 }  // namespace
 
@@ -36,6 +37,7 @@ struct tdvp_ctx {
   char *ws;
   size_t ws_bytes;
   int prof_class;                 // 0: timing off
+  int prof_reps;                  // back-to-back repeats of a timed launch of a class that may repeat
   std::vector<ProfRec> prof;
   std::vector<hipEvent_t> pool;
   size_t pool_used;
@@ -115,11 +117,22 @@ hipEvent_t pool_event(tdvp_ctx *c) {
 // Start/stop a timed launch of class `cls` (no-op unless that class is profiled).
 int prof_begin(tdvp_ctx *c, int cls) {
   if (c->prof_class != cls) return -1;
-  ProfRec r{pool_event(c), pool_event(c), 0.0, 0.0};
+  ProfRec r{pool_event(c), pool_event(c), 0.0, 0.0, 1};
   if (!r.a || !r.b) return -1;
   hipEventRecord(r.a, c->stream);
   c->prof.push_back(r);
   return (int)c->prof.size() - 1;
+}
+// Timed launches of the classes whose launches may be repeated (they
+// overwrite outputs they do not read: GEMM, MPO pass, fused Lanczos step)
+// run prof_reps times back to back, so that the event interval measures the
+// kernels rather than one dispatch each.
+template <typename F> hipError_t timed_repeat(tdvp_ctx *c, int idx, F launch) {
+  hipError_t e = launch();
+  if (idx < 0) return e;
+  for (int r = 1; r < c->prof_reps && e == hipSuccess; ++r) e = launch();
+  c->prof[idx].reps = c->prof_reps;
+  return e;
 }
 void prof_end(tdvp_ctx *c, int idx, double flops, double bytes) {
   if (idx < 0) return;
@@ -195,7 +208,7 @@ hipError_t gemm_t(tdvp_ctx *c, DType ta, DType tb, DType tc, const GemmArgs &g0)
     }
   }
   const int id = prof_begin(c, TDVP_PROF_GEMM);
-  const hipError_t e = gemm_any(c, ta, tb, tc, g);
+  const hipError_t e = timed_repeat(c, id, [&] { return gemm_any(c, ta, tb, tc, g); });
   const double M = g.M, N = g.N, K = g.K, B = g.batch;
   prof_end(c, id, 8.0 * M * N * K * B,
            (g.bsa ? B : 1.0) * M * K * esz(ta) + (g.bsb ? B : 1.0) * K * N * esz(tb) + B * M * N * esz(tc));
@@ -204,7 +217,7 @@ hipError_t gemm_t(tdvp_ctx *c, DType ta, DType tb, DType tc, const GemmArgs &g0)
 
 hipError_t wapply_t(tdvp_ctx *c, DType t, const WApplyArgs &a) {
   const int id = prof_begin(c, TDVP_PROF_WAPPLY);
-  const hipError_t e = wapply(t, a, c->stream);
+  const hipError_t e = timed_repeat(c, id, [&] { return wapply(t, a, c->stream); });
   const double io = (double)a.A * a.C * a.d * esz(t);
   prof_end(c, id, 0.0, io * (a.Wl + a.Wr));
   return e;
@@ -382,7 +395,7 @@ tdvp_status run_lanczos(tdvp_ctx *c, const Layout &lay, const Op &op, double zr,
                         (op.W ? Wl * d * d * Wr * 16.0 : 0.0);
       id = prof_begin(c, TDVP_PROF_LZ_FUSED);
       fa.j = j;
-      CK(heff_small(env_type(c), fa, b.R, c->stream));
+      CK(timed_repeat(c, id, [&] { return heff_small(env_type(c), fa, b.R, c->stream); }));
       prof_end(c, id, fl * b.R, by * b.R + (j + 2) * vb);
       id = prof_begin(c, TDVP_PROF_LZ_UPDATE);
       CK(lz_update(st, pp, U, n, j, n, op.Mr * fa.P, fa.Yp, fa.P, li, c->stream));
@@ -605,6 +618,7 @@ tdvp_status tdvp_create(tdvp_ctx **ctx, int device, void *hip_stream, tdvp_preci
   c->ws = nullptr;
   c->ws_bytes = 0;
   c->prof_class = 0;
+  c->prof_reps = 1;
   c->pool_used = 0;
   c->klog = nullptr;
   c->klog_cap = 0;
@@ -658,6 +672,12 @@ tdvp_status tdvp_profile(tdvp_ctx *ctx, int kernel_class) {
   return TDVP_OK;
 }
 
+tdvp_status tdvp_profile_reps(tdvp_ctx *ctx, int reps) {
+  if (!ctx || reps < 1 || reps > 64) return TDVP_E_ARG;
+  ctx->prof_reps = reps;
+  return TDVP_OK;
+}
+
 tdvp_status tdvp_profile_read(tdvp_ctx *ctx, double *ms, int64_t *launches, double *flops, double *bytes) {
   if (!ctx || !ms || !launches || !flops || !bytes) return TDVP_E_ARG;
   CK(hipStreamSynchronize(ctx->stream));
@@ -665,7 +685,7 @@ tdvp_status tdvp_profile_read(tdvp_ctx *ctx, double *ms, int64_t *launches, doub
   for (const ProfRec &r : ctx->prof) {
     float e = 0.0f;
     CK(hipEventElapsedTime(&e, r.a, r.b));
-    t += e;
+    t += e / r.reps;
     f += r.flops;
     b += r.bytes;
   }

@@ -69,6 +69,7 @@ EXPORTS = {
     "tdvp_set_graph": (c_int, [c_void_p, c_int]),
     "tdvp_set_fused": (c_int, [c_void_p, c_int]),
     "tdvp_set_autotune": (c_int, [c_void_p, c_int]),
+    "tdvp_profile_reps": (c_int, [c_void_p, c_int]),
     "tdvp_autotune_count": (c_int, [c_void_p, c_void_p]),
     "tdvp_ps_step_batched": (c_int, [c_void_p, c_int, POINTER(_Mps), POINTER(_Mpo), POINTER(_Envs),
                                      c_double, c_int, c_int, c_double]),
@@ -348,6 +349,10 @@ def set_krylov_log(ctx, buf):
 
 def profile(ctx, kernel_class):
     _check(lib().tdvp_profile(ctx.h, kernel_class), "tdvp_profile")
+
+
+def profile_reps(ctx, reps):
+    _check(lib().tdvp_profile_reps(ctx.h, reps), "tdvp_profile_reps")
 
 
 def profile_read(ctx):
