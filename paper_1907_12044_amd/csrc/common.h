@@ -10,8 +10,7 @@
 namespace tdvp {
 
 constexpr int KMAX = 32;          // largest Krylov dimension compiled in
-constexpr int LZ_GRID = 512;      // most work-groups of lz_start / lz_update (norm partials)
-constexpr int LZ_DOTS_GRID = 256; // most work-groups of lz_finish
+constexpr int LZ_GRID = 512;      // most work-groups of lz_start / lz_update / lz_finish
 constexpr int LZ_PARTS = 512;     // most per-work-group partials of one reduction
 constexpr int LZ_BLOCK = 256;
 

@@ -552,9 +552,10 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_update_kernel(LzState *st, LzPart
 }
 
 // y = |x| sum_i [exp(z T_k) e_1]_i v_i with k = the final basis size (keff
-// unless the solve stopped early).  Every block evaluates the small
-// exponential redundantly (wave 0), then combines its slice of the basis;
-// the basis loads of a thread's first element are issued first.
+// unless the solve stopped early).  Every work-group evaluates the small
+// exponential redundantly (wave 0) and combines LU_E elements per pass:
+// wave q adds the basis vectors i = q, q + 4, ..., whose loads are issued
+// before the exponential, and wave 0 adds the four wave sums in order.
 template <int KB>
 __global__ __launch_bounds__(LZ_BLOCK) void lz_finish_kernel(LzState *st, const double2 *U,
                                                              int64_t ldu, int64_t n, int keff,
@@ -568,15 +569,19 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_finish_kernel(LzState *st, const 
     if (k_used) k_used += blockIdx.y;
   }
   __shared__ double cr[KMAX], ci[KMAX];
-  constexpr int PF = KB < 8 ? KB : 8;
-  const int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double2 uv[PF];
+  __shared__ double2 ps[4][LU_E];
+  constexpr int NI = (KB + 3) / 4;         // basis vectors per wave
+  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int64_t b0 = (int64_t)blockIdx.x * LU_E, bstride = (int64_t)gridDim.x * LU_E;
+  double2 uv[NI];
 #define LZ_FINISH_LOAD(e)                                                                  \
   do {                                                                                     \
-    _Pragma("unroll") for (int i = 0; i < PF; ++i)                                         \
-      uv[i] = i < keff ? U[(int64_t)i * ldu + (e)] : make_double2(0.0, 0.0);               \
+    _Pragma("unroll") for (int t = 0; t < NI; ++t) {                                       \
+      const int i = q + 4 * t;                                                             \
+      uv[t] = (i < keff && (e) < n) ? U[(int64_t)i * ldu + (e)] : make_double2(0.0, 0.0);  \
+    }                                                                                      \
   } while (0)
-  if (e0 < n) LZ_FINISH_LOAD(e0);
+  if (b0 < n) LZ_FINISH_LOAD(b0 + lane);
   const int k = st->stop ? st->k : keff;
   const double xn = st->xnorm;
   const bool zero = !(xn > 0.0) || k <= 0;
@@ -589,30 +594,40 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_finish_kernel(LzState *st, const 
     ci[threadIdx.x] *= sc;
   }
   __syncthreads();
-  for (int64_t e = e0; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-    if (e != e0) LZ_FINISH_LOAD(e);
+  for (int64_t base = b0; base < n; base += bstride) {
+    const int64_t e = base + lane;
+    double2 ucur[NI];
+#pragma unroll
+    for (int t = 0; t < NI; ++t) ucur[t] = uv[t];
+    if (base + bstride < n) LZ_FINISH_LOAD(base + bstride + lane);
     double yr = 0.0, yi = 0.0;
     if (!zero) {
 #pragma unroll
-      for (int i = 0; i < PF; ++i) {
+      for (int t = 0; t < NI; ++t) {
+        const int i = q + 4 * t;
         if (i < k) {
-          yr += cr[i] * uv[i].x - ci[i] * uv[i].y;
-          yi += cr[i] * uv[i].y + ci[i] * uv[i].x;
+          yr += cr[i] * ucur[t].x - ci[i] * ucur[t].y;
+          yi += cr[i] * ucur[t].y + ci[i] * ucur[t].x;
         }
       }
-#pragma unroll 8
-      for (int i = PF; i < k; ++i) {
-        const double2 u = U[(int64_t)i * ldu + e];
-        yr += cr[i] * u.x - ci[i] * u.y;
-        yi += cr[i] * u.y + ci[i] * u.x;
+    }
+    ps[q][lane] = make_double2(yr, yi);
+    __syncthreads();
+    if (q == 0 && e < n) {
+      double2 v = ps[0][lane];
+#pragma unroll
+      for (int t = 1; t < 4; ++t) {
+        v.x += ps[t][lane].x;
+        v.y += ps[t][lane].y;
+      }
+      if (trows > 0) {
+        const int64_t tcols = n / trows;
+        y[(e % trows) * tcols + e / trows] = v;
+      } else {
+        y[e] = v;
       }
     }
-    if (trows > 0) {
-      const int64_t tcols = n / trows;
-      y[(e % trows) * tcols + e / trows] = make_double2(yr, yi);
-    } else {
-      y[e] = make_double2(yr, yi);
-    }
+    __syncthreads();
   }
 #undef LZ_FINISH_LOAD
   if (k_used && blockIdx.x == 0 && threadIdx.x == 0) *k_used = zero ? 0 : k;
@@ -1052,15 +1067,6 @@ __global__ __launch_bounds__(WT_THREADS) void wtable_kernel(const double2 *W, in
   if (t == 0) rowp[rows] = base_s;
 }
 
-// Work-groups for an n-element vector pass: one element per thread, at most
-// LZ_GRID groups (so the partial sums stay short).
-int grid_for(int64_t n) {
-  int64_t g = (n + LZ_BLOCK - 1) / LZ_BLOCK;
-  if (g > LZ_DOTS_GRID) g = LZ_DOTS_GRID;
-  if (g < 1) g = 1;
-  return (int)g;
-}
-
 // Work-groups of lz_dots: one 256-element chunk each, at most LZ_PARTS.
 int dots_grid(int64_t n) {
   int64_t g = (n + LZ_BLOCK - 1) / LZ_BLOCK;
@@ -1178,12 +1184,14 @@ hipError_t wtable(const double2 *W, int Wl, int d, int Wr, int64_t sW, int *rowp
 
 hipError_t lz_finish(LzState *st, const double2 *U, int64_t ldu, int64_t n, int keff, double2 *y,
                      int32_t *k_used, int trows, const LzInst &in, hipStream_t s) {
-  const dim3 g(grid_for(n), in.count), b(LZ_BLOCK);
+  if (keff > KMAX) return hipErrorInvalidValue;
+  const dim3 g(upd_grid(n), in.count), b(LZ_BLOCK);
 #define LZ_FIN(KB) \
   hipLaunchKernelGGL((lz_finish_kernel<KB>), g, b, 0, s, st, U, ldu, n, keff, y, k_used, trows, in)
   if (keff <= 4) LZ_FIN(4);
   else if (keff <= 8) LZ_FIN(8);
-  else LZ_FIN(16);
+  else if (keff <= 16) LZ_FIN(16);
+  else LZ_FIN(32);
 #undef LZ_FIN
   return hipGetLastError();
 }
