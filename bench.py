@@ -238,7 +238,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the ensemble would shard realisations across GPUs, see DESIGN.md", file=sys.stderr)
+              "independent disorder realisations would be sharded one process per GPU", file=sys.stderr)
         sys.exit(2)
     if args.workload.startswith("ensemble"):
         return ensemble_main(args)

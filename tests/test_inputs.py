@@ -7,6 +7,35 @@ from inputs.fmo import electronic_order, ensemble_bond
 from oracle import mps as om
 
 
+def _golden(name):
+    import os
+    out = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", name)) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                key, *vals = line.split()
+                out[key] = [int(v) for v in vals]
+    return out
+
+
+def test_chain_matches_the_printed_fmo_chain():
+    """Chain order and degree-of-freedom count printed for the paper's
+    7-site model with 35 modes per site (tests/golden/fmo_chain.txt)."""
+    g = _golden("fmo_chain.txt")
+    assert [m + 1 for m in electronic_order(7)] == g["chain_order"]
+    p = draw_params(7, g["modes_per_site"][0], 2, seed=0)
+    sites = chain_sites(p)
+    assert len(sites) == g["total_dofs"][0]
+    assert sum(1 for s in sites if s[0] == "vib") == g["vibrational_dofs"][0]
+    el = [s[1] + 1 for s in sites if s[0] == "el"]
+    assert el == g["chain_order"]
+    # every electronic site is followed by its own modes
+    for i, s in enumerate(sites):
+        if s[0] == "vib":
+            owner = next(t for t in reversed(sites[:i]) if t[0] == "el")
+            assert s[1] == owner[1]
+
+
 def test_chain_order_matches_paper_for_seven_sites():
     # electronic sites in the order 7,5,3,1,2,4,6 (1-based), modes after their site
     assert [m + 1 for m in electronic_order(7)] == [7, 5, 3, 1, 2, 4, 6]
