@@ -104,12 +104,14 @@ def test_fmo77_m32_fp64_matches_oracle(fused):
 
 
 def test_fmo77_m32_full_length_conserves_norm_and_energy():
+    """The run length of this workload (500 steps of 2 fs = 1 ps), in the
+    launch configuration the benchmark times (graph replay)."""
     require_gpu()
     p, sites, phys, dims, raw, w = workload("fmo7x10x8_M32")
     tau = w["dt_fs"] * model.AU_PER_FS
     run = _gpu_run(p, sites, raw)
     e0 = run.observe_host().copy()
-    run.step(tau, 50)
+    run.step(tau, w["steps"])
     obs = run.observe_host()
     assert abs(obs[0] - 1.0) < 1e-11
     # shifted energy (the large constant cancels) conserved to round-off
