@@ -17,7 +17,8 @@
 // inverse on the matrix cores) and cgemm for W R^{-1} and
 // the running product of the R factors (the last ones write Q and R through
 // the caller's strides).
-// n <= 128.
+// One cq_chol call factors n <= 128; up to n = 256 the factorisation is
+// blocked 2 x 2 around two calls (see cholqr).
 #include <utility>
 
 #include "common.h"
@@ -177,10 +178,10 @@ __device__ __forceinline__ double2 grp(double2 v, int gk) { return make_double2(
 // template argument so every lane move is an immediate-controlled DPP /
 // swap and all registers are indexed statically.
 template <int k> __device__ __forceinline__ void chol_step(double2 (&d)[4], double2 (&r)[4], double (&yk)[16],
-                                                           int g, int c) {
+                                                           int g, int c, double pmin) {
   constexpr int qk = k >> 2, gk = k & 3;
   double p = rd_lane(d[qk].x, 16 * gk + k);
-  if (!(p > 1e-300)) p = 1e-300;                    // not positive definite: keep the values finite
+  if (!(p > pmin)) p = pmin;                        // (numerically) singular: floor the pivot
   const double y = rsqrt_nr(p), ip = y * y;
   yk[k] = y;
   const double2 dkc = grp(d[qk], gk);               // D[k][c] in every row group
@@ -218,8 +219,8 @@ template <int k> __device__ __forceinline__ void inv_step(double2 (&b)[4], doubl
 }
 template <int... ks>
 __device__ __forceinline__ void chol_block(double2 (&d)[4], double2 (&r)[4], double (&yk)[16], int g, int c,
-                                           std::integer_sequence<int, ks...>) {
-  (chol_step<ks>(d, r, yk, g, c), ...);
+                                           double pmin, std::integer_sequence<int, ks...>) {
+  (chol_step<ks>(d, r, yk, g, c, pmin), ...);
 }
 template <int... ks>
 __device__ __forceinline__ void inv_block(double2 (&b)[4], double2 (&x)[4], const double2 (&r)[4],
@@ -237,7 +238,9 @@ __device__ __forceinline__ void inv_block(double2 (&b)[4], double2 (&x)[4], cons
 // R^{-1} are written as full n x n matrices (zeros below the diagonal).
 struct CholArgs {
   const double2 *G; double2 *R; double2 *Rinv;
-  int m, n, shift;
+  int n, ld;                       // order of this block; row stride of G, R and Rinv
+  const double *diag;              // device: [0] diagonal shift, [1] pivot floor (cq_diag_kernel)
+  int shift;                       // add diag[0] to the diagonal
   int64_t ws;                      // instance stride of the work area (elements)
 };
 
@@ -255,7 +258,7 @@ __global__ __launch_bounds__(CQ_CHOL_THREADS) void cq_chol_kernel(CholArgs a) {
   const double2 *G = a.G + inst * a.ws;
   double2 *Rout = a.R + inst * a.ws;
   double2 *Rinv = a.Rinv + inst * a.ws;
-  const int n = a.n, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int n = a.n, ld = a.ld, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nb = (n + 15) / 16, np = 16 * nb;
   // row-major copies: thread (i0, j) takes column j, rows i0 + CQ_RSTEP u
   const int cj = tid & (CQ_NMAX - 1), ci0 = tid / CQ_NMAX;
@@ -266,7 +269,7 @@ __global__ __launch_bounds__(CQ_CHOL_THREADS) void cq_chol_kernel(CholArgs a) {
     for (int u = 0; u < CQ_UL; ++u) {
       const int i = ci0 + CQ_RSTEP * u;
       v[u] = make_double2(0.0, 0.0);
-      if (i < n && cj < n && (cj >> 4) >= (i >> 4)) v[u] = G[(int64_t)i * n + cj];
+      if (i < n && cj < n && (cj >> 4) >= (i >> 4)) v[u] = G[(int64_t)i * ld + cj];
       else if (i == cj) v[u] = make_double2(1.0, 0.0);
     }
 #pragma unroll
@@ -276,13 +279,10 @@ __global__ __launch_bounds__(CQ_CHOL_THREADS) void cq_chol_kernel(CholArgs a) {
     }
   }
   __syncthreads();
-  // diagonal shift from the trace (first pass)
+  const double pmin = a.diag[inst * a.ws * 2 + 1];
+  // diagonal shift (first pass)
   if (a.shift && wave == 0) {
-    double tr = 0.0;
-    for (int i = lane; i < n; i += 64) tr += Bk[bidx(i >> 4, i >> 4, nb) * 256 + bo(i & 15, i & 15)].x;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) tr += __shfl_xor(tr, o, 64);
-    const double shift = 11.0 * ((double)a.m * n + (double)n * (n + 1)) * 1.1102230246251565e-16 * tr;
+    const double shift = a.diag[inst * a.ws * 2];
     for (int i = lane; i < n; i += 64) Bk[bidx(i >> 4, i >> 4, nb) * 256 + bo(i & 15, i & 15)].x += shift;
   }
   __syncthreads();
@@ -300,11 +300,11 @@ __global__ __launch_bounds__(CQ_CHOL_THREADS) void cq_chol_kernel(CholArgs a) {
         b[q] = make_double2(i == c ? 1.0 : 0.0, 0.0);
       }
       double yk[16];
-      chol_block(d, r, yk, g, c, std::make_integer_sequence<int, 16>{});
+      chol_block(d, r, yk, g, c, pmin, std::make_integer_sequence<int, 16>{});
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int i = 16 * K + g + 4 * q, jj = 16 * K + c;
-        if (i < n && jj < n) Rout[(int64_t)i * n + jj] = r[q];
+        if (i < n && jj < n) Rout[(int64_t)i * ld + jj] = r[q];
       }
       inv_block(b, x, r, yk, g, std::make_integer_sequence<int, 16>{});
 #pragma unroll
@@ -355,7 +355,7 @@ __global__ __launch_bounds__(CQ_CHOL_THREADS) void cq_chol_kernel(CholArgs a) {
 #pragma unroll
     for (int u = 0; u < CQ_U; ++u) {
       const int i = s0 + ci0 + CQ_RSTEP * u;
-      if (i < n && cj < n && (cj >> 4) != (i >> 4)) Rout[(int64_t)i * n + cj] = v[u];
+      if (i < n && cj < n && (cj >> 4) != (i >> 4)) Rout[(int64_t)i * ld + cj] = v[u];
     }
   }
   __syncthreads();
@@ -395,17 +395,68 @@ __global__ __launch_bounds__(CQ_CHOL_THREADS) void cq_chol_kernel(CholArgs a) {
 #pragma unroll
     for (int u = 0; u < CQ_U; ++u) {
       const int i = s0 + ci0 + CQ_RSTEP * u;
-      if (i < n && cj < n) Rinv[(int64_t)i * n + cj] = v[u];
+      if (i < n && cj < n) Rinv[(int64_t)i * ld + cj] = v[u];
     }
+  }
+}
+
+// Per instance (one work-group each), from the diagonal of G: out[0] = the
+// first pass's shift s = 11 (m n + n (n + 1)) u tr(G) (0 when !shift), and
+// out[1] = the pivot floor 1e-20 max_i (G_ii + s): a Schur-complement pivot
+// below it (a numerically singular G, e.g. from an exactly rank-deficient
+// input) is replaced by it, which lifts the null directions to moderate
+// size so that the next passes orthonormalise them instead of overflowing.
+__global__ __launch_bounds__(256) void cq_diag_kernel(const double2 *G, int m, int n, int shift,
+                                                      double *out, int64_t ws) {
+  __shared__ double part[4], pmax[4];
+  const int64_t inst = blockIdx.x;
+  G += inst * ws;
+  double t = 0.0, mx = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    const double v = G[(int64_t)i * n + i].x;
+    t += v;
+    mx = fmax(mx, v);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    t += __shfl_xor(t, o, 64);
+    mx = fmax(mx, __shfl_xor(mx, o, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    part[threadIdx.x >> 6] = t;
+    pmax[threadIdx.x >> 6] = mx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double tr = part[0] + part[1] + part[2] + part[3];
+    const double gmax = fmax(fmax(pmax[0], pmax[1]), fmax(pmax[2], pmax[3]));
+    const double s = shift ? 11.0 * ((double)m * n + (double)n * (n + 1)) * 1.1102230246251565e-16 * tr : 0.0;
+    out[inst * ws * 2] = s;
+    out[inst * ws * 2 + 1] = fmax(1e-20 * (gmax + s), 1e-300);
+  }
+}
+
+// zero the rows nlo..n-1, columns 0..nlo-1 of two n x n matrices
+__global__ __launch_bounds__(256) void cq_zero_lower_kernel(double2 *A, double2 *B, int n, int nlo,
+                                                            int64_t ws) {
+  const int64_t inst = blockIdx.y;
+  A += inst * ws;
+  B += inst * ws;
+  const int64_t cnt = (int64_t)(n - nlo) * nlo;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < cnt; e += (int64_t)gridDim.x * 256) {
+    const int64_t i = nlo + e / nlo, j = e % nlo;
+    A[i * n + j] = make_double2(0.0, 0.0);
+    B[i * n + j] = make_double2(0.0, 0.0);
   }
 }
 
 }  // namespace
 
-bool cholqr_ok(int m, int n) { return n >= 1 && n <= CQ_NMAX && m >= n; }
+bool cholqr_ok(int m, int n) { return n >= 1 && n <= 2 * CQ_NMAX && m >= n; }
 
 int64_t cholqr_work_elems(int m, int n) {
-  return 3 * (int64_t)m * n + 5 * (int64_t)n * n;   // W_0..W_2, G, R_p, Rinv, two running products
+  // W_0..W_2, G, R_p, Rinv, two running products, a block temporary, the shift
+  return 3 * (int64_t)m * n + 6 * (int64_t)n * n + 16;
 }
 
 hipError_t cholqr(const QrArgs &p, hipStream_t s) {
@@ -423,14 +474,32 @@ hipError_t cholqr(const QrArgs &p, hipStream_t s) {
   double2 *G = p.work + 3 * mn;
   double2 *Rk = G + nn, *Rinv = Rk + nn;
   double2 *Racc[2] = {Rinv + nn, Rinv + 2 * nn};
+  double2 *Tm = Rinv + 3 * nn;
+  double *diagv = reinterpret_cast<double *>(Tm + nn);   // shift, pivot floor
   {
     int64_t gx = (mn + 255) / 256;
     if (gx > 1024) gx = 1024;
     hipLaunchKernelGGL(cq_prep_kernel, dim3((unsigned)gx, R), dim3(256), 0, s, p, Wb[0], ws);
   }
   const int nt = (n + 15) / 16;
-  const int nbk = (n + 15) / 16;
-  const size_t lds = (size_t)(nbk * (nbk + 1) / 2) * 256 * sizeof(double2);
+  // one cq_chol call covers at most CQ_NMAX; beyond that the factorisation
+  // is blocked 2 x 2 (n1 = CQ_NMAX):
+  //   R11 = chol(G11 + s I), R12 = R11^{-H} G12, R22 = chol(G22 + s I - R12^H R12),
+  //   R^{-1} = [R11^{-1}, -R11^{-1} R12 R22^{-1}; 0, R22^{-1}]
+  const int n1 = n <= CQ_NMAX ? n : CQ_NMAX, n2 = n - n1;
+  auto lds_of = [](int k) { const int b = (k + 15) / 16; return (size_t)(b * (b + 1) / 2) * 256 * sizeof(double2); };
+  // general product Z (M x N) = op(X) (M x K) Y (K x N) in the work area, row strides given
+  auto gemm = [&](const double2 *X, int64_t xr, int64_t xc, int conjX, const double2 *Y, int64_t yr,
+                  double2 *Z, int64_t zr, int M_, int N_, int K_, int mode) {
+    GemmArgs g{};
+    g.A = X; g.B = Y; g.C = Z;
+    g.M = M_; g.N = N_; g.K = K_; g.batch = 1;
+    g.sam = xr; g.sak = xc; g.sbk = yr; g.sbn = 1; g.scm = zr; g.scn = 1;
+    g.conjA = conjX;
+    g.mode = mode;
+    g.inst.count = R; g.inst.a = ws; g.inst.b = ws; g.inst.c = ws;
+    return cgemm(F64, F64, F64, g, s);
+  };
   // n x n product X Y (row-major operands in the work area) into Z with
   // strides (zr, zc) and instance stride zs; conj: conjugated result
   auto nn_gemm = [&](const double2 *X, const double2 *Y, double2 *Z, int64_t zr, int64_t zc,
@@ -447,14 +516,38 @@ hipError_t cholqr(const QrArgs &p, hipStream_t s) {
     const bool last = pass == 2;
     hipLaunchKernelGGL(cq_gram_kernel, dim3(nt * (nt + 1) / 2, R), dim3(CQ_THREADS), 0, s, Wb[pass],
                        m, n, G, ws);
+    hipLaunchKernelGGL(cq_diag_kernel, dim3(R), dim3(256), 0, s, G, m, n, pass == 0 ? 1 : 0, diagv, ws);
+    double2 *Rp = pass == 0 ? Racc[0] : Rk;
     CholArgs ca{};
-    ca.G = G; ca.R = pass == 0 ? Racc[0] : Rk; ca.Rinv = Rinv;
-    ca.m = m; ca.n = n; ca.ws = ws;
+    ca.G = G; ca.R = Rp; ca.Rinv = Rinv;
+    ca.n = n1; ca.ld = n; ca.ws = ws;
+    ca.diag = diagv;
     ca.shift = pass == 0;
-    hipLaunchKernelGGL(cq_chol_kernel, dim3(R), dim3(CQ_CHOL_THREADS), lds, s, ca);
+    hipLaunchKernelGGL(cq_chol_kernel, dim3(R), dim3(CQ_CHOL_THREADS), lds_of(n1), s, ca);
+    hipError_t e = hipSuccess;
+    if (n2 > 0) {
+      // R12 = R11^{-H} G12 (into R), then G22 <- G22 - R12^H R12
+      e = gemm(Rinv, 1, n, 1, G + n1, n, Rp + n1, n, n1, n2, n1, 0);
+      if (e == hipSuccess) e = gemm(Rp + n1, 1, n, 1, Rp + n1, n, G + (int64_t)n1 * n + n1, n, n2, n2, n1, 1);
+      if (e != hipSuccess) return e;
+      CholArgs cb = ca;
+      cb.G = G + (int64_t)n1 * n + n1;
+      cb.R = Rp + (int64_t)n1 * n + n1;
+      cb.Rinv = Rinv + (int64_t)n1 * n + n1;
+      cb.n = n2;
+      hipLaunchKernelGGL(cq_chol_kernel, dim3(R), dim3(CQ_CHOL_THREADS), lds_of(n2), s, cb);
+      // upper-right block of R^{-1}: -R11^{-1} (R12 R22^{-1})
+      e = gemm(Rp + n1, n, 1, 0, Rinv + (int64_t)n1 * n + n1, n, Tm, n2, n1, n2, n2, 0);
+      if (e == hipSuccess) e = gemm(Rinv, n, 1, 0, Tm, n2, Rinv + n1, n, n1, n2, n1, 2);
+      if (e != hipSuccess) return e;
+      {
+        int64_t gx = ((int64_t)n2 * n1 + 255) / 256;
+        if (gx > 256) gx = 256;
+        hipLaunchKernelGGL(cq_zero_lower_kernel, dim3((unsigned)gx, R), dim3(256), 0, s, Rp, Rinv, n, n1, ws);
+      }
+    }
     // R = R_3 R_2 R_1, accumulated from the left; the last product goes to
     // the caller's R through its strides
-    hipError_t e = hipSuccess;
     if (pass == 1) e = nn_gemm(Rk, Racc[0], Racc[1], n, 1, ws, 0);
     if (last) e = nn_gemm(Rk, Racc[1], p.R, p.r_rs, p.r_cs, p.inst.c, p.conjR);
     if (e != hipSuccess) return e;

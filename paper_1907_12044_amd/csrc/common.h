@@ -39,6 +39,7 @@ struct GemmArgs {
   Inst inst;                 // a = A, b = B, c = C strides
   int tile;                  // 0: by problem size; 32: 32x32 tiles; 64, 96, 128: 64x64 tiles with
                              // K steps of 16, 32, 64 (the last two in FP32 arithmetic only)
+  int mode;                  // 0: C = op(A) op(B); 1: C = C - op(A) op(B); 2: C = -op(A) op(B)
 };
 
 hipError_t cgemm(DType ta, DType tb, DType tc, const GemmArgs &g, hipStream_t s);
@@ -155,7 +156,7 @@ struct QrArgs {
   Inst inst;      // a = A, b = Q, c = R strides; skip = work stride (elements)
 };
 hipError_t qr(const QrArgs &a, hipStream_t s);
-// Shifted Cholesky QR (three passes) for m >= n, n <= 128; the work area
+// Shifted Cholesky QR (three passes) for m >= n, n <= 256; the work area
 // (QrArgs::work, instance stride inst.skip) must hold cholqr_work_elems c128.
 bool cholqr_ok(int m, int n);
 int64_t cholqr_work_elems(int m, int n);

@@ -166,10 +166,19 @@ __global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs g) {
         const int row = bm0 + wm0 + i * 16 + rr;
         const int col = bn0 + wn0 + j * 16 + (lane & 15);
         if (row < M && col < N) {
+          TM re = p1[i][j][r] - p2[i][j][r], im = p3[i][j][r] - p1[i][j][r] - p2[i][j][r];
+          VC &dst = C[(int64_t)row * g.scm + (int64_t)col * g.scn];
+          if (g.mode == 1) {
+            re = (TM)dst.x - re;
+            im = (TM)dst.y - im;
+          } else if (g.mode == 2) {
+            re = -re;
+            im = -im;
+          }
           VC v;
-          v.x = (TC)(p1[i][j][r] - p2[i][j][r]);
-          v.y = (TC)(p3[i][j][r] - p1[i][j][r] - p2[i][j][r]);
-          C[(int64_t)row * g.scm + (int64_t)col * g.scn] = v;
+          v.x = (TC)re;
+          v.y = (TC)im;
+          dst = v;
         }
       }
 }
@@ -376,7 +385,7 @@ hipError_t launch(const GemmArgs &g, hipStream_t s) {
 }  // namespace
 
 hipError_t cgemm_bf3(DType ta, DType tb, DType tc, const GemmArgs &g, hipStream_t s) {
-  if (tc != F32) return hipErrorInvalidValue;
+  if (tc != F32 || g.mode != 0) return hipErrorInvalidValue;
   if (ta == F64 && tb == F32) return launch_bf3<double, float, float>(g, s);
   if (ta == F32 && tb == F64) return launch_bf3<float, double, float>(g, s);
   if (ta == F32 && tb == F32) return launch_bf3<float, float, float>(g, s);

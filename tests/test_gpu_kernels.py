@@ -307,11 +307,14 @@ def test_qr_rank_deficient_is_still_orthonormal(ctxs):
 
 
 @pytest.mark.parametrize("m,n,kind", [(700, 96, "graded"), (600, 64, "rank-deficient"),
-                                      (1024, 128, "graded"), (300, 33, "rank-deficient")])
+                                      (1024, 128, "graded"), (300, 33, "rank-deficient"),
+                                      (600, 129, "graded"), (2560, 256, "graded"),
+                                      (1500, 100, "rank-deficient"), (1500, 200, "rank-deficient")])
 def test_qr_cholesky_path_hard_cases(ctxs, m, n, kind):
-    """Shapes of the shifted Cholesky QR path: singular values graded down to
-    1e-12, or exactly repeated columns; Q orthonormal and QR = A to round-off,
-    R upper triangular with real non-negative diagonal."""
+    """Shapes of the shifted Cholesky QR path (n > 128: the 2 x 2 blocked
+    factorisation): singular values graded down to 1e-12, or exactly
+    repeated columns; Q orthonormal and QR = A to round-off, R upper
+    triangular with real non-negative diagonal."""
     from paper_1907_12044_amd import tdvp
     ctx = ctxs["fp64"]
     if kind == "graded":
