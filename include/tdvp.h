@@ -143,7 +143,11 @@ tdvp_status tdvp_lanczos_expm(tdvp_ctx *ctx, const void *Lenv, const void *W, co
 
 /* Thin QR of a tall c128 matrix (eq:QR): A (m x n, m >= n, row-major) = Q R,
  * Q (m x n) with orthonormal columns, R (n x n) upper triangular with real
- * non-negative diagonal (Householder, FP64).  Q and R row-major; Q may alias A. */
+ * non-negative diagonal, n <= 256, all in FP64: Householder while the matrix
+ * fits one work-group's LDS (m n <= 8704), else shifted Cholesky QR in three
+ * passes (Gram matrix, Cholesky factor and its inverse, Q = A R^{-1}).
+ * Q and R row-major; Q may alias A.  TDVP_E_SHAPE if n < 1 or m < n,
+ * TDVP_E_UNSUPPORTED if n > 256. */
 tdvp_status tdvp_qr(tdvp_ctx *ctx, const void *A, int m, int n, void *Q, void *R);
 
 /* Right-canonicalise an MPS in place (RQ sweep n-1 -> 1, Sec. II.A) and
