@@ -146,11 +146,12 @@ __device__ __forceinline__ double rd_lane(double v, int l) {
   const unsigned hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
-// lane (g, c) <- lane (g, K): DPP row_newbcast
+// lane (g, c) <- lane (g, K): DPP row_newbcast (every lane is written, so
+// no old value is needed)
 template <int K> __device__ __forceinline__ double nbc(double v) {
   const long long b = __double_as_longlong(v);
-  const unsigned lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x150 + K, 0xF, 0xF, false);
-  const unsigned hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x150 + K, 0xF, 0xF, false);
+  const unsigned lo = __builtin_amdgcn_mov_dpp((int)b, 0x150 + K, 0xF, 0xF, true);
+  const unsigned hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x150 + K, 0xF, 0xF, true);
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 template <int K> __device__ __forceinline__ double2 nbc(double2 v) { return make_double2(nbc<K>(v.x), nbc<K>(v.y)); }
@@ -185,16 +186,20 @@ template <int k> __device__ __forceinline__ void chol_step(double2 (&d)[4], doub
   const double y = rsqrt_nr(p), ip = y * y;
   yk[k] = y;
   const double2 dkc = grp(d[qk], gk);               // D[k][c] in every row group
-  if (g == gk)
-    r[qk] = c > k ? make_double2(dkc.x * y, dkc.y * y)
-                  : (c == k ? make_double2(p * y, 0.0) : make_double2(0.0, 0.0));
+  {                                                 // row k of R (selects, no branch)
+    const bool own = g == gk, above = c > k, diag = c == k;
+    const double rx = above ? dkc.x * y : (diag ? p * y : 0.0);
+    const double ry = above ? dkc.y * y : 0.0;
+    r[qk].x = own ? rx : r[qk].x;
+    r[qk].y = own ? ry : r[qk].y;
+  }
   const double2 t = make_double2(dkc.x * ip, dkc.y * ip);
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     if (4 * q + 3 > k) {                            // some row g + 4 q is below row k
       const double2 dik = nbc<k>(d[q]);             // D[i][k], i = g + 4 q
-      d[q].x -= dik.x * t.x - dik.y * t.y;
-      d[q].y -= dik.x * t.y + dik.y * t.x;
+      d[q].x = fma(dik.y, t.y, fma(-dik.x, t.x, d[q].x));
+      d[q].y = fma(-dik.y, t.x, fma(-dik.x, t.y, d[q].y));
     }
   }
 }
@@ -207,13 +212,14 @@ template <int k> __device__ __forceinline__ void inv_step(double2 (&b)[4], doubl
   constexpr int qk = k >> 2, gk = k & 3;
   const double2 bk = grp(b[qk], gk);
   const double2 xk = make_double2(bk.x * yk[k], bk.y * yk[k]);
-  if (g == gk) x[qk] = xk;
+  x[qk].x = g == gk ? xk.x : x[qk].x;
+  x[qk].y = g == gk ? xk.y : x[qk].y;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     if (4 * q < k) {                                // some row g + 4 q is above row k
       const double2 rik = nbc<k>(r[q]);             // R[i][k]
-      b[q].x -= rik.x * xk.x - rik.y * xk.y;
-      b[q].y -= rik.x * xk.y + rik.y * xk.x;
+      b[q].x = fma(rik.y, xk.y, fma(-rik.x, xk.x, b[q].x));
+      b[q].y = fma(-rik.y, xk.x, fma(-rik.x, xk.y, b[q].y));
     }
   }
 }
