@@ -97,7 +97,7 @@ Layout layout(int64_t n, int wmax, int kmax, int es) {
   L.Y = o; o += al256((size_t)wmax * n * es);
   L.D = o; o += al256((size_t)n * 16);
   L.tmp = o; o += al256((size_t)n * 16);
-  L.qr = o; o += al256((size_t)10 * n * 16 + 16 * 1024);  // QR: panel path 2 m n + 2 n, Cholesky QR 3 m n + 6 n^2 + 16 complex (m n <= n)
+  L.qr = o; o += al256((size_t)10 * n * 16 + 16 * 1024);  // QR: Cholesky QR 3 m n + 6 n^2 + 16 complex, n^2 <= m n
   L.obs = o; o += al256((size_t)3 * n * 16 + 4096);
   L.total = o;
   return L;

@@ -144,9 +144,10 @@ constexpr int WT_MAX = 8192;
 hipError_t wtable(const double2 *W, int Wl, int d, int Wr, int64_t sW, int *rowp, int *col,
                   double2 *coef, int64_t wss, int count, hipStream_t s);
 
-// Householder QR of an m x n (m >= n) c128 matrix given by strides; writes
+// QR of an m x n (m >= n, n <= 256) c128 matrix given by strides; writes
 // Q (m x n) and R (n x n) through output strides, with optional conjugation
-// on input and outputs.  work: m*n c128 + 2n c128.
+// on input and outputs.  Householder in one work-group while m n fits its
+// LDS, else shifted Cholesky QR; work: cholqr_work_elems(m, n) c128.
 struct QrArgs {
   const double2 *A; int64_t a_rs, a_cs; int conjA;
   double2 *Q; int64_t q_rs, q_cs; int conjQ;
