@@ -365,30 +365,53 @@ __global__ __launch_bounds__(CQ_CHOL_THREADS) void cq_chol_kernel(CholArgs a) {
     }
   }
   __syncthreads();
-  // R^{-1} by block rows from the bottom: X_IJ = -X_II sum_{K=I+1..J} R_IK X_KJ;
-  // block row I of R is overwritten by X once formed (rows below I already
-  // hold X, the diagonal blocks hold X_II since the factorisation)
-  for (int I = nb - 2; I >= 0; --I) {
-    // S_J = sum_K R_IK X_KJ (one wave per J), then X_IJ = -X_II S_J
-    const int J = I + 1 + wave;         // nb - 1 <= 7 < 8 waves
-    CAcc sa;
-    if (J < nb)
-      for (int K = I + 1; K <= J; ++K) blk_mma(Bk + bidx(I, K, nb) * 256, false, Bk + bidx(K, J, nb) * 256, sa);
-    __syncthreads();   // every R_IK has been read
-    if (J < nb) {
-      double2 *Xj = Bk + bidx(I, J, nb) * 256;
+  // R^{-1} by block back substitution, X_IJ = -X_II S_IJ with
+  // S_IJ = sum_{K=I+1..J} R_IK X_KJ, right-looking from the bottom: at step
+  // K (nb-1 down to 1) every pair I < K <= J adds R_IK X_KJ to S_IJ, then
+  // block row K-1, whose sums are complete, is formed in the place of R's
+  // row K-1 (read for the last time at this step; the diagonal blocks hold
+  // X_II since the factorisation).  The pairs (I, J) are dealt to the waves
+  // round-robin in row-major order, each keeping its sums in registers, so
+  // the longest chain of block products is ~21 instead of nb (nb + 1) / 2 - 1.
+  {
+    constexpr int NW = CQ_CHOL_THREADS / 64;
+    constexpr int NS = (CQ_NB * (CQ_NB - 1) / 2 + NW - 1) / NW;   // pairs per wave
+    const int npairs = nb * (nb - 1) / 2;
+    int pi[NS], pj[NS];
 #pragma unroll
-      for (int rr = 0; rr < 4; ++rr)
-        Xj[bo(Mf<double>::row(lane, rr), lane & 15)] = make_double2(sa.re(rr), sa.im(rr));
-      __builtin_amdgcn_wave_barrier();
-      CAcc acc;
-      blk_mma(Bk + bidx(I, I, nb) * 256, false, Xj, acc);
-      __builtin_amdgcn_wave_barrier();
-#pragma unroll
-      for (int rr = 0; rr < 4; ++rr)
-        Xj[bo(Mf<double>::row(lane, rr), lane & 15)] = make_double2(-acc.re(rr), -acc.im(rr));
+    for (int t = 0; t < NS; ++t) {
+      int u = wave + NW * t, I = 0;
+      pi[t] = pj[t] = -1;
+      if (u < npairs) {
+        while (u >= nb - 1 - I) { u -= nb - 1 - I; ++I; }
+        pi[t] = I;
+        pj[t] = I + 1 + u;
+      }
     }
-    __syncthreads();
+    CAcc sum[NS];
+    for (int K = nb - 1; K >= 1; --K) {
+#pragma unroll
+      for (int t = 0; t < NS; ++t)
+        if (pi[t] >= 0 && pi[t] < K && K <= pj[t])
+          blk_mma(Bk + bidx(pi[t], K, nb) * 256, false, Bk + bidx(K, pj[t], nb) * 256, sum[t]);
+      __syncthreads();   // every R_IK and X_KJ of this step has been read
+#pragma unroll
+      for (int t = 0; t < NS; ++t)
+        if (pi[t] == K - 1) {
+          double2 *Xj = Bk + bidx(pi[t], pj[t], nb) * 256;
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr)
+            Xj[bo(Mf<double>::row(lane, rr), lane & 15)] = make_double2(sum[t].re(rr), sum[t].im(rr));
+          __builtin_amdgcn_wave_barrier();
+          CAcc acc;
+          blk_mma(Bk + bidx(pi[t], pi[t], nb) * 256, false, Xj, acc);
+          __builtin_amdgcn_wave_barrier();
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr)
+            Xj[bo(Mf<double>::row(lane, rr), lane & 15)] = make_double2(-acc.re(rr), -acc.im(rr));
+        }
+      __syncthreads();   // block row K - 1 of X is formed
+    }
   }
   for (int s0 = 0; s0 < n; s0 += CQ_U * CQ_RSTEP) {
     double2 v[CQ_U];

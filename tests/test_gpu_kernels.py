@@ -274,7 +274,8 @@ def test_fused_and_general_paths_agree(ctxs):
     assert relerr(out[True][0], out[False][0]) < 1e-13
 
 
-@pytest.mark.parametrize("m,n", [(1, 1), (4, 2), (16, 16), (33, 32), (64, 32), (200, 31), (256, 1), (256, 32), (257, 33), (272, 32), (288, 32), (217, 40), (90, 90), (700, 45), (1024, 128), (1500, 100), (2560, 256)])
+@pytest.mark.parametrize("m,n", [(1, 1), (4, 2), (16, 16), (33, 32), (64, 32), (200, 31), (256, 1), (256, 32), (257, 33), (272, 32), (288, 32), (217, 40), (90, 90), (700, 45), (1024, 128), (1500, 100), (2560, 256),
+                                 (9000, 1), (6000, 64), (4096, 256)])
 def test_qr_matches_oracle(ctxs, m, n):
     from paper_1907_12044_amd import tdvp
     ctx = ctxs["fp64"]
