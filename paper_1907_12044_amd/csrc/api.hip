@@ -631,8 +631,8 @@ tdvp_status tdvp_create(tdvp_ctx **ctx, int device, void *hip_stream, tdvp_preci
   c->graph = nullptr;
   c->gexec = nullptr;
   if (hipSetDevice(device) != hipSuccess) { delete c; return TDVP_E_DEVICE; }
-  static bool inited = false;
-  if (!inited) { inited = true; qr_init(); }
+  static const bool inited = (qr_init(), true);   // once per process (thread-safe static)
+  (void)inited;
   *ctx = c;
   return TDVP_OK;
 }

@@ -488,16 +488,15 @@ int64_t cholqr_work_elems(int m, int n) {
   return 3 * (int64_t)m * n + 6 * (int64_t)n * n + 16;
 }
 
+void cholqr_init() {
+  (void)hipFuncSetAttribute((const void *)cq_chol_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            CQ_NB * (CQ_NB + 1) / 2 * 256 * (int)sizeof(double2));
+  (void)hipGetLastError();
+}
+
 hipError_t cholqr(const QrArgs &p, hipStream_t s) {
   const int m = p.m, n = p.n, R = p.inst.count;
   if (!cholqr_ok(m, n)) return hipErrorInvalidValue;
-  static bool attr = false;
-  if (!attr) {
-    attr = true;
-    (void)hipFuncSetAttribute((const void *)cq_chol_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              CQ_NB * (CQ_NB + 1) / 2 * 256 * (int)sizeof(double2));
-    (void)hipGetLastError();
-  }
   const int64_t mn = (int64_t)m * n, nn = (int64_t)n * n, ws = p.inst.skip;
   double2 *Wb[3] = {p.work, p.work + mn, p.work + 2 * mn};
   double2 *G = p.work + 3 * mn;

@@ -162,7 +162,8 @@ hipError_t qr(const QrArgs &a, hipStream_t s);
 bool cholqr_ok(int m, int n);
 int64_t cholqr_work_elems(int m, int n);
 hipError_t cholqr(const QrArgs &a, hipStream_t s);
-void qr_init();   // once per process, outside stream capture
+void cholqr_init();   // called by qr_init
+void qr_init();       // once per process, outside stream capture
 
 }  // namespace tdvp
 

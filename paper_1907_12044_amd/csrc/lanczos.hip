@@ -1140,9 +1140,7 @@ bool heff_small_fits(const HeffSmallArgs &a, int tm_bytes) {
 }
 
 hipError_t heff_small(DType t, const HeffSmallArgs &a, int count, hipStream_t s) {
-  static bool attr = false;
-  if (!attr) {
-    attr = true;
+  static const bool attr = [] {   // once per process (thread-safe static)
 #define HS_ATTR(T, JB, S)                                                               \
   (void)hipFuncSetAttribute((const void *)heff_small_kernel<T, JB, S>,                  \
                             hipFuncAttributeMaxDynamicSharedMemorySize, HEFF_SMALL_LDS)
@@ -1151,7 +1149,9 @@ hipError_t heff_small(DType t, const HeffSmallArgs &a, int count, hipStream_t s)
 #undef HS_ATTR2
 #undef HS_ATTR
     (void)hipGetLastError();
-  }
+    return true;
+  }();
+  (void)attr;
   const dim3 g(a.Mr * a.P, count), b(HS_WAVES * 64);
   const size_t lds = heff_small_lds(a, t == F64 ? 8 : 4);
 #define HS(T, JB, S) hipLaunchKernelGGL((heff_small_kernel<T, JB, S>), g, b, lds, s, a)

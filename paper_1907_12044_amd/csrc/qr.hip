@@ -419,6 +419,7 @@ void qr_init() {
                                hipFuncAttributeMaxDynamicSharedMemorySize,
                                QR_LDS_ELEMS * (int)sizeof(double2)) == hipSuccess;
   (void)hipGetLastError();
+  cholqr_init();
 }
 
 hipError_t qr(const QrArgs &a, hipStream_t s) {
