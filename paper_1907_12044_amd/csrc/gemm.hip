@@ -37,8 +37,11 @@ __device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// FP64 arithmetic: at least two waves per SIMD (registers capped at 256
+// per lane, the accumulators then stay in the architectural registers; the
+// uncapped 64x64 tile took ~390 and ran one wave per SIMD, 22 % slower).
 template <typename TA, typename TB, typename TC, typename TM, int BM, int BN, int BK>
-__global__ __launch_bounds__(256) void cgemm_kernel(GemmArgs g) {
+__global__ __launch_bounds__(256, sizeof(TM) == 8 ? 2 : 1) void cgemm_kernel(GemmArgs g) {
   const int bz = blockIdx.z % g.batch;      // batch index
   const int ri = blockIdx.z / g.batch;      // instance index
   if (g.skip && g.skip[(int64_t)ri * g.inst.skip]) return;
