@@ -1,13 +1,18 @@
 """TDVP-PS throughput on one MI355X.
 
-A step is one full symmetric TDVP-PS time step of the whole chain (left-to-
-right and right-to-left sweeps: forward Lanczos solves, QR gauge shifts,
+A step is one full symmetric TDVP-PS time step of a chain (left-to-right
+and right-to-left sweeps: forward Lanczos solves, QR gauge shifts,
 environment updates, backward bond solves, centre moves) followed by the
-observables (norm, energy, populations) written to device memory; inputs
-are resident in HBM before the timed region starts.
+observables (norm, energy, populations); inputs are resident in HBM before
+the timed region starts.
 
-Default workload: 7 electronic sites x 10 modes x 8 levels (77 MPS sites),
-bond dim 32, dt = 2 fs, complex128, Krylov dim 20.
+Default workload: the static-disorder ensemble -- 64 realisations of the
+77-site chain (7 electronic sites x 10 modes x 8 levels), site energies
+perturbed by N(0, 100 cm^-1), bond dimensions drawn from {32, 64, 96, 128},
+dt = 2 fs, Krylov dimension 20, contractions in FP32 with FP64 Krylov, small
+exponential and QR; ``value`` counts realisation-steps per second.  Its FP64
+twin runs outside the timed region and states the mixed-mode error.
+``--workload fmo7x10x8_M32`` (etc.) times one chain instead.
 Prints ONE JSON line (see the keys below).
 """
 
@@ -31,8 +36,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="fmo7x10x8_M32")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--workload", default="ensemble",
+                    help="ensemble (default: the static-disorder ensemble) or a single-chain workload name")
+    ap.add_argument("--precision", default=None, choices=["fp64", "fp32", "bf16x3"],
+                    help="default: fp32 for the ensemble, fp64 for a single chain")
+    ap.add_argument("--twin-steps", type=int, default=5,
+                    help="steps of the FP64 twin of a mixed-precision ensemble (outside the timed region)")
     ap.add_argument("--kmax", type=int, default=20)
     ap.add_argument("--tol", type=float, default=0.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -54,32 +63,31 @@ def parse():
 
 
 def cpu_baseline(name, nsteps):
-    """The oracle (plain numpy FP64, untuned) on a bounded sample of the same workload."""
-    import numpy as np
-    from threadpoolctl import threadpool_info
+    """The oracle (plain numpy FP64, untuned) on a bounded sample of the same
+    workload: nsteps steps at all host threads, one step at one thread."""
     from inputs import workload
-    from oracle import model, mps as om, ps
+    from oracle import model
 
     p, sites, phys, dims, raw, w = workload(name)
-    Ws, _ = model.mpo(p, sites)
-    m = om.right_canonicalize(raw)
-    R = om.build_right_envs(m, Ws)
     tau = w["dt_fs"] * model.AU_PER_FS
-    t0 = time.perf_counter()
+    total, used = 0.0, 1
     for _ in range(nsteps):
-        m, R, _ = ps.ps_step(m, Ws, R, tau, kmax=20)
-        om.site_populations(m, sites, p.n_e)
-    dt = time.perf_counter() - t0
-    threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
-    return {"value": nsteps / dt, "unit": "steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"{nsteps} step(s) of {name} incl. populations, numpy FP64 "
-                      f"({os.cpu_count()} host CPUs visible)"}
+        t, used = _oracle_step_seconds(p, sites, raw, tau)
+        total += t
+    t1, _ = _oracle_step_seconds(p, sites, raw, tau, threads=1)
+    return {"value": nsteps / total, "unit": "steps/s", "cores": used, "kind": "oracle",
+            "sample": f"{nsteps} first step(s) of {name} incl. populations, numpy FP64, at {used} "
+                      f"threads; one step at 1 thread: {t1:.2f} s",
+            "single_thread_steps_per_s": 1.0 / t1, **_cpu_info()}
 
 
 # Kernel classes that are dense complex contractions (MFMA roof); the others
 # are priced against HBM bandwidth.
-MFMA_CLASSES = ("gemm", "lz_fused")
-KERNEL_OF_CLASS = {"gemm": "cgemm_kernel", "lz_fused": "heff_small_kernel", "lz_update": "lz_update_kernel",
+MFMA_CLASSES = ("gemm", "gemm_heff", "lz_fused")
+# the classes that carry H[i] x and the bond operator (H_eff TFLOP/s)
+HEFF_CLASSES = ("gemm_heff", "lz_fused")
+KERNEL_OF_CLASS = {"gemm": "cgemm_kernel", "gemm_heff": "cgemm_kernel", "lz_fused": "heff_small_kernel",
+                   "lz_update": "lz_update_kernel",
                    "lz_dots": "lz_dots_kernel", "lz_ends": "lz_finish_kernel", "qr": "qr_reg_kernel",
                    "wapply": "wapply_kernel"}
 
@@ -134,7 +142,7 @@ def roofline(prof, prec, ms_per_step, workload=None, precision=None):
     from paper_1907_12044_amd import tdvp
     if not prof:
         return None, None
-    heff_flop = sum(prof[k]["flop"] for k in MFMA_CLASSES if k in prof)
+    heff_flop = sum(prof[k]["flop"] for k in HEFF_CLASSES if k in prof)
     heff_tflops = heff_flop / (ms_per_step * 1e-3) / 1e12
     dom = max(prof, key=lambda k: prof[k]["ms_per_step"])
     d = prof[dom]
@@ -153,58 +161,123 @@ def roofline(prof, prec, ms_per_step, workload=None, precision=None):
     roof["traffic"] = measured_traffic(KERNEL_OF_CLASS.get(dom, dom), workload, precision)
     roof["kernel"] = KERNEL_OF_CLASS.get(dom, dom)
     roof["launches_per_step"] = d["launches"]
-    roof["timing_reps"] = TIMING_REPS if dom in ("gemm", "wapply", "lz_fused") else 1
+    roof["timing_reps"] = TIMING_REPS if dom in ("gemm", "gemm_heff", "wapply", "lz_fused") else 1
     roof["avg_launch_us"] = 1e6 * t / max(d["launches"], 1)
     roof["per_launch"] = {"flop": d["flop"] / max(d["launches"], 1),
                           "bytes": d["bytes"] / max(d["launches"], 1)}
     return roof, heff_tflops
 
 
+def _cpu_info():
+    model_name = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model_name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model_name}
+
+
+def _oracle_step_seconds(p, sites, raw, tau, threads=None):
+    """Wall time of one oracle TDVP-PS step (plain numpy FP64, untuned) of
+    one chain, and the BLAS thread count it ran with."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+    from oracle import model, mps as om, ps
+
+    Ws, _ = model.mpo(p, sites)
+    m = om.right_canonicalize(raw)
+    R = om.build_right_envs(m, Ws)
+    with threadpool_limits(limits=threads):
+        used = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+        t0 = time.perf_counter()
+        m, R, _ = ps.ps_step(m, Ws, R, tau, kmax=20)
+        om.site_populations(m, sites, p.n_e)
+        dt = time.perf_counter() - t0
+    return dt, used
+
+
+def ensemble_cpu_baseline(members, sites, tau, class_flop):
+    """The oracle on a bounded sample of the ensemble: one full step of the
+    first M = 32 realisation (all host threads, then one thread) and of the
+    first M = 64 realisation (all threads).  The per-step time of the
+    M = 96 and 128 classes is extrapolated from the M = 64 step by the
+    ratio of algorithmic contraction FLOP per step (the oracle takes minutes
+    per step there); the ensemble rate is realisations over the summed
+    per-class step times."""
+    first = {}
+    for r, p, M, raw in members:
+        first.setdefault(M, (r, p, raw))
+    t32, used = _oracle_step_seconds(first[32][1], sites, first[32][2], tau)
+    t32_1, _ = _oracle_step_seconds(first[32][1], sites, first[32][2], tau, threads=1)
+    t64, _ = _oracle_step_seconds(first[64][1], sites, first[64][2], tau)
+    per = {32: t32, 64: t64}
+    for M in (96, 128):
+        per[M] = t64 * class_flop[M] / class_flop[64]
+    counts = {}
+    for _, _, M, _ in members:
+        counts[M] = counts.get(M, 0) + 1
+    total = sum(counts[M] * per[M] for M in counts)
+    info = _cpu_info()
+    return {"value": len(members) / total, "unit": "realisation-steps/s", "cores": used, "kind": "oracle",
+            "sample": (f"one oracle step of realisation {first[32][0]} (M=32): {t32:.2f} s at {used} "
+                       f"threads, {t32_1:.2f} s at 1 thread; one step of realisation {first[64][0]} "
+                       f"(M=64): {t64:.2f} s; M=96/128 steps extrapolated from M=64 by algorithmic FLOP "
+                       f"({per[96]:.1f} s, {per[128]:.1f} s); value = {len(members)} realisations / "
+                       f"sum over classes of count x step time"),
+            "single_thread_m32_steps_per_s": 1.0 / t32_1, "all_threads_m32_steps_per_s": 1.0 / t32,
+            **info}
+
+
 def ensemble_main(args):
-    """64 static-disorder realisations, bond dims from {32, 64, 96, 128}: one
-    PsEnsemble per bond-dimension class (every kernel covers the class in one
-    launch), the classes on separate streams so they run concurrently."""
+    """The static-disorder ensemble: realisations of the 77-site chain with
+    bond dimensions from {32, 64, 96, 128}, all advanced together (one
+    ensemble per bond-dimension class, every kernel covering its class in
+    one launch, classes on separate streams).  Timed in the requested
+    (mixed) precision; an FP64 twin of the same ensemble runs outside the
+    timed region to state the mixed-mode error and the FP64 rate."""
     import numpy as np
     import torch
-    from inputs import draw_params, chain_sites, initial_mps_raw
-    from inputs.fmo import ensemble_bond
+    from inputs import chain_sites
+    from inputs.fmo import ENSEMBLE, ensemble_members
     from paper_1907_12044_amd import tdvp
 
     nreal = args.realisations
     prec = {"fp64": tdvp.FP64, "fp32": tdvp.FP32, "bf16x3": tdvp.BF16X3}[args.precision]
-    classes = {}
-    for r in range(nreal):
-        classes.setdefault(ensemble_bond(0, r), []).append(r)
-    ens = []
-    for M, rs in sorted(classes.items()):
-        ps_ = [draw_params(7, 10, 8, seed=0, realisation=r) for r in rs]
-        sites = chain_sites(ps_[0])
-        raws = [initial_mps_raw(p, M, 1e-2, 1) for p in ps_]
-        ens.append((M, rs, tdvp.PsEnsemble(ps_, sites, raws, 0, prec, kmax=args.kmax, tol=args.tol,
-                                           graph=not args.eager, fused=not args.no_fused,
-                                           autotune=autotune_on(args))))
-    tau = 2.0 * tdvp.AU_PER_FS
+    members = ensemble_members(nreal, ENSEMBLE["seed"])
+    sites = chain_sites(members[0][1])
+    tau = ENSEMBLE["dt_fs"] * tdvp.AU_PER_FS
+
+    def build(pr):
+        return tdvp.DisorderEnsemble(members, sites, 0, pr, kmax=args.kmax, tol=args.tol,
+                                     graph=not args.eager, fused=not args.no_fused,
+                                     autotune=autotune_on(args))
+
+    ens = build(prec)
     torch.cuda.synchronize()
+    hist = [ens.observe_host()]          # observables after 0, 1, 2, ... steps
     for _ in range(args.warmup):
-        for _, _, e in ens:
-            e.step(tau, 1)
-            e.observe()
+        ens.step(tau, 1)
+        hist.append(ens.observe_host())
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        for _, _, e in ens:
-            e.step(tau, 1)
-            e.observe()
+        ens.step(tau, 1)
+        hist.append(ens.observe_host())
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms = 1e3 * elapsed / max(args.steps, 1)
+
     prof = {}
+    class_flop = {}
     if not args.no_class_timing:
-        for _, _, e in ens:
+        for _, _, e in ens.classes:
             tdvp.profile_reps(e.ctx, TIMING_REPS)
         for name, cls in tdvp.PROF_CLASSES.items():
             acc = {"ms_per_step": 0.0, "launches": 0, "flop": 0.0, "bytes": 0.0}
-            for _, _, e in ens:
+            for M, rs, e in ens.classes:
                 tdvp.profile(e.ctx, cls)
                 e.step(tau, 1)
                 ms_, n_, f_, b_ = tdvp.profile_read(e.ctx)
@@ -213,24 +286,62 @@ def ensemble_main(args):
                 acc["launches"] += n_
                 acc["flop"] += f_
                 acc["bytes"] += b_
+                if name in HEFF_CLASSES:
+                    class_flop[M] = class_flop.get(M, 0.0) + f_ / len(rs)
             prof[name] = acc
     roof, heff_tflops = roofline(prof, prec, ms, f"ensemble{nreal}", args.precision)
-    pops = np.concatenate([e.observe_host()[:, 2:] for _, _, e in ens])
+    del ens
+    torch.cuda.empty_cache()
+
+    # FP64 twin: same members from t = 0, outside the timed region
+    twin = {}
+    if prec != tdvp.FP64 and args.twin_steps > 0:
+        nt = min(args.twin_steps, len(hist) - 1)
+        e64 = build(tdvp.FP64)
+        e64.step(tau, 1)                  # first step: autotuning, graph capture
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if nt > 1:
+            e64.step(tau, nt - 1)
+        o64 = e64.observe_host()
+        t64 = time.perf_counter() - t1
+        om_ = hist[nt]
+        dP = np.abs(om_[:, 2:] - o64[:, 2:]).max()
+        dn = np.abs(om_[:, 0] - o64[:, 0]).max()
+        dE = np.abs(om_[:, 1] - o64[:, 1]).max()
+        twin = {"steps_compared": nt, "max_abs_dpop": float(dP), "max_abs_dnorm": float(dn),
+                "max_abs_denergy_hartree": float(dE),
+                "max_abs_denergy_cm-1": float(dE / tdvp.HARTREE_PER_CM),
+                "fp64_realisation_steps_per_s": (nreal * (nt - 1) / t64) if nt > 1 else None,
+                "pop_error_within_1e-5": bool(dP <= 1e-5)}
+        del e64
+        torch.cuda.empty_cache()
+
+    pops = hist[-1][:, 2:]
+    counts = {}
+    for _, _, M, _ in members:
+        counts[M] = counts.get(M, 0) + 1
     line = {
-        "metric": "TDVP-PS ensemble steps/s (all realisations advanced one step)",
-        "value": 1e3 / ms, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+        "metric": "TDVP-PS steps/s + H_eff TFLOP/s, mixed/batched vs FP64 at <=1e-5 pop error",
+        "value": nreal * 1e3 / ms, "unit": "realisation-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None,
         "dtype": DTYPE_OF[prec],
         "data": "synthetic",
-        "config": {"workload": f"fmo7x10x8_ensemble{nreal}", "classes": {str(M): len(rs) for M, rs, _ in ens},
-                   "precision": args.precision, "kmax": args.kmax, "autotune": autotune_on(args)},
-        "realisation_steps_per_s": nreal * 1e3 / ms,
+        "config": {"workload": f"fmo7x10x8_disorder_ensemble{nreal}", "sites": len(sites),
+                   "classes": {str(M): counts[M] for M in sorted(counts)}, "dt_fs": ENSEMBLE["dt_fs"],
+                   "precision": args.precision, "kmax": args.kmax, "autotune": autotune_on(args),
+                   "graph": not args.eager, "initial_state_eta": ENSEMBLE["eta"]},
+        "ensemble_steps_per_s": 1e3 / ms,
         "heff_tflops": heff_tflops,
         "class_ms_per_step": {k: round(v["ms_per_step"], 3) for k, v in prof.items()},
         "roofline": roof,
+        "fp64_twin": twin,
         "population_sum_range": [float(pops.sum(1).min()), float(pops.sum(1).max())],
     }
+    if not args.no_cpu_baseline:
+        if len(class_flop) == 4:
+            line["cpu_baseline"] = ensemble_cpu_baseline(members, sites, tau, class_flop)
     print(json.dumps(line), flush=True)
 
 
@@ -240,6 +351,8 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "independent disorder realisations would be sharded one process per GPU", file=sys.stderr)
         sys.exit(2)
+    if args.precision is None:
+        args.precision = "fp32" if args.workload.startswith("ensemble") else "fp64"
     if args.workload.startswith("ensemble"):
         return ensemble_main(args)
     import numpy as np

@@ -33,6 +33,12 @@
  *  - Errors: argument and shape errors return at once and enqueue nothing.
  *    A failed HIP call returns TDVP_E_DEVICE.  No C++ exception crosses the
  *    ABI.  A context is not thread safe; use one per host thread.
+ *  - Non-finite values: a Lanczos solve whose start vector or any Krylov
+ *    norm is NaN or Inf stops, writes NaN to its output (a zero start
+ *    vector still gives a zero output) and raises a sticky device flag in
+ *    the context's workspace; tdvp_observe / tdvp_observe_batched report
+ *    it, or a non-finite observable, as TDVP_E_NUMERIC.  The flag is
+ *    cleared only by tdvp_set_workspace.
  */
 #ifndef TDVP_H
 #define TDVP_H
@@ -50,7 +56,7 @@ typedef enum {
   TDVP_E_SHAPE = 2,      /* inconsistent bond / phys / channel dimensions   */
   TDVP_E_DEVICE = 3,     /* a HIP runtime call failed                       */
   TDVP_E_WORKSPACE = 4,  /* no workspace set, or too small for the call     */
-  TDVP_E_NUMERIC = 5,    /* non-finite norm found by tdvp_observe           */
+  TDVP_E_NUMERIC = 5,    /* a non-finite value reported by tdvp_observe      */
   TDVP_E_UNSUPPORTED = 6 /* sizes beyond the compiled limits                */
 } tdvp_status;
 
@@ -107,7 +113,7 @@ int tdvp_env_elem_bytes(const tdvp_ctx *ctx);
 tdvp_status tdvp_workspace_bytes(const tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo,
                                  int kmax, size_t *bytes);
 /* Hand the context a device workspace of `bytes` bytes (256-byte aligned).
- * Enqueues a small initialisation kernel on the stream. */
+ * Enqueues its initialisation on the stream (clears the non-finite flag). */
 tdvp_status tdvp_set_workspace(tdvp_ctx *ctx, void *dev, size_t bytes);
 
 /* Environment update (eq:tdvp1_h with A = L or R, one site at a time).
@@ -208,7 +214,11 @@ tdvp_status tdvp_autotune_count(const tdvp_ctx *ctx, int32_t *count);
  * [2 + n_el]) receives <psi|psi>, <psi|H|psi> + energy_shift * <psi|psi>, and
  * the populations <psi|a+_m a_m|psi> of the electronic sites el_sites[m]
  * (host array of site indices; local dim 2, level 1 = occupied).  Not
- * divided by the norm.  Needs envs->right[1] valid. */
+ * divided by the norm.  Needs envs->right[1] valid.  This is the one call
+ * of a time loop that waits for the stream: after the observables it
+ * checks the context's non-finite flag and the values it wrote, and
+ * returns TDVP_E_NUMERIC if any is NaN or Inf (out_dev is written either
+ * way). */
 tdvp_status tdvp_observe(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo,
                          const tdvp_envs *envs, const int32_t *el_sites, int n_el,
                          double *out_dev);
@@ -228,18 +238,21 @@ tdvp_status tdvp_set_krylov_log(tdvp_ctx *ctx, int32_t *dev, int capacity);
  * time (ms), the launch count and the summed FLOP and bytes. */
 enum {
   TDVP_PROF_OFF = 0,
-  TDVP_PROF_GEMM = 1,       /* complex MFMA contractions (cgemm_kernel)         */
+  TDVP_PROF_GEMM = 1,       /* complex MFMA contractions outside H x: environment
+                               updates, centre moves, observables (cgemm_kernel) */
   TDVP_PROF_WAPPLY = 2,     /* MPO channel stage (wapply_kernel)                */
   TDVP_PROF_LZ_DOTS = 3,    /* Lanczos projections (lz_dots_kernel)             */
   TDVP_PROF_LZ_UPDATE = 4,  /* Lanczos orthogonalisation (lz_update_kernel)     */
   TDVP_PROF_LZ_ENDS = 5,    /* Lanczos start and final combination + exp(zT)e1  */
   TDVP_PROF_QR = 6,         /* Householder QR (qr_* kernels)                    */
-  TDVP_PROF_LZ_FUSED = 7    /* fused H x + projections (heff_small_kernel)      */
+  TDVP_PROF_LZ_FUSED = 7,   /* fused H x + projections (heff_small_kernel)      */
+  TDVP_PROF_GEMM_HEFF = 8   /* the GEMM stages of H[i] x and of the bond operator
+                               on the general path (cgemm_kernel)              */
 };
 tdvp_status tdvp_profile(tdvp_ctx *ctx, int kernel_class);
 /* Repeat count for timed launches of the classes whose launches overwrite
- * outputs they do not read (TDVP_PROF_GEMM, TDVP_PROF_WAPPLY,
- * TDVP_PROF_LZ_FUSED): each timed launch runs `reps` times back to back
+ * outputs they do not read (TDVP_PROF_GEMM, TDVP_PROF_GEMM_HEFF,
+ * TDVP_PROF_WAPPLY, TDVP_PROF_LZ_FUSED): each timed launch runs `reps` times back to back
  * between its two events and tdvp_profile_read divides by reps, so the time
  * per launch is the kernel's duration plus the gap between two queued
  * kernels rather than one whole dispatch.  1 <= reps <= 64 (default 1);

@@ -91,6 +91,15 @@ def env_left_element(L, A, W, q, y, r):
     return complex(np.sum(np.conj(A[:, :, q]) * T))
 
 
+def env_right_element(R, A, W, b, w, k):
+    """One element (b, w, k) of the right environment update (eq:tdvp1_hiN):
+    the sum over q, y, r, t, s of R[q, y, r] A[k, t, r] W[w, s, t, y] conj(A[b, s, q]).
+    """
+    T = np.tensordot(A[k], R, axes=([1], [2]))              # t q y
+    T = np.tensordot(W[w], T, axes=([1, 2], [0, 2]))        # s q
+    return complex(np.sum(np.conj(A[b]) * T))
+
+
 def bond_op(L, R, D):
     """Zero-site operator of eq:tdvp2_D: sum_w h[1:i]_{l' w l} h[i+1:N]_{r' w r} D_{l r}.
 

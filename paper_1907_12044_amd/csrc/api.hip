@@ -89,6 +89,7 @@ Layout layout(int64_t n, int wmax, int kmax, int es) {
   size_t o = 0;
   L.n = n;
   L.ybytes = (size_t)wmax * n * es;
+  o += CTX_HEADER_BYTES;   // instance 0: the context header; others: unused
   L.st = o; o += al256(sizeof(LzState));
   L.pp = o; o += al256(sizeof(LzPartials));
   L.U = o; o += al256((size_t)(kmax + 1) * n * 16);
@@ -104,6 +105,7 @@ Layout layout(int64_t n, int wmax, int kmax, int es) {
 }
 
 template <typename T> T *at(tdvp_ctx *c, size_t off) { return reinterpret_cast<T *>(c->ws + off); }
+CtxHeader *header(tdvp_ctx *c) { return reinterpret_cast<CtxHeader *>(c->ws); }
 
 hipEvent_t pool_event(tdvp_ctx *c) {
   if (c->pool_used == c->pool.size()) {
@@ -180,7 +182,8 @@ template <typename F> double time_launch(tdvp_ctx *c, F launch, int reps = 3) {
 // With the autotuner on, the tile shape (32x32, or 64x64 with K steps of 16,
 // 32 or 64 in FP32) of a new problem key is chosen by timing each (a GEMM
 // overwrites C, so repeats are harmless).
-hipError_t gemm_t(tdvp_ctx *c, DType ta, DType tb, DType tc, const GemmArgs &g0) {
+hipError_t gemm_t(tdvp_ctx *c, DType ta, DType tb, DType tc, const GemmArgs &g0,
+                  int prof_cls = TDVP_PROF_GEMM) {
   GemmArgs g = g0;
   if (c->autotune) {
     const std::vector<int64_t> key = {0, ta, tb, tc, g.M, g.N, g.K, g.batch, g.inst.count,
@@ -207,7 +210,7 @@ hipError_t gemm_t(tdvp_ctx *c, DType ta, DType tb, DType tc, const GemmArgs &g0)
       g.tile = best;
     }
   }
-  const int id = prof_begin(c, TDVP_PROF_GEMM);
+  const int id = prof_begin(c, prof_cls);
   const hipError_t e = timed_repeat(c, id, [&] { return gemm_any(c, ta, tb, tc, g); });
   const double M = g.M, N = g.N, K = g.K, B = g.batch;
   prof_end(c, id, 8.0 * M * N * K * B,
@@ -268,7 +271,7 @@ tdvp_status apply_op(tdvp_ctx *c, const Layout &lay, const Op &op, const double2
     g.bsa = 0; g.bsb = op.Mr; g.bsc = n;
     g.skip = skip;
     g.inst = inst_of(b, sx, op.sR, wse, wsk);
-    CK(gemm_t(c, F64, et, ct, g));
+    CK(gemm_t(c, F64, et, ct, g, TDVP_PROF_GEMM_HEFF));
     // stage 2: T2[wl][l][s'][r'] = sum_{s, wr} W[wl][s'][s][wr] T1[wr][l][s][r']
     WApplyArgs w{};
     w.in = T1; w.out = T2; w.W = op.W;
@@ -288,7 +291,7 @@ tdvp_status apply_op(tdvp_ctx *c, const Layout &lay, const Op &op, const double2
     h.bsa = op.Ml; h.bsb = n; h.bsc = n;
     h.skip = skip;
     h.inst = inst_of(b, op.sL, wse, wse, wsk);
-    CK(gemm_t(c, et, ct, ct, h));
+    CK(gemm_t(c, et, ct, ct, h, TDVP_PROF_GEMM_HEFF));
   } else {
     // bond operator: T1[w][l][r'] = sum_r D[l][r] R[r'][w][r]; Y[w][l'][r'] = sum_l L[l'][w][l] T1[w][l][r']
     GemmArgs g{};
@@ -299,7 +302,7 @@ tdvp_status apply_op(tdvp_ctx *c, const Layout &lay, const Op &op, const double2
     g.bsa = 0; g.bsb = op.Mr; g.bsc = n;
     g.skip = skip;
     g.inst = inst_of(b, sx, op.sR, wse, wsk);
-    CK(gemm_t(c, F64, et, ct, g));
+    CK(gemm_t(c, F64, et, ct, g, TDVP_PROF_GEMM_HEFF));
     GemmArgs h{};
     h.A = op.L; h.B = T1; h.C = Y;
     h.M = op.Ml; h.N = op.Mr; h.K = op.Ml; h.batch = op.Wl;
@@ -308,7 +311,7 @@ tdvp_status apply_op(tdvp_ctx *c, const Layout &lay, const Op &op, const double2
     h.bsa = op.Ml; h.bsb = n; h.bsc = n;
     h.skip = skip;
     h.inst = inst_of(b, op.sL, wse, wse, wsk);
-    CK(gemm_t(c, et, ct, ct, h));
+    CK(gemm_t(c, et, ct, ct, h, TDVP_PROF_GEMM_HEFF));
   }
   return TDVP_OK;
 }
@@ -382,7 +385,8 @@ tdvp_status run_lanczos(tdvp_ctx *c, const Layout &lay, const Op &op, double zr,
     CK(wtable((const double2 *)op.W, op.Wl, op.d, op.Wr, op.sW, const_cast<int *>(fa.row),
               const_cast<int *>(fa.col), const_cast<double2 *>(fa.coef), b.ws, b.R, c->stream));
   int id = prof_begin(c, TDVP_PROF_LZ_ENDS);
-  CK(lz_start(st, pp, (const double2 *)x, U, n, zr, zi, tol, keff, trows, li, c->stream));
+  CK(lz_start(st, pp, (const double2 *)x, U, n, zr, zi, tol, keff, trows, &header(c)->nonfinite, li,
+              c->stream));
   prof_end(c, id, 4.0 * n * b.R, 2.0 * vb);
   fa.st = st; fa.pp = pp; fa.U = U;
   for (int j = 0; j < keff; ++j) {
@@ -665,7 +669,7 @@ tdvp_status tdvp_set_krylov_log(tdvp_ctx *ctx, int32_t *dev, int capacity) {
 }
 
 tdvp_status tdvp_profile(tdvp_ctx *ctx, int kernel_class) {
-  if (!ctx || kernel_class < 0 || kernel_class > TDVP_PROF_LZ_FUSED) return TDVP_E_ARG;
+  if (!ctx || kernel_class < 0 || kernel_class > TDVP_PROF_GEMM_HEFF) return TDVP_E_ARG;
   ctx->prof_class = kernel_class;
   ctx->prof.clear();
   ctx->pool_used = 0;
@@ -708,11 +712,12 @@ tdvp_status tdvp_workspace_bytes(const tdvp_ctx *ctx, const tdvp_mps *mps, const
 tdvp_status tdvp_set_workspace(tdvp_ctx *ctx, void *dev, size_t bytes) {
   if (!ctx || !dev) return TDVP_E_ARG;
   if (((uintptr_t)dev & 255) != 0) return TDVP_E_ARG;
-  if (bytes < al256(sizeof(LzState))) return TDVP_E_WORKSPACE;
+  if (bytes < CTX_HEADER_BYTES + al256(sizeof(LzState))) return TDVP_E_WORKSPACE;
   ctx->ws = (char *)dev;
   ctx->ws_bytes = bytes;
   CK(hipSetDevice(ctx->device));
-  CK(set_dev_int(&reinterpret_cast<LzState *>(ctx->ws)->stop, 1, ctx->stream));
+  CK(hipMemsetAsync(ctx->ws, 0, CTX_HEADER_BYTES, ctx->stream));
+  CK(set_dev_int(&reinterpret_cast<LzState *>(ctx->ws + CTX_HEADER_BYTES)->stop, 1, ctx->stream));
   return TDVP_OK;
 }
 
@@ -1042,7 +1047,16 @@ tdvp_status tdvp_observe_batched(tdvp_ctx *ctx, int nb, const tdvp_mps *mps, con
   CK(hipSetDevice(ctx->device));
   std::vector<double> shifts(nb);
   for (int r = 0; r < nb; ++r) shifts[r] = mpo[r].energy_shift;
-  return observe_impl(ctx, lay, ch, mps, mpo, envs, el_sites, n_el, out_dev, 2 + n_el, shifts.data(), b, s);
+  CS(observe_impl(ctx, lay, ch, mps, mpo, envs, el_sites, n_el, out_dev, 2 + n_el, shifts.data(), b, s));
+  // non-finite check: the context's sticky Lanczos flag and every observable
+  // just written; the host waits for the stream here
+  CtxHeader *hdr = header(ctx);
+  CK(numeric_check(&hdr->nonfinite, 0, out_dev, 2 + n_el, 2 + n_el, nb, &hdr->numeric_out,
+                   ctx->stream));
+  int bad = 0;
+  CK(hipMemcpyAsync(&bad, &hdr->numeric_out, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  CK(hipStreamSynchronize(ctx->stream));
+  return bad ? TDVP_E_NUMERIC : TDVP_OK;
 }
 
 tdvp_status tdvp_ps_step_batched(tdvp_ctx *ctx, int nb, const tdvp_mps *mps, const tdvp_mpo *mpo,

@@ -77,7 +77,16 @@ struct LzState {
   int k;
   int keff;                   // largest basis for this solve: min(kmax, dim)
   double z_re, z_im, tol;
+  int *nonfinite;             // the context's sticky flag (CtxHeader), set by lz_start
 };
+
+// First bytes of the caller's workspace: context-wide device flags.
+struct CtxHeader {
+  int nonfinite;              // sticky: a Lanczos norm of some solve was NaN or Inf
+                              // (cleared only by tdvp_set_workspace)
+  int numeric_out;            // result of the last numeric_check
+};
+constexpr size_t CTX_HEADER_BYTES = 256;
 
 // Per-work-group partial sums.  Norm partials (lz_start, lz_update) and dot
 // partials (lz_dots) live in separate arrays so a kernel never reads the
@@ -98,8 +107,8 @@ struct LzInst {
 // trows > 0 (lz_start, lz_finish): the basis is stored column-major, index
 // c * trows + r for the element (r, c) of the row-major n / trows-column x, y.
 hipError_t lz_start(LzState *st, LzPartials *pp, const double2 *x, double2 *u0, int64_t n,
-                    double zr, double zi, double tol, int keff, int trows, const LzInst &in,
-                    hipStream_t s);
+                    double zr, double zi, double tol, int keff, int trows, int *nonfinite,
+                    const LzInst &in, hipStream_t s);
 hipError_t lz_dots(LzState *st, LzPartials *pp, DType ty, const void *ypart, int P, int64_t pstride,
                    double2 *U, int64_t ldu, int j, int64_t n, const LzInst &in, hipStream_t s);
 // Gd: number of per-work-group dot partials written by the kernel before

@@ -202,14 +202,18 @@ __device__ bool close_step_finish(LzState *st, const StepPre &p, int j, int Gw) 
   if (threadIdx.x == 0) {
     const double nv = sqrt(nrm_s);
     int stop = 0;
+    // a non-finite norm (from a non-finite input or operator) stops the
+    // solve and raises the sticky flag that tdvp_observe reports
+    const bool bad = !isfinite(nv) || !isfinite(aw_s);
+    if (bad && blockIdx.x == 0) *st->nonfinite = 1;
     if (j == 0) {
-      if (!(nv > 0.0) || !isfinite(nv)) stop = 1;
+      if (!(nv > 0.0) || bad) stop = 1;
       if (blockIdx.x == 0) {
         st->xnorm = nv;
         st->scale[0] = stop ? 0.0 : 1.0 / nv;
       }
     } else {
-      if (!(nv > 1e-12 * aw_s) || !isfinite(nv) || j >= p.keff) stop = 1;
+      if (!(nv > 1e-12 * aw_s) || bad || j >= p.keff) stop = 1;
       if (!stop && blockIdx.x == 0) {
         st->beta[j - 1] = nv;
         st->scale[j] = 1.0 / nv;
@@ -259,7 +263,7 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_start_kernel(LzState *st, LzParti
                                                             const double2 *x, double2 *u0,
                                                             int64_t n, double zr, double zi,
                                                             double tol, int keff, int trows,
-                                                            LzInst in) {
+                                                            int *nonfinite, LzInst in) {
   const int64_t wo = (int64_t)blockIdx.y * in.wss;
   st = shift_bytes(st, wo);
   pp = shift_bytes(pp, wo);
@@ -285,6 +289,7 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_start_kernel(LzState *st, LzParti
       st->z_re = zr;
       st->z_im = zi;
       st->tol = tol;
+      st->nonfinite = nonfinite;
     }
   }
 }
@@ -584,7 +589,10 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_finish_kernel(LzState *st, const 
   if (b0 < n) LZ_FINISH_LOAD(b0 + lane);
   const int k = st->stop ? st->k : keff;
   const double xn = st->xnorm;
-  const bool zero = !(xn > 0.0) || k <= 0;
+  // a zero input gives y = 0; a non-finite one gives y = NaN (never a
+  // finite-looking result)
+  const bool nanout = !isfinite(xn);
+  const bool zero = !(xn > 0.0) || k <= 0 || nanout;
   if (!zero && threadIdx.x < 64)
     exp_tridiag_e1_wave(st->alpha, st->beta, k, st->z_re, st->z_im, cr, ci);
   __syncthreads();
@@ -600,7 +608,7 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_finish_kernel(LzState *st, const 
 #pragma unroll
     for (int t = 0; t < NI; ++t) ucur[t] = uv[t];
     if (base + bstride < n) LZ_FINISH_LOAD(base + bstride + lane);
-    double yr = 0.0, yi = 0.0;
+    double yr = nanout ? __builtin_nan("") : 0.0, yi = yr;
     if (!zero) {
 #pragma unroll
       for (int t = 0; t < NI; ++t) {
@@ -1078,10 +1086,10 @@ int dots_grid(int64_t n) {
 }  // namespace
 
 hipError_t lz_start(LzState *st, LzPartials *pp, const double2 *x, double2 *u0, int64_t n,
-                    double zr, double zi, double tol, int keff, int trows, const LzInst &in,
-                    hipStream_t s) {
+                    double zr, double zi, double tol, int keff, int trows, int *nonfinite,
+                    const LzInst &in, hipStream_t s) {
   hipLaunchKernelGGL(lz_start_kernel, dim3(upd_grid(n), in.count), dim3(LZ_BLOCK), 0, s, st, pp, x,
-                     u0, n, zr, zi, tol, keff, trows, in);
+                     u0, n, zr, zi, tol, keff, trows, nonfinite, in);
   return hipGetLastError();
 }
 

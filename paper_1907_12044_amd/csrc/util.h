@@ -22,5 +22,9 @@ hipError_t sum_partials(DType ty, const void *y, int P, int64_t pstride, int64_t
 hipError_t axpy_scalar(double *dst, const double *src, double c, hipStream_t s, int count = 1,
                        int64_t is = 0);
 hipError_t normalize_c128(double2 *a, int64_t n, hipStream_t s);                  // a /= |a|
+// *out = 1 if any of the count instance flags (flag + r * fstride ints) is set
+// or any of vals[r * vs + 0 .. nv-1] is not finite, else 0
+hipError_t numeric_check(const int *flag, int64_t fstride, const double *vals, int64_t vs, int nv,
+                         int count, int *out, hipStream_t s);
 
 }  // namespace tdvp

@@ -172,4 +172,29 @@ hipError_t normalize_c128(double2 *a, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+// One work-group: thread t looks at the instances t, t + RT, ...
+__global__ __launch_bounds__(RT) void numeric_check_kernel(const int *flag, int64_t fstride,
+                                                           const double *vals, int64_t vs, int nv,
+                                                           int count, int *out) {
+  __shared__ int any;
+  if (threadIdx.x == 0) any = 0;
+  __syncthreads();
+  int bad = 0;
+  for (int r = threadIdx.x; r < count; r += RT) {
+    if (flag[(int64_t)r * fstride] != 0) bad = 1;
+    for (int v = 0; v < nv; ++v)
+      if (!isfinite(vals[(int64_t)r * vs + v])) bad = 1;
+  }
+  if (bad) any = 1;   // benign race: every writer stores 1
+  __syncthreads();
+  if (threadIdx.x == 0) *out = any;
+}
+
+hipError_t numeric_check(const int *flag, int64_t fstride, const double *vals, int64_t vs, int nv,
+                         int count, int *out, hipStream_t s) {
+  hipLaunchKernelGGL(numeric_check_kernel, dim3(1), dim3(RT), 0, s, flag, fstride, vals, vs, nv,
+                     count, out);
+  return hipGetLastError();
+}
+
 }  // namespace tdvp

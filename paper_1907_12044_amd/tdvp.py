@@ -334,7 +334,8 @@ def observe(ctx, mps, mpo, envs, el_sites, out):
 
 PROF_GEMM, PROF_WAPPLY, PROF_LZ_DOTS, PROF_LZ_UPDATE, PROF_LZ_ENDS, PROF_QR = 1, 2, 3, 4, 5, 6
 PROF_LZ_FUSED = 7
-PROF_CLASSES = {"gemm": PROF_GEMM, "wapply": PROF_WAPPLY, "lz_dots": PROF_LZ_DOTS,
+PROF_GEMM_HEFF = 8
+PROF_CLASSES = {"gemm": PROF_GEMM, "gemm_heff": PROF_GEMM_HEFF, "wapply": PROF_WAPPLY, "lz_dots": PROF_LZ_DOTS,
                 "lz_update": PROF_LZ_UPDATE, "lz_ends": PROF_LZ_ENDS, "qr": PROF_QR,
                 "lz_fused": PROF_LZ_FUSED}
 
@@ -536,3 +537,46 @@ class _Wrap:
 
     def __init__(self, desc):
         self.desc = desc
+
+
+class DisorderEnsemble:
+    """Static-disorder realisations of uneven bond dimension evolved together.
+
+    ``members`` = [(r, params, M_r, raw MPS)] on the chain layout ``sites``;
+    realisations that share a bond dimension form one class, held as one PsEnsemble (every kernel covers
+    the class in one launch), each class on a stream of its own so that the
+    classes run concurrently.  ``step`` enqueues one step of every class;
+    ``observe_host`` returns the observables in realisation order.
+    """
+
+    def __init__(self, members, sites, device=0, precision=FP64, kmax=20, tol=0.0, graph=True,
+                 fused=True, autotune=False):
+        import torch
+        self.torch = torch
+        classes = {}
+        for r, p, M, raw in members:
+            classes.setdefault(M, []).append((r, p, raw))
+        self.order = []
+        self.classes = []
+        for M, rs in sorted(classes.items()):
+            e = PsEnsemble([p for _, p, _ in rs], sites, [raw for _, _, raw in rs], device, precision,
+                           kmax=kmax, tol=tol, graph=graph, fused=fused, autotune=autotune)
+            self.classes.append((M, [r for r, _, _ in rs], e))
+        self.nreal = len(members)
+        self.n_e = self.classes[0][2].n_e
+
+    def step(self, dt_au, nsteps=1):
+        for _ in range(nsteps):
+            for _, _, e in self.classes:
+                e.step(dt_au, 1)
+
+    def observe_host(self):
+        out = np.zeros((self.nreal, 2 + self.n_e))
+        for _, rs, e in self.classes:
+            out[rs] = e.observe_host()
+        return out
+
+    def synchronize(self):
+        for _, _, e in self.classes:
+            e.stream.synchronize()
+

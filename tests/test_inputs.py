@@ -1,6 +1,7 @@
 """Checks on the seeded synthetic inputs (no method arithmetic lives there)."""
 
 import numpy as np
+import pytest
 
 from inputs import draw_params, chain_sites, bond_dims, initial_mps_raw, workload, WORKLOADS
 from inputs.fmo import electronic_order, ensemble_bond
@@ -92,3 +93,31 @@ def test_named_workloads_build():
         for i, A in enumerate(raw):
             assert A.shape == (dims[i], phys[i], dims[i + 1])
     assert set(WORKLOADS) >= {"fmo3x1x4_M16", "fmo7x10x8_M32", "fmo7x10x8_M128"}
+
+
+@pytest.mark.parametrize("name", ["fmo7x10x8_M32", "fmo7x10x8_M64", "fmo7x10x8_M96", "fmo7x10x8_M128"])
+def test_initial_populations_within_1e6_of_the_product_state(name):
+    """The small parts that fill the bond channels move the t = 0
+    populations of the normalised state by at most 1e-6 from the Hartree
+    product state (exciton on electronic site 1), at every bond dimension;
+    the state stays in the one-exciton sector (populations sum to 1)."""
+    p, sites, phys, dims, raw, w = workload(name)
+    m = om.right_canonicalize(raw)
+    pops = om.site_populations(m, sites, p.n_e)
+    dev = np.abs(pops - np.eye(p.n_e)[0]).max()
+    assert dev < 1e-6, dev
+    assert dev > 1e-9        # the channels really are filled
+    assert abs(pops.sum() - 1.0) < 1e-12
+
+
+def test_initial_state_of_the_217_site_chain_from_its_golden():
+    """Same bound for the 217-site chain, read from the step-0 record of the
+    oracle run stored in tests/golden/c5.npz (too large to redo here)."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "c5.npz")
+    if not os.path.exists(path):
+        pytest.skip("c5 golden not generated")
+    g = np.load(path)
+    assert int(g["steps"][0]) == 0
+    dev = np.abs(g["pops"][0] - np.eye(7)[0]).max()
+    assert 1e-9 < dev < 1e-6, dev

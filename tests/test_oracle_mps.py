@@ -119,7 +119,7 @@ def test_populations_equal_dense(small_chain):
 
 
 def test_single_elements_match_brute_force_sums():
-    """heff_element / env_left_element against the defining sums written
+    """heff_element / env_left_element / env_right_element against the defining sums written
     out as loops over every index (tiny shapes), and against the full
     applications at a few points."""
     Ml, d, Mr, Wl, Wr = 3, 2, 2, 2, 3
@@ -149,3 +149,14 @@ def test_single_elements_match_brute_force_sums():
                             ref += L[b, w, k] * A[k, t, r] * Wa[w, s, t, y] * np.conj(A[b, s, q])
         assert abs(om.env_left_element(L, A, Wa, q, y, r) - ref) < 1e-13
         assert abs(om.env_left(L, A, Wa)[q, y, r] - ref) < 1e-13
+    Rr = random_complex((Mr, Wr, Mr), 7)
+    for (b, w, k) in [(0, 0, 0), (2, 1, 1), (1, 1, 2)]:
+        ref = 0j
+        for q in range(Mr):
+            for y in range(Wr):
+                for r in range(Mr):
+                    for t in range(d):
+                        for s in range(d):
+                            ref += Rr[q, y, r] * A[k, t, r] * Wa[w, s, t, y] * np.conj(A[b, s, q])
+        assert abs(om.env_right_element(Rr, A, Wa, b, w, k) - ref) < 1e-13
+        assert abs(om.env_right(Rr, A, Wa)[b, w, k] - ref) < 1e-13
