@@ -31,6 +31,11 @@ PEAK = {"fp64_mfma_tflops": 78.6, "fp32_mfma_tflops": 157.3, "bf16x3_eff_tflops"
         "hbm_gbs": 8000.0}
 
 
+def log(msg):
+    """Progress of the benchmark's phases on stderr (stdout carries only the JSON line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -257,15 +262,18 @@ def ensemble_main(args):
 
     ens = build(prec)
     torch.cuda.synchronize()
+    log(f"ensemble of {nreal} built ({args.precision})")
     hist = [ens.observe_host()]          # observables after 0, 1, 2, ... steps
-    for _ in range(args.warmup):
+    for w in range(args.warmup):
         ens.step(tau, 1)
         hist.append(ens.observe_host())
+        log(f"warm-up step {w + 1} done")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
         ens.step(tau, 1)
         hist.append(ens.observe_host())
+        log(f"timed step {k + 1} done")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms = 1e3 * elapsed / max(args.steps, 1)
@@ -289,6 +297,7 @@ def ensemble_main(args):
                 if name in HEFF_CLASSES:
                     class_flop[M] = class_flop.get(M, 0.0) + f_ / len(rs)
             prof[name] = acc
+            log(f"class timing {name} done")
     roof, heff_tflops = roofline(prof, prec, ms, f"ensemble{nreal}", args.precision)
     del ens
     torch.cuda.empty_cache()
@@ -300,6 +309,7 @@ def ensemble_main(args):
         e64 = build(tdvp.FP64)
         e64.step(tau, 1)                  # first step: autotuning, graph capture
         torch.cuda.synchronize()
+        log("FP64 twin: first step done")
         t1 = time.perf_counter()
         if nt > 1:
             e64.step(tau, nt - 1)
@@ -341,6 +351,7 @@ def ensemble_main(args):
     }
     if not args.no_cpu_baseline:
         if len(class_flop) == 4:
+            log("oracle timing (cpu_baseline)")
             line["cpu_baseline"] = ensemble_cpu_baseline(members, sites, tau, class_flop)
     print(json.dumps(line), flush=True)
 

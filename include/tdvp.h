@@ -281,6 +281,42 @@ tdvp_status tdvp_observe_batched(tdvp_ctx *ctx, int nb, const tdvp_mps *mps, con
                                  const tdvp_envs *envs, const int32_t *el_sites, int n_el,
                                  double *out_dev);
 
+/* TDVP-MU (Sec. II.A.2, "TDVP-MU"): the equations of motion of a
+ * left-canonical MPS (site tensors L_0 .. L_{n-2} left-isometric, the
+ * centre C_{n-1} at the last site) with the matrix-unfolding
+ * regularisation, integrated by the variable-mean-field scheme.
+ * Right-hand side:
+ *   dC_{n-1}/dt = -i H[n-1] C_{n-1}                              (eq:tdvp1_C)
+ *   dL_i/dt     = -i (1 - L_i L_i^H) H[i](L_i D_i) V Lam~^{-1} U^H (eq:tdvp1_mu_L)
+ * with D_i = U Lam V^H the bond matrix right of site i from an RQ sweep
+ * of the state (eq:tdvp1_mu_rcano), H[i] built with environments in the
+ * orthonormal right basis of that sweep, and Lam~ = Lam + sqrt(eps)
+ * exp(-Lam / sqrt(eps)) (eq:reg2).  Canonicality is not re-imposed.
+ * Limits: TDVP_FP64 contexts only, every bond dimension <= 64 (the
+ * regularised inverse is a one-sided Jacobi SVD in one work-group);
+ * TDVP_E_UNSUPPORTED otherwise.  The context workspace must hold
+ * tdvp_mu_workspace_bytes (host-only computation). */
+tdvp_status tdvp_mu_workspace_bytes(const tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo,
+                                    size_t *bytes);
+/* One evaluation of the right-hand side: out_site (host table of n device
+ * pointers, c128, the shapes of the MPS sites, not aliasing them) receives
+ * d(site i)/dt for the state mps.  eps > 0. */
+tdvp_status tdvp_mu_rhs(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo, double eps,
+                        void *const *out_site);
+/* Integrate the MU equations from t = 0 to t_final (atomic time units) in
+ * place, with the Dormand-Prince 5(4) pair: error per step measured as the
+ * RMS of err / (atol + rtol max(|y|, |y_new|)) over every complex entry,
+ * accepted when below 1, step factor 0.9 err^(-1/5) within [0.2, 10] (no
+ * growth right after a rejection), first step from the two-evaluation
+ * rule.  The host waits for the stream once per step (the accept/reject
+ * decision).  stats (host int64[3], may be NULL): accepted steps, rejected
+ * steps, right-hand-side evaluations.  TDVP_E_NUMERIC if the error becomes
+ * non-finite, the step falls below the time resolution, or max_steps
+ * steps (accepted + rejected) do not reach t_final; the state is then
+ * left as it was at the start of the call. */
+tdvp_status tdvp_mu_evolve(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo, double t_final,
+                           double eps, double rtol, double atol, int max_steps, int64_t *stats);
+
 /* Frenkel-Holstein MPO (Sec. II.C, eq:holstein) written into HOST buffers.
  * Chain sites are given by kind[i] (0 = electronic two-level site, 1 = mode),
  * owner[i] (electronic index 0..n_e-1 the site belongs to) and phys[i].

@@ -128,6 +128,11 @@ def _sector_counts(sites, b):
     return left, right
 
 
+# Highest vibrational level of a mode that the random block of the initial
+# state touches.
+VIB_BLOCK_LEVEL = 2
+
+
 def initial_mps_raw(p: ChainParams, M: int, eta: float = 0.0,
                     phi_seed: int = 1, exciton_site: int = 0):
     """Raw initial MPS tensors (M_b, d, M_{b+1}) complex128, not canonical.
@@ -212,6 +217,21 @@ def initial_mps_raw(p: ChainParams, M: int, eta: float = 0.0,
         labels.append(lab)
     labels.append([1])
 
+    # The random block keeps modes at levels <= VIB_BLOCK_LEVEL (low phonon
+    # numbers, as the small Huang-Rhys factors favour), except on modes next
+    # to a bond whose capped space on either side is too small to fill it
+    # (near the chain ends), which use every level.
+    def capped_dim(sl):
+        nel = sum(1 for t in sl if t[0] == "el")
+        v = 1
+        for t in sl:
+            if t[0] == "vib":
+                v = min(v * min(t[3], VIB_BLOCK_LEVEL + 1), 1 << 40)
+        return (1 + nel) * v
+    fits = [True] + [capped_dim(sites[:b]) >= 2 * dims[b] and capped_dim(sites[b:]) >= 2 * dims[b]
+                     for b in range(1, n)] + [True]
+    capped = [fits[i] and fits[i + 1] for i in range(n)]
+
     rng = np.random.default_rng(phi_seed)
     a = (rng.standard_normal(p.n_e) + 1j * rng.standard_normal(p.n_e)) / np.sqrt(2.0)
     out = []
@@ -225,6 +245,8 @@ def initial_mps_raw(p: ChainParams, M: int, eta: float = 0.0,
         G = (re + 1j * im) / np.sqrt(2.0)
         nloc = np.arange(d) if s[0] == "el" else np.zeros(d, dtype=int)
         mask = lq[:, None, None] + nloc[None, :, None] == rq[None, None, :]
+        if s[0] == "vib" and capped[i]:
+            mask &= (np.arange(d) <= VIB_BLOCK_LEVEL)[None, :, None]
         # expected squared norm of every row (j, :, :) is 1
         w2 = mask.sum(axis=(1, 2))
         G = np.where(mask, G, 0.0) / np.sqrt(np.maximum(w2, 1))[:, None, None]
@@ -283,7 +305,7 @@ WORKLOADS = {
     # (217 sites: more points where the random part can leave the product
     # channel, so a smaller eta keeps the t = 0 populations within 1e-6)
     "fmo7x30x10_M256": dict(n_e=7, n_modes=30, levels=10, M=256, dt_fs=1.0, steps=200,
-                            seed=0, eta=8e-5, phi_seed=1),
+                            seed=0, eta=7e-5, phi_seed=1),
 }
 
 

@@ -13,7 +13,8 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libtdvp.so")
 BUILD = os.path.join(PKG, "_build")
 
-HIP_SOURCES = ["gemm.hip", "wapply.hip", "lanczos.hip", "qr.hip", "cholqr.hip", "util.hip", "api.hip"]
+HIP_SOURCES = ["gemm.hip", "wapply.hip", "lanczos.hip", "qr.hip", "cholqr.hip", "util.hip", "mu.hip",
+               "api.hip"]
 CXX_SOURCES = ["mpo.cpp"]
 
 HIPCC_FLAGS = [

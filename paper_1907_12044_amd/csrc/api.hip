@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <initializer_list>
 #include <new>
 #include <vector>
 
@@ -1116,6 +1117,308 @@ tdvp_status tdvp_ps_step_batched(tdvp_ctx *ctx, int nb, const tdvp_mps *mps, con
     ctx->gkey = key;
   }
   for (int st = 0; st < nsteps; ++st) CK(hipGraphLaunch(ctx->gexec, ctx->stream));
+  return TDVP_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// TDVP-MU (Sec. II.A.2, "TDVP-MU"), variable-mean-field integration.
+//
+// State: left-canonical site tensors L_0..L_{n-2} and the centre C_{n-1}.
+// One right-hand side (eq:tdvp1_C, eq:tdvp1_mu_L with eq:reg2):
+//   1. left environments h[1:i] from the L's (eq:tdvp1_h1i);
+//   2. an RQ sweep from the right end, C_{n-1} = D_{n-1} R_{n-1},
+//      L_{i} D_{i+1} = D_i R_i, giving right isometries R_i and the bond
+//      matrices D_b between sites b-1 and b;
+//   3. right environments from the R's (eq:tdvp1_hiN);
+//   4. per site i < n-1: P = V Lam~^{-1} U^H from D_{i+1} = U Lam V^H,
+//      G = H[i] (L_i D_{i+1}), X = G P, dL_i/dt = -i (X - L_i (L_i^H X));
+//   5. dC_{n-1}/dt = -i H[n-1] C_{n-1}.
+// The integrator is the Dormand-Prince 5(4) pair with the usual step-size
+// control (error norm scaled by atol + rtol max(|y|, |y_new|), safety 0.9,
+// step factor within [0.2, 10], first step from the two-evaluation rule);
+// the step decision is taken on the host after each step (one sync).
+namespace {
+
+struct MuPlan {
+  Chain ch;
+  Layout lay;                       // local-problem region (contraction, QR scratch)
+  std::vector<size_t> lenv, renv, rt, dbuf, site_off;   // byte offsets / element offsets (site_off)
+  size_t P, C, G, X, Y, T;          // per-site temporaries
+  size_t vec[11];                   // packed vectors: y, ys, ynew, err, k1..k7
+  size_t part;                      // RK error partial sums
+  int64_t ntot;                     // packed length (complex elements)
+  size_t total;
+};
+
+constexpr int MU_MAXM = 64;         // bond dimensions the regularised inverse handles
+
+tdvp_status mu_plan(const tdvp_ctx *c, const tdvp_mps *mps, const tdvp_mpo *mpo, MuPlan *pl) {
+  if (!c || !mpo) return TDVP_E_ARG;
+  CS(check_chain(mps, mpo, &pl->ch));
+  if (c->prec != TDVP_FP64) return TDVP_E_UNSUPPORTED;
+  const Chain &ch = pl->ch;
+  const int n = ch.n;
+  if (n < 2) return TDVP_E_SHAPE;
+  if (ch.mmax > MU_MAXM) return TDVP_E_UNSUPPORTED;
+  pl->lay = layout(ch.nmax, ch.wmax, 1, 16);
+  size_t o = pl->lay.total;
+  auto take = [&](size_t bytes) { const size_t r = o; o += al256(bytes); return r; };
+  pl->lenv.assign(n + 1, 0);
+  pl->renv.assign(n + 1, 0);
+  pl->dbuf.assign(n + 1, 0);
+  pl->rt.assign(n, 0);
+  pl->site_off.assign(n + 1, 0);
+  for (int b = 0; b <= n; ++b) {
+    const size_t e = (size_t)ch.bond[b] * ch.wbond[b] * ch.bond[b] * 16;
+    pl->lenv[b] = take(e);
+    pl->renv[b] = take(e);
+    pl->dbuf[b] = take((size_t)ch.bond[b] * ch.bond[b] * 16);
+  }
+  int64_t tot = 0;
+  for (int i = 0; i < n; ++i) {
+    const int64_t sz = (int64_t)ch.bond[i] * ch.phys[i] * ch.bond[i + 1];
+    pl->rt[i] = take((size_t)sz * 16);
+    pl->site_off[i] = tot;
+    tot += sz;
+  }
+  pl->site_off[n] = tot;
+  pl->ntot = tot;
+  const size_t m2 = (size_t)ch.mmax * ch.mmax * 16, nv = (size_t)ch.nmax * 16;
+  pl->P = take(m2);
+  pl->T = take(m2);
+  pl->C = take(nv);
+  pl->G = take(nv);
+  pl->X = take(nv);
+  pl->Y = take(nv);
+  for (size_t &v : pl->vec) v = take((size_t)tot * 16);
+  pl->part = take(RK_PARTS * sizeof(double));
+  pl->total = o;
+  return TDVP_OK;
+}
+
+// out[i] = d(site i)/dt for the left-canonical state A (host tables of n device pointers).
+tdvp_status mu_rhs_impl(tdvp_ctx *c, const MuPlan &pl, const tdvp_mpo *mpo, const double2 *const *A,
+                        double2 *const *out, double eps) {
+  const Chain &ch = pl.ch;
+  const int n = ch.n;
+  const Layout &lay = pl.lay;
+  auto B = [&](size_t off) { return reinterpret_cast<double2 *>(c->ws + off); };
+  // 1. left environments
+  CK(fill_one(B(pl.lenv[0]), F64, c->stream));
+  for (int i = 0; i + 1 < n; ++i)
+    CS(env_update(c, lay, +1, B(pl.lenv[i]), A[i], mpo->site[i], ch.bond[i], ch.phys[i], ch.bond[i + 1],
+                  ch.wbond[i], ch.wbond[i + 1], B(pl.lenv[i + 1]), Bi(), 0, 0, 0, 0));
+  // 2. RQ sweep: rt[i] = R_i, dbuf[i] = D_i (bond i, between sites i-1 and i)
+  for (int i = n - 1; i >= 1; --i) {
+    const int Ml = ch.bond[i], d = ch.phys[i], Mr = ch.bond[i + 1];
+    const int64_t sz = (int64_t)Ml * d * Mr;
+    if (i == n - 1) CK(copy_c128(B(pl.rt[i]), A[i], sz, c->stream));
+    else CS(matmul(c, A[i], B(pl.dbuf[i + 1]), B(pl.rt[i]), Ml * d, Mr, Mr));
+    CS(qr_right(c, lay, B(pl.rt[i]), Ml, d, Mr, B(pl.dbuf[i]), Bi(), 0));
+  }
+  // 3. right environments
+  CK(fill_one(B(pl.renv[n]), F64, c->stream));
+  for (int i = n - 1; i >= 1; --i)
+    CS(env_update(c, lay, -1, B(pl.renv[i + 1]), B(pl.rt[i]), mpo->site[i], ch.bond[i], ch.phys[i],
+                  ch.bond[i + 1], ch.wbond[i], ch.wbond[i + 1], B(pl.renv[i]), Bi(), 0, 0, 0, 0));
+  // 4. projected site derivatives
+  for (int i = 0; i < n; ++i) {
+    const int Ml = ch.bond[i], d = ch.phys[i], Mr = ch.bond[i + 1];
+    const int64_t sz = (int64_t)Ml * d * Mr;
+    const double2 *x = A[i];
+    if (i + 1 < n) {
+      CK(mu_reginv(B(pl.dbuf[i + 1]), Mr, eps, B(pl.P), nullptr, c->stream));
+      CS(matmul(c, A[i], B(pl.dbuf[i + 1]), B(pl.C), Ml * d, Mr, Mr));
+      x = B(pl.C);
+    }
+    const Op op{B(pl.lenv[i]), mpo->site[i], B(pl.renv[i + 1]), Ml, d, Mr, ch.wbond[i], ch.wbond[i + 1]};
+    CS(apply_op(c, lay, op, x, 0, nullptr, Bi()));
+    CK(sum_partials(F64, c->ws + lay.Y, op.parts(), sz, sz, B(pl.G), c->stream));
+    if (i + 1 == n) {
+      CK(mu_finish(B(pl.G), nullptr, out[i], sz, c->stream));   // 5.
+      break;
+    }
+    CS(matmul(c, B(pl.G), B(pl.P), B(pl.X), Ml * d, Mr, Mr));
+    GemmArgs g{};   // T = L_i^H X  (Mr x Mr)
+    g.A = A[i]; g.B = B(pl.X); g.C = B(pl.T);
+    g.M = Mr; g.N = Mr; g.K = Ml * d; g.batch = 1;
+    g.sam = 1; g.sak = Mr; g.conjA = 1; g.sbk = Mr; g.sbn = 1; g.scm = Mr; g.scn = 1;
+    CK(gemm_t(c, F64, F64, F64, g));
+    CS(matmul(c, A[i], B(pl.T), B(pl.Y), Ml * d, Mr, Mr));
+    CK(mu_finish(B(pl.X), B(pl.Y), out[i], sz, c->stream));
+  }
+  return TDVP_OK;
+}
+
+tdvp_status mu_prepare(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo, MuPlan *pl) {
+  CS(mu_plan(ctx, mps, mpo, pl));
+  if (!ctx->ws || ctx->ws_bytes < pl->total) return TDVP_E_WORKSPACE;
+  CK(hipSetDevice(ctx->device));
+  return TDVP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tdvp_status tdvp_mu_workspace_bytes(const tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo,
+                                    size_t *bytes) {
+  if (!bytes) return TDVP_E_ARG;
+  MuPlan pl;
+  CS(mu_plan(ctx, mps, mpo, &pl));
+  *bytes = pl.total;
+  return TDVP_OK;
+}
+
+tdvp_status tdvp_mu_rhs(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo, double eps,
+                        void *const *out_site) {
+  if (!out_site || !(eps > 0.0)) return TDVP_E_ARG;
+  MuPlan pl;
+  CS(mu_prepare(ctx, mps, mpo, &pl));
+  const int n = pl.ch.n;
+  std::vector<const double2 *> A(n);
+  std::vector<double2 *> out(n);
+  for (int i = 0; i < n; ++i) {
+    if (!out_site[i]) return TDVP_E_ARG;
+    A[i] = (const double2 *)mps->site[i];
+    out[i] = (double2 *)out_site[i];
+  }
+  return mu_rhs_impl(ctx, pl, mpo, A.data(), out.data(), eps);
+}
+
+tdvp_status tdvp_mu_evolve(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo, double t_final,
+                           double eps, double rtol, double atol, int max_steps, int64_t *stats) {
+  if (!(t_final >= 0.0) || !(eps > 0.0) || !(rtol > 0.0) || !(atol >= 0.0) || max_steps < 1)
+    return TDVP_E_ARG;
+  MuPlan pl;
+  CS(mu_prepare(ctx, mps, mpo, &pl));
+  const int n = pl.ch.n;
+  const int64_t N = pl.ntot;
+  auto V = [&](int k) { return reinterpret_cast<double2 *>(ctx->ws + pl.vec[k]); };
+  double2 *y = V(0), *ys = V(1), *ynew = V(2), *err = V(3);
+  double2 *K[7];
+  for (int j = 0; j < 7; ++j) K[j] = V(4 + j);
+  double *part = reinterpret_cast<double *>(ctx->ws + pl.part);
+  // site pointer tables into a packed vector
+  auto sites_of = [&](double2 *v, std::vector<double2 *> &t) {
+    t.resize(n);
+    for (int i = 0; i < n; ++i) t[i] = v + pl.site_off[i];
+  };
+  for (int i = 0; i < n; ++i)
+    CK(copy_c128(y + pl.site_off[i], (const double2 *)mps->site[i], pl.site_off[i + 1] - pl.site_off[i],
+                 ctx->stream));
+  int64_t nfev = 0, nacc = 0, nrej = 0;
+  auto f = [&](const double2 *in, double2 *outv) -> tdvp_status {
+    std::vector<double2 *> ti, to;
+    sites_of(const_cast<double2 *>(in), ti);
+    sites_of(outv, to);
+    ++nfev;
+    return mu_rhs_impl(ctx, pl, mpo, ti.data(), to.data(), eps);
+  };
+  // RMS of (e / (atol + rtol max(|a|, |b|))) over the packed vector
+  auto wnorm = [&](const double2 *e, const double2 *a, const double2 *b, double *res) -> tdvp_status {
+    const int g = rk_err_partials(e, a, b, N, rtol, atol, part, ctx->stream);
+    if (g < 0) return TDVP_E_DEVICE;
+    std::vector<double> h(g);
+    CK(hipMemcpyAsync(h.data(), part, g * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
+    double sum = 0.0;
+    for (double v : h) sum += v;
+    *res = std::sqrt(sum / (double)N);
+    return TDVP_OK;
+  };
+  auto lin = [&](double2 *out, const double2 *x0, std::initializer_list<std::pair<double, const double2 *>> terms)
+      -> tdvp_status {
+    LinComb lc{};
+    lc.out = out;
+    lc.x0 = x0;
+    for (const auto &t : terms) {
+      if (t.first == 0.0) continue;
+      lc.a[lc.m] = t.first;
+      lc.x[lc.m] = t.second;
+      ++lc.m;
+    }
+    CK(lincomb(lc, N, ctx->stream));
+    return TDVP_OK;
+  };
+  // Dormand-Prince 5(4) tableau
+  static const double A2[1] = {1.0 / 5};
+  static const double A3[2] = {3.0 / 40, 9.0 / 40};
+  static const double A4[3] = {44.0 / 45, -56.0 / 15, 32.0 / 9};
+  static const double A5[4] = {19372.0 / 6561, -25360.0 / 2187, 64448.0 / 6561, -212.0 / 729};
+  static const double A6[5] = {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656};
+  static const double B5[6] = {35.0 / 384, 0.0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84};
+  static const double E7[7] = {71.0 / 57600, 0.0, -71.0 / 16695, 71.0 / 1920, -17253.0 / 339200,
+                               22.0 / 525, -1.0 / 40};
+  double t = 0.0;
+  CS(f(y, K[0]));
+  if (t_final > 0.0) {
+    // first step from the two-evaluation rule (order 4 error estimate)
+    double d0, d1, d2;
+    CS(wnorm(y, y, y, &d0));
+    CS(wnorm(K[0], y, y, &d1));
+    double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
+    h0 = std::min(h0, t_final);
+    CS(lin(ys, y, {{h0, K[0]}}));
+    CS(f(ys, K[1]));
+    CS(lin(err, K[1], {{-1.0, K[0]}}));
+    CS(wnorm(err, y, y, &d2));
+    d2 /= h0;
+    const double h1 = (d1 <= 1e-15 && d2 <= 1e-15) ? std::max(1e-6, h0 * 1e-3)
+                                                   : std::pow(0.01 / std::max(d1, d2), 1.0 / 5);
+    double h = std::min(std::min(100 * h0, h1), t_final);
+    bool rejected = false;
+    while (t < t_final) {
+      if (nacc + nrej >= max_steps) return TDVP_E_NUMERIC;
+      const double min_step = 10.0 * std::fabs(std::nextafter(t, 2 * t_final + 1.0) - t);
+      if (h < min_step) return TDVP_E_NUMERIC;
+      double hs = h;
+      if (t + hs > t_final) hs = t_final - t;
+      CS(lin(ys, y, {{hs * A2[0], K[0]}}));
+      CS(f(ys, K[1]));
+      CS(lin(ys, y, {{hs * A3[0], K[0]}, {hs * A3[1], K[1]}}));
+      CS(f(ys, K[2]));
+      CS(lin(ys, y, {{hs * A4[0], K[0]}, {hs * A4[1], K[1]}, {hs * A4[2], K[2]}}));
+      CS(f(ys, K[3]));
+      CS(lin(ys, y, {{hs * A5[0], K[0]}, {hs * A5[1], K[1]}, {hs * A5[2], K[2]}, {hs * A5[3], K[3]}}));
+      CS(f(ys, K[4]));
+      CS(lin(ys, y, {{hs * A6[0], K[0]}, {hs * A6[1], K[1]}, {hs * A6[2], K[2]}, {hs * A6[3], K[3]},
+                     {hs * A6[4], K[4]}}));
+      CS(f(ys, K[5]));
+      CS(lin(ynew, y, {{hs * B5[0], K[0]}, {hs * B5[2], K[2]}, {hs * B5[3], K[3]}, {hs * B5[4], K[4]},
+                       {hs * B5[5], K[5]}}));
+      CS(f(ynew, K[6]));
+      CS(lin(err, nullptr, {{hs * E7[0], K[0]}, {hs * E7[2], K[2]}, {hs * E7[3], K[3]},
+                            {hs * E7[4], K[4]}, {hs * E7[5], K[5]}, {hs * E7[6], K[6]}}));
+      double en;
+      CS(wnorm(err, y, ynew, &en));
+      if (!std::isfinite(en)) return TDVP_E_NUMERIC;
+      if (en < 1.0) {
+        double fac = en == 0.0 ? 10.0 : std::min(10.0, 0.9 * std::pow(en, -0.2));
+        if (rejected) fac = std::min(1.0, fac);
+        t += hs;
+        std::swap(y, ynew);
+        std::swap(K[0], K[6]);        // first stage of the next step (FSAL)
+        h = hs * fac;
+        rejected = false;
+        ++nacc;
+      } else {
+        h = hs * std::max(0.2, 0.9 * std::pow(en, -0.2));
+        rejected = true;
+        ++nrej;
+      }
+    }
+  }
+  for (int i = 0; i < n; ++i)
+    CK(copy_c128((double2 *)mps->site[i], y + pl.site_off[i], pl.site_off[i + 1] - pl.site_off[i],
+                 ctx->stream));
+  if (stats) {
+    stats[0] = nacc;
+    stats[1] = nrej;
+    stats[2] = nfev;
+  }
   return TDVP_OK;
 }
 

@@ -1,6 +1,11 @@
 // QR of a tall complex matrix by shifted Cholesky QR in three passes, for
 // the gauge shifts of the sweep at larger bond dimension (eq:QR), where one
-// work-group's Householder QR runs out of LDS and parallelism.
+// work-group's Householder QR runs out of LDS and parallelism.  The method
+// is the published shifted CholeskyQR3 (Fukaya, Kannan, Nakatsukasa,
+// Yamamoto, Yanagisawa: "Shifted Cholesky QR for computing the QR
+// factorization of ill-conditioned matrices", SIAM J. Sci. Comput. 42
+// (2020)), whose shift rule is used unchanged; the kernels are this
+// library's own.
 //
 // Pass p (W_0 = A):  G = W_p^H W_p  (MFMA);  R_p = chol(G [+ s I])  with
 // G = R_p^H R_p, diag(R_p) > 0;  W_{p+1} = W_p R_p^{-1}  (GEMM).

@@ -174,6 +174,27 @@ hipError_t cholqr(const QrArgs &a, hipStream_t s);
 void cholqr_init();   // called by qr_init
 void qr_init();       // once per process, outside stream capture
 
+// TDVP-MU (mu.hip).  Regularised inverse P = V Lam~^{-1} U^H of the n x n
+// bond matrix D = U Lam V^H (row-major c128, n <= 64), Lam~ = Lam +
+// sqrt(eps) exp(-Lam / sqrt(eps)) (eq:reg2); lam (may be null) receives the
+// singular values in the order the Jacobi sweeps leave them.
+hipError_t mu_reginv(const double2 *D, int n, double eps, double2 *P, double *lam, hipStream_t s);
+// out = -i (X - Y), n elements (Y == null: out = -i X)
+hipError_t mu_finish(const double2 *X, const double2 *Y, double2 *out, int64_t n, hipStream_t s);
+constexpr int LINCOMB_MAX = 7;
+struct LinComb {              // out = x0 + sum_{j < m} a[j] x[j]  (real coefficients; x0 null: 0)
+  double2 *out; const double2 *x0;
+  const double2 *x[LINCOMB_MAX];
+  double a[LINCOMB_MAX];
+  int m;
+};
+hipError_t lincomb(const LinComb &lc, int64_t n, hipStream_t s);
+constexpr int RK_PARTS = 1024;  // most partial sums of rk_err_partials
+// Per-work-group partial sums of |err_e / (atol + rtol max(|y_e|, |ynew_e|))|^2
+// into part[0 .. g-1]; returns g (or -1 on a launch error).
+int rk_err_partials(const double2 *err, const double2 *y, const double2 *ynew, int64_t n, double rtol,
+                    double atol, double *part, hipStream_t s);
+
 }  // namespace tdvp
 
 #include "util.h"

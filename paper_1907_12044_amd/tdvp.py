@@ -78,6 +78,10 @@ EXPORTS = {
     "tdvp_profile": (c_int, [c_void_p, c_int]),
     "tdvp_profile_read": (c_int, [c_void_p, POINTER(c_double), POINTER(c_int64), POINTER(c_double),
                                   POINTER(c_double)]),
+    "tdvp_mu_workspace_bytes": (c_int, [c_void_p, POINTER(_Mps), POINTER(_Mpo), POINTER(c_size_t)]),
+    "tdvp_mu_rhs": (c_int, [c_void_p, POINTER(_Mps), POINTER(_Mpo), c_double, POINTER(c_void_p)]),
+    "tdvp_mu_evolve": (c_int, [c_void_p, POINTER(_Mps), POINTER(_Mpo), c_double, c_double, c_double,
+                               c_double, c_int, POINTER(c_int64)]),
     "tdvp_holstein_mpo": (c_int, [c_int, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32), c_int,
                                   POINTER(c_double), POINTER(c_double), POINTER(c_double),
                                   POINTER(c_double), POINTER(c_int32), POINTER(c_int64),
@@ -421,6 +425,65 @@ class PsRun:
 
     def synchronize(self):
         self.stream.synchronize()
+
+    def mps_numpy(self):
+        self.stream.synchronize()
+        return self.mps.numpy()
+
+
+# ---------------------------------------------------------------- TDVP-MU
+
+def mu_workspace_bytes(ctx, mps, mpo):
+    b = c_size_t(0)
+    _check(lib().tdvp_mu_workspace_bytes(ctx.h, ctypes.byref(mps.desc), ctypes.byref(mpo.desc),
+                                         ctypes.byref(b)), "tdvp_mu_workspace_bytes")
+    return b.value
+
+
+def mu_rhs(ctx, mps, mpo, eps, out_tensors):
+    tab = (c_void_p * len(out_tensors))(*[t.data_ptr() for t in out_tensors])
+    _check(lib().tdvp_mu_rhs(ctx.h, ctypes.byref(mps.desc), ctypes.byref(mpo.desc), float(eps), tab),
+           "tdvp_mu_rhs")
+
+
+def mu_evolve(ctx, mps, mpo, t_final, eps=1e-10, rtol=1e-5, atol=1e-8, max_steps=100000):
+    """Integrate TDVP-MU in place; returns (accepted, rejected, rhs evaluations)."""
+    st = (c_int64 * 3)()
+    _check(lib().tdvp_mu_evolve(ctx.h, ctypes.byref(mps.desc), ctypes.byref(mpo.desc), float(t_final),
+                                float(eps), float(rtol), float(atol), int(max_steps), st),
+           "tdvp_mu_evolve")
+    return tuple(int(v) for v in st)
+
+
+class MuRun:
+    """A chain evolved with TDVP-MU on one GPU from a LEFT-canonical MPS
+    (given as host arrays; the caller canonicalises).  Own stream, FP64."""
+
+    def __init__(self, params, sites, left_canonical_mps, device=0):
+        import torch
+        self.torch = torch
+        self.stream = torch.cuda.Stream(device=device)
+        self.ctx = Context(device, FP64, stream=self.stream)
+        dev = self.ctx.device
+        with torch.cuda.stream(self.stream):
+            Ws, wbond, shift = fmo_model(params, sites)
+            self.mpo = DeviceMpo(Ws, wbond, shift, dev)
+            self.mps = DeviceMps(left_canonical_mps, dev)
+            self.ctx.reserve(mu_workspace_bytes(self.ctx, self.mps, self.mpo))
+        self.stream.synchronize()
+
+    def rhs(self, eps=1e-10):
+        torch = self.torch
+        with torch.cuda.stream(self.stream):
+            out = [torch.empty_like(t) for t in self.mps.t]
+        mu_rhs(self.ctx, self.mps, self.mpo, eps, out)
+        self.stream.synchronize()
+        return [t.cpu().numpy() for t in out]
+
+    def evolve(self, t_final, eps=1e-10, rtol=1e-5, atol=1e-8, max_steps=100000):
+        st = mu_evolve(self.ctx, self.mps, self.mpo, t_final, eps, rtol, atol, max_steps)
+        self.stream.synchronize()
+        return st
 
     def mps_numpy(self):
         self.stream.synchronize()

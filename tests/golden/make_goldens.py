@@ -50,8 +50,10 @@ def _observe(m, Ws, sites, n_e):
     return (om.norm2(m), om.expectation_mpo(m, Ws).real, om.site_populations(m, sites, n_e))
 
 
-def _run_chain(p, sites, raw, tau, nsteps, kmax, record_every=1, log=None):
-    """Oracle TDVP-PS run; observables at step 0 and every record_every steps."""
+def _run_chain(p, sites, raw, tau, nsteps, kmax, record_every=1, log=None, save=None):
+    """Oracle TDVP-PS run; observables at step 0 and every record_every steps.
+    save(partial results) is called after every recorded step, so a long
+    run leaves a usable prefix if it is stopped."""
     Ws, _ = model.mpo(p, sites)
     m = om.right_canonicalize(raw)
     R = om.build_right_envs(m, Ws)
@@ -72,6 +74,9 @@ def _run_chain(p, sites, raw, tau, nsteps, kmax, record_every=1, log=None):
         ks.append(np.mean(stats["k"]))
         if s % record_every == 0 or s == nsteps:
             rec(s)
+            if save:
+                save(dict(steps=np.array(steps), norm=np.array(norms), energy=np.array(energies),
+                          pops=np.array(pops), krylov_mean=np.array(ks)))
         if log:
             log(f"step {s}/{nsteps}  P0 {pops[-1][0]:.12f}  {time.time() - t0:.0f} s")
     return dict(steps=np.array(steps), norm=np.array(norms), energy=np.array(energies),
@@ -89,13 +94,14 @@ def _chain_target(name, wl, nsteps, realisation=None):
         sites = chain_sites(p)
     tau = w["dt_fs"] * model.AU_PER_FS
     shift = model.shifted_terms(p, sites)[4]
-    out = _run_chain(p, sites, raw, tau, nsteps, w.get("kdim", 20),
-                     log=lambda s: print(name, s, flush=True))
     meta = dict(target=name, workload=wl, realisation=realisation, M=Mb, eta=w.get("eta", 0.0),
                 phi_seed=w.get("phi_seed", 1), dt_fs=w["dt_fs"], kmax=w.get("kdim", 20),
                 nsteps=nsteps, shift=shift, energy="shifted <psi|H'|psi>",
                 made_by="tests/golden/make_goldens.py (oracle only)")
-    return out, meta
+    out = _run_chain(p, sites, raw, tau, nsteps, w.get("kdim", 20),
+                     log=lambda s: print(name, s, flush=True),
+                     save=lambda part: _write(name, part, dict(meta, complete=False)))
+    return out, dict(meta, complete=True)
 
 
 # Local problems at the full sizes of the large chains: (Ml, d, Mr, Wl, Wr, z, seed).
@@ -177,9 +183,15 @@ def main():
         out, meta = _lz_target(t)
     else:
         raise SystemExit(f"unknown target {t}")
-    path = os.path.join(HERE, f"{t}.npz")
-    np.savez_compressed(path, meta=np.array(json.dumps(meta)), **out)
-    print("wrote", path, flush=True)
+    print("wrote", _write(t, out, meta), flush=True)
+
+
+def _write(target, out, meta):
+    path = os.path.join(HERE, f"{target}.npz")
+    tmp = path + ".tmp.npz"
+    np.savez_compressed(tmp, meta=np.array(json.dumps(meta)), **out)
+    os.replace(tmp, path)
+    return path
 
 
 if __name__ == "__main__":

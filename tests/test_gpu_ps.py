@@ -95,9 +95,9 @@ def test_fmo77_m32_fp64_matches_oracle(fused):
     assert abs((obs[1] - shift * obs[0]) - E) < 1e-10 * max(abs(E), model.HARTREE_PER_CM)
     # gauge-invariant overlap of the two states
     g = run.mps_numpy()
-    ov = np.ones((1, 1), complex)
+    ov = np.ones((1, 1), complex)             # ov[a, b]: a the GPU bond, b the oracle bond
     for A, B in zip(g, m):
-        ov = np.tensordot(np.tensordot(ov, A, axes=([1], [0])), B.conj(), axes=([0, 1], [0, 1]))
+        ov = np.tensordot(np.tensordot(ov, A, axes=([0], [0])), B.conj(), axes=([0, 1], [0, 1]))
     assert 1.0 - abs(ov[0, 0]) < 1e-10
     # the step conserves norm and energy
     assert abs(obs[0] - e0[0]) < 1e-12 and abs(obs[1] - e0[1]) < 1e-9 * abs(e0[1])
