@@ -147,6 +147,25 @@ tdvp_status tdvp_lanczos_expm(tdvp_ctx *ctx, const void *Lenv, const void *W, co
                               int Ml, int d, int Mr, int Wl, int Wr, double z_re, double z_im,
                               int kmax, double tol, const void *x, void *y, int32_t *k_used_dev);
 
+/* Variant of tdvp_lanczos_expm for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): same arguments and results, but the solve's scratch
+ * memory is a fixed 64 MiB device array inside the library (one per GPU,
+ * held until the process ends) instead of the context's workspace, so no
+ * workspace needs to be set and nothing is allocated or freed.  Launches
+ * only kernels on the context's stream (no memset, no event, no timing or
+ * tuning).  TDVP_E_WORKSPACE if the problem's scratch (the size
+ * tdvp_workspace_bytes gives for one site of these sizes) exceeds 64 MiB:
+ * at kmax = 20 and W = 9, beyond n = Ml d Mr of about 66,000 in TDVP_FP64
+ * and 84,000 in the mixed modes (every site of the bond-dimension-64
+ * chains fits; 128 x 8 x 128 does not).
+ * Every call on one GPU shares that GPU's array: calls that overlap on the
+ * same GPU (other streams, other contexts, other host threads) race, and
+ * the non-finite flag of a call is not reported by tdvp_observe. */
+tdvp_status tdvp_lanczos_expm_noalloc(tdvp_ctx *ctx, const void *Lenv, const void *W, const void *Renv,
+                                      int Ml, int d, int Mr, int Wl, int Wr, double z_re, double z_im,
+                                      int kmax, double tol, const void *x, void *y, int32_t *k_used_dev);
+
 /* Thin QR of a tall c128 matrix (eq:QR): A (m x n, m >= n, row-major) = Q R,
  * Q (m x n) with orthonormal columns, R (n x n) upper triangular with real
  * non-negative diagonal, n <= 256, all in FP64: Householder while the matrix

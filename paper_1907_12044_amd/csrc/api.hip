@@ -14,6 +14,7 @@
 #include <cstring>
 #include <map>
 #include <initializer_list>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -29,6 +30,35 @@ struct ProfRec {
   double flops, bytes;
   int reps;                       // launches between the two events (same work each)
 };
+}  // namespace
+
+// Scratch memory of tdvp_lanczos_expm_noalloc: a fixed device array (one
+// copy per GPU, held until the process ends), used in place of the
+// context's workspace by callers that cannot allocate.  Host code never
+// names it directly; its device address comes from hipGetSymbolAddress.
+constexpr size_t TDVP_SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[TDVP_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void *scratch_ptr[MAX_DEVICES];   // device address of `scratch` on each device (null: not looked up)
+
+// Look up the device address of `scratch` on `device` (current) once.
+bool scratch_init(int device) {
+  if (device < 0 || device >= MAX_DEVICES) return false;
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if (scratch_ptr[device]) return true;
+  void *p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return false;
+  scratch_ptr[device] = p;
+  return true;
+}
+void *scratch_of(int device) {
+  if (device < 0 || device >= MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  return scratch_ptr[device];
+}
 }  // namespace
 
 struct tdvp_ctx {
@@ -638,6 +668,9 @@ tdvp_status tdvp_create(tdvp_ctx **ctx, int device, void *hip_stream, tdvp_preci
   if (hipSetDevice(device) != hipSuccess) { delete c; return TDVP_E_DEVICE; }
   static const bool inited = (qr_init(), true);   // once per process (thread-safe static)
   (void)inited;
+  // device address of the no-allocation scratch array on this device (once
+  // per device); a failure only disables tdvp_lanczos_expm_noalloc
+  (void)scratch_init(device);
   *ctx = c;
   return TDVP_OK;
 }
@@ -762,6 +795,42 @@ tdvp_status tdvp_lanczos_expm(tdvp_ctx *ctx, const void *Lenv, const void *W, co
   CS(need(ctx, lay));
   CK(hipSetDevice(ctx->device));
   return run_lanczos(ctx, lay, op, z_re, z_im, kmax, tol, x, 0, y, 0, k_used_dev, Bi());
+}
+
+tdvp_status tdvp_lanczos_expm_noalloc(tdvp_ctx *ctx, const void *Lenv, const void *W, const void *Renv,
+                                      int Ml, int d, int Mr, int Wl, int Wr, double z_re, double z_im,
+                                      int kmax, double tol, const void *x, void *y, int32_t *k_used_dev) {
+  if (!ctx || !Lenv || !Renv || !x || !y) return TDVP_E_ARG;
+  if (kmax < 1 || kmax > KMAX || !(tol >= 0.0)) return TDVP_E_ARG;
+  if (Ml < 1 || d < 1 || Mr < 1 || Wl < 1 || Wr < 1) return TDVP_E_SHAPE;
+  if (!W && (d != 1 || Wl != Wr)) return TDVP_E_SHAPE;
+  if ((int64_t)std::max(Wl, Wr) * d > 1024) return TDVP_E_UNSUPPORTED;
+  const Op op{Lenv, W, Renv, Ml, d, Mr, Wl, Wr};
+  const Layout lay = layout(op.size(), std::max(Wl, Wr), kmax, env_bytes(ctx));
+  if (lay.total > TDVP_SCRATCH_BYTES) return TDVP_E_WORKSPACE;
+  CK(hipSetDevice(ctx->device));
+  char *sp = static_cast<char *>(scratch_of(ctx->device));
+  if (!sp) return TDVP_E_DEVICE;
+  // run the solve on the scratch array in place of the context's workspace;
+  // no timing or tuning (both create events and time launches)
+  char *ws = ctx->ws;
+  const size_t wsb = ctx->ws_bytes;
+  const int prof = ctx->prof_class, tune = ctx->autotune;
+  ctx->ws = sp;
+  ctx->ws_bytes = TDVP_SCRATCH_BYTES;
+  ctx->prof_class = 0;
+  ctx->autotune = 0;
+  // the header's non-finite flag starts at zero for every call (a kernel,
+  // not a memset, so that the call can be captured into a graph)
+  tdvp_status st = TDVP_OK;
+  if (set_dev_int(&header(ctx)->nonfinite, 0, ctx->stream) != hipSuccess) st = TDVP_E_DEVICE;
+  if (st == TDVP_OK)
+    st = run_lanczos(ctx, lay, op, z_re, z_im, kmax, tol, x, 0, y, 0, k_used_dev, Bi());
+  ctx->ws = ws;
+  ctx->ws_bytes = wsb;
+  ctx->prof_class = prof;
+  ctx->autotune = tune;
+  return st;
 }
 
 tdvp_status tdvp_qr(tdvp_ctx *ctx, const void *A, int m, int n, void *Q, void *R) {

@@ -58,6 +58,9 @@ EXPORTS = {
     "tdvp_lanczos_expm": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_int,
                                   c_int, c_double, c_double, c_int, c_double, c_void_p, c_void_p,
                                   c_void_p]),
+    "tdvp_lanczos_expm_noalloc": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_int,
+                                          c_int, c_int, c_double, c_double, c_int, c_double, c_void_p,
+                                          c_void_p, c_void_p]),
     "tdvp_qr": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p]),
     "tdvp_right_canonicalize": (c_int, [c_void_p, POINTER(_Mps)]),
     "tdvp_envs_build": (c_int, [c_void_p, POINTER(_Mps), POINTER(_Mpo), POINTER(_Envs)]),
@@ -291,6 +294,14 @@ def lanczos_expm(ctx, Lenv, W, Renv, Ml, d, Mr, Wl, Wr, z, kmax, tol, x, y, k_us
                                    Ml, d, Mr, Wl, Wr, float(np.real(z)), float(np.imag(z)), kmax,
                                    float(tol), _ptr(x), _ptr(y),
                                    _ptr(k_used) if k_used is not None else None), "tdvp_lanczos_expm")
+
+
+def lanczos_expm_noalloc(ctx, Lenv, W, Renv, Ml, d, Mr, Wl, Wr, z, kmax, tol, x, y, k_used=None):
+    _check(lib().tdvp_lanczos_expm_noalloc(ctx.h, _ptr(Lenv), _ptr(W) if W is not None else None,
+                                           _ptr(Renv), Ml, d, Mr, Wl, Wr, float(np.real(z)),
+                                           float(np.imag(z)), kmax, float(tol), _ptr(x), _ptr(y),
+                                           _ptr(k_used) if k_used is not None else None),
+           "tdvp_lanczos_expm_noalloc")
 
 
 def qr(ctx, A, m, n, Q, R):
