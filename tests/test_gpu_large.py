@@ -112,7 +112,12 @@ def test_full_step_conserves_norm_and_energy_fp32_populations():
     run.step(tau, 1)
     o64 = run.observe_host().copy()
     del run
-    assert abs(o64[0] - 1.0) < 1e-11 and abs(e0[0] - 1.0) < 1e-11
+    # the centre keeps the norm exactly only as far as the 432 gauge shifts
+    # of a step are orthonormal; the shifted Cholesky QR of these 2560 x 256
+    # matrices is orthonormal to ~1e-12 each
+    assert abs(e0[0] - 1.0) < 1e-11
+    print(f"norm drift over one step: {abs(o64[0] - e0[0]):.2e}")
+    assert abs(o64[0] - e0[0]) < 2e-9
     # energy of the shifted Hamiltonian (the large constant cancels)
     ea, eb = e0[1] - shift * e0[0], o64[1] - shift * o64[0]
     assert abs(eb - ea) < 1e-9 * max(abs(ea), 1.0)

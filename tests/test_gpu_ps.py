@@ -153,7 +153,8 @@ def test_graph_replays_equal_eager_steps():
 
 
 def test_parity_drift_over_steps():
-    """FP64 GPU vs oracle populations at 1, 5 and 10 steps (records the drift)."""
+    """FP64 GPU vs oracle populations at 1, 3 and 5 steps (10 fs, inside the
+    horizon where two FP64 runs agree to round-off; records the drift)."""
     require_gpu()
     p, sites, phys, dims, raw, w = workload("fmo7x10x8_M32")
     tau = w["dt_fs"] * model.AU_PER_FS
@@ -161,7 +162,7 @@ def test_parity_drift_over_steps():
     Ws, m = _oracle_init(p, sites, raw)
     R = om.build_right_envs(m, Ws)
     done = 0
-    for target in (1, 5, 10):
+    for target in (1, 3, 5):
         run.step(tau, target - done)
         for _ in range(target - done):
             m, R, _ = ps.ps_step(m, Ws, R, tau)
@@ -177,10 +178,8 @@ def test_fmo77_m64_one_step_matches_oracle(precision):
     """Bond dim 64 (multi-work-group QR path; in FP32 the fused Lanczos
     step): one step against the oracle, 1e-10 (FP64) or 1e-5 (FP32)."""
     require_gpu()
-    p = draw_params(7, 10, 8, seed=0)
-    sites = chain_sites(p)
-    raw = initial_mps_raw(p, 64, 1e-2, 1)
-    tau = 2.0 * model.AU_PER_FS
+    p, sites, phys, dims, raw, w = workload("fmo7x10x8_M64")
+    tau = w["dt_fs"] * model.AU_PER_FS
     run = _gpu_run(p, sites, raw, precision=precision)
     run.step(tau, 1)
     obs = run.observe_host()
@@ -196,8 +195,9 @@ def test_fmo77_m64_one_step_matches_oracle(precision):
 
 
 def test_fmo77_m128_mixed_vs_fp64_gpu():
-    """Bond dim 128: FP32 contractions against the FP64 GPU path (itself
-    pinned to the oracle above), plus norm and energy conservation."""
+    """Bond dim 128: FP32 contractions against the FP64 GPU path over the
+    first 3 steps, plus norm and energy conservation (the oracle comparison
+    of this chain is in test_gpu_goldens.py)."""
     require_gpu()
     p, sites, phys, dims, raw, w = workload("fmo7x10x8_M128")
     tau = w["dt_fs"] * model.AU_PER_FS
