@@ -45,6 +45,11 @@ def parse():
                     help="ensemble (default: the static-disorder ensemble) or a single-chain workload name")
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32", "bf16x3"],
                     help="default: fp32 for the ensemble, fp64 for a single chain")
+    ap.add_argument("--grouped", action="store_true",
+                    help="ensemble: time the grouped launches (one launch sequence per Krylov solve for "
+                         "every class) instead of one batched ensemble per class on its own stream")
+    ap.add_argument("--alt-steps", type=int, default=2,
+                    help="ensemble: steps of the other launch mode, timed after the main run")
     ap.add_argument("--twin-steps", type=int, default=5,
                     help="steps of the FP64 twin of a mixed-precision ensemble (outside the timed region)")
     ap.add_argument("--kmax", type=int, default=20)
@@ -236,6 +241,29 @@ def ensemble_cpu_baseline(members, sites, tau, class_flop):
             **info}
 
 
+def step_flops(params, sites, M, k):
+    """Algorithmic FLOP of the contractions of one PS step (structural MPO
+    nonzeros; every Krylov solve of dimension k): per site 2 (k F_heff +
+    F_env), per bond 2 k F_bond (F_heff = F_env = 8 [W_l M_l^2 d M_r +
+    nnz(W) M_l M_r + W_r M_l d M_r^2], F_bond = 16 W M^3)."""
+    import numpy as np
+    from inputs import bond_dims
+    from paper_1907_12044_amd import tdvp
+    Ws, wb, _ = tdvp.fmo_model(params, sites)
+    phys = [s_[3] for s_ in sites]
+    mb = bond_dims(phys, M)
+    n = len(sites)
+    f = 0.0
+    for i in range(n):
+        Ml, d, Mr = mb[i], phys[i], mb[i + 1]
+        nnz = int(np.count_nonzero(Ws[i]))
+        fh = 8.0 * (wb[i] * Ml * Ml * d * Mr + nnz * Ml * Mr + wb[i + 1] * Ml * d * Mr * Mr)
+        f += 2.0 * (k * fh + fh)
+        if i < n - 1:
+            f += 2.0 * k * 16.0 * wb[i + 1] * Mr ** 3
+    return f
+
+
 def ensemble_main(args):
     """The static-disorder ensemble: realisations of the 77-site chain with
     bond dimensions from {32, 64, 96, 128}, all advanced together (one
@@ -255,10 +283,10 @@ def ensemble_main(args):
     sites = chain_sites(members[0][1])
     tau = ENSEMBLE["dt_fs"] * tdvp.AU_PER_FS
 
-    def build(pr):
+    def build(pr, grouped=args.grouped):
         return tdvp.DisorderEnsemble(members, sites, 0, pr, kmax=args.kmax, tol=args.tol,
                                      graph=not args.eager, fused=not args.no_fused,
-                                     autotune=autotune_on(args))
+                                     autotune=autotune_on(args), grouped=grouped)
 
     ens = build(prec)
     torch.cuda.synchronize()
@@ -279,28 +307,46 @@ def ensemble_main(args):
     ms = 1e3 * elapsed / max(args.steps, 1)
 
     prof = {}
-    class_flop = {}
     if not args.no_class_timing:
-        for _, _, e in ens.classes:
-            tdvp.profile_reps(e.ctx, TIMING_REPS)
+        for c_, _ in ens.contexts():
+            tdvp.profile_reps(c_, TIMING_REPS)
         for name, cls in tdvp.PROF_CLASSES.items():
             acc = {"ms_per_step": 0.0, "launches": 0, "flop": 0.0, "bytes": 0.0}
-            for M, rs, e in ens.classes:
-                tdvp.profile(e.ctx, cls)
-                e.step(tau, 1)
-                ms_, n_, f_, b_ = tdvp.profile_read(e.ctx)
-                tdvp.profile(e.ctx, 0)
+            for c_, _ in ens.contexts():
+                tdvp.profile(c_, cls)
+            ens.step(tau, 1)
+            for c_, _ in ens.contexts():
+                ms_, n_, f_, b_ = tdvp.profile_read(c_)
+                tdvp.profile(c_, 0)
                 acc["ms_per_step"] += ms_
                 acc["launches"] += n_
                 acc["flop"] += f_
                 acc["bytes"] += b_
-                if name in HEFF_CLASSES:
-                    class_flop[M] = class_flop.get(M, 0.0) + f_ / len(rs)
             prof[name] = acc
             log(f"class timing {name} done")
+    # algorithmic contraction FLOP of one step per bond-dimension class
+    # (Krylov dimension kmax in every solve), for the CPU-baseline scaling
+    class_flop = {M: step_flops(members[[m[2] for m in members].index(M)][1], sites, M, args.kmax)
+                  for M in sorted({m[2] for m in members})}
     roof, heff_tflops = roofline(prof, prec, ms, f"ensemble{nreal}", args.precision)
     del ens
     torch.cuda.empty_cache()
+
+    # the other launch mode, same precision, a few steps after one warm-up
+    alt = {}
+    if args.alt_steps > 0:
+        ea = build(prec, grouped=not args.grouped)
+        ea.step(tau, 1)
+        ea.synchronize()
+        ta = time.perf_counter()
+        ea.step(tau, args.alt_steps)
+        ea.observe_host()
+        ta = time.perf_counter() - ta
+        alt = {"launch_mode": "grouped" if not args.grouped else "per-class streams", "steps": args.alt_steps,
+               "realisation_steps_per_s": nreal * args.alt_steps / ta, "ms_per_step": 1e3 * ta / args.alt_steps}
+        log(f"other launch mode: {alt['realisation_steps_per_s']:.2f} realisation-steps/s")
+        del ea
+        torch.cuda.empty_cache()
 
     # FP64 twin: same members from t = 0, outside the timed region
     twin = {}
@@ -341,16 +387,19 @@ def ensemble_main(args):
         "config": {"workload": f"fmo7x10x8_disorder_ensemble{nreal}", "sites": len(sites),
                    "classes": {str(M): counts[M] for M in sorted(counts)}, "dt_fs": ENSEMBLE["dt_fs"],
                    "precision": args.precision, "kmax": args.kmax, "autotune": autotune_on(args),
-                   "graph": not args.eager, "initial_state_eta": ENSEMBLE["eta"]},
+                   "graph": not args.eager,
+                   "launch_mode": "grouped" if args.grouped else "per-class streams",
+                   "initial_state_eta": ENSEMBLE["eta"]},
         "ensemble_steps_per_s": 1e3 / ms,
         "heff_tflops": heff_tflops,
         "class_ms_per_step": {k: round(v["ms_per_step"], 3) for k, v in prof.items()},
         "roofline": roof,
         "fp64_twin": twin,
+        "other_launch_mode": alt,
         "population_sum_range": [float(pops.sum(1).min()), float(pops.sum(1).max())],
     }
     if not args.no_cpu_baseline:
-        if len(class_flop) == 4:
+        if set(class_flop) >= {32, 64, 96, 128}:
             log("oracle timing (cpu_baseline)")
             line["cpu_baseline"] = ensemble_cpu_baseline(members, sites, tau, class_flop)
     print(json.dumps(line), flush=True)

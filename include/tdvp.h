@@ -336,6 +336,41 @@ tdvp_status tdvp_mu_rhs(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo,
 tdvp_status tdvp_mu_evolve(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo, double t_final,
                            double eps, double rtol, double atol, int max_steps, int64_t *stats);
 
+/* Grouped form for an ensemble of UNEVEN bond dimensions (e.g. static-
+ * disorder realisations whose bond dimensions are drawn from several
+ * values): the nb = sum counts[q] chains are given group by group
+ * (mps[0 .. counts[0]-1] form group 0, the next counts[1] group 1, ...;
+ * 1 <= ngroups <= 4).  Inside a group the chains obey the rules of
+ * tdvp_ps_step_batched (identical shapes, constant strides); across groups
+ * the site count, physical dims and MPO channel dims must agree and the
+ * MPS bond dims may differ (TDVP_E_SHAPE otherwise).  Every Krylov solve
+ * of a sweep position is one launch sequence for all groups: per Krylov
+ * step one fused-step launch covering the groups on the fused small-bond
+ * path, one launch per contraction stage and one projection launch
+ * covering the groups on the general path, and one orthogonalisation
+ * launch covering every group (each launch reads a per-group argument
+ * table); gauge shifts, environment updates and centre moves run per
+ * group.  Groups whose bond dimensions all stay on the fused path and the
+ * other groups form two lanes that run concurrently: the first on the
+ * context stream, the second on an auxiliary stream of the context
+ * (created on first use, default priority) forked from and joined to it
+ * inside each call (parallel branches of the captured graph).  The GEMM tile of a grouped launch is the built-in choice of its
+ * largest group (the autotuner is not consulted), so a group's results
+ * agree with its own batched run to rounding order.  The workspace must
+ * hold tdvp_workspace_bytes_grouped (groups laid out one after another);
+ * the Krylov log is not written.  Graph mode as for tdvp_ps_step. */
+tdvp_status tdvp_workspace_bytes_grouped(const tdvp_ctx *ctx, int ngroups, const int32_t *counts,
+                                         const tdvp_mps *mps, const tdvp_mpo *mpo, int kmax,
+                                         size_t *bytes);
+tdvp_status tdvp_ps_step_grouped(tdvp_ctx *ctx, int ngroups, const int32_t *counts, const tdvp_mps *mps,
+                                 const tdvp_mpo *mpo, const tdvp_envs *envs, double dt, int nsteps,
+                                 int kmax, double tol);
+/* Observables of every chain of a grouped ensemble, out_dev[r * (2 + n_el)]
+ * in chain order r = 0 .. nb-1 (waits for the stream, as tdvp_observe). */
+tdvp_status tdvp_observe_grouped(tdvp_ctx *ctx, int ngroups, const int32_t *counts, const tdvp_mps *mps,
+                                 const tdvp_mpo *mpo, const tdvp_envs *envs, const int32_t *el_sites,
+                                 int n_el, double *out_dev);
+
 /* Frenkel-Holstein MPO (Sec. II.C, eq:holstein) written into HOST buffers.
  * Chain sites are given by kind[i] (0 = electronic two-level site, 1 = mode),
  * owner[i] (electronic index 0..n_e-1 the site belongs to) and phys[i].

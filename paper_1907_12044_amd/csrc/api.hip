@@ -86,6 +86,10 @@ struct tdvp_ctx {
   int tune_now;                   // predicated launches may be timed (a step that cannot be stopped)
   std::map<std::vector<int64_t>, int> tuned;
   hipEvent_t tune_ev[2];
+  // second lane of the grouped ensemble step (default priority, created on
+  // first use) and the events that fork it from and join it to `stream`
+  hipStream_t aux;
+  hipEvent_t fork_ev, join_ev;
 };
 
 namespace {
@@ -284,17 +288,27 @@ struct Op {
   int parts() const { return Wl; }
 };
 
-// y_parts[p] (p < Wl) with sum_p y_parts[p] = Op x.  x is c128 with instance stride sx.
-tdvp_status apply_op(tdvp_ctx *c, const Layout &lay, const Op &op, const double2 *x, int64_t sx,
-                     const int *skip, const Bi &b) {
-  const DType et = env_type(c), ct = et;
+// The launches of Op x (stage-1 GEMM, MPO pass, stage-3 GEMM; the bond
+// operator has no MPO pass) for the instances b with workspace base `base`:
+// y_parts[p] (p < Wl) in the Y buffer with sum_p y_parts[p] = Op x.  x is
+// c128 with instance stride sx.
+struct OpLaunch {
+  GemmArgs g1, g3;
+  WApplyArgs w;
+  bool has_w;
+};
+
+OpLaunch op_args(const tdvp_ctx *c, char *base, const Layout &lay, const Op &op, const double2 *x,
+                 int64_t sx, const int *skip, const Bi &b) {
   const int es = env_bytes(c);
   const int64_t n = op.size();
-  void *T1 = c->ws + lay.T1, *T2 = c->ws + lay.T2, *Y = c->ws + lay.Y;
+  void *T1 = base + lay.T1, *T2 = base + lay.T2, *Y = base + lay.Y;
   const int64_t wse = b.wsel(es), wsk = skip ? b.wsint() : 0;
+  OpLaunch L{};
+  L.has_w = op.W != nullptr;
   if (op.W) {
     // stage 1: T1[wr][l s][r'] = sum_r x[l s][r] R[r'][wr][r]
-    GemmArgs g{};
+    GemmArgs &g = L.g1;
     g.A = x; g.B = op.R; g.C = T1;
     g.M = op.Ml * op.d; g.N = op.Mr; g.K = op.Mr; g.batch = op.Wr;
     g.sam = op.Mr; g.sak = 1; g.sbk = 1; g.sbn = (int64_t)op.Wr * op.Mr;
@@ -302,9 +316,8 @@ tdvp_status apply_op(tdvp_ctx *c, const Layout &lay, const Op &op, const double2
     g.bsa = 0; g.bsb = op.Mr; g.bsc = n;
     g.skip = skip;
     g.inst = inst_of(b, sx, op.sR, wse, wsk);
-    CK(gemm_t(c, F64, et, ct, g, TDVP_PROF_GEMM_HEFF));
     // stage 2: T2[wl][l][s'][r'] = sum_{s, wr} W[wl][s'][s][wr] T1[wr][l][s][r']
-    WApplyArgs w{};
+    WApplyArgs &w = L.w;
     w.in = T1; w.out = T2; w.W = op.W;
     w.Wl = op.Wl; w.Wr = op.Wr; w.d = op.d; w.A = op.Ml; w.C = op.Mr;
     w.w_in_right = 1;
@@ -312,9 +325,8 @@ tdvp_status apply_op(tdvp_ctx *c, const Layout &lay, const Op &op, const double2
     w.so_w = n; w.so_s = op.Mr; w.so_a = (int64_t)op.d * op.Mr; w.so_c = 1;
     w.skip = skip;
     w.inst = inst_of(b, wse, op.sW, wse, wsk);
-    CK(wapply_t(c, ct, w));
     // stage 3 (batched over wl): Y[wl][l'][s' r'] = sum_l L[l'][wl][l] T2[wl][l][s' r']
-    GemmArgs h{};
+    GemmArgs &h = L.g3;
     h.A = op.L; h.B = T2; h.C = Y;
     h.M = op.Ml; h.N = op.d * op.Mr; h.K = op.Ml; h.batch = op.Wl;
     h.sam = (int64_t)op.Wl * op.Ml; h.sak = 1; h.sbk = (int64_t)op.d * op.Mr; h.sbn = 1;
@@ -322,10 +334,9 @@ tdvp_status apply_op(tdvp_ctx *c, const Layout &lay, const Op &op, const double2
     h.bsa = op.Ml; h.bsb = n; h.bsc = n;
     h.skip = skip;
     h.inst = inst_of(b, op.sL, wse, wse, wsk);
-    CK(gemm_t(c, et, ct, ct, h, TDVP_PROF_GEMM_HEFF));
   } else {
     // bond operator: T1[w][l][r'] = sum_r D[l][r] R[r'][w][r]; Y[w][l'][r'] = sum_l L[l'][w][l] T1[w][l][r']
-    GemmArgs g{};
+    GemmArgs &g = L.g1;
     g.A = x; g.B = op.R; g.C = T1;
     g.M = op.Ml; g.N = op.Mr; g.K = op.Mr; g.batch = op.Wr;
     g.sam = op.Mr; g.sak = 1; g.sbk = 1; g.sbn = (int64_t)op.Wr * op.Mr;
@@ -333,8 +344,7 @@ tdvp_status apply_op(tdvp_ctx *c, const Layout &lay, const Op &op, const double2
     g.bsa = 0; g.bsb = op.Mr; g.bsc = n;
     g.skip = skip;
     g.inst = inst_of(b, sx, op.sR, wse, wsk);
-    CK(gemm_t(c, F64, et, ct, g, TDVP_PROF_GEMM_HEFF));
-    GemmArgs h{};
+    GemmArgs &h = L.g3;
     h.A = op.L; h.B = T1; h.C = Y;
     h.M = op.Ml; h.N = op.Mr; h.K = op.Ml; h.batch = op.Wl;
     h.sam = (int64_t)op.Wl * op.Ml; h.sak = 1; h.sbk = op.Mr; h.sbn = 1;
@@ -342,8 +352,18 @@ tdvp_status apply_op(tdvp_ctx *c, const Layout &lay, const Op &op, const double2
     h.bsa = op.Ml; h.bsb = n; h.bsc = n;
     h.skip = skip;
     h.inst = inst_of(b, op.sL, wse, wse, wsk);
-    CK(gemm_t(c, et, ct, ct, h, TDVP_PROF_GEMM_HEFF));
   }
+  return L;
+}
+
+// y_parts[p] (p < Wl) with sum_p y_parts[p] = Op x.  x is c128 with instance stride sx.
+tdvp_status apply_op(tdvp_ctx *c, const Layout &lay, const Op &op, const double2 *x, int64_t sx,
+                     const int *skip, const Bi &b) {
+  const DType et = env_type(c), ct = et;
+  const OpLaunch L = op_args(c, c->ws, lay, op, x, sx, skip, b);
+  CK(gemm_t(c, F64, et, ct, L.g1, TDVP_PROF_GEMM_HEFF));
+  if (L.has_w) CK(wapply_t(c, ct, L.w));
+  CK(gemm_t(c, et, ct, ct, L.g3, TDVP_PROF_GEMM_HEFF));
   return TDVP_OK;
 }
 
@@ -358,7 +378,9 @@ tdvp_status apply_op(tdvp_ctx *c, const Layout &lay, const Op &op, const double2
 constexpr int FUSED_MAX_MR = 64;
 constexpr int FUSED_MAX_MR_BOND = 64;
 
-bool fused_args(const tdvp_ctx *c, const Layout &lay, const Op &op, const Bi &b, HeffSmallArgs &a) {
+bool fused_args(const tdvp_ctx *c, const Layout &lay, const Op &op, const Bi &b, HeffSmallArgs &a,
+                char *base = nullptr) {
+  if (!base) base = c->ws;
   if (c->fused_off || op.Mr > (op.W ? FUSED_MAX_MR : FUSED_MAX_MR_BOND)) return false;
   if (!op.W && (op.Wl != op.Wr || op.d != 1)) return false;
   a = HeffSmallArgs{};
@@ -384,15 +406,15 @@ bool fused_args(const tdvp_ctx *c, const Layout &lay, const Op &op, const Bi &b,
     a.staged = 0;
     if (!heff_small_fits(a, env_bytes(c) / 2)) return false;
   }
-  a.Yp = reinterpret_cast<double2 *>(c->ws + lay.T1);
+  a.Yp = reinterpret_cast<double2 *>(base + lay.T1);
   if (op.W) {
     const size_t rows = (size_t)op.Wl * op.d, cap = (size_t)op.d * op.Wr;
     const size_t o_col = al256((rows + 1) * 4), o_coef = o_col + al256(rows * cap * 4);
     if (o_coef + rows * cap * 16 > lay.ybytes) return false;
-    char *base = c->ws + lay.Y;
-    a.row = reinterpret_cast<const int *>(base);
-    a.col = reinterpret_cast<const int *>(base + o_col);
-    a.coef = reinterpret_cast<const double2 *>(base + o_coef);
+    char *tb = base + lay.Y;
+    a.row = reinterpret_cast<const int *>(tb);
+    a.col = reinterpret_cast<const int *>(tb + o_col);
+    a.coef = reinterpret_cast<const double2 *>(tb + o_coef);
   }
   return true;
 }
@@ -665,6 +687,8 @@ tdvp_status tdvp_create(tdvp_ctx **ctx, int device, void *hip_stream, tdvp_preci
   c->tune_ev[0] = c->tune_ev[1] = nullptr;
   c->graph = nullptr;
   c->gexec = nullptr;
+  c->aux = nullptr;
+  c->fork_ev = c->join_ev = nullptr;
   if (hipSetDevice(device) != hipSuccess) { delete c; return TDVP_E_DEVICE; }
   static const bool inited = (qr_init(), true);   // once per process (thread-safe static)
   (void)inited;
@@ -682,6 +706,9 @@ tdvp_status tdvp_destroy(tdvp_ctx *ctx) {
     if (e) hipEventDestroy(e);
   if (ctx->gexec) hipGraphExecDestroy(ctx->gexec);
   if (ctx->graph) hipGraphDestroy(ctx->graph);
+  if (ctx->fork_ev) hipEventDestroy(ctx->fork_ev);
+  if (ctx->join_ev) hipEventDestroy(ctx->join_ev);
+  if (ctx->aux) hipStreamDestroy(ctx->aux);
   delete ctx;
   return TDVP_OK;
 }
@@ -1093,6 +1120,399 @@ tdvp_status check_batch(tdvp_ctx *ctx, int nb, const tdvp_mps *mps, const tdvp_m
 
 }  // namespace
 
+namespace {
+
+// Graph key fields common to every step entry point.
+void step_key_head(const tdvp_ctx *ctx, double dt, double tol, int kmax, std::vector<uint64_t> *key) {
+  uint64_t bits;
+  std::memcpy(&bits, &dt, 8); key->push_back(bits);
+  std::memcpy(&bits, &tol, 8); key->push_back(bits);
+  key->push_back((uint64_t)kmax);
+  key->push_back((uint64_t)(int)ctx->prec);
+  key->push_back((uint64_t)ctx->fused_off);
+  key->push_back((uint64_t)ctx->autotune);
+  key->push_back((uint64_t)(uintptr_t)ctx->ws);
+  key->push_back((uint64_t)(uintptr_t)ctx->stream);
+}
+
+// nsteps steps through a captured graph of one step (captured the first
+// time `key` is met; with the autotuner on, one eager step first so that
+// new problem keys are timed outside the capture).  enqueue(k) enqueues k
+// steps eagerly.
+template <typename F>
+tdvp_status run_graphed(tdvp_ctx *ctx, const std::vector<uint64_t> &key, int nsteps, F enqueue) {
+  if (!ctx->gexec || key != ctx->gkey) {
+    if (ctx->autotune && nsteps > 0) {
+      CS(enqueue(1));
+      --nsteps;
+    }
+    if (ctx->gexec) { hipGraphExecDestroy(ctx->gexec); ctx->gexec = nullptr; }
+    if (ctx->graph) { hipGraphDestroy(ctx->graph); ctx->graph = nullptr; }
+    ctx->gkey.clear();
+    CK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeRelaxed));
+    const tdvp_status st = enqueue(1);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(ctx->stream, &g);
+    if (st != TDVP_OK) { if (g) hipGraphDestroy(g); return st; }
+    if (ec != hipSuccess || !g) return TDVP_E_DEVICE;
+    ctx->graph = g;
+    CK(hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0));
+    ctx->gkey = key;
+  }
+  for (int st = 0; st < nsteps; ++st) CK(hipGraphLaunch(ctx->gexec, ctx->stream));
+  return TDVP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Ensembles of uneven bond dimension: groups of instances (one group per
+// bond-dimension class; identical shapes and constant strides inside a
+// group, the same chain layout and MPO channel dims across groups) advanced
+// together.  Every Krylov solve of a sweep position is one grouped sequence
+// for all groups: per Krylov step one fused-step launch for the groups on
+// the fused path, one launch per contraction stage and one projection
+// launch for the groups on the general path, and one orthogonalisation
+// launch for all; the gauge shifts, environment updates and centre moves
+// run per group.
+struct GroupRun {
+  Chain ch;
+  Layout lay;
+  Bi b;
+  Strides s;
+  const tdvp_mps *mps;
+  const tdvp_mpo *mpo;
+  const tdvp_envs *envs;
+  char *base;                      // workspace slice of the group's first instance
+};
+
+struct LzJob {
+  Op op;
+  const void *x;
+  int64_t sx;
+  void *y;
+  int64_t sy;
+  const GroupRun *g;
+};
+
+tdvp_status run_lanczos_grouped(tdvp_ctx *c, const std::vector<LzJob> &jobs, double zr, double zi,
+                                int kmax, double tol) {
+  const int ng = (int)jobs.size();
+  if (ng == 0) return TDVP_OK;
+  if (ng > GMAX) return TDVP_E_UNSUPPORTED;
+  const DType et = env_type(c), ct = et;
+  const bool bf3 = c->prec == TDVP_BF16X3;
+  HeffSmallArgs fa[GMAX];
+  bool fused[GMAX];
+  LzStartArgs sa[GMAX];
+  LzFinishArgs fi[GMAX];
+  LzInst li[GMAX];
+  LzState *st[GMAX];
+  LzPartials *pp[GMAX];
+  double2 *U[GMAX];
+  int64_t nn[GMAX];
+  int kall = 0;
+  WtableArgs wt[GMAX];
+  int nwt = 0;
+  for (int k = 0; k < ng; ++k) {
+    const LzJob &J = jobs[k];
+    const GroupRun &G = *J.g;
+    const int64_t n = J.op.size();
+    nn[k] = n;
+    const int keff = (int)std::min<int64_t>(kmax, n);
+    kall = std::max(kall, keff);
+    fused[k] = fused_args(c, G.lay, J.op, G.b, fa[k], G.base);
+    const int trows = fused[k] ? J.op.Ml * J.op.d : 0;
+    st[k] = reinterpret_cast<LzState *>(G.base + G.lay.st);
+    pp[k] = reinterpret_cast<LzPartials *>(G.base + G.lay.pp);
+    U[k] = reinterpret_cast<double2 *>(G.base + G.lay.U);
+    li[k].count = G.b.R; li[k].wss = G.b.ws; li[k].xs = J.sx; li[k].ys = J.sy;
+    sa[k] = LzStartArgs{st[k], pp[k], (const double2 *)J.x, U[k], n, zr, zi, tol, keff, trows,
+                        &header(c)->nonfinite, li[k]};
+    fi[k] = LzFinishArgs{st[k], U[k], n, n, keff, (double2 *)J.y, nullptr, trows, li[k]};
+    if (fused[k]) {
+      fa[k].st = st[k]; fa[k].pp = pp[k]; fa[k].U = U[k];
+      if (J.op.W)
+        wt[nwt++] = WtableArgs{(const double2 *)J.op.W, J.op.Wl * J.op.d, J.op.d * J.op.Wr, J.op.sW,
+                               const_cast<int *>(fa[k].row), const_cast<int *>(fa[k].col),
+                               const_cast<double2 *>(fa[k].coef), G.b.ws, G.b.R};
+    }
+  }
+  if (nwt) CK(wtable_grouped(wt, nwt, c->stream));
+  CK(lz_start_grouped(sa, ng, c->stream));
+  for (int j = 0; j < kall; ++j) {
+    // fused path: one launch per staging variant
+    for (int stg = 0; stg < 2; ++stg) {
+      HeffSmallArgs ha[GMAX];
+      int cnt[GMAX], nh = 0;
+      for (int k = 0; k < ng; ++k)
+        if (fused[k] && fa[k].staged == stg) {
+          ha[nh] = fa[k];
+          ha[nh].j = j;
+          cnt[nh++] = jobs[k].g->b.R;
+        }
+      if (nh) {
+        const int id = prof_begin(c, TDVP_PROF_LZ_FUSED);
+        CK(timed_repeat(c, id, [&] { return heff_small_grouped(et, ha, cnt, nh, c->stream); }));
+        double fl = 0.0, by = 0.0;
+        for (int q = 0; q < nh; ++q) {
+          const double Ml = ha[q].Ml, d = ha[q].d, Mr = ha[q].Mr, Wl = ha[q].Wl, Wr = ha[q].Wr, n = ha[q].n;
+          fl += cnt[q] * (8.0 * (Ml * d * Mr * Wr * Mr + Wl * Ml * Ml * d * Mr) + 8.0 * (j + 1) * n);
+          by += cnt[q] * ((Ml * Wl * Ml + Mr * Wr * Mr) * env_bytes(c) + (j + 2) * 16.0 * n);
+        }
+        prof_end(c, id, fl, by);
+      }
+    }
+    // general path: contraction stages and projections
+    GemmArgs g1[GMAX], g3[GMAX];
+    WApplyArgs wa[GMAX];
+    LzDotsArgs da[GMAX];
+    int ngen = 0, nw = 0;
+    for (int k = 0; k < ng; ++k) {
+      if (fused[k]) continue;
+      const LzJob &J = jobs[k];
+      const GroupRun &G = *J.g;
+      const OpLaunch L = op_args(c, G.base, G.lay, J.op, U[k] + (int64_t)j * nn[k], G.b.wsel(16),
+                                 &st[k]->stop, G.b);
+      g1[ngen] = L.g1;
+      g3[ngen] = L.g3;
+      if (L.has_w) wa[nw++] = L.w;
+      da[ngen] = LzDotsArgs{st[k], pp[k], G.base + G.lay.Y, J.op.parts(), nn[k], U[k], nn[k], j, nn[k], li[k]};
+      ++ngen;
+    }
+    if (ngen) {
+      // algorithmic work of a grouped GEMM: 8 M N K per batch and instance;
+      // operands read once, result written once
+      auto gw = [&](const GemmArgs *g, DType ta, DType tb, DType tc, double *fl, double *by) {
+        *fl = *by = 0.0;
+        for (int q = 0; q < ngen; ++q) {
+          const double M = g[q].M, N = g[q].N, K = g[q].K, B = g[q].batch, R = g[q].inst.count;
+          *fl += 8.0 * M * N * K * B * R;
+          *by += R * ((g[q].bsa ? B : 1.0) * M * K * esz(ta) + (g[q].bsb ? B : 1.0) * K * N * esz(tb) +
+                      B * M * N * esz(tc));
+        }
+      };
+      double fl, gb;
+      int id = prof_begin(c, TDVP_PROF_GEMM_HEFF);
+      CK(timed_repeat(c, id, [&] { return cgemm_grouped(F64, et, ct, g1, ngen, bf3 && ct == F32, c->stream); }));
+      gw(g1, F64, et, ct, &fl, &gb);
+      prof_end(c, id, fl, gb);
+      if (nw) {
+        id = prof_begin(c, TDVP_PROF_WAPPLY);
+        CK(timed_repeat(c, id, [&] { return wapply_grouped(ct, wa, nw, c->stream); }));
+        double by = 0.0;
+        for (int q = 0; q < nw; ++q)
+          by += (double)wa[q].A * wa[q].C * wa[q].d * esz(ct) * (wa[q].Wl + wa[q].Wr) * wa[q].inst.count;
+        prof_end(c, id, 0.0, by);
+      }
+      id = prof_begin(c, TDVP_PROF_GEMM_HEFF);
+      CK(timed_repeat(c, id, [&] { return cgemm_grouped(et, ct, ct, g3, ngen, bf3 && ct == F32, c->stream); }));
+      gw(g3, et, ct, ct, &fl, &gb);
+      prof_end(c, id, fl, gb);
+      id = prof_begin(c, TDVP_PROF_LZ_DOTS);
+      CK(lz_dots_grouped(ct, da, ngen, c->stream));
+      fl = gb = 0.0;
+      for (int q = 0; q < ngen; ++q) {
+        const double n = (double)da[q].n, R = da[q].in.count;
+        fl += 8.0 * (j + 1) * n * R;
+        gb += R * ((double)da[q].P * n * env_bytes(c) + (j + 2) * 16.0 * n);
+      }
+      prof_end(c, id, fl, gb);
+    }
+    LzUpdateArgs ua[GMAX];
+    for (int k = 0; k < ng; ++k) {
+      if (fused[k])
+        ua[k] = LzUpdateArgs{st[k], pp[k], U[k], nn[k], j, nn[k], jobs[k].op.Mr * fa[k].P, fa[k].Yp, fa[k].P, li[k]};
+      else
+        ua[k] = LzUpdateArgs{st[k], pp[k], U[k], nn[k], j, nn[k], 0, nullptr, 0, li[k]};
+    }
+    const int id = prof_begin(c, TDVP_PROF_LZ_UPDATE);
+    CK(lz_update_grouped(ua, ng, c->stream));
+    double fl = 0.0, by = 0.0;
+    for (int k = 0; k < ng; ++k) {
+      fl += 8.0 * (j + 1) * nn[k] * li[k].count;
+      by += (j + 3) * 16.0 * nn[k] * li[k].count;
+    }
+    prof_end(c, id, fl, by);
+  }
+  const int id = prof_begin(c, TDVP_PROF_LZ_ENDS);
+  CK(lz_finish_grouped(fi, ng, c->stream));
+  double fl = 0.0, by = 0.0;
+  for (int k = 0; k < ng; ++k) {
+    fl += 8.0 * fi[k].keff * nn[k] * li[k].count;
+    by += (fi[k].keff + 1) * 16.0 * nn[k] * li[k].count;
+  }
+  prof_end(c, id, fl, by);
+  return TDVP_OK;
+}
+
+// Run per-group helpers (QR, environment update, centre move) on group g's
+// workspace: the helpers address the workspace through ctx->ws.
+template <typename F> tdvp_status on_group(tdvp_ctx *c, const GroupRun &g, F f) {
+  char *ws = c->ws;
+  c->ws = g.base;
+  const tdvp_status st = f();
+  c->ws = ws;
+  return st;
+}
+
+tdvp_status enqueue_steps_grouped(tdvp_ctx *ctx, std::vector<GroupRun> &gr, double dt, int nsteps,
+                                  int kmax, double tol) {
+  const int ng = (int)gr.size();
+  const int n = gr[0].ch.n;
+  const double h = 0.5 * dt;
+  auto site = [&](const GroupRun &g, int i) { return (double2 *)g.mps->site[i]; };
+  auto Dp = [&](const GroupRun &g) { return reinterpret_cast<double2 *>(g.base + g.lay.D); };
+  auto Tp = [&](const GroupRun &g) { return reinterpret_cast<double2 *>(g.base + g.lay.tmp); };
+  for (int step = 0; step < nsteps; ++step) {
+    std::vector<const double2 *> xin(ng);
+    std::vector<int64_t> sxin(ng);
+    for (int q = 0; q < ng; ++q) { xin[q] = site(gr[q], 0); sxin[q] = gr[q].s.site[0]; }
+    // left-to-right half sweep
+    for (int i = 0; i < n; ++i) {
+      const bool last = (i == n - 1);
+      std::vector<LzJob> jobs;
+      for (int q = 0; q < ng; ++q) {
+        const GroupRun &g = gr[q];
+        Op f{g.envs->left[i], g.mpo->site[i], g.envs->right[i + 1], g.ch.bond[i], g.ch.phys[i],
+             g.ch.bond[i + 1], g.ch.wbond[i], g.ch.wbond[i + 1]};
+        f.sL = g.s.envl[i]; f.sW = g.s.mpo[i]; f.sR = g.s.envr[i + 1];
+        jobs.push_back(LzJob{f, xin[q], sxin[q], site(g, i), g.s.site[i], &g});
+      }
+      CS(run_lanczos_grouped(ctx, jobs, 0.0, -(last ? dt : h), kmax, tol));
+      if (last) break;
+      std::vector<LzJob> bj;
+      for (int q = 0; q < ng; ++q) {
+        const GroupRun &g = gr[q];
+        const int Ml = g.ch.bond[i], d = g.ch.phys[i], Mr = g.ch.bond[i + 1];
+        CS(on_group(ctx, g, [&] {
+          CS(qr_left(ctx, g.lay, site(g, i), Ml, d, Mr, Dp(g), g.b, g.s.site[i]));
+          return env_update(ctx, g.lay, +1, g.envs->left[i], site(g, i), g.mpo->site[i], Ml, d, Mr,
+                            g.ch.wbond[i], g.ch.wbond[i + 1], g.envs->left[i + 1], g.b, g.s.envl[i],
+                            g.s.site[i], g.s.mpo[i], g.s.envl[i + 1]);
+        }));
+        const int Wb = g.ch.wbond[i + 1];
+        Op k{g.envs->left[i + 1], nullptr, g.envs->right[i + 1], Mr, 1, Mr, Wb, Wb};
+        k.sL = g.s.envl[i + 1]; k.sR = g.s.envr[i + 1];
+        bj.push_back(LzJob{k, Dp(g), g.b.wsel(16), Dp(g), g.b.wsel(16), &g});
+      }
+      CS(run_lanczos_grouped(ctx, bj, 0.0, +h, kmax, tol));
+      for (int q = 0; q < ng; ++q) {
+        const GroupRun &g = gr[q];
+        const int Mr = g.ch.bond[i + 1], dn = g.ch.phys[i + 1], Mn = g.ch.bond[i + 2];
+        const int64_t wsx = g.b.wsel(16);
+        CS(on_group(ctx, g, [&] {
+          return matmul(ctx, Dp(g), site(g, i + 1), Tp(g), Mr, Mr, dn * Mn, g.b, wsx, g.s.site[i + 1], wsx);
+        }));
+        xin[q] = Tp(g);
+        sxin[q] = wsx;
+      }
+    }
+    // right-to-left half sweep (the last site was advanced by dt above)
+    for (int i = n - 1; i >= 0; --i) {
+      if (i < n - 1) {
+        std::vector<LzJob> jobs;
+        for (int q = 0; q < ng; ++q) {
+          const GroupRun &g = gr[q];
+          Op f{g.envs->left[i], g.mpo->site[i], g.envs->right[i + 1], g.ch.bond[i], g.ch.phys[i],
+               g.ch.bond[i + 1], g.ch.wbond[i], g.ch.wbond[i + 1]};
+          f.sL = g.s.envl[i]; f.sW = g.s.mpo[i]; f.sR = g.s.envr[i + 1];
+          jobs.push_back(LzJob{f, xin[q], sxin[q], site(g, i), g.s.site[i], &g});
+        }
+        CS(run_lanczos_grouped(ctx, jobs, 0.0, -h, kmax, tol));
+      }
+      if (i == 0) break;
+      std::vector<LzJob> bj;
+      for (int q = 0; q < ng; ++q) {
+        const GroupRun &g = gr[q];
+        const int Ml = g.ch.bond[i], d = g.ch.phys[i], Mr = g.ch.bond[i + 1];
+        CS(on_group(ctx, g, [&] {
+          CS(qr_right(ctx, g.lay, site(g, i), Ml, d, Mr, Dp(g), g.b, g.s.site[i]));
+          return env_update(ctx, g.lay, -1, g.envs->right[i + 1], site(g, i), g.mpo->site[i], Ml, d, Mr,
+                            g.ch.wbond[i], g.ch.wbond[i + 1], g.envs->right[i], g.b, g.s.envr[i + 1],
+                            g.s.site[i], g.s.mpo[i], g.s.envr[i]);
+        }));
+        const int Wb = g.ch.wbond[i];
+        Op k{g.envs->left[i], nullptr, g.envs->right[i], Ml, 1, Ml, Wb, Wb};
+        k.sL = g.s.envl[i]; k.sR = g.s.envr[i];
+        bj.push_back(LzJob{k, Dp(g), g.b.wsel(16), Dp(g), g.b.wsel(16), &g});
+      }
+      CS(run_lanczos_grouped(ctx, bj, 0.0, +h, kmax, tol));
+      for (int q = 0; q < ng; ++q) {
+        const GroupRun &g = gr[q];
+        const int Ml = g.ch.bond[i], Mp = g.ch.bond[i - 1], dp = g.ch.phys[i - 1];
+        const int64_t wsx = g.b.wsel(16);
+        CS(on_group(ctx, g, [&] {
+          return matmul(ctx, site(g, i - 1), Dp(g), Tp(g), Mp * dp, Ml, Ml, g.b, g.s.site[i - 1], wsx, wsx);
+        }));
+        xin[q] = Tp(g);
+        sxin[q] = wsx;
+      }
+    }
+  }
+  return TDVP_OK;
+}
+
+// The groups of a grouped step in two lanes that run concurrently: groups
+// whose bond dimensions all take the fused small-bond Lanczos step (latency
+// bound) on the context stream, the others (contraction GEMMs, MFMA bound)
+// on the auxiliary stream, forked from and joined to the context stream
+// (in graph mode the two lanes become parallel branches of the graph).
+// Without profiling, the Krylov log or a second lane, one lane.
+tdvp_status enqueue_lanes(tdvp_ctx *ctx, std::vector<GroupRun> &gr, double dt, int nsteps, int kmax,
+                          double tol) {
+  std::vector<GroupRun> small, large;
+  for (const GroupRun &g : gr) (g.ch.mmax <= FUSED_MAX_MR ? small : large).push_back(g);
+  if (small.empty() || large.empty() || ctx->prof_class != 0 || ctx->fused_off || !ctx->aux || !ctx->stream)
+    return enqueue_steps_grouped(ctx, gr, dt, nsteps, kmax, tol);
+  hipStream_t main = ctx->stream;
+  CK(hipEventRecord(ctx->fork_ev, main));
+  CK(hipStreamWaitEvent(ctx->aux, ctx->fork_ev, 0));
+  ctx->stream = ctx->aux;
+  const tdvp_status sl = enqueue_steps_grouped(ctx, large, dt, nsteps, kmax, tol);
+  ctx->stream = main;
+  // join the auxiliary lane even on an error, so that a capture ends cleanly
+  const hipError_t e1 = hipEventRecord(ctx->join_ev, ctx->aux);
+  const tdvp_status ss = sl == TDVP_OK ? enqueue_steps_grouped(ctx, small, dt, nsteps, kmax, tol) : sl;
+  const hipError_t e2 = hipStreamWaitEvent(main, ctx->join_ev, 0);
+  if (ss != TDVP_OK) return ss;
+  if (e1 != hipSuccess || e2 != hipSuccess) return TDVP_E_DEVICE;
+  return TDVP_OK;
+}
+
+// Validate the groups of a grouped call and lay out their workspaces.
+tdvp_status plan_groups(tdvp_ctx *ctx, int ng, const int32_t *counts, const tdvp_mps *mps,
+                        const tdvp_mpo *mpo, const tdvp_envs *envs, int kmax,
+                        std::vector<GroupRun> *gr, size_t *bytes) {
+  if (!ctx || ng < 1 || ng > GMAX || !counts || !mps || !mpo) return TDVP_E_ARG;
+  gr->clear();
+  size_t off = 0;
+  int first = 0;
+  for (int q = 0; q < ng; ++q) {
+    if (counts[q] < 1) return TDVP_E_ARG;
+    GroupRun g;
+    if (envs) {
+      CS(check_batch(ctx, counts[q], mps + first, mpo + first, envs + first, &g.ch, &g.s));
+    } else {
+      CS(check_chain(&mps[first], &mpo[first], &g.ch));
+    }
+    if (q > 0 && (g.ch.n != (*gr)[0].ch.n || g.ch.phys != (*gr)[0].ch.phys || g.ch.wbond != (*gr)[0].ch.wbond))
+      return TDVP_E_SHAPE;
+    g.lay = layout(g.ch.nmax, g.ch.wmax, kmax, env_bytes(ctx));
+    g.b.R = counts[q];
+    g.b.ws = (int64_t)g.lay.total;
+    g.mps = mps + first;
+    g.mpo = mpo + first;
+    g.envs = envs ? envs + first : nullptr;
+    g.base = ctx->ws ? ctx->ws + off : nullptr;
+    off += (size_t)counts[q] * g.lay.total;
+    first += counts[q];
+    gr->push_back(g);
+  }
+  *bytes = off;
+  return TDVP_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 tdvp_status tdvp_observe(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo, const tdvp_envs *envs,
@@ -1146,15 +1566,8 @@ tdvp_status tdvp_ps_step_batched(tdvp_ctx *ctx, int nb, const tdvp_mps *mps, con
     return enqueue_steps(ctx, lay, ch, &mps[0], &mpo[0], &envs[0], dt, nsteps, kmax, tol, b, s);
   std::vector<uint64_t> key;
   auto put = [&](const void *p) { key.push_back((uint64_t)(uintptr_t)p); };
-  uint64_t bits;
-  std::memcpy(&bits, &dt, 8); key.push_back(bits);
-  std::memcpy(&bits, &tol, 8); key.push_back(bits);
-  key.push_back((uint64_t)kmax);
-  key.push_back((uint64_t)(int)ctx->prec);
+  step_key_head(ctx, dt, tol, kmax, &key);
   key.push_back((uint64_t)nb);
-  key.push_back((uint64_t)ctx->fused_off);
-  key.push_back((uint64_t)ctx->autotune);
-  put(ctx->ws); put(ctx->stream);
   for (int i = 0; i < ch.n; ++i) {
     put(mps[0].site[i]); put(mpo[0].site[i]);
     key.push_back((uint64_t)s.site[i]); key.push_back((uint64_t)s.mpo[i]);
@@ -1165,28 +1578,90 @@ tdvp_status tdvp_ps_step_batched(tdvp_ctx *ctx, int nb, const tdvp_mps *mps, con
     key.push_back((uint64_t)s.envl[bb]); key.push_back((uint64_t)s.envr[bb]);
     key.push_back((uint64_t)ch.bond[bb] << 32 | (uint32_t)ch.wbond[bb]);
   }
-  if (!ctx->gexec || key != ctx->gkey) {
-    if (ctx->autotune) {
-      // one eager step first, so that the tuner can time the shapes it has
-      // not met yet; the graph captured next uses its choices
-      CS(enqueue_steps(ctx, lay, ch, &mps[0], &mpo[0], &envs[0], dt, 1, kmax, tol, b, s));
-      --nsteps;
-    }
-    if (ctx->gexec) { hipGraphExecDestroy(ctx->gexec); ctx->gexec = nullptr; }
-    if (ctx->graph) { hipGraphDestroy(ctx->graph); ctx->graph = nullptr; }
-    ctx->gkey.clear();
-    CK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeRelaxed));
-    const tdvp_status st = enqueue_steps(ctx, lay, ch, &mps[0], &mpo[0], &envs[0], dt, 1, kmax, tol, b, s);
-    hipGraph_t g = nullptr;
-    const hipError_t ec = hipStreamEndCapture(ctx->stream, &g);
-    if (st != TDVP_OK) { if (g) hipGraphDestroy(g); return st; }
-    if (ec != hipSuccess || !g) return TDVP_E_DEVICE;
-    ctx->graph = g;
-    CK(hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0));
-    ctx->gkey = key;
+  return run_graphed(ctx, key, nsteps, [&](int k) {
+    return enqueue_steps(ctx, lay, ch, &mps[0], &mpo[0], &envs[0], dt, k, kmax, tol, b, s);
+  });
+}
+
+}  // extern "C"
+
+extern "C" {
+
+tdvp_status tdvp_workspace_bytes_grouped(const tdvp_ctx *ctx, int ngroups, const int32_t *counts,
+                                         const tdvp_mps *mps, const tdvp_mpo *mpo, int kmax,
+                                         size_t *bytes) {
+  if (!bytes || kmax < 1 || kmax > KMAX) return TDVP_E_ARG;
+  std::vector<GroupRun> gr;
+  return plan_groups(const_cast<tdvp_ctx *>(ctx), ngroups, counts, mps, mpo, nullptr, kmax, &gr, bytes);
+}
+
+tdvp_status tdvp_ps_step_grouped(tdvp_ctx *ctx, int ngroups, const int32_t *counts, const tdvp_mps *mps,
+                                 const tdvp_mpo *mpo, const tdvp_envs *envs, double dt, int nsteps,
+                                 int kmax, double tol) {
+  if (nsteps < 0 || kmax < 1 || kmax > KMAX || !(tol >= 0.0) || !std::isfinite(dt) || !envs)
+    return TDVP_E_ARG;
+  std::vector<GroupRun> gr;
+  size_t bytes = 0;
+  CS(plan_groups(ctx, ngroups, counts, mps, mpo, envs, kmax, &gr, &bytes));
+  if (!ctx->ws || ctx->ws_bytes < bytes) return TDVP_E_WORKSPACE;
+  CK(hipSetDevice(ctx->device));
+  ctx->klog_pos = 0;
+  if (!ctx->aux) {
+    CK(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
+    CK(hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming));
+    CK(hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming));
   }
-  for (int st = 0; st < nsteps; ++st) CK(hipGraphLaunch(ctx->gexec, ctx->stream));
-  return TDVP_OK;
+  if (!ctx->graph_mode || ctx->prof_class != 0 || !ctx->stream || nsteps == 0)
+    return enqueue_lanes(ctx, gr, dt, nsteps, kmax, tol);
+  std::vector<uint64_t> key;
+  auto put = [&](const void *p) { key.push_back((uint64_t)(uintptr_t)p); };
+  step_key_head(ctx, dt, tol, kmax, &key);
+  key.push_back(0x67726f7570ull);   // grouped
+  for (const GroupRun &g : gr) {
+    key.push_back((uint64_t)g.b.R);
+    for (int i = 0; i < g.ch.n; ++i) {
+      put(g.mps->site[i]); put(g.mpo->site[i]);
+      key.push_back((uint64_t)g.s.site[i]); key.push_back((uint64_t)g.s.mpo[i]);
+      key.push_back((uint64_t)g.ch.phys[i]);
+    }
+    for (int bb = 0; bb <= g.ch.n; ++bb) {
+      put(g.envs->left[bb]); put(g.envs->right[bb]);
+      key.push_back((uint64_t)g.s.envl[bb]); key.push_back((uint64_t)g.s.envr[bb]);
+      key.push_back((uint64_t)g.ch.bond[bb] << 32 | (uint32_t)g.ch.wbond[bb]);
+    }
+  }
+  return run_graphed(ctx, key, nsteps, [&](int k) { return enqueue_lanes(ctx, gr, dt, k, kmax, tol); });
+}
+
+tdvp_status tdvp_observe_grouped(tdvp_ctx *ctx, int ngroups, const int32_t *counts, const tdvp_mps *mps,
+                                 const tdvp_mpo *mpo, const tdvp_envs *envs, const int32_t *el_sites,
+                                 int n_el, double *out_dev) {
+  if (!out_dev || n_el < 0 || (n_el > 0 && !el_sites) || !envs) return TDVP_E_ARG;
+  std::vector<GroupRun> gr;
+  size_t bytes = 0;
+  CS(plan_groups(ctx, ngroups, counts, mps, mpo, envs, 1, &gr, &bytes));
+  if (!ctx->ws || ctx->ws_bytes < bytes) return TDVP_E_WORKSPACE;
+  for (int m = 0; m < n_el; ++m)
+    if (el_sites[m] < 0 || el_sites[m] >= gr[0].ch.n || gr[0].ch.phys[el_sites[m]] != 2) return TDVP_E_SHAPE;
+  CK(hipSetDevice(ctx->device));
+  const int so = 2 + n_el;
+  int first = 0, total = 0;
+  for (const GroupRun &g : gr) {
+    std::vector<double> shifts(g.b.R);
+    for (int r = 0; r < g.b.R; ++r) shifts[r] = g.mpo[r].energy_shift;
+    CS(on_group(ctx, g, [&] {
+      return observe_impl(ctx, g.lay, g.ch, g.mps, g.mpo, g.envs, el_sites, n_el, out_dev + (int64_t)first * so,
+                          so, shifts.data(), g.b, g.s);
+    }));
+    first += g.b.R;
+    total += g.b.R;
+  }
+  CtxHeader *hdr = header(ctx);
+  CK(numeric_check(&hdr->nonfinite, 0, out_dev, so, so, total, &hdr->numeric_out, ctx->stream));
+  int bad = 0;
+  CK(hipMemcpyAsync(&bad, &hdr->numeric_out, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  CK(hipStreamSynchronize(ctx->stream));
+  return bad ? TDVP_E_NUMERIC : TDVP_OK;
 }
 
 }  // extern "C"

@@ -25,6 +25,62 @@ struct Inst {
   int64_t a = 0, b = 0, c = 0, skip = 0;
 };
 
+// Grouped launches: one launch covers up to GMAX groups of instances whose
+// shapes differ between groups (the bond-dimension classes of a disorder
+// ensemble).  The grid is one-dimensional: group k owns the flat blocks
+// [start[k], start[k + 1]), which it reads as its own (gx, gy, gz) grid in
+// the order x fastest, then y, then z, as a launch of that group alone
+// would; every group has its own argument set.
+constexpr int GMAX = 4;
+struct BlockXYZ {
+  int x, y, z, gx, gy, gz;
+};
+template <typename A> struct Grp {
+  A a[GMAX];
+  int ng = 0;
+  int gx[GMAX] = {}, gy[GMAX] = {}, gz[GMAX] = {};
+  int start[GMAX + 1] = {};
+#ifdef __HIPCC__
+  __device__ __forceinline__ BlockXYZ locate(int flat, int &k) const {
+    k = 0;
+    while (k + 1 < ng && flat >= start[k + 1]) ++k;
+    const int local = flat - start[k];
+    BlockXYZ b;
+    b.gx = gx[k];
+    b.gy = gy[k];
+    b.gz = gz[k];
+    b.x = local % b.gx;
+    b.y = (local / b.gx) % b.gy;
+    b.z = local / (b.gx * b.gy);
+    return b;
+  }
+#endif
+  // append a group with grid (x, y, z); false if full
+  bool add(const A &args, int x, int y, int z) {
+    if (ng >= GMAX || x <= 0 || y <= 0 || z <= 0) return ng < GMAX;
+    a[ng] = args;
+    gx[ng] = x;
+    gy[ng] = y;
+    gz[ng] = z;
+    start[ng + 1] = start[ng] + x * y * z;
+    ++ng;
+    return true;
+  }
+  int blocks() const { return start[ng]; }
+};
+#ifdef __HIPCC__
+__device__ __forceinline__ BlockXYZ native_block() {
+  BlockXYZ b;
+  b.x = blockIdx.x;
+  b.y = blockIdx.y;
+  b.z = blockIdx.z;
+  b.gx = gridDim.x;
+  b.gy = gridDim.y;
+  b.gz = gridDim.z;
+  return b;
+}
+#endif
+
 // Complex GEMM  C[b][m,n] = sum_k opA(A)[b][m,k] * opB(B)[b][k,n]
 // with arbitrary element strides (in complex elements) and optional
 // conjugation.  Batches b = 0..batch-1.  Optional `skip`: if non-null and
@@ -43,6 +99,10 @@ struct GemmArgs {
 };
 
 hipError_t cgemm(DType ta, DType tb, DType tc, const GemmArgs &g, hipStream_t s);
+// One launch for up to GMAX argument sets of the same types (FP32 output
+// with split-BF16 arithmetic when bf3 != 0); tile: one tile choice for the
+// launch (0: by the largest group).
+hipError_t cgemm_grouped(DType ta, DType tb, DType tc, const GemmArgs *g, int ng, int bf3, hipStream_t s);
 // Same product with split-BF16 matrix-core arithmetic and FP32 accumulation
 // (about 17 significant bits per operand); FP32 output only.
 hipError_t cgemm_bf3(DType ta, DType tb, DType tc, const GemmArgs &g, hipStream_t s);
@@ -62,6 +122,7 @@ struct WApplyArgs {
   Inst inst;                        // a = in, b = W, c = out strides
 };
 hipError_t wapply(DType t, const WApplyArgs &a, hipStream_t s);
+hipError_t wapply_grouped(DType t, const WApplyArgs *a, int ng, hipStream_t s);
 
 // Lanczos state kept in device memory for the solve in flight.  Scalars
 // are written by work-group 0 of the kernel that reduces them; every
@@ -118,6 +179,29 @@ hipError_t lz_dots(LzState *st, LzPartials *pp, DType ty, const void *ypart, int
 hipError_t lz_update(LzState *st, LzPartials *pp, double2 *U, int64_t ldu, int j, int64_t n, int Gd,
                      const double2 *Yp, int P, const LzInst &in, hipStream_t s);
 int lz_grid(int64_t n);   // work-groups of the Lanczos vector kernels for an n-vector
+
+// Argument sets of the Lanczos kernels for grouped launches (one per group;
+// every group of a launch is at the same Krylov index j).
+struct LzStartArgs {
+  LzState *st; LzPartials *pp; const double2 *x; double2 *u0; int64_t n;
+  double zr, zi, tol; int keff, trows; int *nonfinite; LzInst in;
+};
+struct LzDotsArgs {
+  LzState *st; LzPartials *pp; const void *ypart; int P; int64_t pstride;
+  double2 *U; int64_t ldu; int j; int64_t n; LzInst in;
+};
+struct LzUpdateArgs {
+  LzState *st; LzPartials *pp; double2 *U; int64_t ldu; int j; int64_t n; int Gd;
+  const double2 *Yp; int P; LzInst in;
+};
+struct LzFinishArgs {
+  LzState *st; const double2 *U; int64_t ldu; int64_t n; int keff; double2 *y; int32_t *k_used;
+  int trows; LzInst in;
+};
+hipError_t lz_start_grouped(const LzStartArgs *a, int ng, hipStream_t s);
+hipError_t lz_dots_grouped(DType ty, const LzDotsArgs *a, int ng, hipStream_t s);
+hipError_t lz_update_grouped(const LzUpdateArgs *a, int ng, hipStream_t s);
+hipError_t lz_finish_grouped(const LzFinishArgs *a, int ng, hipStream_t s);
 hipError_t lz_finish(LzState *st, const double2 *U, int64_t ldu, int64_t n, int keff, double2 *y,
                      int32_t *k_used, int trows, const LzInst &in, hipStream_t s);
 
@@ -145,6 +229,9 @@ struct HeffSmallArgs {
 size_t heff_small_lds(const HeffSmallArgs &a, int tm_bytes);
 bool heff_small_fits(const HeffSmallArgs &a, int tm_bytes);
 hipError_t heff_small(DType t, const HeffSmallArgs &a, int count, hipStream_t s);
+// One launch over ng argument sets (count[k] instances each, the same
+// Krylov index j and the same `staged` choice in every set).
+hipError_t heff_small_grouped(DType t, const HeffSmallArgs *a, const int *count, int ng, hipStream_t s);
 // CSR table of W[wl][s'][s][wr] (instance stride sW elements) over rows
 // wl d + s' (Wl d <= 256, Wl d d Wr <= WT_MAX): row pointers rowp[Wl d + 1],
 // then col (s Wr + wr) and coef of each nonzero in index order.  Outputs at
@@ -152,6 +239,11 @@ hipError_t heff_small(DType t, const HeffSmallArgs &a, int count, hipStream_t s)
 constexpr int WT_MAX = 8192;
 hipError_t wtable(const double2 *W, int Wl, int d, int Wr, int64_t sW, int *rowp, int *col,
                   double2 *coef, int64_t wss, int count, hipStream_t s);
+struct WtableArgs {
+  const double2 *W; int rows, cap; int64_t sW; int *rowp; int *col; double2 *coef; int64_t wss;
+  int count;
+};
+hipError_t wtable_grouped(const WtableArgs *a, int ng, hipStream_t s);
 
 // QR of an m x n (m >= n, n <= 256) c128 matrix given by strides; writes
 // Q (m x n) and R (n x n) through output strides, with optional conjugation

@@ -41,9 +41,9 @@ __device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
 // per lane, the accumulators then stay in the architectural registers; the
 // uncapped 64x64 tile took ~390 and ran one wave per SIMD, 22 % slower).
 template <typename TA, typename TB, typename TC, typename TM, int BM, int BN, int BK>
-__global__ __launch_bounds__(256, sizeof(TM) == 8 ? 2 : 1) void cgemm_kernel(GemmArgs g) {
-  const int bz = blockIdx.z % g.batch;      // batch index
-  const int ri = blockIdx.z / g.batch;      // instance index
+__device__ __forceinline__ void cgemm_tile(const GemmArgs &g, const BlockXYZ &blk) {
+  const int bz = blk.z % g.batch;           // batch index
+  const int ri = blk.z / g.batch;           // instance index
   if (g.skip && g.skip[(int64_t)ri * g.inst.skip]) return;
   using VA = typename Cplx<TA>::type;
   using VB = typename Cplx<TB>::type;
@@ -59,8 +59,8 @@ __global__ __launch_bounds__(256, sizeof(TM) == 8 ? 2 : 1) void cgemm_kernel(Gem
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int bm0 = blockIdx.y * BM;
-  const int bn0 = blockIdx.x * BN;
+  const int bm0 = blk.y * BM;
+  const int bn0 = blk.x * BN;
   const VA *A = reinterpret_cast<const VA *>(g.A) + (int64_t)bz * g.bsa + (int64_t)ri * g.inst.a;
   const VB *B = reinterpret_cast<const VB *>(g.B) + (int64_t)bz * g.bsb + (int64_t)ri * g.inst.b;
   VC *C = reinterpret_cast<VC *>(g.C) + (int64_t)bz * g.bsc + (int64_t)ri * g.inst.c;
@@ -186,6 +186,17 @@ __global__ __launch_bounds__(256, sizeof(TM) == 8 ? 2 : 1) void cgemm_kernel(Gem
       }
 }
 
+template <typename TA, typename TB, typename TC, typename TM, int BM, int BN, int BK>
+__global__ __launch_bounds__(256, sizeof(TM) == 8 ? 2 : 1) void cgemm_kernel(GemmArgs g) {
+  cgemm_tile<TA, TB, TC, TM, BM, BN, BK>(g, native_block());
+}
+template <typename TA, typename TB, typename TC, typename TM, int BM, int BN, int BK>
+__global__ __launch_bounds__(256, sizeof(TM) == 8 ? 2 : 1) void cgemm_grouped_kernel(Grp<GemmArgs> gg) {
+  int k;
+  const BlockXYZ b = gg.locate(blockIdx.x, k);
+  cgemm_tile<TA, TB, TC, TM, BM, BN, BK>(gg.a[k], b);
+}
+
 // Split-BF16 variant (FP32 accumulation): every real operand x is stored as
 // x_hi = bf16(x) and x_lo = bf16(x - x_hi), so x = x_hi + x_lo to about
 // 2^-17 |x|, and a real product is x_hi y_hi + x_hi y_lo + x_lo y_hi (the
@@ -208,9 +219,9 @@ __device__ __forceinline__ void split_bf16(float x, __bf16 &hi, __bf16 &lo) {
 // Two waves per SIMD (at most 256 registers per lane): uncapped, the 64x64
 // tile took 288 and ran one wave per SIMD, 15 % slower at M = 256.
 template <typename TA, typename TB, typename TC, int BM, int BN>
-__global__ __launch_bounds__(256, 2) void cgemm_bf3_kernel(GemmArgs g) {
-  const int bz = blockIdx.z % g.batch;
-  const int ri = blockIdx.z / g.batch;
+__device__ __forceinline__ void cgemm_bf3_tile(const GemmArgs &g, const BlockXYZ &blk) {
+  const int bz = blk.z % g.batch;
+  const int ri = blk.z / g.batch;
   if (g.skip && g.skip[(int64_t)ri * g.inst.skip]) return;
   using VA = typename Cplx<TA>::type;
   using VB = typename Cplx<TB>::type;
@@ -225,8 +236,8 @@ __global__ __launch_bounds__(256, 2) void cgemm_bf3_kernel(GemmArgs g) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int bm0 = blockIdx.y * BM;
-  const int bn0 = blockIdx.x * BN;
+  const int bm0 = blk.y * BM;
+  const int bn0 = blk.x * BN;
   const VA *A = reinterpret_cast<const VA *>(g.A) + (int64_t)bz * g.bsa + (int64_t)ri * g.inst.a;
   const VB *B = reinterpret_cast<const VB *>(g.B) + (int64_t)bz * g.bsb + (int64_t)ri * g.inst.b;
   VC *C = reinterpret_cast<VC *>(g.C) + (int64_t)bz * g.bsc + (int64_t)ri * g.inst.c;
@@ -341,6 +352,17 @@ __global__ __launch_bounds__(256, 2) void cgemm_bf3_kernel(GemmArgs g) {
       }
 }
 
+template <typename TA, typename TB, typename TC, int BM, int BN>
+__global__ __launch_bounds__(256, 2) void cgemm_bf3_kernel(GemmArgs g) {
+  cgemm_bf3_tile<TA, TB, TC, BM, BN>(g, native_block());
+}
+template <typename TA, typename TB, typename TC, int BM, int BN>
+__global__ __launch_bounds__(256, 2) void cgemm_bf3_grouped_kernel(Grp<GemmArgs> gg) {
+  int k;
+  const BlockXYZ b = gg.locate(blockIdx.x, k);
+  cgemm_bf3_tile<TA, TB, TC, BM, BN>(gg.a[k], b);
+}
+
 template <typename TA, typename TB, typename TC>
 hipError_t launch_bf3(const GemmArgs &g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.inst.count <= 0) return hipSuccess;
@@ -387,7 +409,71 @@ hipError_t launch(const GemmArgs &g, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Tile of a grouped launch: the choice the largest group (by 64x64 tiles)
+// would make alone, so that group computes exactly as its own launch.
+int grouped_tile(const GemmArgs *g, int ng, bool f32m) {
+  int64_t best = -1;
+  int tile = 32;
+  for (int k = 0; k < ng; ++k) {
+    const int64_t t64 = (int64_t)((g[k].M + 63) / 64) * ((g[k].N + 63) / 64) * g[k].batch * g[k].inst.count;
+    if (t64 > best) {
+      best = t64;
+      const int64_t one = (int64_t)((g[k].M + 63) / 64) * ((g[k].N + 63) / 64) * g[k].batch;
+      tile = g[k].tile != 0 ? g[k].tile : (one >= 240 ? 64 : 32);
+    }
+  }
+  if (!f32m && tile > 64) tile = 64;
+  return tile;
+}
+
+template <typename TA, typename TB, typename TC, typename TM>
+hipError_t launch_grouped(const GemmArgs *g, int ng, bool bf3, hipStream_t s) {
+  constexpr bool F32M = sizeof(TM) == 4;
+  const int tile = bf3 ? (grouped_tile(g, ng, false) == 64 ? 64 : 32) : grouped_tile(g, ng, F32M);
+  const int bmn = tile == 32 ? 32 : 64;
+  Grp<GemmArgs> gg;
+  for (int k = 0; k < ng; ++k) {
+    if (g[k].M <= 0 || g[k].N <= 0 || g[k].batch <= 0 || g[k].inst.count <= 0) continue;
+    gg.add(g[k], (g[k].N + bmn - 1) / bmn, (g[k].M + bmn - 1) / bmn, g[k].batch * g[k].inst.count);
+  }
+  if (gg.ng == 0) return hipSuccess;
+  const dim3 grid(gg.blocks()), blk(256);
+  if (bf3) {
+    if (tile == 64) hipLaunchKernelGGL((cgemm_bf3_grouped_kernel<TA, TB, TC, 64, 64>), grid, blk, 0, s, gg);
+    else hipLaunchKernelGGL((cgemm_bf3_grouped_kernel<TA, TB, TC, 32, 32>), grid, blk, 0, s, gg);
+  } else if (F32M && tile == 96) {
+    hipLaunchKernelGGL((cgemm_grouped_kernel<TA, TB, TC, TM, 64, 64, F32M ? 32 : 16>), grid, blk, 0, s, gg);
+  } else if (F32M && tile == 128) {
+    hipLaunchKernelGGL((cgemm_grouped_kernel<TA, TB, TC, TM, 64, 64, F32M ? 64 : 16>), grid, blk, 0, s, gg);
+  } else if (tile == 64) {
+    hipLaunchKernelGGL((cgemm_grouped_kernel<TA, TB, TC, TM, 64, 64, 16>), grid, blk, 0, s, gg);
+  } else {
+    hipLaunchKernelGGL((cgemm_grouped_kernel<TA, TB, TC, TM, 32, 32, 32>), grid, blk, 0, s, gg);
+  }
+  return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t cgemm_grouped(DType ta, DType tb, DType tc, const GemmArgs *g, int ng, int bf3, hipStream_t s) {
+  if (ng < 1 || ng > GMAX) return hipErrorInvalidValue;
+  if (bf3) {
+    if (tc != F32) return hipErrorInvalidValue;
+    for (int k = 0; k < ng; ++k)
+      if (g[k].mode != 0) return hipErrorInvalidValue;
+    if (ta == F64 && tb == F32) return launch_grouped<double, float, float, float>(g, ng, true, s);
+    if (ta == F32 && tb == F64) return launch_grouped<float, double, float, float>(g, ng, true, s);
+    if (ta == F32 && tb == F32) return launch_grouped<float, float, float, float>(g, ng, true, s);
+    if (ta == F64 && tb == F64) return launch_grouped<double, double, float, float>(g, ng, true, s);
+    return hipErrorInvalidValue;
+  }
+  if (ta == F64 && tb == F64 && tc == F64) return launch_grouped<double, double, double, double>(g, ng, false, s);
+  if (ta == F64 && tb == F32 && tc == F32) return launch_grouped<double, float, float, float>(g, ng, false, s);
+  if (ta == F32 && tb == F64 && tc == F32) return launch_grouped<float, double, float, float>(g, ng, false, s);
+  if (ta == F32 && tb == F32 && tc == F32) return launch_grouped<float, float, float, float>(g, ng, false, s);
+  if (ta == F64 && tb == F64 && tc == F32) return launch_grouped<double, double, float, float>(g, ng, false, s);
+  return hipErrorInvalidValue;
+}
 
 hipError_t cgemm_bf3(DType ta, DType tb, DType tc, const GemmArgs &g, hipStream_t s) {
   if (tc != F32 || g.mode != 0) return hipErrorInvalidValue;

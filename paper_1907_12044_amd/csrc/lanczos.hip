@@ -179,7 +179,7 @@ __device__ __forceinline__ void close_step_load(const LzState *st, const LzParti
   }
 }
 
-__device__ bool close_step_finish(LzState *st, const StepPre &p, int j, int Gw) {
+__device__ bool close_step_finish(LzState *st, const StepPre &p, int j, int Gw, int bx) {
   __shared__ int stop_s;
   __shared__ double nrm_s, aw_s, tol_s;
   __shared__ double coefr[KMAX], coefi[KMAX];
@@ -205,16 +205,16 @@ __device__ bool close_step_finish(LzState *st, const StepPre &p, int j, int Gw) 
     // a non-finite norm (from a non-finite input or operator) stops the
     // solve and raises the sticky flag that tdvp_observe reports
     const bool bad = !isfinite(nv) || !isfinite(aw_s);
-    if (bad && blockIdx.x == 0) *st->nonfinite = 1;
+    if (bad && bx == 0) *st->nonfinite = 1;
     if (j == 0) {
       if (!(nv > 0.0) || bad) stop = 1;
-      if (blockIdx.x == 0) {
+      if (bx == 0) {
         st->xnorm = nv;
         st->scale[0] = stop ? 0.0 : 1.0 / nv;
       }
     } else {
       if (!(nv > 1e-12 * aw_s) || bad || j >= p.keff) stop = 1;
-      if (!stop && blockIdx.x == 0) {
+      if (!stop && bx == 0) {
         st->beta[j - 1] = nv;
         st->scale[j] = 1.0 / nv;
       }
@@ -236,18 +236,13 @@ __device__ bool close_step_finish(LzState *st, const StepPre &p, int j, int Gw) 
     __syncthreads();
   }
   const bool stop = stop_s != 0;
-  if (stop && blockIdx.x == 0 && threadIdx.x == 0) {
+  if (stop && bx == 0 && threadIdx.x == 0) {
     st->k = j;
     st->stop = 1;
   }
   return stop;
 }
 
-__device__ bool close_step(LzState *st, LzPartials *pp, int Gprev, int j, int Gw) {
-  StepPre p;
-  close_step_load(st, pp, Gprev, j, Gw, p);
-  return close_step_finish(st, p, j, Gw);
-}
 
 constexpr int LU_E = 64;
 // Work-groups of lz_start and lz_update (one norm partial each): LU_E
@@ -259,21 +254,20 @@ __host__ __device__ inline int upd_grid(int64_t n) {
   return (int)g;
 }
 
-__global__ __launch_bounds__(LZ_BLOCK) void lz_start_kernel(LzState *st, LzPartials *pp,
-                                                            const double2 *x, double2 *u0,
-                                                            int64_t n, double zr, double zi,
-                                                            double tol, int keff, int trows,
-                                                            int *nonfinite, LzInst in) {
-  const int64_t wo = (int64_t)blockIdx.y * in.wss;
+__device__ __forceinline__ void lz_start_body(LzState *st, LzPartials *pp, const double2 *x,
+                                              double2 *u0, int64_t n, double zr, double zi,
+                                              double tol, int keff, int trows, int *nonfinite,
+                                              LzInst in, const BlockXYZ &blk) {
+  const int64_t wo = (int64_t)blk.y * in.wss;
   st = shift_bytes(st, wo);
   pp = shift_bytes(pp, wo);
   u0 = shift_bytes(u0, wo);
-  x += (int64_t)blockIdx.y * in.xs;
+  x += (int64_t)blk.y * in.xs;
   __shared__ double sh[8];
   double s = 0.0;
   const int64_t tcols = trows > 0 ? n / trows : 0;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t e = (int64_t)blk.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)blk.gx * blockDim.x) {
     // column-major basis: u0[c * trows + r] = x[r * tcols + c]
     const double2 v = trows > 0 ? x[(e % trows) * tcols + e / trows] : x[e];
     u0[e] = v;
@@ -281,8 +275,8 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_start_kernel(LzState *st, LzParti
   }
   s = block_sum(s, sh);
   if (threadIdx.x == 0) {
-    pp->nrm[blockIdx.x] = s;
-    if (blockIdx.x == 0) {
+    pp->nrm[blk.x] = s;
+    if (blk.x == 0) {
       st->stop = 0;
       st->k = 0;
       st->keff = keff;
@@ -294,17 +288,29 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_start_kernel(LzState *st, LzParti
   }
 }
 
+__global__ __launch_bounds__(LZ_BLOCK) void lz_start_kernel(LzState *st, LzPartials *pp,
+                                                            const double2 *x, double2 *u0,
+                                                            int64_t n, double zr, double zi,
+                                                            double tol, int keff, int trows,
+                                                            int *nonfinite, LzInst in) {
+  lz_start_body(st, pp, x, u0, n, zr, zi, tol, keff, trows, nonfinite, in, native_block());
+}
+__global__ __launch_bounds__(LZ_BLOCK) void lz_start_grouped_kernel(Grp<LzStartArgs> g) {
+  int k;
+  const BlockXYZ b = g.locate(blockIdx.x, k);
+  const LzStartArgs &a = g.a[k];
+  lz_start_body(a.st, a.pp, a.x, a.u0, a.n, a.zr, a.zi, a.tol, a.keff, a.trows, a.nonfinite, a.in, b);
+}
+
 // Start of step j: close step j-1 (beta_{j-1}, breakdown and tolerance
 // tests, scale_j), then w = sum_p ypart[p] -> U[j+1] with per-block partial
 // dots <u_i, w> (i <= j) and |w|^2.
 template <typename TY, int JB>
-__global__ __launch_bounds__(LZ_BLOCK) void lz_dots_kernel(LzState *st, LzPartials *pp,
-                                                           const TY *ypart, int P,
-                                                           int64_t pstride, double2 *U,
-                                                           int64_t ldu, int j, int64_t n,
-                                                           LzInst in) {
+__device__ __forceinline__ void lz_dots_body(LzState *st, LzPartials *pp, const TY *ypart, int P,
+                                             int64_t pstride, double2 *U, int64_t ldu, int j,
+                                             int64_t n, LzInst in, const BlockXYZ &blk) {
   {
-    const int64_t wo = (int64_t)blockIdx.y * in.wss;
+    const int64_t wo = (int64_t)blk.y * in.wss;
     st = shift_bytes(st, wo);
     pp = shift_bytes(pp, wo);
     ypart = shift_bytes(ypart, wo);
@@ -312,7 +318,7 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_dots_kernel(LzState *st, LzPartia
   }
   // the stop flag is loaded with the other inputs and tested before any write
   const int stopped = st->stop;
-  const int G = gridDim.x;
+  const int G = blk.gx;
   StepPre pre;
   close_step_load(st, pp, upd_grid(n), j, 0, pre);
   // Chunks of 256 elements (one chunk per work-group while n <= 256 LZ_PARTS).
@@ -332,7 +338,7 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_dots_kernel(LzState *st, LzPartia
   double w2 = 0.0;
   double2 *wdst = U + (int64_t)(j + 1) * ldu;
   bool first = true;
-  for (int64_t c0 = (int64_t)blockIdx.x * LZ_BLOCK; c0 < n; c0 += (int64_t)G * LZ_BLOCK) {
+  for (int64_t c0 = (int64_t)blk.x * LZ_BLOCK; c0 < n; c0 += (int64_t)G * LZ_BLOCK) {
     const int64_t e = c0 + threadIdx.x;
     double2 ur[NQ][LZ_BLOCK / 32];
 #pragma unroll
@@ -354,7 +360,7 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_dots_kernel(LzState *st, LzPartia
     }
     if (first) {
       first = false;
-      if (stopped || close_step_finish(st, pre, j, 0)) return;   // (synchronises the work-group)
+      if (stopped || close_step_finish(st, pre, j, 0, blk.x)) return;   // (synchronises the work-group)
     }
     double wr = 0.0, wi = 0.0;
     if (e < n) {
@@ -399,7 +405,7 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_dots_kernel(LzState *st, LzPartia
     }
     const int i = g8 + 8 * q;
     if (t32 == 0 && i <= j) {
-      pp->dot[i][blockIdx.x] = make_double2(ar[q], ai[q]);
+      pp->dot[i][blk.x] = make_double2(ar[q], ai[q]);
     }
   }
   w2 = wave_sum(w2);
@@ -408,8 +414,24 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_dots_kernel(LzState *st, LzPartia
   if (threadIdx.x == 0) {
     double a = 0.0;
     for (int w = 0; w < LZ_BLOCK / 64; ++w) a += w2s[w];
-    pp->w2[blockIdx.x] = a;
+    pp->w2[blk.x] = a;
   }
+}
+
+template <typename TY, int JB>
+__global__ __launch_bounds__(LZ_BLOCK) void lz_dots_kernel(LzState *st, LzPartials *pp,
+                                                           const TY *ypart, int P,
+                                                           int64_t pstride, double2 *U,
+                                                           int64_t ldu, int j, int64_t n,
+                                                           LzInst in) {
+  lz_dots_body<TY, JB>(st, pp, ypart, P, pstride, U, ldu, j, n, in, native_block());
+}
+template <typename TY, int JB>
+__global__ __launch_bounds__(LZ_BLOCK) void lz_dots_grouped_kernel(Grp<LzDotsArgs> g) {
+  int k;
+  const BlockXYZ b = g.locate(blockIdx.x, k);
+  const LzDotsArgs &a = g.a[k];
+  lz_dots_body<TY, JB>(a.st, a.pp, (const TY *)a.ypart, a.P, a.pstride, a.U, a.ldu, a.j, a.n, a.in, b);
 }
 
 // u_{j+1} = scale_j w - sum_{i<=j} c_i scale_i u_i ; per-block |u_{j+1}|^2.
@@ -421,13 +443,11 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_dots_kernel(LzState *st, LzPartia
 // pass are issued before the reduction of the dot partials, so the two
 // latencies overlap.
 template <int JB>
-__global__ __launch_bounds__(LZ_BLOCK) void lz_update_kernel(LzState *st, LzPartials *pp,
-                                                             double2 *U, int64_t ldu, int j,
-                                                             int64_t n, int Gd,
-                                                             const double2 *Yp, int P,
-                                                             LzInst in) {
+__device__ __forceinline__ void lz_update_body(LzState *st, LzPartials *pp, double2 *U, int64_t ldu,
+                                               int j, int64_t n, int Gd, const double2 *Yp, int P,
+                                               LzInst in, const BlockXYZ &blk) {
   {
-    const int64_t wo = (int64_t)blockIdx.y * in.wss;
+    const int64_t wo = (int64_t)blk.y * in.wss;
     st = shift_bytes(st, wo);
     pp = shift_bytes(pp, wo);
     U = shift_bytes(U, wo);
@@ -442,7 +462,7 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_update_kernel(LzState *st, LzPart
   __shared__ double2 pw[4][LU_E], ps[4][LU_E];
   const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
   double2 *w = U + (int64_t)(j + 1) * ldu;
-  const int64_t b0 = (int64_t)blockIdx.x * LU_E, bstride = (int64_t)gridDim.x * LU_E;
+  const int64_t b0 = (int64_t)blk.x * LU_E, bstride = (int64_t)blk.gx * LU_E;
   constexpr int NI = (JB + 3) / 4;         // basis vectors per wave
   constexpr int NP = (HS_PMAX + 3) / 4;    // partial vectors per wave
   double2 uv[NI], yv[NP];
@@ -493,9 +513,9 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_update_kernel(LzState *st, LzPart
       const double sc = si * sj;
       cr[i] = a * sc * si;      // c_i scale_i
       ci[i] = b * sc * si;
-      if (i == j && blockIdx.x == 0) st->alpha[j] = a * sc;
+      if (i == j && blk.x == 0) st->alpha[j] = a * sc;
     }
-    if (!Yp && blockIdx.x == 0 && threadIdx.x >= 192) {   // last wave: |H v_j|
+    if (!Yp && blk.x == 0 && threadIdx.x >= 192) {   // last wave: |H v_j|
       double t = 0.0;
       for (int blk = threadIdx.x - 192; blk < Gd; blk += 64) t += pp->w2[blk];
       t = wave_sum(t);
@@ -551,9 +571,25 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_update_kernel(LzState *st, LzPart
   s2 = block_sum(s2, sh);
   if (Yp) sw = block_sum(sw, sh + 4);
   if (threadIdx.x == 0) {
-    pp->nrm[blockIdx.x] = s2;
-    if (Yp) pp->w2[blockIdx.x] = sw;
+    pp->nrm[blk.x] = s2;
+    if (Yp) pp->w2[blk.x] = sw;
   }
+}
+
+template <int JB>
+__global__ __launch_bounds__(LZ_BLOCK) void lz_update_kernel(LzState *st, LzPartials *pp,
+                                                             double2 *U, int64_t ldu, int j,
+                                                             int64_t n, int Gd,
+                                                             const double2 *Yp, int P,
+                                                             LzInst in) {
+  lz_update_body<JB>(st, pp, U, ldu, j, n, Gd, Yp, P, in, native_block());
+}
+template <int JB>
+__global__ __launch_bounds__(LZ_BLOCK) void lz_update_grouped_kernel(Grp<LzUpdateArgs> g) {
+  int k;
+  const BlockXYZ b = g.locate(blockIdx.x, k);
+  const LzUpdateArgs &a = g.a[k];
+  lz_update_body<JB>(a.st, a.pp, a.U, a.ldu, a.j, a.n, a.Gd, a.Yp, a.P, a.in, b);
 }
 
 // y = |x| sum_i [exp(z T_k) e_1]_i v_i with k = the final basis size (keff
@@ -562,22 +598,21 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_update_kernel(LzState *st, LzPart
 // wave q adds the basis vectors i = q, q + 4, ..., whose loads are issued
 // before the exponential, and wave 0 adds the four wave sums in order.
 template <int KB>
-__global__ __launch_bounds__(LZ_BLOCK) void lz_finish_kernel(LzState *st, const double2 *U,
-                                                             int64_t ldu, int64_t n, int keff,
-                                                             double2 *y, int32_t *k_used,
-                                                             int trows, LzInst in) {
+__device__ __forceinline__ void lz_finish_body(LzState *st, const double2 *U, int64_t ldu, int64_t n,
+                                               int keff, double2 *y, int32_t *k_used, int trows,
+                                               LzInst in, const BlockXYZ &blk) {
   {
-    const int64_t wo = (int64_t)blockIdx.y * in.wss;
+    const int64_t wo = (int64_t)blk.y * in.wss;
     st = shift_bytes(st, wo);
     U = shift_bytes(U, wo);
-    y += (int64_t)blockIdx.y * in.ys;
-    if (k_used) k_used += blockIdx.y;
+    y += (int64_t)blk.y * in.ys;
+    if (k_used) k_used += blk.y;
   }
   __shared__ double cr[KMAX], ci[KMAX];
   __shared__ double2 ps[4][LU_E];
   constexpr int NI = (KB + 3) / 4;         // basis vectors per wave
   const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
-  const int64_t b0 = (int64_t)blockIdx.x * LU_E, bstride = (int64_t)gridDim.x * LU_E;
+  const int64_t b0 = (int64_t)blk.x * LU_E, bstride = (int64_t)blk.gx * LU_E;
   double2 uv[NI];
 #define LZ_FINISH_LOAD(e)                                                                  \
   do {                                                                                     \
@@ -638,7 +673,22 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_finish_kernel(LzState *st, const 
     __syncthreads();
   }
 #undef LZ_FINISH_LOAD
-  if (k_used && blockIdx.x == 0 && threadIdx.x == 0) *k_used = zero ? 0 : k;
+  if (k_used && blk.x == 0 && threadIdx.x == 0) *k_used = zero ? 0 : k;
+}
+
+template <int KB>
+__global__ __launch_bounds__(LZ_BLOCK) void lz_finish_kernel(LzState *st, const double2 *U,
+                                                             int64_t ldu, int64_t n, int keff,
+                                                             double2 *y, int32_t *k_used,
+                                                             int trows, LzInst in) {
+  lz_finish_body<KB>(st, U, ldu, n, keff, y, k_used, trows, in, native_block());
+}
+template <int KB>
+__global__ __launch_bounds__(LZ_BLOCK) void lz_finish_grouped_kernel(Grp<LzFinishArgs> g) {
+  int k;
+  const BlockXYZ b = g.locate(blockIdx.x, k);
+  const LzFinishArgs &a = g.a[k];
+  lz_finish_body<KB>(a.st, a.U, a.ldu, a.n, a.keff, a.y, a.k_used, a.trows, a.in, b);
 }
 
 // ---------------------------------------------------------------------------
@@ -778,13 +828,13 @@ struct HsLayout {
 };
 
 template <typename T, int JB, bool STG>
-__global__ __launch_bounds__(HS_WAVES * 64) void heff_small_kernel(HeffSmallArgs a) {
+__device__ __forceinline__ void heff_small_body(const HeffSmallArgs &a, const BlockXYZ &blk) {
   using VE = typename Mf<T>::c2;
   constexpr int NT = HS_WAVES * 64;
   extern __shared__ char smem[];
   const int Ml = a.Ml, d = a.d, Mr = a.Mr, Wl = a.Wl, Wr = a.Wr;
-  const int rp = blockIdx.x % Mr, part = blockIdx.x / Mr;   // output column r', part p
-  const int inst = blockIdx.y;
+  const int rp = blk.x % Mr, part = blk.x / Mr;   // output column r', part p
+  const int inst = blk.y;
   LzState *st = shift_bytes(a.st, (int64_t)inst * a.wss);
   LzPartials *pp = shift_bytes(a.pp, (int64_t)inst * a.wss);
   double2 *U = shift_bytes(a.U, (int64_t)inst * a.wss);
@@ -919,7 +969,7 @@ __global__ __launch_bounds__(HS_WAVES * 64) void heff_small_kernel(HeffSmallArgs
     t2_im[e] = 0;
   }
   if (stopped) return;
-  if (close_step_finish(st, pre, j, j > 0 ? a.Gw : 0)) return;   // (synchronises the work-group)
+  if (close_step_finish(st, pre, j, j > 0 ? a.Gw : 0, blk.x)) return;   // (synchronises the work-group)
 
   // stage 1: T1 (MP x Wr) = X[l0 d .., :] (MP x Mr) Rr (Mr x Wr)
   auto st1 = [&](int row, int col, T re, T im) {
@@ -981,7 +1031,7 @@ __global__ __launch_bounds__(HS_WAVES * 64) void heff_small_kernel(HeffSmallArgs
   // y_p -> Yp[p] (column r'); <u_i, y_p> partials: group g takes i = g, g + NG, ...
   double2 *wdst = Yp + (int64_t)part * a.n + (int64_t)rp * ML1;
   for (int e = threadIdx.x; e < ML1; e += NT) wdst[e] = ycol[e];
-  const int slot = blockIdx.x;
+  const int slot = blk.x;
   double dr[NQ], di[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
@@ -1021,16 +1071,26 @@ __global__ __launch_bounds__(HS_WAVES * 64) void heff_small_kernel(HeffSmallArgs
   }
 }
 
+template <typename T, int JB, bool STG>
+__global__ __launch_bounds__(HS_WAVES * 64) void heff_small_kernel(HeffSmallArgs a) {
+  heff_small_body<T, JB, STG>(a, native_block());
+}
+template <typename T, int JB, bool STG>
+__global__ __launch_bounds__(HS_WAVES * 64) void heff_small_grouped_kernel(Grp<HeffSmallArgs> g) {
+  int k;
+  const BlockXYZ b = g.locate(blockIdx.x, k);
+  heff_small_body<T, JB, STG>(g.a[k], b);
+}
+
 // CSR table of an MPO site tensor W[wl][s'][s][wr] over rows (wl, s'): one
 // work-group per instance.  Every thread loads its candidates (index
 // e = t + 1024 q) at once; a work-group scan over the nonzero flags, chunk
 // by chunk in index order, gives each nonzero its position.
 constexpr int WT_THREADS = 1024;
-__global__ __launch_bounds__(WT_THREADS) void wtable_kernel(const double2 *W, int rows, int cap,
-                                                            int64_t sW, int *rowp, int *col,
-                                                            double2 *coef, int64_t wss) {
+__device__ __forceinline__ void wtable_body(const double2 *W, int rows, int cap, int64_t sW, int *rowp,
+                                            int *col, double2 *coef, int64_t wss, const BlockXYZ &blk) {
   constexpr int QN = WT_MAX / WT_THREADS;
-  const int inst = blockIdx.x, t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int inst = blk.x, t = threadIdx.x, lane = t & 63, wave = t >> 6;
   W += (int64_t)inst * sW;
   rowp = shift_bytes(rowp, (int64_t)inst * wss);
   col = shift_bytes(col, (int64_t)inst * wss);
@@ -1073,6 +1133,18 @@ __global__ __launch_bounds__(WT_THREADS) void wtable_kernel(const double2 *W, in
     __syncthreads();
   }
   if (t == 0) rowp[rows] = base_s;
+}
+
+__global__ __launch_bounds__(WT_THREADS) void wtable_kernel(const double2 *W, int rows, int cap,
+                                                            int64_t sW, int *rowp, int *col,
+                                                            double2 *coef, int64_t wss) {
+  wtable_body(W, rows, cap, sW, rowp, col, coef, wss, native_block());
+}
+__global__ __launch_bounds__(WT_THREADS) void wtable_grouped_kernel(Grp<WtableArgs> g) {
+  int k;
+  const BlockXYZ b = g.locate(blockIdx.x, k);
+  const WtableArgs &a = g.a[k];
+  wtable_body(a.W, a.rows, a.cap, a.sW, a.rowp, a.col, a.coef, a.wss, b);
 }
 
 // Work-groups of lz_dots: one 256-element chunk each, at most LZ_PARTS.
@@ -1187,6 +1259,141 @@ hipError_t wtable(const double2 *W, int Wl, int d, int Wr, int64_t sW, int *rowp
   if (Wl * d > 256 || (int64_t)Wl * d * d * Wr > WT_MAX) return hipErrorInvalidValue;
   hipLaunchKernelGGL(wtable_kernel, dim3(count), dim3(WT_THREADS), 0, s, W, Wl * d, d * Wr, sW,
                      rowp, col, coef, wss);
+  return hipGetLastError();
+}
+
+hipError_t lz_start_grouped(const LzStartArgs *a, int ng, hipStream_t s) {
+  if (ng < 1 || ng > GMAX) return hipErrorInvalidValue;
+  Grp<LzStartArgs> g;
+  for (int k = 0; k < ng; ++k) g.add(a[k], upd_grid(a[k].n), a[k].in.count, 1);
+  if (g.ng == 0) return hipSuccess;
+  hipLaunchKernelGGL(lz_start_grouped_kernel, dim3(g.blocks()), dim3(LZ_BLOCK), 0, s, g);
+  return hipGetLastError();
+}
+
+hipError_t lz_dots_grouped(DType ty, const LzDotsArgs *a, int ng, hipStream_t s) {
+  if (ng < 1 || ng > GMAX) return hipErrorInvalidValue;
+  Grp<LzDotsArgs> g;
+  for (int k = 0; k < ng; ++k) {
+    if (a[k].j != a[0].j) return hipErrorInvalidValue;
+    g.add(a[k], dots_grid(a[k].n), a[k].in.count, 1);
+  }
+  if (g.ng == 0) return hipSuccess;
+  const int j = a[0].j;
+  const dim3 gr(g.blocks()), b(LZ_BLOCK);
+#define LZ_DOTS_G(T, JB) hipLaunchKernelGGL((lz_dots_grouped_kernel<T, JB>), gr, b, 0, s, g)
+  if (ty == F64) {
+    if (j < 4) LZ_DOTS_G(double2, 4);
+    else if (j < 8) LZ_DOTS_G(double2, 8);
+    else if (j < 16) LZ_DOTS_G(double2, 16);
+    else LZ_DOTS_G(double2, 32);
+  } else {
+    if (j < 4) LZ_DOTS_G(float2, 4);
+    else if (j < 8) LZ_DOTS_G(float2, 8);
+    else if (j < 16) LZ_DOTS_G(float2, 16);
+    else LZ_DOTS_G(float2, 32);
+  }
+#undef LZ_DOTS_G
+  return hipGetLastError();
+}
+
+hipError_t lz_update_grouped(const LzUpdateArgs *a, int ng, hipStream_t s) {
+  if (ng < 1 || ng > GMAX) return hipErrorInvalidValue;
+  Grp<LzUpdateArgs> g;
+  for (int k = 0; k < ng; ++k) {
+    LzUpdateArgs ak = a[k];
+    if (ak.j != a[0].j) return hipErrorInvalidValue;
+    if (ak.Gd <= 0) ak.Gd = dots_grid(ak.n);
+    if (ak.Yp && (ak.P < 1 || ak.P > HS_PMAX)) return hipErrorInvalidValue;
+    g.add(ak, upd_grid(ak.n), ak.in.count, 1);
+  }
+  if (g.ng == 0) return hipSuccess;
+  const int j = a[0].j;
+  const dim3 gr(g.blocks()), b(LZ_BLOCK);
+#define LZ_UPD_G(JB) hipLaunchKernelGGL((lz_update_grouped_kernel<JB>), gr, b, 0, s, g)
+  if (j < 4) LZ_UPD_G(4);
+  else if (j < 8) LZ_UPD_G(8);
+  else if (j < 16) LZ_UPD_G(16);
+  else LZ_UPD_G(32);
+#undef LZ_UPD_G
+  return hipGetLastError();
+}
+
+hipError_t lz_finish_grouped(const LzFinishArgs *a, int ng, hipStream_t s) {
+  if (ng < 1 || ng > GMAX) return hipErrorInvalidValue;
+  Grp<LzFinishArgs> g;
+  int kb = 0;
+  for (int k = 0; k < ng; ++k) {
+    if (a[k].keff > KMAX) return hipErrorInvalidValue;
+    kb = std::max(kb, a[k].keff);
+    g.add(a[k], upd_grid(a[k].n), a[k].in.count, 1);
+  }
+  if (g.ng == 0) return hipSuccess;
+  const dim3 gr(g.blocks()), b(LZ_BLOCK);
+#define LZ_FIN_G(KB) hipLaunchKernelGGL((lz_finish_grouped_kernel<KB>), gr, b, 0, s, g)
+  if (kb <= 4) LZ_FIN_G(4);
+  else if (kb <= 8) LZ_FIN_G(8);
+  else if (kb <= 16) LZ_FIN_G(16);
+  else LZ_FIN_G(32);
+#undef LZ_FIN_G
+  return hipGetLastError();
+}
+
+hipError_t heff_small_grouped(DType t, const HeffSmallArgs *a, const int *count, int ng, hipStream_t s) {
+  if (ng < 1 || ng > GMAX) return hipErrorInvalidValue;
+  static const bool attr = [] {   // once per process (thread-safe static)
+#define HSG_ATTR(T, JB, S)                                                              \
+  (void)hipFuncSetAttribute((const void *)heff_small_grouped_kernel<T, JB, S>,          \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, HEFF_SMALL_LDS)
+#define HSG_ATTR2(T, S) HSG_ATTR(T, 4, S); HSG_ATTR(T, 8, S); HSG_ATTR(T, 16, S); HSG_ATTR(T, 32, S)
+    HSG_ATTR2(double, false); HSG_ATTR2(double, true); HSG_ATTR2(float, false); HSG_ATTR2(float, true);
+#undef HSG_ATTR2
+#undef HSG_ATTR
+    (void)hipGetLastError();
+    return true;
+  }();
+  (void)attr;
+  Grp<HeffSmallArgs> g;
+  size_t lds = 0;
+  const int tb = t == F64 ? 8 : 4;
+  for (int k = 0; k < ng; ++k) {
+    if (a[k].j != a[0].j || a[k].staged != a[0].staged) return hipErrorInvalidValue;
+    lds = std::max(lds, heff_small_lds(a[k], tb));
+    g.add(a[k], a[k].Mr * a[k].P, count[k], 1);
+  }
+  if (g.ng == 0) return hipSuccess;
+  if (lds > HEFF_SMALL_LDS) return hipErrorInvalidValue;
+  const dim3 gr(g.blocks()), b(HS_WAVES * 64);
+  const int j = a[0].j;
+#define HSG(T, JB, S) hipLaunchKernelGGL((heff_small_grouped_kernel<T, JB, S>), gr, b, lds, s, g)
+#define HSG_J(T, S)                  \
+  do {                               \
+    if (j < 4) HSG(T, 4, S);         \
+    else if (j < 8) HSG(T, 8, S);    \
+    else if (j < 16) HSG(T, 16, S);  \
+    else HSG(T, 32, S);              \
+  } while (0)
+  if (t == F64) {
+    if (a[0].staged) HSG_J(double, true);
+    else HSG_J(double, false);
+  } else {
+    if (a[0].staged) HSG_J(float, true);
+    else HSG_J(float, false);
+  }
+#undef HSG_J
+#undef HSG
+  return hipGetLastError();
+}
+
+hipError_t wtable_grouped(const WtableArgs *a, int ng, hipStream_t s) {
+  if (ng < 1 || ng > GMAX) return hipErrorInvalidValue;
+  Grp<WtableArgs> g;
+  for (int k = 0; k < ng; ++k) {
+    if (a[k].rows > 256 || (int64_t)a[k].rows * a[k].cap > WT_MAX) return hipErrorInvalidValue;
+    g.add(a[k], a[k].count, 1, 1);
+  }
+  if (g.ng == 0) return hipSuccess;
+  hipLaunchKernelGGL(wtable_grouped_kernel, dim3(g.blocks()), dim3(WT_THREADS), 0, s, g);
   return hipGetLastError();
 }
 

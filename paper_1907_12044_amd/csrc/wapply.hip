@@ -20,15 +20,15 @@ template <> struct Cplx<double> { using type = double2; };
 template <> struct Cplx<float> { using type = float2; };
 
 template <typename T>
-__global__ __launch_bounds__(256) void wapply_kernel(WApplyArgs p) {
-  const int ri = blockIdx.z;   // instance
+__device__ __forceinline__ void wapply_body(const WApplyArgs &p, const BlockXYZ &blk) {
+  const int ri = blk.z;   // instance
   if (p.skip && p.skip[(int64_t)ri * p.inst.skip]) return;
   using V = typename Cplx<T>::type;
   __shared__ T cre[MAXNZ], cim[MAXNZ];
   __shared__ int cw[MAXNZ], cs[MAXNZ];
   __shared__ int nnz_s;
   const int d = p.d;
-  const int wo = blockIdx.y / d, so = blockIdx.y % d;
+  const int wo = blk.y / d, so = blk.y % d;
   const int Win = p.w_in_right ? p.Wr : p.Wl;
   const double2 *W = reinterpret_cast<const double2 *>(p.W) + (int64_t)ri * p.inst.b;
   const int ncand = Win * d;
@@ -69,8 +69,8 @@ __global__ __launch_bounds__(256) void wapply_kernel(WApplyArgs p) {
   const V *in = reinterpret_cast<const V *>(p.in) + (int64_t)ri * p.inst.a;
   V *out = reinterpret_cast<V *>(p.out) + (int64_t)ri * p.inst.c;
   const int64_t total = (int64_t)p.A * p.C;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t e = (int64_t)blk.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)blk.gx * blockDim.x) {
     const int64_t a = e / p.C, c = e % p.C;
     const V *ip = in + a * p.si_a + c * p.si_c;
     T re = 0, im = 0;
@@ -86,17 +86,55 @@ __global__ __launch_bounds__(256) void wapply_kernel(WApplyArgs p) {
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void wapply_kernel(WApplyArgs p) {
+  wapply_body<T>(p, native_block());
+}
+template <typename T>
+__global__ __launch_bounds__(256) void wapply_grouped_kernel(Grp<WApplyArgs> g) {
+  int k;
+  const BlockXYZ b = g.locate(blockIdx.x, k);
+  wapply_body<T>(g.a[k], b);
+}
+
+// grid of one argument set: x covers the (a, c) outputs (at most 64
+// work-groups, grid-stride), y the output rows (wo, so), z the instances
+bool wapply_grid(const WApplyArgs &a, dim3 &grid) {
+  const int Wout = a.w_in_right ? a.Wl : a.Wr;
+  const int64_t total = (int64_t)a.A * a.C;
+  if (total <= 0 || Wout <= 0 || a.inst.count <= 0) return false;
+  int gx = (int)((total + 255) / 256);
+  if (gx > 64) gx = 64;
+  grid = dim3(gx, Wout * a.d, a.inst.count);
+  return true;
+}
+
 }  // namespace
+
+hipError_t wapply_grouped(DType t, const WApplyArgs *a, int ng, hipStream_t s) {
+  if (ng < 1 || ng > GMAX) return hipErrorInvalidValue;
+  Grp<WApplyArgs> g;
+  for (int k = 0; k < ng; ++k) {
+    const int Win = a[k].w_in_right ? a[k].Wr : a[k].Wl;
+    if (Win * a[k].d > MAXNZ) return hipErrorInvalidValue;
+    dim3 gr;
+    if (wapply_grid(a[k], gr)) g.add(a[k], gr.x, gr.y, gr.z);
+  }
+  if (g.ng == 0) return hipSuccess;
+  if (t == F64)
+    hipLaunchKernelGGL(wapply_grouped_kernel<double>, dim3(g.blocks()), dim3(256), 0, s, g);
+  else
+    hipLaunchKernelGGL(wapply_grouped_kernel<float>, dim3(g.blocks()), dim3(256), 0, s, g);
+  return hipGetLastError();
+}
 
 hipError_t wapply(DType t, const WApplyArgs &a, hipStream_t s) {
   const int Wout = a.w_in_right ? a.Wl : a.Wr;
   const int Win = a.w_in_right ? a.Wr : a.Wl;
   if (Win * a.d > MAXNZ) return hipErrorInvalidValue;
-  const int64_t total = (int64_t)a.A * a.C;
-  if (total <= 0 || Wout <= 0 || a.inst.count <= 0) return hipSuccess;
-  int gx = (int)((total + 255) / 256);
-  if (gx > 64) gx = 64;
-  dim3 grid(gx, Wout * a.d, a.inst.count);
+  (void)Wout;
+  dim3 grid;
+  if (!wapply_grid(a, grid)) return hipSuccess;
   if (t == F64)
     hipLaunchKernelGGL(wapply_kernel<double>, grid, dim3(256), 0, s, a);
   else

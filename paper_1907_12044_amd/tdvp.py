@@ -81,6 +81,12 @@ EXPORTS = {
     "tdvp_profile": (c_int, [c_void_p, c_int]),
     "tdvp_profile_read": (c_int, [c_void_p, POINTER(c_double), POINTER(c_int64), POINTER(c_double),
                                   POINTER(c_double)]),
+    "tdvp_workspace_bytes_grouped": (c_int, [c_void_p, c_int, POINTER(c_int32), POINTER(_Mps),
+                                             POINTER(_Mpo), c_int, POINTER(c_size_t)]),
+    "tdvp_ps_step_grouped": (c_int, [c_void_p, c_int, POINTER(c_int32), POINTER(_Mps), POINTER(_Mpo),
+                                     POINTER(_Envs), c_double, c_int, c_int, c_double]),
+    "tdvp_observe_grouped": (c_int, [c_void_p, c_int, POINTER(c_int32), POINTER(_Mps), POINTER(_Mpo),
+                                     POINTER(_Envs), POINTER(c_int32), c_int, c_void_p]),
     "tdvp_mu_workspace_bytes": (c_int, [c_void_p, POINTER(_Mps), POINTER(_Mpo), POINTER(c_size_t)]),
     "tdvp_mu_rhs": (c_int, [c_void_p, POINTER(_Mps), POINTER(_Mpo), c_double, POINTER(c_void_p)]),
     "tdvp_mu_evolve": (c_int, [c_void_p, POINTER(_Mps), POINTER(_Mpo), c_double, c_double, c_double,
@@ -617,40 +623,132 @@ class DisorderEnsemble:
     """Static-disorder realisations of uneven bond dimension evolved together.
 
     ``members`` = [(r, params, M_r, raw MPS)] on the chain layout ``sites``;
-    realisations that share a bond dimension form one class, held as one PsEnsemble (every kernel covers
-    the class in one launch), each class on a stream of its own so that the
-    classes run concurrently.  ``step`` enqueues one step of every class;
+    realisations that share a bond dimension form one group (one (nb, ...)
+    array per site tensor, so the group's chains sit at constant strides).
+    With ``grouped=True`` (the default) all groups share one context and
+    every step is one tdvp_ps_step_grouped call: each Krylov solve of a
+    sweep position is one launch sequence covering every realisation.  With
+    ``grouped=False`` each group is a PsEnsemble on a stream of its own
+    (groups run concurrently, one launch sequence per group).
     ``observe_host`` returns the observables in realisation order.
     """
 
     def __init__(self, members, sites, device=0, precision=FP64, kmax=20, tol=0.0, graph=True,
-                 fused=True, autotune=False):
+                 fused=True, autotune=False, grouped=True):
         import torch
         self.torch = torch
         classes = {}
         for r, p, M, raw in members:
             classes.setdefault(M, []).append((r, p, raw))
-        self.order = []
-        self.classes = []
-        for M, rs in sorted(classes.items()):
-            e = PsEnsemble([p for _, p, _ in rs], sites, [raw for _, _, raw in rs], device, precision,
-                           kmax=kmax, tol=tol, graph=graph, fused=fused, autotune=autotune)
-            self.classes.append((M, [r for r, _, _ in rs], e))
         self.nreal = len(members)
-        self.n_e = self.classes[0][2].n_e
+        self.grouped = grouped
+        self.kmax, self.tol = kmax, tol
+        self.classes = []
+        if not grouped:
+            for M, rs in sorted(classes.items()):
+                e = PsEnsemble([p for _, p, _ in rs], sites, [raw for _, _, raw in rs], device, precision,
+                               kmax=kmax, tol=tol, graph=graph, fused=fused, autotune=autotune)
+                self.classes.append((M, [r for r, _, _ in rs], e))
+            self.n_e = self.classes[0][2].n_e
+            return
+        self.stream = torch.cuda.Stream(device=device)
+        self.ctx = Context(device, precision, stream=self.stream)
+        dev = self.ctx.device
+        n = len(sites)
+        self.n_e = members[0][1].n_e
+        self.el_sites = [0] * self.n_e
+        for i, s_ in enumerate(sites):
+            if s_[0] == "el":
+                self.el_sites[s_[1]] = i
+        phys = [s_[3] for s_ in sites]
+        self._keep = []
+        self.order = []                   # realisation index of every chain, group-major
+        self.counts = []
+        groups = sorted(classes.items())
+        nb = len(members)
+        mps_arr, mpo_arr, env_arr = (_Mps * nb)(), (_Mpo * nb)(), (_Envs * nb)()
+        pp = _i32(phys)
+        self._keep.append(pp)
+        self.tensors = []
+        k = 0
+        with torch.cuda.stream(self.stream):
+            for M, rs in groups:
+                models = [fmo_model(p, sites) for _, p, _ in rs]
+                wbond = models[0][1]
+                if any(m_[1] != wbond for m_ in models):
+                    raise TdvpError("realisations have different MPO bond dims")
+                W = [torch.as_tensor(np.stack([m_[0][i] for m_ in models]), dtype=torch.complex128).to(dev)
+                     for i in range(n)]
+                A = [torch.as_tensor(np.stack([raw[i] for _, _, raw in rs]), dtype=torch.complex128).to(dev)
+                     for i in range(n)]
+                bond = [rs[0][2][0].shape[0]] + [a.shape[2] for a in rs[0][2]]
+                et = self.ctx.env_dtype
+                L = [torch.zeros((len(rs), bond[b], wbond[b], bond[b]), dtype=et, device=dev) for b in range(n + 1)]
+                R = [torch.zeros((len(rs), bond[b], wbond[b], bond[b]), dtype=et, device=dev) for b in range(n + 1)]
+                self.tensors.append((M, A, W, L, R))
+                pb, pw = _i32(bond), _i32(wbond)
+                self._keep += [pb, pw]
+                for q, (r, p, raw) in enumerate(rs):
+                    site = (c_void_p * n)(*[t[q].data_ptr() for t in A])
+                    wsite = (c_void_p * n)(*[t[q].data_ptr() for t in W])
+                    lft = (c_void_p * (n + 1))(*[t[q].data_ptr() for t in L])
+                    rgt = (c_void_p * (n + 1))(*[t[q].data_ptr() for t in R])
+                    self._keep += [site, wsite, lft, rgt]
+                    mps_arr[k] = _Mps(n, pp, pb, site)
+                    mpo_arr[k] = _Mpo(n, pp, pw, wsite, float(models[q][2]))
+                    env_arr[k] = _Envs(lft, rgt)
+                    self.order.append(r)
+                    k += 1
+                self.counts.append(len(rs))
+            self.obs = torch.zeros((nb, 2 + self.n_e), dtype=torch.float64, device=dev)
+        self.stream.synchronize()
+        self.descs = (mps_arr, mpo_arr, env_arr)
+        self._counts = _i32(self.counts)
+        b = c_size_t(0)
+        _check(lib().tdvp_workspace_bytes_grouped(self.ctx.h, len(self.counts), self._counts, mps_arr, mpo_arr,
+                                                  kmax, ctypes.byref(b)), "tdvp_workspace_bytes_grouped")
+        self.ctx.reserve(b.value)
+        set_graph(self.ctx, graph)
+        set_fused(self.ctx, fused)
+        set_autotune(self.ctx, autotune)
+        for q in range(nb):
+            _check(lib().tdvp_right_canonicalize(self.ctx.h, ctypes.byref(mps_arr[q])), "tdvp_right_canonicalize")
+            _check(lib().tdvp_envs_build(self.ctx.h, ctypes.byref(mps_arr[q]), ctypes.byref(mpo_arr[q]),
+                                         ctypes.byref(env_arr[q])), "tdvp_envs_build")
 
     def step(self, dt_au, nsteps=1):
-        for _ in range(nsteps):
-            for _, _, e in self.classes:
-                e.step(dt_au, 1)
+        if not self.grouped:
+            for _ in range(nsteps):
+                for _, _, e in self.classes:
+                    e.step(dt_au, 1)
+            return
+        m, w, e = self.descs
+        _check(lib().tdvp_ps_step_grouped(self.ctx.h, len(self.counts), self._counts, m, w, e, float(dt_au),
+                                          int(nsteps), int(self.kmax), float(self.tol)), "tdvp_ps_step_grouped")
 
     def observe_host(self):
         out = np.zeros((self.nreal, 2 + self.n_e))
-        for _, rs, e in self.classes:
-            out[rs] = e.observe_host()
+        if not self.grouped:
+            for _, rs, e in self.classes:
+                out[rs] = e.observe_host()
+            return out
+        m, w, e = self.descs
+        arr = _i32(self.el_sites)
+        _check(lib().tdvp_observe_grouped(self.ctx.h, len(self.counts), self._counts, m, w, e, arr,
+                                          len(self.el_sites), _ptr(self.obs)), "tdvp_observe_grouped")
+        o = self.obs.cpu().numpy()
+        out[self.order] = o
         return out
 
-    def synchronize(self):
-        for _, _, e in self.classes:
-            e.stream.synchronize()
+    def contexts(self):
+        """(context, realisations per context) pairs, for kernel timing."""
+        if not self.grouped:
+            return [(e.ctx, len(rs)) for _, rs, e in self.classes]
+        return [(self.ctx, self.nreal)]
 
+    def synchronize(self):
+        if not self.grouped:
+            for _, _, e in self.classes:
+                e.stream.synchronize()
+        else:
+            self.stream.synchronize()
