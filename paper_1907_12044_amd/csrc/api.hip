@@ -247,16 +247,17 @@ hipError_t gemm_t(tdvp_ctx *c, DType ta, DType tb, DType tc, const GemmArgs &g0,
   }
   const int id = prof_begin(c, prof_cls);
   const hipError_t e = timed_repeat(c, id, [&] { return gemm_any(c, ta, tb, tc, g); });
-  const double M = g.M, N = g.N, K = g.K, B = g.batch;
-  prof_end(c, id, 8.0 * M * N * K * B,
-           (g.bsa ? B : 1.0) * M * K * esz(ta) + (g.bsb ? B : 1.0) * K * N * esz(tb) + B * M * N * esz(tc));
+  // every instance of a batched launch does the work of one
+  const double M = g.M, N = g.N, K = g.K, B = g.batch, R = g.inst.count;
+  prof_end(c, id, 8.0 * M * N * K * B * R,
+           R * ((g.bsa ? B : 1.0) * M * K * esz(ta) + (g.bsb ? B : 1.0) * K * N * esz(tb) + B * M * N * esz(tc)));
   return e;
 }
 
 hipError_t wapply_t(tdvp_ctx *c, DType t, const WApplyArgs &a) {
   const int id = prof_begin(c, TDVP_PROF_WAPPLY);
   const hipError_t e = timed_repeat(c, id, [&] { return wapply(t, a, c->stream); });
-  const double io = (double)a.A * a.C * a.d * esz(t);
+  const double io = (double)a.A * a.C * a.d * esz(t) * a.inst.count;
   prof_end(c, id, 0.0, io * (a.Wl + a.Wr));
   return e;
 }
