@@ -23,13 +23,37 @@ def qr_pos(A):
     return Q * ph[None, :], R * np.conj(ph)[:, None]
 
 
-def right_canonicalize(mps):
+def qr_cholesky3(A):
+    """Thin QR A = Q R (m >= n) by shifted Cholesky QR in three passes
+    (Fukaya, Kannan, Nakatsukasa, Yamamoto, Yanagisawa, SIAM J. Sci.
+    Comput. 42 (2020)): W_0 = A; pass p: G = W_p^H W_p, R_p = chol(G [+ s I])
+    with G = R_p^H R_p, W_{p+1} = W_p R_p^{-1}; the first pass adds the shift
+    s = 11 (m n + n (n + 1)) u tr(G), u = 2^-53.  Q = W_3, R = R_3 R_2 R_1
+    (upper triangular, real positive diagonal: the factorisation of eq:QR,
+    unique for full-rank A).  A second backward-stable QR for the oracle:
+    on numerically rank-deficient site tensors two such QRs choose
+    different (equally valid) bases for the negligible directions, and the
+    one-site TDVP-PS trajectory can amplify that difference."""
+    m, n = A.shape
+    W = A
+    Rt = np.eye(n, dtype=complex)
+    for p in range(3):
+        G = W.conj().T @ W
+        if p == 0:
+            G = G + 11.0 * (m * n + n * (n + 1)) * 2.0 ** -53 * np.trace(G).real * np.eye(n)
+        Rp = np.linalg.cholesky(G).conj().T           # G = Rp^H Rp
+        W = np.linalg.solve(Rp.T, W.T).T              # W Rp^{-1}
+        Rt = Rp @ Rt
+    return W, Rt
+
+
+def right_canonicalize(mps, qr=qr_pos):
     """RQ sweep N-1 -> 1 (eq:QR, mirrored); then normalise the centre at site 0."""
     mps = [A.copy() for A in mps]
     for i in range(len(mps) - 1, 0, -1):
         ml, d, mr = mps[i].shape
         C = mps[i].reshape(ml, d * mr)
-        Q, Rf = qr_pos(C.conj().T)          # C^H = Q Rf  ->  C = Rf^H Q^H
+        Q, Rf = qr(C.conj().T)              # C^H = Q Rf  ->  C = Rf^H Q^H
         mps[i] = Q.conj().T.reshape(ml, d, mr)
         mps[i - 1] = np.einsum("lsk,kr->lsr", mps[i - 1], Rf.conj().T)
     mps[0] = mps[0] / np.linalg.norm(mps[0])

@@ -14,6 +14,9 @@ left-to-right sweep then a right-to-left sweep, each with h = tau/2:
 The two forward factors on the last site use the same projector one after
 the other, so they are merged into a single exp(-i tau H[N-1]).
 Returns the new MPS (same gauge as on entry) and the updated environments.
+qr is the thin QR of eq:QR: numpy's Householder QR by default; the
+shifted Cholesky QR of oracle.mps.qr_cholesky3 gives a second,
+equally valid run for measuring the trajectory's rounding sensitivity.
 """
 
 from __future__ import annotations
@@ -24,7 +27,7 @@ from .krylov import expm_lanczos
 from .mps import qr_pos, env_left, env_right, heff, bond_op, ones_env, build_right_envs
 
 
-def ps_step(mps, Ws, R, tau, kmax=20, tol=0.0, L=None, stats=None):
+def ps_step(mps, Ws, R, tau, kmax=20, tol=0.0, L=None, stats=None, qr=qr_pos):
     n = len(mps)
     mps = [A.copy() for A in mps]
     R = list(R)
@@ -57,7 +60,7 @@ def ps_step(mps, Ws, R, tau, kmax=20, tol=0.0, L=None, stats=None):
         if last:
             break
         ml, d, mr = mps[i].shape
-        Q, D = qr_pos(mps[i].reshape(ml * d, mr))
+        Q, D = qr(mps[i].reshape(ml * d, mr))
         mps[i] = Q.reshape(ml, d, mr)
         L[i + 1] = env_left(L[i], mps[i], Ws[i])
         D = bwd(i + 1, D, 1j * h)
@@ -69,7 +72,7 @@ def ps_step(mps, Ws, R, tau, kmax=20, tol=0.0, L=None, stats=None):
         if i == 0:
             break
         ml, d, mr = mps[i].shape
-        Q, Rf = qr_pos(mps[i].reshape(ml, d * mr).conj().T)
+        Q, Rf = qr(mps[i].reshape(ml, d * mr).conj().T)
         mps[i] = Q.conj().T.reshape(ml, d, mr)
         D = Rf.conj().T
         R[i] = env_right(R[i + 1], mps[i], Ws[i])

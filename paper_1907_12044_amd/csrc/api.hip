@@ -79,6 +79,7 @@ struct tdvp_ctx {
   hipGraphExec_t gexec;
   std::vector<uint64_t> gkey;     // what the captured graph was built for
   int fused_off;                  // 1: never use the fused small-bond Lanczos step
+  int s3_per_channel;             // 1: stage 3 of H x in one part per left MPO channel
   // autotuner: per problem key (kind, shapes, instance count, types) the
   // candidate that ran fastest when the key was first met outside a graph
   // capture; later launches (and captured graphs) reuse it
@@ -285,9 +286,24 @@ struct Op {
   const void *L, *W, *R;
   int Ml, d, Mr, Wl, Wr;
   int64_t sL = 0, sW = 0, sR = 0;
+  int P = 0;   // partial outputs of the stage-3 GEMM (a divisor of Wl; 0: Wl)
   int64_t size() const { return (int64_t)Ml * d * Mr; }
-  int parts() const { return Wl; }
+  int parts() const { return P > 0 ? P : Wl; }
 };
+
+// Partial outputs of Op x for a batch of R instances.  Stage 3 sums over
+// the pairs (wl, l), K = Wl Ml; it is split into P equal runs of whole wl
+// blocks, each run a GEMM of its own whose output is one part.  Every part
+// is one more vector for the projections to read, so P is the smallest
+// divisor of Wl that gives about four 32 x 32 output tiles per compute unit
+// (1024 in all); a large batch needs no split.
+int stage3_parts(const Op &op, int R, int per_channel) {
+  if (per_channel) return op.Wl;
+  const int64_t tiles = (int64_t)((op.Ml + 31) / 32) * ((op.d * op.Mr + 31) / 32) * R;
+  for (int p = 1; p < op.Wl; ++p)
+    if (op.Wl % p == 0 && tiles * p >= 1024) return p;
+  return op.Wl;
+}
 
 // The launches of Op x (stage-1 GEMM, MPO pass, stage-3 GEMM; the bond
 // operator has no MPO pass) for the instances b with workspace base `base`:
@@ -326,13 +342,15 @@ OpLaunch op_args(const tdvp_ctx *c, char *base, const Layout &lay, const Op &op,
     w.so_w = n; w.so_s = op.Mr; w.so_a = (int64_t)op.d * op.Mr; w.so_c = 1;
     w.skip = skip;
     w.inst = inst_of(b, wse, op.sW, wse, wsk);
-    // stage 3 (batched over wl): Y[wl][l'][s' r'] = sum_l L[l'][wl][l] T2[wl][l][s' r']
+    // stage 3: Y[p][l'][s' r'] = sum_{(wl, l) in run p} L[l'][wl][l] T2[wl][l][s' r']
+    // (K = (Wl / P) Ml per part; the pairs (wl, l) are contiguous in both operands)
     GemmArgs &h = L.g3;
+    const int64_t kc = (int64_t)(op.Wl / op.parts()) * op.Ml;
     h.A = op.L; h.B = T2; h.C = Y;
-    h.M = op.Ml; h.N = op.d * op.Mr; h.K = op.Ml; h.batch = op.Wl;
+    h.M = op.Ml; h.N = op.d * op.Mr; h.K = (int)kc; h.batch = op.parts();
     h.sam = (int64_t)op.Wl * op.Ml; h.sak = 1; h.sbk = (int64_t)op.d * op.Mr; h.sbn = 1;
     h.scm = (int64_t)op.d * op.Mr; h.scn = 1;
-    h.bsa = op.Ml; h.bsb = n; h.bsc = n;
+    h.bsa = kc; h.bsb = kc * h.sbk; h.bsc = n;
     h.skip = skip;
     h.inst = inst_of(b, op.sL, wse, wse, wsk);
   } else {
@@ -346,11 +364,12 @@ OpLaunch op_args(const tdvp_ctx *c, char *base, const Layout &lay, const Op &op,
     g.skip = skip;
     g.inst = inst_of(b, sx, op.sR, wse, wsk);
     GemmArgs &h = L.g3;
+    const int64_t kc = (int64_t)(op.Wl / op.parts()) * op.Ml;
     h.A = op.L; h.B = T1; h.C = Y;
-    h.M = op.Ml; h.N = op.Mr; h.K = op.Ml; h.batch = op.Wl;
+    h.M = op.Ml; h.N = op.Mr; h.K = (int)kc; h.batch = op.parts();
     h.sam = (int64_t)op.Wl * op.Ml; h.sak = 1; h.sbk = op.Mr; h.sbn = 1;
     h.scm = op.Mr; h.scn = 1;
-    h.bsa = op.Ml; h.bsb = n; h.bsc = n;
+    h.bsa = kc; h.bsb = kc * h.sbk; h.bsc = n;
     h.skip = skip;
     h.inst = inst_of(b, op.sL, wse, wse, wsk);
   }
@@ -421,9 +440,11 @@ bool fused_args(const tdvp_ctx *c, const Layout &lay, const Op &op, const Bi &b,
 }
 
 // y = exp(z Op) x for every instance; x, y c128 with instance strides sx, sy.
-tdvp_status run_lanczos(tdvp_ctx *c, const Layout &lay, const Op &op, double zr, double zi,
+tdvp_status run_lanczos(tdvp_ctx *c, const Layout &lay, const Op &op_in, double zr, double zi,
                         int kmax, double tol, const void *x, int64_t sx, void *y, int64_t sy,
                         int32_t *kused, const Bi &b) {
+  Op op = op_in;
+  op.P = stage3_parts(op, b.R, c->s3_per_channel);
   const int64_t n = op.size();
   const int keff = (int)std::min<int64_t>(kmax, n);
   LzState *st = at<LzState>(c, lay.st);
@@ -683,6 +704,7 @@ tdvp_status tdvp_create(tdvp_ctx **ctx, int device, void *hip_stream, tdvp_preci
   c->klog_pos = 0;
   c->graph_mode = 0;
   c->fused_off = 0;
+  c->s3_per_channel = 0;
   c->autotune = 0;
   c->tune_now = 0;
   c->tune_ev[0] = c->tune_ev[1] = nullptr;
@@ -1002,6 +1024,12 @@ tdvp_status tdvp_set_fused(tdvp_ctx *ctx, int enable) {
   return TDVP_OK;
 }
 
+tdvp_status tdvp_set_stage3_split(tdvp_ctx *ctx, int per_channel) {
+  if (!ctx) return TDVP_E_ARG;
+  ctx->s3_per_channel = per_channel ? 1 : 0;
+  return TDVP_OK;
+}
+
 tdvp_status tdvp_set_autotune(tdvp_ctx *ctx, int enable) {
   if (!ctx) return TDVP_E_ARG;
   ctx->autotune = enable ? 1 : 0;
@@ -1131,6 +1159,7 @@ void step_key_head(const tdvp_ctx *ctx, double dt, double tol, int kmax, std::ve
   key->push_back((uint64_t)kmax);
   key->push_back((uint64_t)(int)ctx->prec);
   key->push_back((uint64_t)ctx->fused_off);
+  key->push_back((uint64_t)ctx->s3_per_channel);
   key->push_back((uint64_t)ctx->autotune);
   key->push_back((uint64_t)(uintptr_t)ctx->ws);
   key->push_back((uint64_t)(uintptr_t)ctx->stream);
@@ -1194,8 +1223,10 @@ struct LzJob {
   const GroupRun *g;
 };
 
-tdvp_status run_lanczos_grouped(tdvp_ctx *c, const std::vector<LzJob> &jobs, double zr, double zi,
+tdvp_status run_lanczos_grouped(tdvp_ctx *c, const std::vector<LzJob> &jobs_in, double zr, double zi,
                                 int kmax, double tol) {
+  std::vector<LzJob> jobs = jobs_in;
+  for (LzJob &J : jobs) J.op.P = stage3_parts(J.op, J.g->b.R, c->s3_per_channel);   // as run_lanczos
   const int ng = (int)jobs.size();
   if (ng == 0) return TDVP_OK;
   if (ng > GMAX) return TDVP_E_UNSUPPORTED;

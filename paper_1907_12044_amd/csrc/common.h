@@ -13,6 +13,7 @@ constexpr int KMAX = 32;          // largest Krylov dimension compiled in
 constexpr int LZ_GRID = 512;      // most work-groups of lz_start / lz_update / lz_finish
 constexpr int LZ_PARTS = 512;     // most per-work-group partials of one reduction
 constexpr int LZ_BLOCK = 256;
+static_assert(LZ_GRID <= LZ_PARTS, "one dot partial per work-group of the vector kernels");
 
 enum DType { F64 = 0, F32 = 1 };
 

@@ -30,6 +30,13 @@ template <typename T> __device__ __forceinline__ T *shift_bytes(T *p, int64_t by
   return reinterpret_cast<T *>(reinterpret_cast<char *>(const_cast<typename std::remove_const<T>::type *>(p)) + bytes);
 }
 
+// largest power of two <= x (x >= 1)
+constexpr int pow2_floor(int x) {
+  int p = 1;
+  while (2 * p <= x) p *= 2;
+  return p;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -305,6 +312,12 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_start_grouped_kernel(Grp<LzStartA
 // Start of step j: close step j-1 (beta_{j-1}, breakdown and tolerance
 // tests, scale_j), then w = sum_p ypart[p] -> U[j+1] with per-block partial
 // dots <u_i, w> (i <= j) and |w|^2.
+// The element layout is lz_update's: a work-group takes LU_E elements per
+// pass, wave q projects onto u_i for i = q, q + 4, ..., and every wave forms
+// w for the pass from the P parts itself (the four waves read the same
+// parts; the repeats hit the cache), so no pass needs a barrier; wave 0
+// stores w and adds |w|^2.  The loads of the next pass are issued before
+// the arithmetic of this one.
 template <typename TY, int JB>
 __device__ __forceinline__ void lz_dots_body(LzState *st, LzPartials *pp, const TY *ypart, int P,
                                              int64_t pstride, double2 *U, int64_t ldu, int j,
@@ -318,103 +331,78 @@ __device__ __forceinline__ void lz_dots_body(LzState *st, LzPartials *pp, const 
   }
   // the stop flag is loaded with the other inputs and tested before any write
   const int stopped = st->stop;
-  const int G = blk.gx;
   StepPre pre;
   close_step_load(st, pp, upd_grid(n), j, 0, pre);
-  // Chunks of 256 elements (one chunk per work-group while n <= 256 LZ_PARTS).
-  // Thread (g, t), g = tid / 32, t = tid % 32, projects onto u_i for
-  // i = g, g+8, g+16, g+24 over the elements t + 32 v of the chunk; its
-  // basis elements and the parts of its own w element are all requested
-  // before any is used (one memory round trip per chunk).  w for the chunk
-  // goes through LDS.
-  constexpr int NQ = (JB + 7) / 8;
-  constexpr int PR = 8;                 // parts of w held in registers (more: loaded after)
-  __shared__ double2 wl[LZ_BLOCK];
-  __shared__ double w2s[LZ_BLOCK / 64];
-  const int g8 = threadIdx.x >> 5, t32 = threadIdx.x & 31;
-  double ar[NQ], ai[NQ];
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) { ar[q] = 0.0; ai[q] = 0.0; }
-  double w2 = 0.0;
+  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+  constexpr int NI = (JB + 3) / 4;        // basis vectors per wave
+  constexpr int PR = 4;                   // parts of w held in registers (more: loaded after)
   double2 *wdst = U + (int64_t)(j + 1) * ldu;
-  bool first = true;
-  for (int64_t c0 = (int64_t)blk.x * LZ_BLOCK; c0 < n; c0 += (int64_t)G * LZ_BLOCK) {
-    const int64_t e = c0 + threadIdx.x;
-    double2 ur[NQ][LZ_BLOCK / 32];
+  const int64_t b0 = (int64_t)blk.x * LU_E, bstride = (int64_t)blk.gx * LU_E;
+  double2 uv[NI];
+  TY yv[PR];
+  auto load = [&](int64_t e) {
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int i = g8 + 8 * q;
-      const double2 *ui = U + (int64_t)i * ldu + c0;
-#pragma unroll
-      for (int t = 0; t < LZ_BLOCK / 32; ++t) {
-        const int el = t32 + 32 * t;
-        ur[q][t] = (i <= j && c0 + el < n) ? ui[el] : make_double2(0.0, 0.0);
-      }
+    for (int t = 0; t < NI; ++t) {
+      const int i = q + 4 * t;
+      uv[t] = (i <= j && e < n) ? U[(int64_t)i * ldu + e] : make_double2(0.0, 0.0);
     }
-    TY yv[PR];
 #pragma unroll
     for (int p = 0; p < PR; ++p) {
       yv[p].x = 0;
       yv[p].y = 0;
       if (p < P && e < n) yv[p] = ypart[(int64_t)p * pstride + e];
     }
-    if (first) {
-      first = false;
-      if (stopped || close_step_finish(st, pre, j, 0, blk.x)) return;   // (synchronises the work-group)
-    }
+  };
+  load(b0 + lane);
+  if (stopped || close_step_finish(st, pre, j, 0, blk.x)) return;   // (synchronises the work-group)
+  double ar[NI], ai[NI];
+#pragma unroll
+  for (int t = 0; t < NI; ++t) { ar[t] = 0.0; ai[t] = 0.0; }
+  double w2 = 0.0;
+  for (int64_t base = b0; base < n; base += bstride) {
+    const int64_t e = base + lane;
+    double2 ucur[NI];
+    TY ycur[PR];
+#pragma unroll
+    for (int t = 0; t < NI; ++t) ucur[t] = uv[t];
+#pragma unroll
+    for (int p = 0; p < PR; ++p) ycur[p] = yv[p];
+    if (base + bstride < n) load(base + bstride + lane);
     double wr = 0.0, wi = 0.0;
     if (e < n) {
 #pragma unroll
       for (int p = 0; p < PR; ++p) {
-        wr += (double)yv[p].x;
-        wi += (double)yv[p].y;
+        wr += (double)ycur[p].x;
+        wi += (double)ycur[p].y;
       }
       for (int p = PR; p < P; ++p) {
         const TY v = ypart[(int64_t)p * pstride + e];
         wr += (double)v.x;
         wi += (double)v.y;
       }
-      wdst[e] = make_double2(wr, wi);
-      w2 += wr * wr + wi * wi;
-    }
-    wl[threadIdx.x] = make_double2(wr, wi);
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int i = g8 + 8 * q;
-      if (i <= j) {
-#pragma unroll
-        for (int t = 0; t < LZ_BLOCK / 32; ++t) {
-          const double2 u = ur[q][t];
-          const double2 w = wl[t32 + 32 * t];
-          ar[q] += u.x * w.x + u.y * w.y;
-          ai[q] += u.x * w.y - u.y * w.x;
-        }
+      if (q == 0) {
+        wdst[e] = make_double2(wr, wi);
+        w2 += wr * wr + wi * wi;
       }
     }
-    __syncthreads();
-  }
-  if (stopped) return;
-  // reduce over the 32 threads of each group (half a wave), fixed tree
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-#pragma unroll
-    for (int o = 16; o > 0; o >>= 1) {
-      ar[q] += __shfl_xor(ar[q], o, 32);
-      ai[q] += __shfl_xor(ai[q], o, 32);
-    }
-    const int i = g8 + 8 * q;
-    if (t32 == 0 && i <= j) {
-      pp->dot[i][blk.x] = make_double2(ar[q], ai[q]);
+    for (int t = 0; t < NI; ++t) {
+      if (q + 4 * t <= j) {
+        ar[t] += ucur[t].x * wr + ucur[t].y * wi;
+        ai[t] += ucur[t].x * wi - ucur[t].y * wr;
+      }
     }
   }
-  w2 = wave_sum(w2);
-  if ((threadIdx.x & 63) == 0) w2s[threadIdx.x >> 6] = w2;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double a = 0.0;
-    for (int w = 0; w < LZ_BLOCK / 64; ++w) a += w2s[w];
-    pp->w2[blk.x] = a;
+  // wave sums (fixed tree) -> one partial per work-group and basis vector
+#pragma unroll
+  for (int t = 0; t < NI; ++t) {
+    const int i = q + 4 * t;
+    const double a = wave_sum(ar[t]), b = wave_sum(ai[t]);
+    if (lane == 0 && i <= j) pp->dot[i][blk.x] = make_double2(a, b);
+  }
+  if (q == 0) {
+    w2 = wave_sum(w2);
+    if (lane == 0) pp->w2[blk.x] = w2;
   }
 }
 
@@ -486,11 +474,12 @@ __device__ __forceinline__ void lz_update_body(LzState *st, LzPartials *pp, doub
   } while (0)
   if (b0 < n) LZ_UPDATE_LOAD(b0 + lane);
   const double sj = st->scale[j];
-  // Reduce the Gd dot partials of the previous kernel: LPI = 256 / JB lanes
-  // per basis index i (lane l adds partials l, l + LPI, ...), then a fixed
-  // tree over the LPI lanes.
+  // Reduce the Gd dot partials of the previous kernel: LPI lanes per basis
+  // index i (256 / JB rounded down to a power of two; lane l adds partials
+  // l, l + LPI, ...), then a fixed tree over the LPI lanes.
   {
-    constexpr int LPI = LZ_BLOCK / JB;
+    constexpr int LPI = pow2_floor(LZ_BLOCK / JB);
+    static_assert(LPI * JB <= LZ_BLOCK && LPI <= 64, "lanes per basis index");
     const int i = threadIdx.x / LPI, l8 = threadIdx.x % LPI;
     double a = 0.0, b = 0.0;
     if (i <= j) {
@@ -1147,13 +1136,9 @@ __global__ __launch_bounds__(WT_THREADS) void wtable_grouped_kernel(Grp<WtableAr
   wtable_body(a.W, a.rows, a.cap, a.sW, a.rowp, a.col, a.coef, a.wss, b);
 }
 
-// Work-groups of lz_dots: one 256-element chunk each, at most LZ_PARTS.
-int dots_grid(int64_t n) {
-  int64_t g = (n + LZ_BLOCK - 1) / LZ_BLOCK;
-  if (g > LZ_PARTS) g = LZ_PARTS;
-  if (g < 1) g = 1;
-  return (int)g;
-}
+// Work-groups of lz_dots: the element layout of lz_update (LU_E elements
+// per pass), so both kernels take the same grid.
+int dots_grid(int64_t n) { return upd_grid(n); }
 
 }  // namespace
 
@@ -1175,11 +1160,13 @@ hipError_t lz_dots(LzState *st, LzPartials *pp, DType ty, const void *ypart, int
     if (j < 4) LZ_DOTS(double2, 4);
     else if (j < 8) LZ_DOTS(double2, 8);
     else if (j < 16) LZ_DOTS(double2, 16);
+    else if (j < 24) LZ_DOTS(double2, 24);
     else LZ_DOTS(double2, 32);
   } else {
     if (j < 4) LZ_DOTS(float2, 4);
     else if (j < 8) LZ_DOTS(float2, 8);
     else if (j < 16) LZ_DOTS(float2, 16);
+    else if (j < 24) LZ_DOTS(float2, 24);
     else LZ_DOTS(float2, 32);
   }
 #undef LZ_DOTS
@@ -1196,6 +1183,7 @@ hipError_t lz_update(LzState *st, LzPartials *pp, double2 *U, int64_t ldu, int j
   if (j < 4) LZ_UPD(4);
   else if (j < 8) LZ_UPD(8);
   else if (j < 16) LZ_UPD(16);
+  else if (j < 24) LZ_UPD(24);
   else LZ_UPD(32);
 #undef LZ_UPD
   return hipGetLastError();
@@ -1286,11 +1274,13 @@ hipError_t lz_dots_grouped(DType ty, const LzDotsArgs *a, int ng, hipStream_t s)
     if (j < 4) LZ_DOTS_G(double2, 4);
     else if (j < 8) LZ_DOTS_G(double2, 8);
     else if (j < 16) LZ_DOTS_G(double2, 16);
+    else if (j < 24) LZ_DOTS_G(double2, 24);
     else LZ_DOTS_G(double2, 32);
   } else {
     if (j < 4) LZ_DOTS_G(float2, 4);
     else if (j < 8) LZ_DOTS_G(float2, 8);
     else if (j < 16) LZ_DOTS_G(float2, 16);
+    else if (j < 24) LZ_DOTS_G(float2, 24);
     else LZ_DOTS_G(float2, 32);
   }
 #undef LZ_DOTS_G
@@ -1314,6 +1304,7 @@ hipError_t lz_update_grouped(const LzUpdateArgs *a, int ng, hipStream_t s) {
   if (j < 4) LZ_UPD_G(4);
   else if (j < 8) LZ_UPD_G(8);
   else if (j < 16) LZ_UPD_G(16);
+  else if (j < 24) LZ_UPD_G(24);
   else LZ_UPD_G(32);
 #undef LZ_UPD_G
   return hipGetLastError();

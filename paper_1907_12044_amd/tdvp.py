@@ -71,6 +71,7 @@ EXPORTS = {
     "tdvp_set_krylov_log": (c_int, [c_void_p, c_void_p, c_int]),
     "tdvp_set_graph": (c_int, [c_void_p, c_int]),
     "tdvp_set_fused": (c_int, [c_void_p, c_int]),
+    "tdvp_set_stage3_split": (c_int, [c_void_p, c_int]),
     "tdvp_set_autotune": (c_int, [c_void_p, c_int]),
     "tdvp_profile_reps": (c_int, [c_void_p, c_int]),
     "tdvp_autotune_count": (c_int, [c_void_p, c_void_p]),
@@ -331,6 +332,10 @@ def set_fused(ctx, enable):
     _check(lib().tdvp_set_fused(ctx.h, 1 if enable else 0), "tdvp_set_fused")
 
 
+def set_stage3_split(ctx, per_channel):
+    _check(lib().tdvp_set_stage3_split(ctx.h, 1 if per_channel else 0), "tdvp_set_stage3_split")
+
+
 def set_autotune(ctx, enable):
     _check(lib().tdvp_set_autotune(ctx.h, 1 if enable else 0), "tdvp_set_autotune")
 
@@ -398,7 +403,7 @@ class PsRun:
     """
 
     def __init__(self, params, sites, raw_mps, device=0, precision=FP64, kmax=20, tol=0.0,
-                 graph=True, fused=True, autotune=False):
+                 graph=True, fused=True, autotune=False, stage3_split=False):
         import torch
         self.torch = torch
         self.stream = torch.cuda.Stream(device=device)
@@ -422,6 +427,7 @@ class PsRun:
         self.stream.synchronize()
         set_graph(self.ctx, graph)
         set_fused(self.ctx, fused)
+        set_stage3_split(self.ctx, stage3_split)
         set_autotune(self.ctx, autotune)
         right_canonicalize(self.ctx, self.mps)
         envs_build(self.ctx, self.mps, self.mpo, self.envs)
@@ -533,7 +539,7 @@ class PsEnsemble:
     """
 
     def __init__(self, params_list, sites, raw_list, device=0, precision=FP64, kmax=20, tol=0.0,
-                 graph=True, stream=None, fused=True, autotune=False):
+                 graph=True, stream=None, fused=True, autotune=False, stage3_split=False):
         import torch
         self.torch = torch
         nb = len(params_list)
@@ -587,6 +593,7 @@ class PsEnsemble:
         self.ctx.reserve(nb * one)
         set_graph(self.ctx, graph)
         set_fused(self.ctx, fused)
+        set_stage3_split(self.ctx, stage3_split)
         set_autotune(self.ctx, autotune)
         for r in range(nb):
             _check(lib().tdvp_right_canonicalize(self.ctx.h, ctypes.byref(mps_arr[r])),
@@ -634,7 +641,7 @@ class DisorderEnsemble:
     """
 
     def __init__(self, members, sites, device=0, precision=FP64, kmax=20, tol=0.0, graph=True,
-                 fused=True, autotune=False, grouped=True):
+                 fused=True, autotune=False, grouped=True, stage3_split=False):
         import torch
         self.torch = torch
         classes = {}
@@ -647,7 +654,8 @@ class DisorderEnsemble:
         if not grouped:
             for M, rs in sorted(classes.items()):
                 e = PsEnsemble([p for _, p, _ in rs], sites, [raw for _, _, raw in rs], device, precision,
-                               kmax=kmax, tol=tol, graph=graph, fused=fused, autotune=autotune)
+                               kmax=kmax, tol=tol, graph=graph, fused=fused, autotune=autotune,
+                               stage3_split=stage3_split)
                 self.classes.append((M, [r for r, _, _ in rs], e))
             self.n_e = self.classes[0][2].n_e
             return
@@ -710,6 +718,7 @@ class DisorderEnsemble:
         self.ctx.reserve(b.value)
         set_graph(self.ctx, graph)
         set_fused(self.ctx, fused)
+        set_stage3_split(self.ctx, stage3_split)
         set_autotune(self.ctx, autotune)
         for q in range(nb):
             _check(lib().tdvp_right_canonicalize(self.ctx.h, ctypes.byref(mps_arr[q])), "tdvp_right_canonicalize")

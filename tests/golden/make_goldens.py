@@ -14,6 +14,12 @@ Targets (run one per process, e.g. ``python tests/golden/make_goldens.py c2``):
   c4_<M>    one static-disorder realisation per bond-dimension class
             M in {32, 64, 96, 128} (the first realisation of that class):
             10 steps
+  c3_cq, c4_96_cq, c4_128_cq
+            the same runs with the shifted Cholesky QR of the oracle in
+            place of Householder QR (10 / 6 steps): a second valid oracle
+            trajectory, whose distance from the first measures how much the
+            trajectory amplifies the choice of QR (the GPU factors the
+            larger site tensors by shifted Cholesky QR)
   c5        217-site chain, M = 256, dt = 1 fs: the first step
   lz_<name> Krylov propagator exp(z H) x at the full local sizes of the
             M = 128 and M = 256 chains (H[i] and the bond operator):
@@ -50,12 +56,12 @@ def _observe(m, Ws, sites, n_e):
     return (om.norm2(m), om.expectation_mpo(m, Ws).real, om.site_populations(m, sites, n_e))
 
 
-def _run_chain(p, sites, raw, tau, nsteps, kmax, record_every=1, log=None, save=None):
+def _run_chain(p, sites, raw, tau, nsteps, kmax, record_every=1, log=None, save=None, qr=om.qr_pos):
     """Oracle TDVP-PS run; observables at step 0 and every record_every steps.
     save(partial results) is called after every recorded step, so a long
-    run leaves a usable prefix if it is stopped."""
+    run leaves a usable prefix if it is stopped.  qr: the QR of eq:QR."""
     Ws, _ = model.mpo(p, sites)
-    m = om.right_canonicalize(raw)
+    m = om.right_canonicalize(raw, qr=qr)
     R = om.build_right_envs(m, Ws)
     steps, norms, energies, pops, ks = [], [], [], [], []
 
@@ -70,7 +76,7 @@ def _run_chain(p, sites, raw, tau, nsteps, kmax, record_every=1, log=None, save=
     t0 = time.time()
     for s in range(1, nsteps + 1):
         stats = {}
-        m, R, _ = ps.ps_step(m, Ws, R, tau, kmax=kmax, stats=stats)
+        m, R, _ = ps.ps_step(m, Ws, R, tau, kmax=kmax, stats=stats, qr=qr)
         ks.append(np.mean(stats["k"]))
         if s % record_every == 0 or s == nsteps:
             rec(s)
@@ -83,7 +89,7 @@ def _run_chain(p, sites, raw, tau, nsteps, kmax, record_every=1, log=None, save=
                 pops=np.array(pops), krylov_mean=np.array(ks))
 
 
-def _chain_target(name, wl, nsteps, realisation=None):
+def _chain_target(name, wl, nsteps, realisation=None, qr=om.qr_pos):
     if realisation is None:
         w = dict(WORKLOADS[wl])
         p, sites, _, _, raw, _ = workload(wl)
@@ -97,10 +103,11 @@ def _chain_target(name, wl, nsteps, realisation=None):
     meta = dict(target=name, workload=wl, realisation=realisation, M=Mb, eta=w.get("eta", 0.0),
                 phi_seed=w.get("phi_seed", 1), dt_fs=w["dt_fs"], kmax=w.get("kdim", 20),
                 nsteps=nsteps, shift=shift, energy="shifted <psi|H'|psi>",
+                qr="householder" if qr is om.qr_pos else "shifted cholesky qr3",
                 made_by="tests/golden/make_goldens.py (oracle only)")
     out = _run_chain(p, sites, raw, tau, nsteps, w.get("kdim", 20),
                      log=lambda s: print(name, s, flush=True),
-                     save=lambda part: _write(name, part, dict(meta, complete=False)))
+                     save=lambda part: _write(name, part, dict(meta, complete=False)), qr=qr)
     return out, dict(meta, complete=True)
 
 
@@ -174,6 +181,11 @@ def main():
         out, meta = _chain_target(t, "fmo7x10x8_M32", 500)
     elif t == "c3":
         out, meta = _chain_target(t, "fmo7x10x8_M128", 50)
+    elif t == "c3_cq":
+        out, meta = _chain_target(t, "fmo7x10x8_M128", 10, qr=om.qr_cholesky3)
+    elif t.startswith("c4_") and t.endswith("_cq"):
+        M = int(t[3:-3])
+        out, meta = _chain_target(t, "ensemble", 6, realisation=c4_realisation(M), qr=om.qr_cholesky3)
     elif t.startswith("c4_"):
         M = int(t[3:])
         out, meta = _chain_target(t, "ensemble", 10, realisation=c4_realisation(M))

@@ -41,6 +41,35 @@ def test_qr_identities():
     assert np.all(np.diag(R).real >= 0) and np.abs(np.diag(R).imag).max() == 0.0
 
 
+def test_cholesky_qr_is_the_unique_positive_diagonal_qr():
+    """Shifted Cholesky QR (three passes): orthonormal Q, A = Q R, R upper
+    triangular with positive real diagonal -- for full-rank A that
+    factorisation is unique, so it must equal the Householder one."""
+    A = random_complex((40, 12), 2)
+    Q, R = om.qr_cholesky3(A)
+    assert np.abs(Q.conj().T @ Q - np.eye(12)).max() < 1e-14
+    assert np.abs(Q @ R - A).max() < 1e-13
+    assert np.abs(np.tril(R, -1)).max() < 1e-15
+    assert np.all(np.diag(R).real > 0) and np.abs(np.diag(R).imag).max() < 1e-15
+    Qh, Rh = om.qr_pos(A)
+    assert np.abs(Q - Qh).max() < 1e-13 and np.abs(R - Rh).max() < 1e-13
+
+
+def test_cholesky_qr_ill_conditioned():
+    """Singular values down to 1e-12 |A| (condition far beyond 1/sqrt(u)):
+    still orthonormal to round-off and backward stable; the leading
+    columns (well separated from the tiny singular values) agree with
+    Householder."""
+    U, _ = np.linalg.qr(random_complex((60, 16), 4))
+    V, _ = np.linalg.qr(random_complex((16, 16), 5))
+    A = (U * np.logspace(0, -12, 16)[None, :]) @ V.conj().T
+    Q, R = om.qr_cholesky3(A)
+    assert np.abs(Q.conj().T @ Q - np.eye(16)).max() < 1e-13
+    assert np.abs(Q @ R - A).max() < 1e-14
+    Qh, _ = om.qr_pos(A)
+    assert np.abs(Q[:, 0] - Qh[:, 0]).max() < 1e-12
+
+
 def test_right_canonical_condition(small_chain):
     _, _, _, _, mps = small_chain
     for A in mps[1:]:
