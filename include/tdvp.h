@@ -203,7 +203,9 @@ tdvp_status tdvp_set_graph(tdvp_ctx *ctx, int enable);
 /* Kernel path of the local Lanczos solves (eq:tdvp2_C, eq:tdvp2_D).  With
  * enable != 0 (the default) a solve whose bond dimensions are small enough
  * (right bond dimension <= 64, MPO bonds <= 16, and the tiles of the
- * work-groups that share an output column fit in LDS) runs each Krylov step
+ * work-groups that share an output column fit in LDS) and whose batch has
+ * fewer than 256 output columns in all (right bond dimension times the
+ * number of instances solved together) runs each Krylov step
  * as two kernels: the fused H x with its projections, then the
  * orthogonalisation.  enable = 0 forces the general path (three contraction
  * kernels, projections, orthogonalisation) for every solve.  Both paths

@@ -394,14 +394,20 @@ tdvp_status apply_op(tdvp_ctx *c, const Layout &lay, const Op &op, const double2
 // instance cover the chip.  Fills everything except st, pp, U, j.
 // Measured on the 77-site chain: the fused step wins up to bond dimension
 // 64 (FP64 and FP32); at 128 the tiled GEMM path is faster, for H[i] and for
-// the bond operator alike.
+// the bond operator alike.  A batch whose output columns (Mr per instance)
+// already number 256 or more fills the chip with the general path's tiles:
+// on the disorder ensemble (FP32) the general path took 0.86x the kernel
+// time of the fused step for 15 instances of M = 32 and 0.54x for 12 of
+// M = 64.
 constexpr int FUSED_MAX_MR = 64;
 constexpr int FUSED_MAX_MR_BOND = 64;
+constexpr int FUSED_MAX_COLS = 256;
 
 bool fused_args(const tdvp_ctx *c, const Layout &lay, const Op &op, const Bi &b, HeffSmallArgs &a,
                 char *base = nullptr) {
   if (!base) base = c->ws;
   if (c->fused_off || op.Mr > (op.W ? FUSED_MAX_MR : FUSED_MAX_MR_BOND)) return false;
+  if ((int64_t)op.Mr * b.R >= FUSED_MAX_COLS) return false;
   if (!op.W && (op.Wl != op.Wr || op.d != 1)) return false;
   a = HeffSmallArgs{};
   a.L = op.L; a.R = op.R;
@@ -1484,9 +1490,10 @@ tdvp_status enqueue_steps_grouped(tdvp_ctx *ctx, std::vector<GroupRun> &gr, doub
 }
 
 // The groups of a grouped step in two lanes that run concurrently: groups
-// whose bond dimensions all take the fused small-bond Lanczos step (latency
-// bound) on the context stream, the others (contraction GEMMs, MFMA bound)
-// on the auxiliary stream, forked from and joined to the context stream
+// whose bond dimensions are all small (<= 64: latency-bound solves, on the
+// fused step for a small batch) on the context stream, the others
+// (contraction GEMMs, MFMA bound) on the auxiliary stream, forked from and
+// joined to the context stream
 // (in graph mode the two lanes become parallel branches of the graph).
 // Without profiling, the Krylov log or a second lane, one lane.
 tdvp_status enqueue_lanes(tdvp_ctx *ctx, std::vector<GroupRun> &gr, double dt, int nsteps, int kmax,

@@ -14,6 +14,7 @@ namespace tdvp {
 namespace {
 
 constexpr int MAXNZ = 1024;
+constexpr int WA_EPT = 8;   // outputs per thread and pass
 
 template <typename T> struct Cplx;
 template <> struct Cplx<double> { using type = double2; };
@@ -67,22 +68,50 @@ __device__ __forceinline__ void wapply_body(const WApplyArgs &p, const BlockXYZ 
   __syncthreads();
   const int nnz = nnz_s;
   const V *in = reinterpret_cast<const V *>(p.in) + (int64_t)ri * p.inst.a;
-  V *out = reinterpret_cast<V *>(p.out) + (int64_t)ri * p.inst.c;
-  const int64_t total = (int64_t)p.A * p.C;
-  for (int64_t e = (int64_t)blk.x * blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)blk.gx * blockDim.x) {
-    const int64_t a = e / p.C, c = e % p.C;
-    const V *ip = in + a * p.si_a + c * p.si_c;
-    T re = 0, im = 0;
-    for (int t = 0; t < nnz; ++t) {
-      const V v = ip[(int64_t)cw[t] * p.si_w + (int64_t)cs[t] * p.si_s];
-      re += cre[t] * v.x - cim[t] * v.y;
-      im += cre[t] * v.y + cim[t] * v.x;
+  V *out = reinterpret_cast<V *>(p.out) + (int64_t)ri * p.inst.c + (int64_t)wo * p.so_w + (int64_t)so * p.so_s;
+  const int total = p.A * p.C;   // < 2^31 (checked by the launchers)
+  // WA_EPT outputs per thread, 256 apart (coalesced): their input loads for
+  // one nonzero are issued together, and the compaction above is shared by
+  // 256 WA_EPT outputs.  Each output adds its terms in compaction order.
+  for (int e0 = blk.x * (256 * WA_EPT) + threadIdx.x; e0 < total; e0 += blk.gx * (256 * WA_EPT)) {
+    int64_t io[WA_EPT], oo[WA_EPT];
+    bool ok[WA_EPT];
+    T re[WA_EPT], im[WA_EPT];
+#pragma unroll
+    for (int u = 0; u < WA_EPT; ++u) {
+      const int e = e0 + 256 * u;
+      ok[u] = e < total;
+      const int a = ok[u] ? e / p.C : 0, c = ok[u] ? e - a * p.C : 0;
+      io[u] = (int64_t)a * p.si_a + (int64_t)c * p.si_c;
+      oo[u] = (int64_t)a * p.so_a + (int64_t)c * p.so_c;
+      re[u] = 0;
+      im[u] = 0;
     }
-    V o;
-    o.x = re;
-    o.y = im;
-    out[(int64_t)wo * p.so_w + (int64_t)so * p.so_s + a * p.so_a + c * p.so_c] = o;
+    for (int t = 0; t < nnz; ++t) {
+      const int64_t off = (int64_t)cw[t] * p.si_w + (int64_t)cs[t] * p.si_s;
+      const T wr = cre[t], wi = cim[t];
+      V v[WA_EPT];
+#pragma unroll
+      for (int u = 0; u < WA_EPT; ++u) {
+        v[u].x = 0;
+        v[u].y = 0;
+        if (ok[u]) v[u] = in[io[u] + off];
+      }
+#pragma unroll
+      for (int u = 0; u < WA_EPT; ++u) {
+        re[u] += wr * v[u].x - wi * v[u].y;
+        im[u] += wr * v[u].y + wi * v[u].x;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < WA_EPT; ++u) {
+      if (ok[u]) {
+        V o;
+        o.x = re[u];
+        o.y = im[u];
+        out[oo[u]] = o;
+      }
+    }
   }
 }
 
@@ -97,13 +126,14 @@ __global__ __launch_bounds__(256) void wapply_grouped_kernel(Grp<WApplyArgs> g) 
   wapply_body<T>(g.a[k], b);
 }
 
-// grid of one argument set: x covers the (a, c) outputs (at most 64
-// work-groups, grid-stride), y the output rows (wo, so), z the instances
+// grid of one argument set: x covers the (a, c) outputs (256 WA_EPT per
+// work-group, at most 64 work-groups, grid-stride), y the output rows
+// (wo, so), z the instances
 bool wapply_grid(const WApplyArgs &a, dim3 &grid) {
   const int Wout = a.w_in_right ? a.Wl : a.Wr;
   const int64_t total = (int64_t)a.A * a.C;
   if (total <= 0 || Wout <= 0 || a.inst.count <= 0) return false;
-  int gx = (int)((total + 255) / 256);
+  int gx = (int)((total + 256 * WA_EPT - 1) / (256 * WA_EPT));
   if (gx > 64) gx = 64;
   grid = dim3(gx, Wout * a.d, a.inst.count);
   return true;
@@ -116,7 +146,7 @@ hipError_t wapply_grouped(DType t, const WApplyArgs *a, int ng, hipStream_t s) {
   Grp<WApplyArgs> g;
   for (int k = 0; k < ng; ++k) {
     const int Win = a[k].w_in_right ? a[k].Wr : a[k].Wl;
-    if (Win * a[k].d > MAXNZ) return hipErrorInvalidValue;
+    if (Win * a[k].d > MAXNZ || (int64_t)a[k].A * a[k].C >= (1ll << 31)) return hipErrorInvalidValue;
     dim3 gr;
     if (wapply_grid(a[k], gr)) g.add(a[k], gr.x, gr.y, gr.z);
   }
@@ -131,7 +161,7 @@ hipError_t wapply_grouped(DType t, const WApplyArgs *a, int ng, hipStream_t s) {
 hipError_t wapply(DType t, const WApplyArgs &a, hipStream_t s) {
   const int Wout = a.w_in_right ? a.Wl : a.Wr;
   const int Win = a.w_in_right ? a.Wr : a.Wl;
-  if (Win * a.d > MAXNZ) return hipErrorInvalidValue;
+  if (Win * a.d > MAXNZ || (int64_t)a.A * a.C >= (1ll << 31)) return hipErrorInvalidValue;
   (void)Wout;
   dim3 grid;
   if (!wapply_grid(a, grid)) return hipSuccess;

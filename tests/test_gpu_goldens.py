@@ -32,8 +32,13 @@ cannot hide an error of the GPU path, applies at every time:
 
 * FP64: populations within max(1e-10, 30 x oracle QR spread) up to
   12 fs; later within max(1e-10, 30 x the larger spread);
-* mixed modes: populations within max(1e-5, 30 x oracle QR spread) up to
-  20 fs; later within max(1e-5, 30 x the larger spread);
+* mixed modes: the rounding of the mode itself (2^-24 relative for FP32,
+  2^-17 for split-BF16) is a perturbation the trajectory amplifies like
+  any other, so an FP64 run is started from the initial state with every
+  entry perturbed by that relative amount, and its distance from the FP64
+  run is a spread that applies at every time: populations within
+  max(1e-5, 30 x max(oracle QR spread, that spread)) up to 20 fs; later
+  also 30 x the GPU's FP64 spread;
 * norm and shifted energy (exact invariants of the method, not sensitive):
   FP64 1e-12 / 1e-10 relative to max(|E'|, 1 cm^-1) at every step.  Mixed
   modes: norm 1e-6; energy 1e-6 relative to the unshifted |E| = |E' + c|.
@@ -87,8 +92,10 @@ SPREAD_FACTOR = 30.0
 def _compare(tag, obs, g, row, prec, errs, t_fs=0.0, spread=0.0, qspread=0.0):
     """obs = [norm, energy + shift * norm, pops...] (GPU) against golden row;
     spread: largest population difference so far of the GPU's two FP64 runs;
-    qspread: that of the oracle's two QR runs (applies at every time: it
-    cannot hide an error of the GPU path)."""
+    qspread: spreads that apply at every time because they cannot hide an
+    error of the path under test -- the oracle's two QR runs and, for a
+    mixed mode, the FP64 run from a start perturbed at the mode's rounding
+    size."""
     dP = np.abs(obs[2:] - g["pops"][row]).max()
     dn = abs(obs[0] - g["norm"][row])
     dE = abs((obs[1] - _shift(g) * obs[0]) - g["energy"][row])
@@ -129,6 +136,24 @@ def _qr_spread(name):
             for i, st in enumerate(c["steps"]) if int(st) in rows}
 
 
+# relative size of one rounding of each mode's contraction arithmetic: the
+# perturbation given to the start of an FP64 run that measures how far the
+# trajectory carries errors of that size (split-BF16: two bf16 planes per
+# operand, 2^-17 relative)
+ROUNDING = {"fp32": 2.0 ** -24, "bf16x3": 2.0 ** -17}
+
+
+def _perturbed(raw, rel, seed=7):
+    """Every entry of every site tensor times (1 + rel xi), xi a seeded
+    complex normal: zeros (the sector structure) stay zero."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for A in raw:
+        xi = (rng.standard_normal(A.shape) + 1j * rng.standard_normal(A.shape)) / np.sqrt(2.0)
+        out.append(A * (1.0 + rel * xi))
+    return out
+
+
 def _run_vs_golden(name, wl, prec):
     """GPU run of workload wl in precision prec against the oracle's golden
     run, in the benchmark's launch configuration (step graph), with two FP64
@@ -146,6 +171,11 @@ def _run_vs_golden(name, wl, prec):
     a = tdvp.PsRun(p, sites, raw, 0, tdvp.FP64, kmax=kmax, graph=True, fused=True, autotune=at)
     b = tdvp.PsRun(p, sites, raw, 0, tdvp.FP64, kmax=kmax, graph=True, fused=False, autotune=at,
                    stage3_split=True)
+    runs = [run, a, b]
+    if prec != "fp64":   # FP64 from a start perturbed at the mode's rounding size
+        c = tdvp.PsRun(p, sites, _perturbed(raw, ROUNDING[prec]), 0, tdvp.FP64, kmax=kmax, graph=True,
+                       autotune=at)
+        runs.append(c)
     steps = [int(s) for s in g["steps"]]
     qsp = _qr_spread(name)
     errs = []
@@ -153,12 +183,14 @@ def _run_vs_golden(name, wl, prec):
     spread = qspread = 0.0
     for row, s in enumerate(steps):
         if s > done:
-            for r in (run, a, b):
+            for r in runs:
                 r.step(tau, s - done)
             done = s
         oa, ob = a.observe_host(), b.observe_host()
         spread = max(spread, float(np.abs(oa[2:] - ob[2:]).max()))
         qspread = max(qspread, qsp.get(s, 0.0))
+        if prec != "fp64":   # (an FP64 run: it cannot hide an error of the mixed path)
+            qspread = max(qspread, float(np.abs(c.observe_host()[2:] - oa[2:]).max()))
         _compare(f"{name}/{prec}", run.observe_host(), g, row, prec, errs, s * w["dt_fs"], spread, qspread)
     _report(f"{name} {prec}", errs)
     return errs
