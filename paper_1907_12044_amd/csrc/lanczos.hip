@@ -1136,9 +1136,14 @@ __global__ __launch_bounds__(WT_THREADS) void wtable_grouped_kernel(Grp<WtableAr
   wtable_body(a.W, a.rows, a.cap, a.sW, a.rowp, a.col, a.coef, a.wss, b);
 }
 
-// Work-groups of lz_dots: the element layout of lz_update (LU_E elements
-// per pass), so both kernels take the same grid.
-int dots_grid(int64_t n) { return upd_grid(n); }
+// Work-groups of lz_dots per instance: lz_update's grid, but for a batch of
+// `count` instances no more than give ~1024 work-groups in all.  Every
+// lz_update work-group adds all of lz_dots' partials, so a batch (which
+// fills the chip with fewer work-groups per instance) writes fewer of them.
+int dots_grid(int64_t n, int count) {
+  const int want = std::max(16, (1024 + std::max(count, 1) - 1) / std::max(count, 1));
+  return std::min(upd_grid(n), want);
+}
 
 }  // namespace
 
@@ -1152,7 +1157,7 @@ hipError_t lz_start(LzState *st, LzPartials *pp, const double2 *x, double2 *u0, 
 
 hipError_t lz_dots(LzState *st, LzPartials *pp, DType ty, const void *ypart, int P, int64_t pstride,
                    double2 *U, int64_t ldu, int j, int64_t n, const LzInst &in, hipStream_t s) {
-  const dim3 g(dots_grid(n), in.count), b(LZ_BLOCK);
+  const dim3 g(dots_grid(n, in.count), in.count), b(LZ_BLOCK);
 #define LZ_DOTS(T, JB)                                                                         \
   hipLaunchKernelGGL((lz_dots_kernel<T, JB>), g, b, 0, s, st, pp, (const T *)ypart, P, pstride, \
                      U, ldu, j, n, in)
@@ -1176,7 +1181,7 @@ hipError_t lz_dots(LzState *st, LzPartials *pp, DType ty, const void *ypart, int
 hipError_t lz_update(LzState *st, LzPartials *pp, double2 *U, int64_t ldu, int j, int64_t n, int Gd,
                      const double2 *Yp, int P, const LzInst &in, hipStream_t s) {
   const dim3 g(upd_grid(n), in.count), b(LZ_BLOCK);
-  if (Gd <= 0) Gd = dots_grid(n);
+  if (Gd <= 0) Gd = dots_grid(n, in.count);
   if (Yp && (P < 1 || P > HS_PMAX)) return hipErrorInvalidValue;
 #define LZ_UPD(JB) \
   hipLaunchKernelGGL((lz_update_kernel<JB>), g, b, 0, s, st, pp, U, ldu, j, n, Gd, Yp, P, in)
@@ -1264,7 +1269,7 @@ hipError_t lz_dots_grouped(DType ty, const LzDotsArgs *a, int ng, hipStream_t s)
   Grp<LzDotsArgs> g;
   for (int k = 0; k < ng; ++k) {
     if (a[k].j != a[0].j) return hipErrorInvalidValue;
-    g.add(a[k], dots_grid(a[k].n), a[k].in.count, 1);
+    g.add(a[k], dots_grid(a[k].n, a[k].in.count), a[k].in.count, 1);
   }
   if (g.ng == 0) return hipSuccess;
   const int j = a[0].j;
@@ -1293,7 +1298,7 @@ hipError_t lz_update_grouped(const LzUpdateArgs *a, int ng, hipStream_t s) {
   for (int k = 0; k < ng; ++k) {
     LzUpdateArgs ak = a[k];
     if (ak.j != a[0].j) return hipErrorInvalidValue;
-    if (ak.Gd <= 0) ak.Gd = dots_grid(ak.n);
+    if (ak.Gd <= 0) ak.Gd = dots_grid(ak.n, ak.in.count);
     if (ak.Yp && (ak.P < 1 || ak.P > HS_PMAX)) return hipErrorInvalidValue;
     g.add(ak, upd_grid(ak.n), ak.in.count, 1);
   }
