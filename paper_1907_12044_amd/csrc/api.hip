@@ -413,8 +413,8 @@ bool fused_args(const tdvp_ctx *c, const Layout &lay, const Op &op, const Bi &b,
   a.L = op.L; a.R = op.R;
   a.Ml = op.Ml; a.d = op.d; a.Mr = op.Mr; a.Wl = op.Wl; a.Wr = op.Wr;
   a.n = op.size();
-  a.Gprev = lz_grid(a.n);
-  a.Gw = lz_grid(a.n);
+  a.Gprev = lz_grid(a.n, b.R);
+  a.Gw = lz_grid(a.n, b.R);
   a.wss = b.ws; a.sL = op.sL; a.sR = op.sR;
   // P is chosen so that all instances together cover the chip: one chain
   // gets up to 8 parts per column, a large batch 1 (each part adds

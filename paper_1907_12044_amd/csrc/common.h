@@ -179,7 +179,7 @@ hipError_t lz_dots(LzState *st, LzPartials *pp, DType ty, const void *ypart, int
 // kernel also writes the |H u_j|^2 partials.
 hipError_t lz_update(LzState *st, LzPartials *pp, double2 *U, int64_t ldu, int j, int64_t n, int Gd,
                      const double2 *Yp, int P, const LzInst &in, hipStream_t s);
-int lz_grid(int64_t n);   // work-groups of the Lanczos vector kernels for an n-vector
+int lz_grid(int64_t n, int count);   // work-groups per instance of the Lanczos vector kernels
 
 // Argument sets of the Lanczos kernels for grouped launches (one per group;
 // every group of a launch is at the same Krylov index j).

@@ -252,11 +252,18 @@ __device__ bool close_step_finish(LzState *st, const StepPre &p, int j, int Gw, 
 
 
 constexpr int LU_E = 64;
-// Work-groups of lz_start and lz_update (one norm partial each): LU_E
-// elements per work-group and pass.
-__host__ __device__ inline int upd_grid(int64_t n) {
+// Work-groups per instance of lz_start, lz_update and lz_finish (the first
+// two write one norm partial each): LU_E elements per work-group and pass,
+// at most LZ_GRID, and for a batch of `count` instances no more than give
+// ~1024 work-groups in all (a batch fills the chip with fewer work-groups
+// per instance, and each runs more passes with the next pass's loads in
+// flight).  One instance: min(n / LU_E, LZ_GRID).
+__host__ __device__ inline int upd_grid(int64_t n, int count) {
   int64_t g = (n + LU_E - 1) / LU_E;
   if (g > LZ_GRID) g = LZ_GRID;
+  const int c = count > 1 ? count : 1;
+  const int64_t want = (1024 + c - 1) / c;
+  if (g > want) g = want < 16 ? 16 : want;
   if (g < 1) g = 1;
   return (int)g;
 }
@@ -332,7 +339,7 @@ __device__ __forceinline__ void lz_dots_body(LzState *st, LzPartials *pp, const 
   // the stop flag is loaded with the other inputs and tested before any write
   const int stopped = st->stop;
   StepPre pre;
-  close_step_load(st, pp, upd_grid(n), j, 0, pre);
+  close_step_load(st, pp, upd_grid(n, in.count), j, 0, pre);
   const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
   constexpr int NI = (JB + 3) / 4;        // basis vectors per wave
   constexpr int PR = 4;                   // parts of w held in registers (more: loaded after)
@@ -1136,21 +1143,17 @@ __global__ __launch_bounds__(WT_THREADS) void wtable_grouped_kernel(Grp<WtableAr
   wtable_body(a.W, a.rows, a.cap, a.sW, a.rowp, a.col, a.coef, a.wss, b);
 }
 
-// Work-groups of lz_dots per instance: lz_update's grid, but for a batch of
-// `count` instances no more than give ~1024 work-groups in all.  Every
-// lz_update work-group adds all of lz_dots' partials, so a batch (which
-// fills the chip with fewer work-groups per instance) writes fewer of them.
-int dots_grid(int64_t n, int count) {
-  const int want = std::max(16, (1024 + std::max(count, 1) - 1) / std::max(count, 1));
-  return std::min(upd_grid(n), want);
-}
+// Work-groups of lz_dots per instance: the grid of lz_update (every lz_update
+// work-group adds all of lz_dots' partials, so a batch, which takes fewer
+// work-groups per instance, also writes fewer of them).
+int dots_grid(int64_t n, int count) { return upd_grid(n, count); }
 
 }  // namespace
 
 hipError_t lz_start(LzState *st, LzPartials *pp, const double2 *x, double2 *u0, int64_t n,
                     double zr, double zi, double tol, int keff, int trows, int *nonfinite,
                     const LzInst &in, hipStream_t s) {
-  hipLaunchKernelGGL(lz_start_kernel, dim3(upd_grid(n), in.count), dim3(LZ_BLOCK), 0, s, st, pp, x,
+  hipLaunchKernelGGL(lz_start_kernel, dim3(upd_grid(n, in.count), in.count), dim3(LZ_BLOCK), 0, s, st, pp, x,
                      u0, n, zr, zi, tol, keff, trows, nonfinite, in);
   return hipGetLastError();
 }
@@ -1180,7 +1183,7 @@ hipError_t lz_dots(LzState *st, LzPartials *pp, DType ty, const void *ypart, int
 
 hipError_t lz_update(LzState *st, LzPartials *pp, double2 *U, int64_t ldu, int j, int64_t n, int Gd,
                      const double2 *Yp, int P, const LzInst &in, hipStream_t s) {
-  const dim3 g(upd_grid(n), in.count), b(LZ_BLOCK);
+  const dim3 g(upd_grid(n, in.count), in.count), b(LZ_BLOCK);
   if (Gd <= 0) Gd = dots_grid(n, in.count);
   if (Yp && (P < 1 || P > HS_PMAX)) return hipErrorInvalidValue;
 #define LZ_UPD(JB) \
@@ -1194,7 +1197,7 @@ hipError_t lz_update(LzState *st, LzPartials *pp, double2 *U, int64_t ldu, int j
   return hipGetLastError();
 }
 
-int lz_grid(int64_t n) { return upd_grid(n); }
+int lz_grid(int64_t n, int count) { return upd_grid(n, count); }
 
 size_t heff_small_lds(const HeffSmallArgs &a, int tm_bytes) {
   return HsLayout(a.Ml, a.d, a.Mr, a.Wl, a.Wr, a.nl, a.staged != 0, tm_bytes).total_b;
@@ -1258,7 +1261,7 @@ hipError_t wtable(const double2 *W, int Wl, int d, int Wr, int64_t sW, int *rowp
 hipError_t lz_start_grouped(const LzStartArgs *a, int ng, hipStream_t s) {
   if (ng < 1 || ng > GMAX) return hipErrorInvalidValue;
   Grp<LzStartArgs> g;
-  for (int k = 0; k < ng; ++k) g.add(a[k], upd_grid(a[k].n), a[k].in.count, 1);
+  for (int k = 0; k < ng; ++k) g.add(a[k], upd_grid(a[k].n, a[k].in.count), a[k].in.count, 1);
   if (g.ng == 0) return hipSuccess;
   hipLaunchKernelGGL(lz_start_grouped_kernel, dim3(g.blocks()), dim3(LZ_BLOCK), 0, s, g);
   return hipGetLastError();
@@ -1300,7 +1303,7 @@ hipError_t lz_update_grouped(const LzUpdateArgs *a, int ng, hipStream_t s) {
     if (ak.j != a[0].j) return hipErrorInvalidValue;
     if (ak.Gd <= 0) ak.Gd = dots_grid(ak.n, ak.in.count);
     if (ak.Yp && (ak.P < 1 || ak.P > HS_PMAX)) return hipErrorInvalidValue;
-    g.add(ak, upd_grid(ak.n), ak.in.count, 1);
+    g.add(ak, upd_grid(ak.n, ak.in.count), ak.in.count, 1);
   }
   if (g.ng == 0) return hipSuccess;
   const int j = a[0].j;
@@ -1322,7 +1325,7 @@ hipError_t lz_finish_grouped(const LzFinishArgs *a, int ng, hipStream_t s) {
   for (int k = 0; k < ng; ++k) {
     if (a[k].keff > KMAX) return hipErrorInvalidValue;
     kb = std::max(kb, a[k].keff);
-    g.add(a[k], upd_grid(a[k].n), a[k].in.count, 1);
+    g.add(a[k], upd_grid(a[k].n, a[k].in.count), a[k].in.count, 1);
   }
   if (g.ng == 0) return hipSuccess;
   const dim3 gr(g.blocks()), b(LZ_BLOCK);
@@ -1396,7 +1399,7 @@ hipError_t wtable_grouped(const WtableArgs *a, int ng, hipStream_t s) {
 hipError_t lz_finish(LzState *st, const double2 *U, int64_t ldu, int64_t n, int keff, double2 *y,
                      int32_t *k_used, int trows, const LzInst &in, hipStream_t s) {
   if (keff > KMAX) return hipErrorInvalidValue;
-  const dim3 g(upd_grid(n), in.count), b(LZ_BLOCK);
+  const dim3 g(upd_grid(n, in.count), in.count), b(LZ_BLOCK);
 #define LZ_FIN(KB) \
   hipLaunchKernelGGL((lz_finish_kernel<KB>), g, b, 0, s, st, U, ldu, n, keff, y, k_used, trows, in)
   if (keff <= 4) LZ_FIN(4);
