@@ -210,6 +210,7 @@ __global__ __launch_bounds__(256, sizeof(TM) == 8 ? 2 : 1) void cgemm_grouped_ke
 // element k % 8; B[k][j] in lane j + 16 (k / 8), element k % 8; the result as
 // for v_mfma_f32_16x16x4_f32.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ void split_bf16(float x, __bf16 &hi, __bf16 &lo) {
   hi = (__bf16)x;
@@ -260,52 +261,143 @@ __device__ __forceinline__ void cgemm_bf3_tile(const GemmArgs &g, const BlockXYZ
     }
 
   constexpr int NA = BM * BK / 256, NB = BK * BN / 256;
+  // Operands contiguous in k (rows of A with sak = 1, columns of B with
+  // sbk = 1) are staged four consecutive k per thread when K is a multiple
+  // of 4: each plane then gets one 8-byte LDS store per four values instead
+  // of four 2-byte stores.  Otherwise one element per thread.  (The same
+  // values land in LDS either way.)
+  const bool a_vec = a_kfast && K % 4 == 0;
+  const bool b_vec = !b_nfast && K % 4 == 0;
   VA ra[NA];
   VB rb[NB];
   auto load_tiles = [&](int k0) {
+    if (a_vec) {
 #pragma unroll
-    for (int q = 0; q < NA; ++q) {
-      const int e = tid + 256 * q;
-      int mm, kk;
-      if (a_kfast) { kk = e % BK; mm = e / BK; } else { mm = e % BM; kk = e / BM; }
-      const int gm = bm0 + mm, gk = k0 + kk;
-      ra[q].x = 0;
-      ra[q].y = 0;
-      if (gm < M && gk < K) ra[q] = A[(int64_t)gm * g.sam + (int64_t)gk * g.sak];
+      for (int q = 0; q < NA / 4; ++q) {
+        const int c = tid + 256 * q, mm = c / (BK / 4), kk = 4 * (c % (BK / 4));
+        const int gm = bm0 + mm, gk = k0 + kk;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          ra[4 * q + u].x = 0;
+          ra[4 * q + u].y = 0;
+        }
+        if (gm < M && gk < K) {
+          const VA *src = A + (int64_t)gm * g.sam + gk;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) ra[4 * q + u] = src[u];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < NA; ++q) {
+        const int e = tid + 256 * q;
+        int mm, kk;
+        if (a_kfast) { kk = e % BK; mm = e / BK; } else { mm = e % BM; kk = e / BM; }
+        const int gm = bm0 + mm, gk = k0 + kk;
+        ra[q].x = 0;
+        ra[q].y = 0;
+        if (gm < M && gk < K) ra[q] = A[(int64_t)gm * g.sam + (int64_t)gk * g.sak];
+      }
     }
+    if (b_vec) {
 #pragma unroll
-    for (int q = 0; q < NB; ++q) {
-      const int e = tid + 256 * q;
-      int nn, kk;
-      if (b_nfast) { nn = e % BN; kk = e / BN; } else { kk = e % BK; nn = e / BK; }
-      const int gn = bn0 + nn, gk = k0 + kk;
-      rb[q].x = 0;
-      rb[q].y = 0;
-      if (gn < N && gk < K) rb[q] = B[(int64_t)gk * g.sbk + (int64_t)gn * g.sbn];
+      for (int q = 0; q < NB / 4; ++q) {
+        const int c = tid + 256 * q, nn = c / (BK / 4), kk = 4 * (c % (BK / 4));
+        const int gn = bn0 + nn, gk = k0 + kk;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          rb[4 * q + u].x = 0;
+          rb[4 * q + u].y = 0;
+        }
+        if (gn < N && gk < K) {
+          const VB *src = B + (int64_t)gn * g.sbn + gk;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) rb[4 * q + u] = src[u];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        const int e = tid + 256 * q;
+        int nn, kk;
+        if (b_nfast) { nn = e % BN; kk = e / BN; } else { kk = e % BK; nn = e / BK; }
+        const int gn = bn0 + nn, gk = k0 + kk;
+        rb[q].x = 0;
+        rb[q].y = 0;
+        if (gn < N && gk < K) rb[q] = B[(int64_t)gk * g.sbk + (int64_t)gn * g.sbn];
+      }
     }
   };
   load_tiles(0);
   const int fr = lane & 15, fk = 8 * (lane >> 4);
   for (int k0 = 0; k0 < K; k0 += BK) {
+    if (a_vec) {
 #pragma unroll
-    for (int q = 0; q < NA; ++q) {
-      const int e = tid + 256 * q;
-      int mm, kk;
-      if (a_kfast) { kk = e % BK; mm = e / BK; } else { mm = e % BM; kk = e / BM; }
-      const float xr = (float)ra[q].x, xi = sa * (float)ra[q].y;
-      split_bf16(xr, As[0][mm][kk], As[1][mm][kk]);
-      split_bf16(xi, As[2][mm][kk], As[3][mm][kk]);
-      split_bf16(xr + xi, As[4][mm][kk], As[5][mm][kk]);
+      for (int q = 0; q < NA / 4; ++q) {
+        const int c = tid + 256 * q, mm = c / (BK / 4), kk = 4 * (c % (BK / 4));
+        bf16x4 h[6];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const float xr = (float)ra[4 * q + u].x, xi = sa * (float)ra[4 * q + u].y;
+          __bf16 hi, lo;
+          split_bf16(xr, hi, lo);
+          h[0][u] = hi;
+          h[1][u] = lo;
+          split_bf16(xi, hi, lo);
+          h[2][u] = hi;
+          h[3][u] = lo;
+          split_bf16(xr + xi, hi, lo);
+          h[4][u] = hi;
+          h[5][u] = lo;
+        }
+#pragma unroll
+        for (int pl = 0; pl < 6; ++pl) *reinterpret_cast<bf16x4 *>(&As[pl][mm][kk]) = h[pl];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < NA; ++q) {
+        const int e = tid + 256 * q;
+        int mm, kk;
+        if (a_kfast) { kk = e % BK; mm = e / BK; } else { mm = e % BM; kk = e / BM; }
+        const float xr = (float)ra[q].x, xi = sa * (float)ra[q].y;
+        split_bf16(xr, As[0][mm][kk], As[1][mm][kk]);
+        split_bf16(xi, As[2][mm][kk], As[3][mm][kk]);
+        split_bf16(xr + xi, As[4][mm][kk], As[5][mm][kk]);
+      }
     }
+    if (b_vec) {
 #pragma unroll
-    for (int q = 0; q < NB; ++q) {
-      const int e = tid + 256 * q;
-      int nn, kk;
-      if (b_nfast) { nn = e % BN; kk = e / BN; } else { kk = e % BK; nn = e / BK; }
-      const float yr = (float)rb[q].x, yi = sb * (float)rb[q].y;
-      split_bf16(yr, Bs[0][nn][kk], Bs[1][nn][kk]);
-      split_bf16(yi, Bs[2][nn][kk], Bs[3][nn][kk]);
-      split_bf16(yr + yi, Bs[4][nn][kk], Bs[5][nn][kk]);
+      for (int q = 0; q < NB / 4; ++q) {
+        const int c = tid + 256 * q, nn = c / (BK / 4), kk = 4 * (c % (BK / 4));
+        bf16x4 h[6];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const float yr = (float)rb[4 * q + u].x, yi = sb * (float)rb[4 * q + u].y;
+          __bf16 hi, lo;
+          split_bf16(yr, hi, lo);
+          h[0][u] = hi;
+          h[1][u] = lo;
+          split_bf16(yi, hi, lo);
+          h[2][u] = hi;
+          h[3][u] = lo;
+          split_bf16(yr + yi, hi, lo);
+          h[4][u] = hi;
+          h[5][u] = lo;
+        }
+#pragma unroll
+        for (int pl = 0; pl < 6; ++pl) *reinterpret_cast<bf16x4 *>(&Bs[pl][nn][kk]) = h[pl];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        const int e = tid + 256 * q;
+        int nn, kk;
+        if (b_nfast) { nn = e % BN; kk = e / BN; } else { kk = e % BK; nn = e / BK; }
+        const float yr = (float)rb[q].x, yi = sb * (float)rb[q].y;
+        split_bf16(yr, Bs[0][nn][kk], Bs[1][nn][kk]);
+        split_bf16(yi, Bs[2][nn][kk], Bs[3][nn][kk]);
+        split_bf16(yr + yi, Bs[4][nn][kk], Bs[5][nn][kk]);
+      }
     }
     __syncthreads();
     if (k0 + BK < K) load_tiles(k0 + BK);
