@@ -52,7 +52,14 @@ cannot hide an error of the GPU path, applies at every time:
   terms are of the size of the unshifted energy (site energies and
   vibrational zero-point energies, ~0.2 hartree here), so its rounding is
   a few u |E| however small the shifted value E' (~3e-4 hartree) is;
-  measured: FP32 up to 1.5e-7 |E|, split-BF16 1.1e-6 |E|.  Printed.
+  measured: FP32 up to 1.5e-7 |E| over the first 20 fs, split-BF16 1.1e-6
+  |E|.  With FP32 environments the conserved quantity of the local
+  propagations moves by rounding at every environment update, and the
+  energy drifts about linearly with the step count, in the same direction
+  on both kernel paths: 4.2e-8 |E| per step (FP32) and 2.4e-7 |E| per
+  step (split-BF16) on the 500-step M = 32 run (2.1e-5 |E| = 0.9 cm^-1 and
+  1.2e-4 |E| at step 500).  The bar adds 1e-7 |E| (FP32) / 6e-7 |E|
+  (split-BF16) per step.  Printed.
 """
 
 import json
@@ -96,6 +103,9 @@ MIXED_BAR = {"fp32": 1e-5, "bf16x3": 5e-5}
 # unit round-off of a mode's contractions (split-BF16: 16 mantissa bits kept
 # per operand in its two bf16 planes)
 UNIT = {"fp32": 2.0 ** -24, "bf16x3": 2.0 ** -17}
+# allowance for the mixed modes' energy drift per step, relative to |E|
+# (measured on the 500-step M = 32 run: 4.2e-8 FP32, 2.4e-7 split-BF16)
+ENERGY_DRIFT = {"fp32": 1e-7, "bf16x3": 6e-7}
 SPREAD_FACTOR = 30.0
 
 
@@ -122,7 +132,8 @@ def _compare(tag, obs, g, row, prec, errs, t_fs=0.0, spread=0.0, qspread=0.0):
         ptol = max(bar, SPREAD_FACTOR * (qspread if t_fs <= MIXED_HORIZON_FS else max(spread, qspread)))
         assert dP < ptol, (tag, row, dP, ptol)
         assert dn < 1e-6, (tag, row, dn)
-        assert dE < 16.0 * UNIT[prec] * escale, (tag, row, dE)
+        etol = (16.0 * UNIT[prec] + ENERGY_DRIFT[prec] * int(g["steps"][row])) * escale
+        assert dE < etol, (tag, row, dE, etol)
 
 
 def _report(tag, errs):
@@ -130,7 +141,7 @@ def _report(tag, errs):
     print(f"{tag}: max |dP| {max(e[1] for e in errs):.2e} (step {worst[0]}), "
           f"max |dnorm| {max(e[2] for e in errs):.2e}, max |dE|/scale {max(e[3] for e in errs):.2e}")
     for e in errs[:: max(1, len(errs) // 12)] + [errs[-1]]:
-        print(f"    step {e[0]:4d}: |dP| {e[1]:.1e}  spread {e[4]:.1e}")
+        print(f"    step {e[0]:4d}: |dP| {e[1]:.1e}  spread {e[4]:.1e}  |dE|/scale {e[3]:.1e}")
 
 
 def _qr_spread(name):
@@ -171,6 +182,7 @@ def _run_vs_golden(name, wl, prec):
     steps = [int(s) for s in g["steps"]]
     qsp = _qr_spread(name)
     errs = []
+    fails = []
     done = 0
     spread = qspread = 0.0
     for row, s in enumerate(steps):
@@ -184,8 +196,14 @@ def _run_vs_golden(name, wl, prec):
         if prec != "fp64":
             spread = max(spread, float(np.abs(c.observe_host()[2:] - obs[2:]).max()))
         qspread = max(qspread, qsp.get(s, 0.0))
-        _compare(f"{name}/{prec}", obs, g, row, prec, errs, s * w["dt_fs"], spread, qspread)
+        try:
+            _compare(f"{name}/{prec}", obs, g, row, prec, errs, s * w["dt_fs"], spread, qspread)
+        except AssertionError as e:   # finish the run, so that the report shows every step
+            fails.append(str(e))
     _report(f"{name} {prec}", errs)
+    for f in fails[:10]:
+        print("    FAIL", f)
+    assert not fails, f"{len(fails)} of {len(steps)} rows out of tolerance, first: {fails[0]}"
     return errs
 
 
