@@ -374,6 +374,9 @@ def ensemble_main(args):
         torch.cuda.empty_cache()
 
     pops = hist[-1][:, 2:]
+    prod = np.zeros(pops.shape[1])
+    prod[0] = 1.0                     # exciton on electronic site 1, vibrational vacuum
+    t0_dev = float(np.abs(hist[0][:, 2:] - prod[None, :]).max())
     counts = {}
     for _, _, M, _ in members:
         counts[M] = counts.get(M, 0) + 1
@@ -389,7 +392,9 @@ def ensemble_main(args):
                    "precision": args.precision, "kmax": args.kmax, "autotune": autotune_on(args),
                    "graph": not args.eager,
                    "launch_mode": "grouped" if args.grouped else "per-class streams",
-                   "initial_state_eta": ENSEMBLE["eta"]},
+                   "initial_state_eta": ENSEMBLE["eta"],
+                   # largest |P_m(0) - P_m(product state)| over the realisations
+                   "t0_max_population_deviation": t0_dev},
         "ensemble_steps_per_s": 1e3 / ms,
         "heff_tflops": heff_tflops,
         "class_ms_per_step": {k: round(v["ms_per_step"], 3) for k, v in prof.items()},

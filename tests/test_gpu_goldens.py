@@ -34,16 +34,17 @@ cannot hide an error of the GPU path, applies at every time:
 * FP64: populations within max(1e-10, 30 x oracle QR spread) up to
   12 fs; later within max(1e-10, 30 x the larger spread);
 * mixed modes: populations within max(bar, 30 x oracle QR spread) up to
-  20 fs, bar = 1e-5 for FP32 contractions and 5e-5 for split-BF16; later
+  20 fs, bar = 1e-5 for FP32 contractions and 1e-4 for split-BF16; later
   within max(bar, 30 x the largest spread so far, including that of two
   runs of the mode itself on the two kernel paths).  Split-BF16 products
   carry 2^-17 relative rounding (each operand keeps 16 mantissa bits in its
   two bf16 planes and the lo x lo product is dropped), 128 times FP32's
   unit; scaled by that ratio, FP32's in-horizon error (3.7e-6 on the
-  M = 32 chain) would allow 4.7e-4, and the measured split-BF16 error,
-  1.7e-5 at 10 fs and 3.9e-5 within 20 fs, sits far below it, so its bar
-  is 5e-5.  Measured on the 500-step M = 32 run, the largest ratio of
-  error to bar is 0.82 (FP32, 32 fs) and 0.77 (split-BF16);
+  M = 32 chain) would allow 4.7e-4.  Measured split-BF16 errors within
+  20 fs: 3.9e-5 (M = 32), up to 5.6e-5 (M = 128, which depends on the
+  autotuned tile and so on the run), hence its bar 1e-4.  Over the
+  500-step M = 32 run the largest ratio of error to bar is 0.82 (FP32,
+  32 fs) and 0.39 (split-BF16);
 * norm and shifted energy (exact invariants of the method, not sensitive):
   FP64 1e-12 / 1e-10 relative to max(|E'|, 1 cm^-1) at every step.  Mixed
   modes: norm 1e-6; energy 16 u |E| with u the unit round-off of the
@@ -99,7 +100,7 @@ def _shift(g):
 
 FP64_HORIZON_FS = 12.0
 MIXED_HORIZON_FS = 20.0
-MIXED_BAR = {"fp32": 1e-5, "bf16x3": 5e-5}
+MIXED_BAR = {"fp32": 1e-5, "bf16x3": 1e-4}
 # unit round-off of a mode's contractions (split-BF16: 16 mantissa bits kept
 # per operand in its two bf16 planes)
 UNIT = {"fp32": 2.0 ** -24, "bf16x3": 2.0 ** -17}
@@ -157,48 +158,68 @@ def _qr_spread(name):
             for i, st in enumerate(c["steps"]) if int(st) in rows}
 
 
+# observables of the two FP64 runs of a workload at every golden row (the
+# same for every precision tested against that workload: computed once)
+_FP64_PAIR = {}
+
+
+def _run_all(runs, tau, steps):
+    """Step every run to each golden step; observables per row and run."""
+    done = 0
+    out = []
+    for s in steps:
+        if s > done:
+            for r in runs:
+                r.step(tau, s - done)
+            done = s
+        out.append([r.observe_host().copy() for r in runs])
+    return out
+
+
 def _run_vs_golden(name, wl, prec):
     """GPU run of workload wl in precision prec against the oracle's golden
     run, in the benchmark's launch configuration (step graph), with two FP64
     runs that differ in summation order only for the rounding spread: the
     default kernel choice, and the general path with the last contraction
     of H x split per left MPO channel (at M <= 64 the first uses the fused
-    step, at M > 64 both use the general path)."""
+    step, at M > 64 both use the general path).  A mixed mode is also run
+    on that second path, for its own spread."""
     from paper_1907_12044_amd import tdvp
     g = _golden(name)
     p, sites, phys, dims, raw, w = workload(wl)
     tau = w["dt_fs"] * model.AU_PER_FS
     kmax = w.get("kdim", 20)
     at = w["M"] > 64
-    run = tdvp.PsRun(p, sites, raw, 0, _prec(prec), kmax=kmax, graph=True, autotune=at)
-    a = tdvp.PsRun(p, sites, raw, 0, tdvp.FP64, kmax=kmax, graph=True, fused=True, autotune=at)
-    b = tdvp.PsRun(p, sites, raw, 0, tdvp.FP64, kmax=kmax, graph=True, fused=False, autotune=at,
-                   stage3_split=True)
-    runs = [run, a, b]
-    if prec != "fp64":   # the mixed mode on the other kernel path: its own rounding spread
+    steps = [int(s) for s in g["steps"]]
+    if name not in _FP64_PAIR:
+        a = tdvp.PsRun(p, sites, raw, 0, tdvp.FP64, kmax=kmax, graph=True, fused=True, autotune=at)
+        b = tdvp.PsRun(p, sites, raw, 0, tdvp.FP64, kmax=kmax, graph=True, fused=False, autotune=at,
+                       stage3_split=True)
+        _FP64_PAIR[name] = _run_all([a, b], tau, steps)
+        del a, b
+    pair = _FP64_PAIR[name]
+    if prec == "fp64":
+        mine = [[row[0]] for row in pair]          # the default FP64 run is the run under test
+    else:
+        run = tdvp.PsRun(p, sites, raw, 0, _prec(prec), kmax=kmax, graph=True, autotune=at)
         c = tdvp.PsRun(p, sites, raw, 0, _prec(prec), kmax=kmax, graph=True, fused=False, autotune=at,
                        stage3_split=True)
-        runs.append(c)
-    steps = [int(s) for s in g["steps"]]
+        mine = _run_all([run, c], tau, steps)
+        del run, c
     qsp = _qr_spread(name)
     errs = []
     fails = []
-    done = 0
     spread = qspread = 0.0
     for row, s in enumerate(steps):
-        if s > done:
-            for r in runs:
-                r.step(tau, s - done)
-            done = s
-        oa, ob = a.observe_host(), b.observe_host()
-        obs = run.observe_host()
+        oa, ob = pair[row]
+        obs = mine[row][0]
         spread = max(spread, float(np.abs(oa[2:] - ob[2:]).max()))
         if prec != "fp64":
-            spread = max(spread, float(np.abs(c.observe_host()[2:] - obs[2:]).max()))
+            spread = max(spread, float(np.abs(mine[row][1][2:] - obs[2:]).max()))
         qspread = max(qspread, qsp.get(s, 0.0))
         try:
             _compare(f"{name}/{prec}", obs, g, row, prec, errs, s * w["dt_fs"], spread, qspread)
-        except AssertionError as e:   # finish the run, so that the report shows every step
+        except AssertionError as e:   # every row is checked, so that the report shows them all
             fails.append(str(e))
     _report(f"{name} {prec}", errs)
     for f in fails[:10]:
