@@ -223,7 +223,8 @@ hipError_t gemm_t(tdvp_ctx *c, DType ta, DType tb, DType tc, const GemmArgs &g0,
   GemmArgs g = g0;
   if (c->autotune) {
     const std::vector<int64_t> key = {0, ta, tb, tc, g.M, g.N, g.K, g.batch, g.inst.count,
-                                      g.sak == 1, g.sbn == 1, g.scn == 1, (int64_t)c->prec};
+                                      g.sak == 1, g.sbn == 1, g.scn == 1, (int64_t)c->prec,
+                                      g.lzU != nullptr};
     auto it = c->tuned.find(key);
     if (it != c->tuned.end()) {
       g.tile = it->second;
@@ -377,14 +378,32 @@ OpLaunch op_args(const tdvp_ctx *c, char *base, const Layout &lay, const Op &op,
 }
 
 // y_parts[p] (p < Wl) with sum_p y_parts[p] = Op x.  x is c128 with instance stride sx.
+// With lzU set (a Krylov step of run_lanczos whose stage 3 runs in one
+// part): stage 3 writes H x to basis vector lzj + 1 instead, with the
+// projection partials (GEMM epilogue).
 tdvp_status apply_op(tdvp_ctx *c, const Layout &lay, const Op &op, const double2 *x, int64_t sx,
-                     const int *skip, const Bi &b) {
+                     const int *skip, const Bi &b, double2 *lzU = nullptr, LzPartials *lzpp = nullptr,
+                     int lzj = 0) {
   const DType et = env_type(c), ct = et;
-  const OpLaunch L = op_args(c, c->ws, lay, op, x, sx, skip, b);
+  OpLaunch L = op_args(c, c->ws, lay, op, x, sx, skip, b);
+  if (lzU) {
+    L.g3.lzU = lzU;
+    L.g3.lzpp = lzpp;
+    L.g3.lzj = lzj;
+    L.g3.lzwss = b.ws;
+  }
   CK(gemm_t(c, F64, et, ct, L.g1, TDVP_PROF_GEMM_HEFF));
   if (L.has_w) CK(wapply_t(c, ct, L.w));
   CK(gemm_t(c, et, ct, ct, L.g3, TDVP_PROF_GEMM_HEFF));
   return TDVP_OK;
+}
+
+// May the Krylov steps of `op` (stage 3 in P parts) take the projection
+// epilogue: one part, not split-BF16 (its GEMM has no epilogue), and few
+// enough output tiles for one partial each.
+bool lz_epilogue_ok(const tdvp_ctx *c, const Op &op) {
+  return op.parts() == 1 && c->prec != TDVP_BF16X3 &&
+         (int64_t)((op.Ml + 31) / 32) * ((op.d * op.Mr + 31) / 32) <= LZ_PARTS;
 }
 
 // Arguments of the fused Lanczos step (heff_small) for Op, if it applies:
@@ -461,6 +480,7 @@ tdvp_status run_lanczos(tdvp_ctx *c, const Layout &lay, const Op &op_in, double 
   const double vb = 16.0 * n * b.R;
   HeffSmallArgs fa;
   const bool fused = fused_args(c, lay, op, b, fa);
+  const bool epi = !fused && lz_epilogue_ok(c, op);
   const int trows = fused ? op.Ml * op.d : 0;
   if (fused && op.W)
     CK(wtable((const double2 *)op.W, op.Wl, op.d, op.Wr, op.sW, const_cast<int *>(fa.row),
@@ -488,6 +508,17 @@ tdvp_status run_lanczos(tdvp_ctx *c, const Layout &lay, const Op &op_in, double 
       continue;
     }
     c->tune_now = j == 0;   // the first Krylov step is never stopped
+    if (epi) {
+      // stage 3 writes H u_j to U[j+1] with the projection partials; the
+      // update kernel closes step j - 1 itself
+      const tdvp_status so = apply_op(c, lay, op, U + (int64_t)j * n, b.wsel(16), &st->stop, b, U, pp, j);
+      c->tune_now = 0;
+      CS(so);
+      id = prof_begin(c, TDVP_PROF_LZ_UPDATE);
+      CK(lz_update(st, pp, U, n, j, n, -1, nullptr, 0, li, c->stream, 1));
+      prof_end(c, id, 8.0 * (j + 1) * n * b.R, 2.0 * vb + (j + 1) * vb);
+      continue;
+    }
     const tdvp_status so = apply_op(c, lay, op, U + (int64_t)j * n, b.wsel(16), &st->stop, b);
     c->tune_now = 0;
     CS(so);

@@ -86,6 +86,8 @@ __device__ __forceinline__ BlockXYZ native_block() {
 // with arbitrary element strides (in complex elements) and optional
 // conjugation.  Batches b = 0..batch-1.  Optional `skip`: if non-null and
 // *skip != 0 the kernel returns at once (used to predicate Krylov steps).
+struct LzPartials;
+
 struct GemmArgs {
   const void *A; const void *B; void *C;
   int M, N, K, batch;
@@ -97,6 +99,17 @@ struct GemmArgs {
   int tile;                  // 0: by problem size; 32: 32x32 tiles; 64, 96, 128: 64x64 tiles with
                              // K steps of 16, 32, 64 (the last two in FP32 arithmetic only)
   int mode;                  // 0: C = op(A) op(B); 1: C = C - op(A) op(B); 2: C = -op(A) op(B)
+  // Lanczos projection epilogue (lzU != NULL; mode 0, batch 1, C row-major
+  // with scn = 1, so that element (m, n) is entry m N + n of a length-M N
+  // vector): C is not written; instead w = op(A) op(B) goes in FP64 to basis
+  // vector lzj + 1 of lzU (vectors of length M N, consecutive), and every
+  // work-group writes its partials <u_i, w> (i <= lzj) and |w|^2 to slot
+  // (tile index) of lzpp->dot / lzpp->w2, and the tile count to
+  // lzpp->ndot.  lzU and lzpp step by lzwss bytes per instance.
+  double2 *lzU;
+  LzPartials *lzpp;
+  int lzj;
+  int64_t lzwss;
 };
 
 hipError_t cgemm(DType ta, DType tb, DType tc, const GemmArgs &g, hipStream_t s);
@@ -155,8 +168,13 @@ constexpr size_t CTX_HEADER_BYTES = 256;
 // array it writes.
 struct LzPartials {
   double nrm[LZ_GRID];
+  // second buffer of the norm partials for lz_update with close: step k
+  // writes (k odd ? nrm : nrm_odd) and closes step k - 1 from the other
+  // buffer, so no work-group overwrites partials that another still reads
+  double nrm_odd[LZ_GRID];
   double2 dot[KMAX + 1][LZ_PARTS];   // <u_i, H u_j> partials, [i][work-group]
   double w2[LZ_PARTS];          // |H u_j|^2 partials (lz_dots, or lz_update on the fused path)
+  int ndot;                     // partials written by a GEMM projection epilogue
 };
 
 // Lanczos kernels over `inst.count` instances: instance r uses the state,
@@ -174,11 +192,14 @@ hipError_t lz_start(LzState *st, LzPartials *pp, const double2 *x, double2 *u0, 
 hipError_t lz_dots(LzState *st, LzPartials *pp, DType ty, const void *ypart, int P, int64_t pstride,
                    double2 *U, int64_t ldu, int j, int64_t n, const LzInst &in, hipStream_t s);
 // Gd: number of per-work-group dot partials written by the kernel before
-// (0 = the lz_dots grid for n).  Yp != NULL (fused path): H u_j is the sum
-// of the P partial vectors Yp + p n (instance stride in.wss bytes), and the
-// kernel also writes the |H u_j|^2 partials.
+// (0 = the lz_dots grid for n; < 0: pp->ndot, written by a GEMM projection
+// epilogue).  Yp != NULL (fused path): H u_j is the sum of the P partial
+// vectors Yp + p n (instance stride in.wss bytes), and the kernel also
+// writes the |H u_j|^2 partials.  close != 0 (after a GEMM projection
+// epilogue, which has no step close of its own): the kernel first closes
+// step j - 1 as lz_dots does (beta, scale_j, stop tests).
 hipError_t lz_update(LzState *st, LzPartials *pp, double2 *U, int64_t ldu, int j, int64_t n, int Gd,
-                     const double2 *Yp, int P, const LzInst &in, hipStream_t s);
+                     const double2 *Yp, int P, const LzInst &in, hipStream_t s, int close = 0);
 int lz_grid(int64_t n, int count);   // work-groups per instance of the Lanczos vector kernels
 
 // Argument sets of the Lanczos kernels for grouped launches (one per group;
@@ -193,7 +214,7 @@ struct LzDotsArgs {
 };
 struct LzUpdateArgs {
   LzState *st; LzPartials *pp; double2 *U; int64_t ldu; int j; int64_t n; int Gd;
-  const double2 *Yp; int P; LzInst in;
+  const double2 *Yp; int P; LzInst in; int close = 0;
 };
 struct LzFinishArgs {
   LzState *st; const double2 *U; int64_t ldu; int64_t n; int keff; double2 *y; int32_t *k_used;

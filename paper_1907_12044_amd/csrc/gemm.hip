@@ -13,6 +13,8 @@
 // the 16x16x4 shapes: A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k;
 // result D[i][j] in lane j + 16 (i / 4), register i % 4 for f32, but in lane
 // j + 16 (i % 4), register i / 4 for f64.
+#include <type_traits>
+
 #include "common.h"
 
 namespace tdvp {
@@ -37,10 +39,114 @@ __device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// Lanczos projection epilogue of a stage-3 GEMM (GemmArgs::lzU): the tile's
+// results w (rounded to the output type TC, as a stored C would be) go to
+// basis vector j + 1 in FP64, and the work-group's partials <u_i, w>
+// (i <= j) and |w|^2 to its slot (tile index) of the partial arrays.  The
+// basis elements of the tile are read four vectors at a time, each wave
+// sums its lanes and wave 0 adds the four waves in order (fixed order: the
+// partials do not depend on timing).
+template <typename TC, typename TM, int BM, int BN, typename AccT>
+__device__ __forceinline__ void lz_epilogue(const GemmArgs &g, const BlockXYZ &blk, int ri,
+                                            const AccT (&p1)[BM / 32][BN / 32],
+                                            const AccT (&p2)[BM / 32][BN / 32],
+                                            const AccT (&p3)[BM / 32][BN / 32]) {
+  constexpr int TI = BM / 32, TJ = BN / 32;
+  constexpr bool IS_F64 = sizeof(TM) == 8;
+  constexpr int NE = TI * TJ * 4;          // results per lane
+  __shared__ double red[4][8];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm0 = (wave >> 1) * (BM / 2), wn0 = (wave & 1) * (BN / 2);
+  const int M = g.M, N = g.N;
+  const int64_t n = (int64_t)M * N;
+  double2 *U = reinterpret_cast<double2 *>(reinterpret_cast<char *>(g.lzU) + (int64_t)ri * g.lzwss);
+  LzPartials *pp = reinterpret_cast<LzPartials *>(reinterpret_cast<char *>(g.lzpp) + (int64_t)ri * g.lzwss);
+  const int jj = g.lzj;
+  const int slot = blk.y * blk.gx + blk.x;
+  double wr[NE], wi[NE];
+  int64_t ei[NE];
+  bool ok[NE];
+  double w2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int q = (i * TJ + j) * 4 + r;
+        const int rr = IS_F64 ? (4 * r + (lane >> 4)) : (4 * (lane >> 4) + r);
+        const int row = blk.y * BM + wm0 + i * 16 + rr;
+        const int col = blk.x * BN + wn0 + j * 16 + (lane & 15);
+        ok[q] = row < M && col < N;
+        ei[q] = (int64_t)row * N + col;
+        const TC re = (TC)(p1[i][j][r] - p2[i][j][r]), im = (TC)(p3[i][j][r] - p1[i][j][r] - p2[i][j][r]);
+        wr[q] = ok[q] ? (double)re : 0.0;
+        wi[q] = ok[q] ? (double)im : 0.0;
+        if (ok[q]) U[(int64_t)(jj + 1) * n + ei[q]] = make_double2(wr[q], wi[q]);
+        w2 += wr[q] * wr[q] + wi[q] * wi[q];
+      }
+  auto wsum = [](double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+  };
+  for (int i0 = 0; i0 <= jj; i0 += 4) {
+    double dr[4], di[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      dr[t] = 0.0;
+      di[t] = 0.0;
+      const int i = i0 + t;
+      if (i <= jj) {
+        const double2 *ui = U + (int64_t)i * n;
+        double2 u[NE];
+#pragma unroll
+        for (int q = 0; q < NE; ++q) u[q] = ok[q] ? ui[ei[q]] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < NE; ++q) {
+          dr[t] += u[q].x * wr[q] + u[q].y * wi[q];
+          di[t] += u[q].x * wi[q] - u[q].y * wr[q];
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      dr[t] = wsum(dr[t]);
+      di[t] = wsum(di[t]);
+    }
+    __syncthreads();   // (red is reused by the next group of four)
+    if (lane == 0) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        red[wave][2 * t] = dr[t];
+        red[wave][2 * t + 1] = di[t];
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < 4 && i0 + (int)threadIdx.x <= jj) {
+      const int t = threadIdx.x;
+      double a = 0.0, b = 0.0;
+      for (int w = 0; w < 4; ++w) {
+        a += red[w][2 * t];
+        b += red[w][2 * t + 1];
+      }
+      pp->dot[i0 + t][slot] = make_double2(a, b);
+    }
+  }
+  w2 = wsum(w2);
+  __syncthreads();
+  if (lane == 0) red[wave][0] = w2;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    pp->w2[slot] = red[0][0] + red[1][0] + red[2][0] + red[3][0];
+    if (slot == 0) pp->ndot = blk.gx * blk.gy;
+  }
+}
+
 // FP64 arithmetic: at least two waves per SIMD (registers capped at 256
 // per lane, the accumulators then stay in the architectural registers; the
 // uncapped 64x64 tile took ~390 and ran one wave per SIMD, 22 % slower).
-template <typename TA, typename TB, typename TC, typename TM, int BM, int BN, int BK>
+template <typename TA, typename TB, typename TC, typename TM, int BM, int BN, int BK, bool LZ = false>
 __device__ __forceinline__ void cgemm_tile(const GemmArgs &g, const BlockXYZ &blk) {
   const int bz = blk.z % g.batch;           // batch index
   const int ri = blk.z / g.batch;           // instance index
@@ -157,6 +263,10 @@ __device__ __forceinline__ void cgemm_tile(const GemmArgs &g, const BlockXYZ &bl
     __syncthreads();
   }
 
+  if (LZ) {
+    lz_epilogue<TC, TM, BM, BN>(g, blk, ri, p1, p2, p3);
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < TI; ++i)
 #pragma unroll
@@ -189,6 +299,11 @@ __device__ __forceinline__ void cgemm_tile(const GemmArgs &g, const BlockXYZ &bl
 template <typename TA, typename TB, typename TC, typename TM, int BM, int BN, int BK>
 __global__ __launch_bounds__(256, sizeof(TM) == 8 ? 2 : 1) void cgemm_kernel(GemmArgs g) {
   cgemm_tile<TA, TB, TC, TM, BM, BN, BK>(g, native_block());
+}
+// with the Lanczos projection epilogue
+template <typename TA, typename TB, typename TC, typename TM, int BM, int BN, int BK>
+__global__ __launch_bounds__(256, sizeof(TM) == 8 ? 2 : 1) void cgemm_lz_kernel(GemmArgs g) {
+  cgemm_tile<TA, TB, TC, TM, BM, BN, BK, true>(g, native_block());
 }
 template <typename TA, typename TB, typename TC, typename TM, int BM, int BN, int BK>
 __global__ __launch_bounds__(256, sizeof(TM) == 8 ? 2 : 1) void cgemm_grouped_kernel(Grp<GemmArgs> gg) {
@@ -473,12 +588,30 @@ hipError_t launch_bf3(const GemmArgs &g, hipStream_t s) {
 template <typename TA, typename TB, typename TC, typename TM>
 hipError_t launch(const GemmArgs &g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.inst.count <= 0) return hipSuccess;
+  if (g.lzU) {
+    // the projection epilogue: C = A B for one batch, row-major, at most
+    // LZ_PARTS tiles of the smallest shape, same element types throughout
+    constexpr bool same = std::is_same<TA, TB>::value && std::is_same<TB, TC>::value &&
+                          std::is_same<TC, TM>::value;
+    if (!same || g.mode != 0 || g.batch != 1 || g.scn != 1 || g.scm != g.N || !g.lzpp ||
+        (int64_t)((g.M + 31) / 32) * ((g.N + 31) / 32) > LZ_PARTS || g.lzj < 0 || g.lzj >= KMAX)
+      return hipErrorInvalidValue;
+    // 32 x 32 tiles only (the epilogue holds a lane's four results and their
+    // basis elements; the 64 x 64 tile would hold sixteen)
+    if constexpr (same) {
+      dim3 grid((g.N + 31) / 32, (g.M + 31) / 32, g.inst.count);
+      hipLaunchKernelGGL((cgemm_lz_kernel<TA, TB, TC, TM, 32, 32, 32>), grid, dim3(256), 0, s, g);
+    }
+    return hipGetLastError();
+  }
   const int nz = g.batch * g.inst.count;
   // the tile shape depends on one instance's problem only, so a batched
   // launch computes every instance exactly as a single launch would.
   // tile 64: 64x64 with K steps of 16; 96 / 128: 64x64 with K steps of 32 /
   // 64 (FP32 arithmetic only: fewer, longer steps hide more load latency
   // when K is short); 32: 32x32 with K steps of 32.
+#define GEMM_LAUNCH(BM_, BN_, BK_) \
+  hipLaunchKernelGGL((cgemm_kernel<TA, TB, TC, TM, BM_, BN_, BK_>), grid, dim3(256), 0, s, g)
   const int64_t tiles64 = (int64_t)((g.M + 63) / 64) * ((g.N + 63) / 64) * g.batch;
   constexpr bool F32M = sizeof(TM) == 4;
   int tile = g.tile;
@@ -486,18 +619,19 @@ hipError_t launch(const GemmArgs &g, hipStream_t s) {
   if (!F32M && tile > 64) tile = 64;
   if (F32M && tile == 96) {
     dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, nz);
-    hipLaunchKernelGGL((cgemm_kernel<TA, TB, TC, TM, 64, 64, F32M ? 32 : 16>), grid, dim3(256), 0, s, g);
+    GEMM_LAUNCH(64, 64, F32M ? 32 : 16);
   } else if (F32M && tile == 128) {
     dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, nz);
-    hipLaunchKernelGGL((cgemm_kernel<TA, TB, TC, TM, 64, 64, F32M ? 64 : 16>), grid, dim3(256), 0, s, g);
+    GEMM_LAUNCH(64, 64, F32M ? 64 : 16);
   } else if (tile == 64) {
     dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, nz);
-    hipLaunchKernelGGL((cgemm_kernel<TA, TB, TC, TM, 64, 64, 16>), grid, dim3(256), 0, s, g);
+    GEMM_LAUNCH(64, 64, 16);
   } else {
     // small problems: 32 x 32 tiles, K in steps of 32 (one LDS phase for K <= 32)
     dim3 grid((g.N + 31) / 32, (g.M + 31) / 32, nz);
-    hipLaunchKernelGGL((cgemm_kernel<TA, TB, TC, TM, 32, 32, 32>), grid, dim3(256), 0, s, g);
+    GEMM_LAUNCH(32, 32, 32);
   }
+#undef GEMM_LAUNCH
   return hipGetLastError();
 }
 
@@ -549,6 +683,8 @@ hipError_t launch_grouped(const GemmArgs *g, int ng, bool bf3, hipStream_t s) {
 
 hipError_t cgemm_grouped(DType ta, DType tb, DType tc, const GemmArgs *g, int ng, int bf3, hipStream_t s) {
   if (ng < 1 || ng > GMAX) return hipErrorInvalidValue;
+  for (int k = 0; k < ng; ++k)
+    if (g[k].lzU) return hipErrorInvalidValue;   // (no projection epilogue in grouped launches)
   if (bf3) {
     if (tc != F32) return hipErrorInvalidValue;
     for (int k = 0; k < ng; ++k)
@@ -568,7 +704,7 @@ hipError_t cgemm_grouped(DType ta, DType tb, DType tc, const GemmArgs *g, int ng
 }
 
 hipError_t cgemm_bf3(DType ta, DType tb, DType tc, const GemmArgs &g, hipStream_t s) {
-  if (tc != F32 || g.mode != 0) return hipErrorInvalidValue;
+  if (tc != F32 || g.mode != 0 || g.lzU) return hipErrorInvalidValue;
   if (ta == F64 && tb == F32) return launch_bf3<double, float, float>(g, s);
   if (ta == F32 && tb == F64) return launch_bf3<float, double, float>(g, s);
   if (ta == F32 && tb == F32) return launch_bf3<float, float, float>(g, s);

@@ -163,7 +163,9 @@ struct StepPre {
   int keff;
 };
 __device__ __forceinline__ void close_step_load(const LzState *st, const LzPartials *pp, int Gprev,
-                                                int j, int Gw, StepPre &p) {
+                                                int j, int Gw, StepPre &p,
+                                                const double *nrm = nullptr) {
+  if (!nrm) nrm = pp->nrm;
 #pragma unroll
   for (int q = 0; q < SP_Q; ++q) p.nr[q] = p.w2[q] = 0.0;
   p.aw = p.sprev = p.tol = 0.0;
@@ -172,7 +174,7 @@ __device__ __forceinline__ void close_step_load(const LzState *st, const LzParti
 #pragma unroll
     for (int q = 0; q < SP_Q; ++q) {
       const int b = threadIdx.x + 64 * q;
-      if (b < Gprev) p.nr[q] = pp->nrm[b];
+      if (b < Gprev) p.nr[q] = nrm[b];
       if (j > 0 && b < Gw) p.w2[q] = pp->w2[b];
     }
     if (threadIdx.x == 0) {
@@ -186,7 +188,8 @@ __device__ __forceinline__ void close_step_load(const LzState *st, const LzParti
   }
 }
 
-__device__ bool close_step_finish(LzState *st, const StepPre &p, int j, int Gw, int bx) {
+__device__ bool close_step_finish(LzState *st, const StepPre &p, int j, int Gw, int bx,
+                                  double *scale_out = nullptr) {
   __shared__ int stop_s;
   __shared__ double nrm_s, aw_s, tol_s;
   __shared__ double coefr[KMAX], coefi[KMAX];
@@ -226,6 +229,7 @@ __device__ bool close_step_finish(LzState *st, const StepPre &p, int j, int Gw, 
         st->scale[j] = 1.0 / nv;
       }
     }
+    if (scale_out) *scale_out = stop ? 0.0 : 1.0 / nv;   // (shared; read after the barrier below)
     stop_s = stop;
   }
   __syncthreads();
@@ -440,7 +444,7 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_dots_grouped_kernel(Grp<LzDotsArg
 template <int JB>
 __device__ __forceinline__ void lz_update_body(LzState *st, LzPartials *pp, double2 *U, int64_t ldu,
                                                int j, int64_t n, int Gd, const double2 *Yp, int P,
-                                               LzInst in, const BlockXYZ &blk) {
+                                               LzInst in, const BlockXYZ &blk, int close = 0) {
   {
     const int64_t wo = (int64_t)blk.y * in.wss;
     st = shift_bytes(st, wo);
@@ -480,7 +484,18 @@ __device__ __forceinline__ void lz_update_body(LzState *st, LzPartials *pp, doub
     }                                                                                      \
   } while (0)
   if (b0 < n) LZ_UPDATE_LOAD(b0 + lane);
-  const double sj = st->scale[j];
+  if (Gd < 0) Gd = pp->ndot;
+  double sj;
+  if (close) {
+    // close step j - 1 here (the projections came from a GEMM epilogue)
+    __shared__ double sj_s;
+    StepPre pre;
+    close_step_load(st, pp, upd_grid(n, in.count), j, 0, pre, ((j - 1) & 1) ? pp->nrm : pp->nrm_odd);
+    if (stopped || close_step_finish(st, pre, j, 0, blk.x, &sj_s)) return;   // (synchronises)
+    sj = sj_s;
+  } else {
+    sj = st->scale[j];
+  }
   // Reduce the Gd dot partials of the previous kernel: LPI lanes per basis
   // index i (256 / JB rounded down to a power of two; lane l adds partials
   // l, l + LPI, ...), then a fixed tree over the LPI lanes.
@@ -505,7 +520,8 @@ __device__ __forceinline__ void lz_update_body(LzState *st, LzPartials *pp, doub
     }
     if (stopped) return;   // (the same value in every thread)
     if (l8 == 0 && i <= j) {
-      const double si = st->scale[i];
+      // scale_j: this kernel's own close (WG 0 writes it to st concurrently)
+      const double si = i == j ? sj : st->scale[i];
       const double sc = si * sj;
       cr[i] = a * sc * si;      // c_i scale_i
       ci[i] = b * sc * si;
@@ -567,7 +583,8 @@ __device__ __forceinline__ void lz_update_body(LzState *st, LzPartials *pp, doub
   s2 = block_sum(s2, sh);
   if (Yp) sw = block_sum(sw, sh + 4);
   if (threadIdx.x == 0) {
-    pp->nrm[blk.x] = s2;
+    if (close) (j & 1 ? pp->nrm : pp->nrm_odd)[blk.x] = s2;
+    else pp->nrm[blk.x] = s2;
     if (Yp) pp->w2[blk.x] = sw;
   }
 }
@@ -577,15 +594,15 @@ __global__ __launch_bounds__(LZ_BLOCK) void lz_update_kernel(LzState *st, LzPart
                                                              double2 *U, int64_t ldu, int j,
                                                              int64_t n, int Gd,
                                                              const double2 *Yp, int P,
-                                                             LzInst in) {
-  lz_update_body<JB>(st, pp, U, ldu, j, n, Gd, Yp, P, in, native_block());
+                                                             LzInst in, int close) {
+  lz_update_body<JB>(st, pp, U, ldu, j, n, Gd, Yp, P, in, native_block(), close);
 }
 template <int JB>
 __global__ __launch_bounds__(LZ_BLOCK) void lz_update_grouped_kernel(Grp<LzUpdateArgs> g) {
   int k;
   const BlockXYZ b = g.locate(blockIdx.x, k);
   const LzUpdateArgs &a = g.a[k];
-  lz_update_body<JB>(a.st, a.pp, a.U, a.ldu, a.j, a.n, a.Gd, a.Yp, a.P, a.in, b);
+  lz_update_body<JB>(a.st, a.pp, a.U, a.ldu, a.j, a.n, a.Gd, a.Yp, a.P, a.in, b, a.close);
 }
 
 // y = |x| sum_i [exp(z T_k) e_1]_i v_i with k = the final basis size (keff
@@ -1182,12 +1199,12 @@ hipError_t lz_dots(LzState *st, LzPartials *pp, DType ty, const void *ypart, int
 }
 
 hipError_t lz_update(LzState *st, LzPartials *pp, double2 *U, int64_t ldu, int j, int64_t n, int Gd,
-                     const double2 *Yp, int P, const LzInst &in, hipStream_t s) {
+                     const double2 *Yp, int P, const LzInst &in, hipStream_t s, int close) {
   const dim3 g(upd_grid(n, in.count), in.count), b(LZ_BLOCK);
-  if (Gd <= 0) Gd = dots_grid(n, in.count);
+  if (Gd == 0) Gd = dots_grid(n, in.count);
   if (Yp && (P < 1 || P > HS_PMAX)) return hipErrorInvalidValue;
 #define LZ_UPD(JB) \
-  hipLaunchKernelGGL((lz_update_kernel<JB>), g, b, 0, s, st, pp, U, ldu, j, n, Gd, Yp, P, in)
+  hipLaunchKernelGGL((lz_update_kernel<JB>), g, b, 0, s, st, pp, U, ldu, j, n, Gd, Yp, P, in, close)
   if (j < 4) LZ_UPD(4);
   else if (j < 8) LZ_UPD(8);
   else if (j < 16) LZ_UPD(16);
@@ -1301,7 +1318,7 @@ hipError_t lz_update_grouped(const LzUpdateArgs *a, int ng, hipStream_t s) {
   for (int k = 0; k < ng; ++k) {
     LzUpdateArgs ak = a[k];
     if (ak.j != a[0].j) return hipErrorInvalidValue;
-    if (ak.Gd <= 0) ak.Gd = dots_grid(ak.n, ak.in.count);
+    if (ak.Gd == 0) ak.Gd = dots_grid(ak.n, ak.in.count);
     if (ak.Yp && (ak.P < 1 || ak.P > HS_PMAX)) return hipErrorInvalidValue;
     g.add(ak, upd_grid(ak.n, ak.in.count), ak.in.count, 1);
   }

@@ -266,6 +266,12 @@ def test_disorder_ensemble_one_realisation_per_class(prec):
     for e in {id(ens): ens, id(a): a, id(b): b}.values():
         e.step(tau, 5)
     obs, oa, ob = ens.observe_host(), a.observe_host(), b.observe_host()
+    # every realisation, not only the compared ones: the norm is kept by
+    # the FP64 Krylov and QR arithmetic, and the populations of the
+    # one-exciton sector add up to it
+    for o in (obs, oa, ob):
+        assert np.abs(o[:, 0] - 1.0).max() < 1e-9, np.abs(o[:, 0] - 1.0).max()
+        assert np.abs(o[:, 2:].sum(1) - o[:, 0]).max() < (1e-12 if o is not obs or prec == "fp64" else 1e-6)
     for M in (32, 64, 96, 128):
         g = _golden(f"c4_{M}")
         r = json.loads(str(g["meta"]))["realisation"]
