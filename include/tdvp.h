@@ -214,10 +214,11 @@ tdvp_status tdvp_set_fused(tdvp_ctx *ctx, int enable);
 
 /* Split of the last contraction of H[i] x on the general path (the sum over
  * the pairs (w_l, l) of the left MPO channel and the left bond index,
- * eq:tdvp1_h).  per_channel = 0 (the default): the sum runs in as few equal
- * parts as give the launch about four 32 x 32 output tiles per compute unit
- * (one part when the batch alone fills the chip); per_channel != 0: one part
- * per left MPO channel.  The parts are added by the projection kernel.  Both
+ * eq:tdvp1_h).  per_channel = 0 (the default): one part for a batch of 8
+ * or more instances (the projections then run in the GEMM's epilogue),
+ * otherwise as few equal parts as give the launch about four 32 x 32
+ * output tiles per compute unit; per_channel != 0: one part per left MPO
+ * channel.  The parts are added by the projection kernel.  Both
  * settings compute the same quantity; results differ by rounding order
  * only. */
 tdvp_status tdvp_set_stage3_split(tdvp_ctx *ctx, int per_channel);
