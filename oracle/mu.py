@@ -20,19 +20,23 @@ Right-hand side at a given state:
 4. i dC_{N-1}/dt = H[N-1] C_{N-1} (eq:tdvp1_C).
 
 The coupled equations are integrated by the adaptive Dormand-Prince 5(4)
-method (scipy.integrate.solve_ivp, "RK45"), as in the paper's VMF runs.
+method (scipy.integrate.solve_ivp, "RK45"), as in the paper's VMF runs, or
+by the second-order constant-mean-field scheme (mu_cmf_step, below).
 Canonicality is not re-imposed during the integration.
 
 Pins: at full bond dimension and full Schmidt rank the TDVP equations are
 exact, so MU must follow exp(-iHt)psi (tests).  Agreement with TDVP-PS at
 truncated bond dimension is stated by the paper only qualitatively: parity
-unpinned, tolerance from measurement.
+unpinned, tolerance from measurement.  CMF: second-order convergence in tau
+to the VMF solution at truncated bond dimension and to exp(-iHt)psi at full
+bond dimension; norm and gauge kept to the integrator's tolerance (tests).
 """
 
 from __future__ import annotations
 
 import numpy as np
 import scipy.integrate
+import scipy.linalg
 
 from .mps import qr_pos, env_left, env_right, heff, ones_env
 
@@ -49,8 +53,15 @@ def left_canonicalize(mps):
     return m
 
 
-def mu_rhs(mps, Ws, eps=1e-10):
-    """d/dt of every site tensor (list) for the left-canonical state ``mps``."""
+def mu_fields(mps, Ws, eps=1e-10):
+    """The mean fields of every site at the state ``mps`` (steps 1-3 above).
+
+    Entry i < N-1 is (Lenv_i, Renv_{i+1}, D_i, P_i) with P_i = V Lam~^{-1} U^H
+    the regularised inverse factor of eq:tdvp1_mu_L; entry N-1 is
+    (Lenv_{N-1}, ones, None, None).  Everything here depends on the state
+    outside site i only through the environments and on the sites right of
+    i through D_i: the quantities the constant-mean-field scheme holds fixed.
+    """
     n = len(mps)
     L = [None] * (n + 1)
     L[0] = ones_env()
@@ -70,21 +81,35 @@ def mu_rhs(mps, Ws, eps=1e-10):
     Renv[n] = ones_env()
     for i in range(n - 1, 0, -1):
         Renv[i] = env_right(Renv[i + 1], Rt[i], Ws[i])
-    out = [None] * n
     se = np.sqrt(eps)
+    fields = []
     for i in range(n - 1):
-        A = mps[i]
-        ml, d, mr = A.shape
         U, lam, Vh = np.linalg.svd(D[i])
         lam_t = lam + se * np.exp(-lam / se)
-        C = np.einsum("lsk,kr->lsr", A, D[i])
-        G = heff(L[i], Ws[i], Renv[i + 1], C).reshape(ml * d, mr)
-        X = G @ Vh.conj().T @ np.diag(1.0 / lam_t) @ U.conj().T
-        Am = A.reshape(ml * d, mr)
-        X = X - Am @ (Am.conj().T @ X)
-        out[i] = (-1j * X).reshape(ml, d, mr)
-    out[n - 1] = -1j * heff(L[n - 1], Ws[n - 1], Renv[n], mps[n - 1])
-    return out
+        P = Vh.conj().T @ np.diag(1.0 / lam_t) @ U.conj().T
+        fields.append((L[i], Renv[i + 1], D[i], P))
+    fields.append((L[n - 1], Renv[n], None, None))
+    return fields
+
+
+def site_rhs(A, W, field):
+    """d/dt of one site tensor with its mean field held fixed (step 3 or 4)."""
+    Lenv, Renv, D, P = field
+    if D is None:
+        return -1j * heff(Lenv, W, Renv, A)
+    ml, d, mr = A.shape
+    C = np.einsum("lsk,kr->lsr", A, D)
+    G = heff(Lenv, W, Renv, C).reshape(ml * d, mr)
+    X = G @ P
+    Am = A.reshape(ml * d, mr)
+    X = X - Am @ (Am.conj().T @ X)
+    return (-1j * X).reshape(ml, d, mr)
+
+
+def mu_rhs(mps, Ws, eps=1e-10):
+    """d/dt of every site tensor (list) for the left-canonical state ``mps``."""
+    fields = mu_fields(mps, Ws, eps)
+    return [site_rhs(A, W, f) for A, W, f in zip(mps, Ws, fields)]
 
 
 def _pack(mps):
@@ -118,3 +143,60 @@ def mu_evolve(mps, Ws, t_final, eps=1e-10, rtol=1e-5, atol=1e-8, t_eval=None, ma
     final = _unpack(sol.y[:, -1], shapes)
     snaps = [_unpack(sol.y[:, k], shapes) for k in range(sol.y.shape[1])] if t_eval is not None else []
     return final, snaps, {"nfev": sol.nfev}
+
+
+# ---------------------------------------------------------------------------
+# Constant mean field, second order (Sec. II.A.2, the CMF paragraph after
+# eq:tdvp1_L_cano).  The mean fields of a site (its environments, and the
+# bond matrix with its regularised inverse, i.e. H[i] and S[i+1:N]) are held
+# fixed while the site tensor alone is integrated; each site's equation is
+# then independent of the others.  Midpoint scheme: the fields of the state
+# at t carry every site to t + tau/2; the fields of that midpoint state then
+# carry every site of the state at t to t + tau.  The site tensors L_i obey
+# a nonlinear equation (through the projector built from L_i itself) and are
+# integrated by RK45; the centre obeys a linear one and is propagated by the
+# exponential of its frozen effective Hamiltonian, which the paper computes
+# by Krylov and this oracle computes exactly (a dense matrix exponential).
+
+def _frozen_center(C, W, field, h):
+    """exp(-i h H[N-1]) C with H[N-1] built from the frozen left environment."""
+    Lenv, Renv, _, _ = field
+    n = C.size
+    Hm = np.empty((n, n), dtype=np.complex128)
+    for k in range(n):
+        e = np.zeros(n, dtype=np.complex128)
+        e[k] = 1.0
+        Hm[:, k] = heff(Lenv, W, Renv, e.reshape(C.shape)).reshape(-1)
+    return (scipy.linalg.expm(-1j * h * Hm) @ C.reshape(-1)).reshape(C.shape)
+
+
+def cmf_propagate(mps, Ws, fields, h, rtol=1e-10, atol=1e-12):
+    """Every site carried over time h with the given frozen mean fields."""
+    out = []
+    n = len(mps)
+    for i in range(n - 1):
+        shape = mps[i].shape
+
+        def f(t, y, W=Ws[i], fl=fields[i], shape=shape):
+            return site_rhs(y.reshape(shape), W, fl).reshape(-1)
+
+        sol = scipy.integrate.solve_ivp(f, (0.0, h), mps[i].reshape(-1).astype(np.complex128),
+                                        method="RK45", rtol=rtol, atol=atol)
+        if not sol.success:
+            raise RuntimeError(sol.message)
+        out.append(sol.y[:, -1].reshape(shape))
+    out.append(_frozen_center(mps[n - 1], Ws[n - 1], fields[n - 1], h))
+    return out
+
+
+def mu_cmf_step(mps, Ws, tau, eps=1e-10, rtol=1e-10, atol=1e-12):
+    """One second-order CMF step of length tau (midpoint mean fields)."""
+    half = cmf_propagate(mps, Ws, mu_fields(mps, Ws, eps), 0.5 * tau, rtol, atol)
+    return cmf_propagate(mps, Ws, mu_fields(half, Ws, eps), tau, rtol, atol)
+
+
+def mu_cmf_evolve(mps, Ws, tau, nsteps, eps=1e-10, rtol=1e-10, atol=1e-12):
+    m = [A.astype(np.complex128) for A in mps]
+    for _ in range(nsteps):
+        m = mu_cmf_step(m, Ws, tau, eps, rtol, atol)
+    return m

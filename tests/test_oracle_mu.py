@@ -148,3 +148,71 @@ def test_mu_rhs_regularised_direction_scales_as_inverse_sqrt_eps():
     ratio = np.linalg.norm(b @ U[:, k]) / np.linalg.norm(a @ U[:, k])
     assert ratio == pytest.approx(10.0, rel=1e-3)
     assert np.linalg.norm(b @ U[:, big]) == pytest.approx(np.linalg.norm(a @ U[:, big]), rel=1e-9)
+
+
+# --- constant mean field, second order (midpoint) --------------------------
+
+def _cmf_case():
+    p = draw_params(3, 1, 4, seed=0)
+    sites = chain_sites(p)
+    Ws, _ = model.mpo(p, sites)
+    m0 = mu.left_canonicalize(initial_mps_raw(p, 4, 1e-1, 1))
+    return p, sites, Ws, m0
+
+
+def test_cmf_is_second_order_in_tau():
+    """At truncated bond dimension the CMF steps converge to the solution of
+    the same equations of motion integrated with live mean fields (VMF,
+    tight tolerance) at second order in tau, as the paper reports for its
+    CMF runs (error slope 2 against tau).  The same schedule with the mean
+    fields of the step's start state held over the whole step (a first-order
+    scheme) converges at first order only, so the test tells the midpoint
+    fields from a mistaken freeze."""
+    _, _, Ws, m0 = _cmf_case()
+    T = 10 * model.AU_PER_FS
+    mf, _, _ = mu.mu_evolve(m0, Ws, T, eps=1e-10, rtol=1e-11, atol=1e-13)
+    ref = om.mps_to_dense(mf)
+    errs, errs1 = [], []
+    for nst in (10, 20, 40):
+        m = mu.mu_cmf_evolve(m0, Ws, T / nst, nst, rtol=1e-11, atol=1e-13)
+        errs.append(np.abs(om.mps_to_dense(m) - ref).max())
+        m1 = [A.copy() for A in m0]
+        for _ in range(nst):
+            m1 = mu.cmf_propagate(m1, Ws, mu.mu_fields(m1, Ws), T / nst, 1e-11, 1e-13)
+        errs1.append(np.abs(om.mps_to_dense(m1) - ref).max())
+    assert errs[-1] < 2e-5
+    for a, b in zip(errs, errs[1:]):
+        assert 3.5 < a / b < 4.6
+    for a, b in zip(errs1, errs1[1:]):
+        assert 1.6 < a / b < 2.4
+
+
+def test_cmf_full_bond_converges_to_exact():
+    """Full bond dimension, full Schmidt rank: the equations of motion are
+    exact, so CMF converges to exp(-iHt) psi(0) at second order."""
+    p = draw_params(2, 1, 3, seed=4)
+    sites = chain_sites(p)
+    H, _ = model.dense_hamiltonian(p, sites)
+    Ws, _ = model.mpo(p, sites)
+    m0 = mu.left_canonicalize(initial_mps_raw(p, 6, 0.3, 2))
+    T = 10 * model.AU_PER_FS
+    ref = dense.exact_evolve(H, om.mps_to_dense(m0), [T])[0]
+    errs = []
+    for nst in (10, 20, 40):
+        m = mu.mu_cmf_evolve(m0, Ws, T / nst, nst, eps=1e-14, rtol=1e-11, atol=1e-13)
+        errs.append(np.abs(om.mps_to_dense(m) - ref).max())
+    for a, b in zip(errs, errs[1:]):
+        assert 3.5 < a / b < 4.6
+
+
+def test_cmf_keeps_norm_and_gauge():
+    """The centre's propagator is unitary and each L_i's frozen-field
+    equation keeps L_i^H L_i constant, so both survive to the integrator's
+    tolerance."""
+    _, _, Ws, m0 = _cmf_case()
+    m = mu.mu_cmf_evolve(m0, Ws, 2 * model.AU_PER_FS, 3, rtol=1e-11, atol=1e-13)
+    assert abs(np.linalg.norm(om.mps_to_dense(m)) - 1.0) < 1e-10
+    for A in m[:-1]:
+        ml, d, mr = A.shape
+        X = A.reshape(ml * d, mr)
+        assert np.abs(X.conj().T @ X - np.eye(mr)).max() < 1e-9
