@@ -12,7 +12,10 @@ perturbed by N(0, 100 cm^-1), bond dimensions drawn from {32, 64, 96, 128},
 dt = 2 fs, Krylov dimension 20, contractions in FP32 with FP64 Krylov, small
 exponential and QR; ``value`` counts realisation-steps per second.  Its FP64
 twin runs outside the timed region and states the mixed-mode error.
-``--workload fmo7x10x8_M32`` (etc.) times one chain instead.
+``--workload fmo7x10x8_M32`` (etc.) times one chain instead;
+``--scheme mu-cmf`` / ``mu-vmf`` times TDVP-MU on such a chain (bond
+dimension <= 64, FP64): a step is one constant-mean-field step of length
+dt, or the variable-mean-field integration over dt.
 Prints ONE JSON line (see the keys below).
 """
 
@@ -67,6 +70,9 @@ def parse():
                          "step (tdvp_set_autotune); auto: on where the tiled GEMMs carry the "
                          "contractions (bond dimension > 64, the ensemble), off where the fused "
                          "small-bond step does (measured: no gain there)")
+    ap.add_argument("--scheme", default="ps", choices=["ps", "mu-cmf", "mu-vmf"],
+                    help="single chain: TDVP-PS (default) or TDVP-MU with constant or variable mean "
+                         "field (tolerances rtol 1e-5, atol 1e-8, eps 1e-10)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 256 MiB device copy first (reference for HBM counters)")
     return ap.parse_args()
@@ -410,6 +416,69 @@ def ensemble_main(args):
     print(json.dumps(line), flush=True)
 
 
+def mu_main(args):
+    """TDVP-MU on one chain: steps of length dt, the MPS left-canonicalised on
+    the device first; the host takes every Runge-Kutta step decision."""
+    import numpy as np
+    import torch
+    from inputs import workload
+    from paper_1907_12044_amd import tdvp
+
+    if args.precision != "fp64":
+        log("TDVP-MU runs in FP64 only")
+        sys.exit(2)
+    p, sites, phys, dims, raw, w = workload(args.workload)
+    run = tdvp.MuRun(p, sites, raw, 0, canonicalize=True)
+    tau = w["dt_fs"] * tdvp.AU_PER_FS
+    tol = dict(eps=1e-10, rtol=1e-5, atol=1e-8)
+    if args.scheme == "mu-cmf":
+        def step():
+            return run.cmf_step(tau, 1, kmax=args.kmax, tol=args.tol, **tol)
+    else:
+        def step():
+            return run.evolve(tau, **tol)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stats = [0, 0, 0]
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st = step()
+        stats = [a + b for a, b in zip(stats, st)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / max(args.steps, 1)
+    m = run.mps_numpy()
+    gauge = 0.0
+    for A in m[:-1]:
+        X = A.reshape(-1, A.shape[2])
+        gauge = max(gauge, float(np.abs(X.conj().T @ X - np.eye(X.shape[1])).max()))
+    name = {"mu-cmf": "TDVP-MU (CMF)", "mu-vmf": "TDVP-MU (VMF)"}[args.scheme]
+    line = {
+        "metric": f"{name} steps/s",
+        "value": 1e3 / ms_per_step,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "scheme": args.scheme, "sites": len(sites),
+                   "bond_dim": w["M"], "dt_fs": w["dt_fs"], "kmax": args.kmax, **tol},
+        "rk_steps_per_step": stats[0] / max(args.steps, 1),
+        "rk_rejected_per_step": stats[1] / max(args.steps, 1),
+        "rhs_evals_per_step": stats[2] / max(args.steps, 1),
+        "final_norm": float(np.linalg.norm(m[-1])),
+        "final_gauge_error": gauge,
+        "roofline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -420,6 +489,8 @@ def main():
         args.precision = "fp32" if args.workload.startswith("ensemble") else "fp64"
     if args.workload.startswith("ensemble"):
         return ensemble_main(args)
+    if args.scheme != "ps":
+        return mu_main(args)
     import numpy as np
     import torch
     from inputs import workload

@@ -179,6 +179,12 @@ tdvp_status tdvp_qr(tdvp_ctx *ctx, const void *A, int m, int n, void *Q, void *R
  * normalise the centre tensor at site 0. */
 tdvp_status tdvp_right_canonicalize(tdvp_ctx *ctx, const tdvp_mps *mps);
 
+/* Left-canonicalise an MPS in place (QR sweep 0 -> n-2, eq:QR: site i =
+ * Q R, Q kept, R absorbed into site i+1) and normalise the centre tensor
+ * at site n-1: the gauge of the TDVP-MU state.  Every site must satisfy
+ * bond[i] * phys[i] >= bond[i+1] (TDVP_E_SHAPE otherwise). */
+tdvp_status tdvp_left_canonicalize(tdvp_ctx *ctx, const tdvp_mps *mps);
+
 /* Build every right environment right[n-1..1] of a right-canonical MPS and
  * set left[0] = right[n] = 1 (left[1..n-1] are produced by the sweep). */
 tdvp_status tdvp_envs_build(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo,
@@ -348,6 +354,30 @@ tdvp_status tdvp_mu_rhs(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo,
  * left as it was at the start of the call. */
 tdvp_status tdvp_mu_evolve(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo, double t_final,
                            double eps, double rtol, double atol, int max_steps, int64_t *stats);
+
+/* TDVP-MU with the second-order constant-mean-field scheme (Sec. II.A.2,
+ * the paragraph on VMF and CMF): one step of length tau > 0 in place.  The
+ * mean fields of a site (its left and right environments, the bond matrix
+ * D_i and the regularised inverse V Lam~^{-1} U^H) are taken at one state
+ * and held; each site then obeys its own equation.  The fields of the
+ * state at t carry every site to t + tau/2, the fields of that midpoint
+ * state carry the state at t to t + tau.  The left-isometric sites follow
+ *   dL_i/dt = -i (1 - L_i L_i^H) H[i](L_i D_i) V Lam~^{-1} U^H
+ * with the frozen fields, integrated together on one packed vector by the
+ * Dormand-Prince 5(4) pair of tdvp_mu_evolve (one step size for all
+ * sites, error control over all of them; rtol, atol, max_steps per solve);
+ * the centre follows its linear equation by the Lanczos propagator
+ * exp(-i h H[n-1]) (Krylov dimension <= kmax, early stop at tol as in
+ * tdvp_lanczos_expm).  Same limits as tdvp_mu_evolve; the workspace must
+ * hold tdvp_mu_cmf_workspace_bytes for this kmax (1 <= kmax <= 32).  stats
+ * (host int64[3], may be NULL): accepted and rejected Runge-Kutta steps
+ * and site right-hand-side evaluations, summed over the two solves.
+ * TDVP_E_NUMERIC as for tdvp_mu_evolve; the MPS then holds its start
+ * state. */
+tdvp_status tdvp_mu_cmf_workspace_bytes(const tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo,
+                                        int kmax, size_t *bytes);
+tdvp_status tdvp_mu_cmf_step(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo, double tau, double eps,
+                             double rtol, double atol, int max_steps, int kmax, double tol, int64_t *stats);
 
 /* Grouped form for an ensemble of UNEVEN bond dimensions (e.g. static-
  * disorder realisations whose bond dimensions are drawn from several

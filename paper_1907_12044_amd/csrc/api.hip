@@ -16,6 +16,7 @@
 #include <initializer_list>
 #include <mutex>
 #include <new>
+#include <functional>
 #include <vector>
 
 #include "common.h"
@@ -960,6 +961,28 @@ tdvp_status tdvp_right_canonicalize(tdvp_ctx *ctx, const tdvp_mps *mps) {
   return TDVP_OK;
 }
 
+tdvp_status tdvp_left_canonicalize(tdvp_ctx *ctx, const tdvp_mps *mps) {
+  if (!ctx) return TDVP_E_ARG;
+  Chain ch;
+  CS(check_chain(mps, nullptr, &ch));
+  const Layout lay = layout(ch.nmax, 1, 1, env_bytes(ctx));
+  CS(need(ctx, lay));
+  CK(hipSetDevice(ctx->device));
+  double2 *R = at<double2>(ctx, lay.D), *tmp = at<double2>(ctx, lay.tmp);
+  const int n = ch.n;
+  for (int i = 0; i + 1 < n; ++i) {
+    const int Ml = ch.bond[i], d = ch.phys[i], Mr = ch.bond[i + 1];
+    if ((int64_t)Ml * d < Mr) return TDVP_E_SHAPE;
+    CS(qr_left(ctx, lay, (double2 *)mps->site[i], Ml, d, Mr, R, Bi(), 0));
+    const int64_t cols = (int64_t)ch.phys[i + 1] * ch.bond[i + 2];
+    CS(matmul(ctx, R, (const double2 *)mps->site[i + 1], tmp, Mr, Mr, (int)cols));
+    CK(copy_c128((double2 *)mps->site[i + 1], tmp, (int64_t)Mr * cols, ctx->stream));
+  }
+  CK(normalize_c128((double2 *)mps->site[n - 1], (int64_t)ch.bond[n - 1] * ch.phys[n - 1] * ch.bond[n],
+                    ctx->stream));
+  return TDVP_OK;
+}
+
 tdvp_status tdvp_envs_build(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo,
                             const tdvp_envs *envs) {
   if (!ctx || !envs || !envs->left || !envs->right) return TDVP_E_ARG;
@@ -1757,14 +1780,24 @@ tdvp_status tdvp_observe_grouped(tdvp_ctx *ctx, int ngroups, const int32_t *coun
 // control (error norm scaled by atol + rtol max(|y|, |y_new|), safety 0.9,
 // step factor within [0.2, 10], first step from the two-evaluation rule);
 // the step decision is taken on the host after each step (one sync).
+//
+// Constant mean field, second order: steps 1-3 and the regularised inverse
+// of step 4 (the mean fields) are taken at one state and held; with them
+// each site's equation involves that site alone.  The fields of the state
+// at t carry every site to t + tau/2, the fields of that midpoint state
+// carry the state at t to t + tau.  The site tensors L_i follow their
+// frozen-field equations with the Dormand-Prince pair, all sites together
+// on one packed vector with one step size (the equations do not couple, so
+// this is their joint solution; the error control takes the worst site);
+// the centre follows its linear one by the Lanczos propagator.
 namespace {
 
 struct MuPlan {
   Chain ch;
   Layout lay;                       // local-problem region (contraction, QR scratch)
-  std::vector<size_t> lenv, renv, rt, dbuf, site_off;   // byte offsets / element offsets (site_off)
-  size_t P, C, G, X, Y, T;          // per-site temporaries
-  size_t vec[11];                   // packed vectors: y, ys, ynew, err, k1..k7
+  std::vector<size_t> lenv, renv, rt, dbuf, pbuf, site_off;   // byte offsets / element offsets (site_off)
+  size_t C, G, X, Y, T;             // per-site temporaries
+  size_t vec[12];                   // packed vectors: y, ys, ynew, err, k1..k7, start state (CMF)
   size_t part;                      // RK error partial sums
   int64_t ntot;                     // packed length (complex elements)
   size_t total;
@@ -1772,7 +1805,9 @@ struct MuPlan {
 
 constexpr int MU_MAXM = 64;         // bond dimensions the regularised inverse handles
 
-tdvp_status mu_plan(const tdvp_ctx *c, const tdvp_mps *mps, const tdvp_mpo *mpo, MuPlan *pl) {
+// kmax: Krylov dimension the local-problem region must hold (1 without the
+// centre's Lanczos propagator).
+tdvp_status mu_plan(const tdvp_ctx *c, const tdvp_mps *mps, const tdvp_mpo *mpo, MuPlan *pl, int kmax = 1) {
   if (!c || !mpo) return TDVP_E_ARG;
   CS(check_chain(mps, mpo, &pl->ch));
   if (c->prec != TDVP_FP64) return TDVP_E_UNSUPPORTED;
@@ -1780,12 +1815,13 @@ tdvp_status mu_plan(const tdvp_ctx *c, const tdvp_mps *mps, const tdvp_mpo *mpo,
   const int n = ch.n;
   if (n < 2) return TDVP_E_SHAPE;
   if (ch.mmax > MU_MAXM) return TDVP_E_UNSUPPORTED;
-  pl->lay = layout(ch.nmax, ch.wmax, 1, 16);
+  pl->lay = layout(ch.nmax, ch.wmax, kmax, 16);
   size_t o = pl->lay.total;
   auto take = [&](size_t bytes) { const size_t r = o; o += al256(bytes); return r; };
   pl->lenv.assign(n + 1, 0);
   pl->renv.assign(n + 1, 0);
   pl->dbuf.assign(n + 1, 0);
+  pl->pbuf.assign(n + 1, 0);
   pl->rt.assign(n, 0);
   pl->site_off.assign(n + 1, 0);
   for (int b = 0; b <= n; ++b) {
@@ -1793,6 +1829,7 @@ tdvp_status mu_plan(const tdvp_ctx *c, const tdvp_mps *mps, const tdvp_mpo *mpo,
     pl->lenv[b] = take(e);
     pl->renv[b] = take(e);
     pl->dbuf[b] = take((size_t)ch.bond[b] * ch.bond[b] * 16);
+    pl->pbuf[b] = take((size_t)ch.bond[b] * ch.bond[b] * 16);
   }
   int64_t tot = 0;
   for (int i = 0; i < n; ++i) {
@@ -1804,7 +1841,6 @@ tdvp_status mu_plan(const tdvp_ctx *c, const tdvp_mps *mps, const tdvp_mpo *mpo,
   pl->site_off[n] = tot;
   pl->ntot = tot;
   const size_t m2 = (size_t)ch.mmax * ch.mmax * 16, nv = (size_t)ch.nmax * 16;
-  pl->P = take(m2);
   pl->T = take(m2);
   pl->C = take(nv);
   pl->G = take(nv);
@@ -1816,9 +1852,11 @@ tdvp_status mu_plan(const tdvp_ctx *c, const tdvp_mps *mps, const tdvp_mpo *mpo,
   return TDVP_OK;
 }
 
-// out[i] = d(site i)/dt for the left-canonical state A (host tables of n device pointers).
-tdvp_status mu_rhs_impl(tdvp_ctx *c, const MuPlan &pl, const tdvp_mpo *mpo, const double2 *const *A,
-                        double2 *const *out, double eps) {
+// Mean fields of the left-canonical state A (host table of n device
+// pointers): steps 1-3 and, per site i < n-1, the regularised inverse factor
+// P_i = V Lam~^{-1} U^H of D_{i+1} (pbuf[i+1]).
+tdvp_status mu_fields(tdvp_ctx *c, const MuPlan &pl, const tdvp_mpo *mpo, const double2 *const *A,
+                      double eps) {
   const Chain &ch = pl.ch;
   const int n = ch.n;
   const Layout &lay = pl.lay;
@@ -1841,13 +1879,25 @@ tdvp_status mu_rhs_impl(tdvp_ctx *c, const MuPlan &pl, const tdvp_mpo *mpo, cons
   for (int i = n - 1; i >= 1; --i)
     CS(env_update(c, lay, -1, B(pl.renv[i + 1]), B(pl.rt[i]), mpo->site[i], ch.bond[i], ch.phys[i],
                   ch.bond[i + 1], ch.wbond[i], ch.wbond[i + 1], B(pl.renv[i]), Bi(), 0, 0, 0, 0));
-  // 4. projected site derivatives
-  for (int i = 0; i < n; ++i) {
+  // regularised inverse factors of step 4
+  for (int i = 0; i + 1 < n; ++i)
+    CK(mu_reginv(B(pl.dbuf[i + 1]), ch.bond[i + 1], eps, B(pl.pbuf[i + 1]), nullptr, c->stream));
+  return TDVP_OK;
+}
+
+// out[i] = d(site i)/dt for sites i0 <= i < i1 of the state A with the mean
+// fields mu_fields last computed (steps 4 and 5).
+tdvp_status mu_site_rhs(tdvp_ctx *c, const MuPlan &pl, const tdvp_mpo *mpo, const double2 *const *A,
+                        double2 *const *out, int i0, int i1) {
+  const Chain &ch = pl.ch;
+  const int n = ch.n;
+  const Layout &lay = pl.lay;
+  auto B = [&](size_t off) { return reinterpret_cast<double2 *>(c->ws + off); };
+  for (int i = i0; i < i1; ++i) {
     const int Ml = ch.bond[i], d = ch.phys[i], Mr = ch.bond[i + 1];
     const int64_t sz = (int64_t)Ml * d * Mr;
     const double2 *x = A[i];
     if (i + 1 < n) {
-      CK(mu_reginv(B(pl.dbuf[i + 1]), Mr, eps, B(pl.P), nullptr, c->stream));
       CS(matmul(c, A[i], B(pl.dbuf[i + 1]), B(pl.C), Ml * d, Mr, Mr));
       x = B(pl.C);
     }
@@ -1858,7 +1908,7 @@ tdvp_status mu_rhs_impl(tdvp_ctx *c, const MuPlan &pl, const tdvp_mpo *mpo, cons
       CK(mu_finish(B(pl.G), nullptr, out[i], sz, c->stream));   // 5.
       break;
     }
-    CS(matmul(c, B(pl.G), B(pl.P), B(pl.X), Ml * d, Mr, Mr));
+    CS(matmul(c, B(pl.G), B(pl.pbuf[i + 1]), B(pl.X), Ml * d, Mr, Mr));
     GemmArgs g{};   // T = L_i^H X  (Mr x Mr)
     g.A = A[i]; g.B = B(pl.X); g.C = B(pl.T);
     g.M = Mr; g.N = Mr; g.K = Ml * d; g.batch = 1;
@@ -1870,71 +1920,33 @@ tdvp_status mu_rhs_impl(tdvp_ctx *c, const MuPlan &pl, const tdvp_mpo *mpo, cons
   return TDVP_OK;
 }
 
-tdvp_status mu_prepare(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo, MuPlan *pl) {
-  CS(mu_plan(ctx, mps, mpo, pl));
+// out[i] = d(site i)/dt for the left-canonical state A (host tables of n device pointers).
+tdvp_status mu_rhs_impl(tdvp_ctx *c, const MuPlan &pl, const tdvp_mpo *mpo, const double2 *const *A,
+                        double2 *const *out, double eps) {
+  CS(mu_fields(c, pl, mpo, A, eps));
+  return mu_site_rhs(c, pl, mpo, A, out, 0, pl.ch.n);
+}
+
+tdvp_status mu_prepare(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo, MuPlan *pl, int kmax = 1) {
+  CS(mu_plan(ctx, mps, mpo, pl, kmax));
   if (!ctx->ws || ctx->ws_bytes < pl->total) return TDVP_E_WORKSPACE;
   CK(hipSetDevice(ctx->device));
   return TDVP_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-tdvp_status tdvp_mu_workspace_bytes(const tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo,
-                                    size_t *bytes) {
-  if (!bytes) return TDVP_E_ARG;
-  MuPlan pl;
-  CS(mu_plan(ctx, mps, mpo, &pl));
-  *bytes = pl.total;
-  return TDVP_OK;
-}
-
-tdvp_status tdvp_mu_rhs(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo, double eps,
-                        void *const *out_site) {
-  if (!out_site || !(eps > 0.0)) return TDVP_E_ARG;
-  MuPlan pl;
-  CS(mu_prepare(ctx, mps, mpo, &pl));
-  const int n = pl.ch.n;
-  std::vector<const double2 *> A(n);
-  std::vector<double2 *> out(n);
-  for (int i = 0; i < n; ++i) {
-    if (!out_site[i]) return TDVP_E_ARG;
-    A[i] = (const double2 *)mps->site[i];
-    out[i] = (double2 *)out_site[i];
-  }
-  return mu_rhs_impl(ctx, pl, mpo, A.data(), out.data(), eps);
-}
-
-tdvp_status tdvp_mu_evolve(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo, double t_final,
-                           double eps, double rtol, double atol, int max_steps, int64_t *stats) {
-  if (!(t_final >= 0.0) || !(eps > 0.0) || !(rtol > 0.0) || !(atol >= 0.0) || max_steps < 1)
-    return TDVP_E_ARG;
-  MuPlan pl;
-  CS(mu_prepare(ctx, mps, mpo, &pl));
-  const int n = pl.ch.n;
-  const int64_t N = pl.ntot;
+// Integrates dy/dt = f(y) from 0 to t_final on the packed vector y (N
+// complex entries; initial values in place) with the Dormand-Prince 5(4)
+// pair, using the plan's vectors 1..10 as stages; *res receives the buffer
+// that holds the result (y itself or one of those vectors).
+tdvp_status dp45(tdvp_ctx *ctx, const MuPlan &pl, double2 *y, int64_t N, double t_final, double rtol,
+                 double atol, int max_steps, const std::function<tdvp_status(const double2 *, double2 *)> &f,
+                 double2 **res, int64_t *nacc_out, int64_t *nrej_out) {
   auto V = [&](int k) { return reinterpret_cast<double2 *>(ctx->ws + pl.vec[k]); };
-  double2 *y = V(0), *ys = V(1), *ynew = V(2), *err = V(3);
+  double2 *ys = V(1), *ynew = V(2), *err = V(3);
   double2 *K[7];
   for (int j = 0; j < 7; ++j) K[j] = V(4 + j);
   double *part = reinterpret_cast<double *>(ctx->ws + pl.part);
-  // site pointer tables into a packed vector
-  auto sites_of = [&](double2 *v, std::vector<double2 *> &t) {
-    t.resize(n);
-    for (int i = 0; i < n; ++i) t[i] = v + pl.site_off[i];
-  };
-  for (int i = 0; i < n; ++i)
-    CK(copy_c128(y + pl.site_off[i], (const double2 *)mps->site[i], pl.site_off[i + 1] - pl.site_off[i],
-                 ctx->stream));
-  int64_t nfev = 0, nacc = 0, nrej = 0;
-  auto f = [&](const double2 *in, double2 *outv) -> tdvp_status {
-    std::vector<double2 *> ti, to;
-    sites_of(const_cast<double2 *>(in), ti);
-    sites_of(outv, to);
-    ++nfev;
-    return mu_rhs_impl(ctx, pl, mpo, ti.data(), to.data(), eps);
-  };
+  int64_t nacc = 0, nrej = 0;
   // RMS of (e / (atol + rtol max(|a|, |b|))) over the packed vector
   auto wnorm = [&](const double2 *e, const double2 *a, const double2 *b, double *res) -> tdvp_status {
     const int g = rk_err_partials(e, a, b, N, rtol, atol, part, ctx->stream);
@@ -2029,8 +2041,134 @@ tdvp_status tdvp_mu_evolve(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *m
       }
     }
   }
+  *res = y;
+  *nacc_out += nacc;
+  *nrej_out += nrej;
+  return TDVP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tdvp_status tdvp_mu_workspace_bytes(const tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo,
+                                    size_t *bytes) {
+  if (!bytes) return TDVP_E_ARG;
+  MuPlan pl;
+  CS(mu_plan(ctx, mps, mpo, &pl));
+  *bytes = pl.total;
+  return TDVP_OK;
+}
+
+tdvp_status tdvp_mu_rhs(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo, double eps,
+                        void *const *out_site) {
+  if (!out_site || !(eps > 0.0)) return TDVP_E_ARG;
+  MuPlan pl;
+  CS(mu_prepare(ctx, mps, mpo, &pl));
+  const int n = pl.ch.n;
+  std::vector<const double2 *> A(n);
+  std::vector<double2 *> out(n);
+  for (int i = 0; i < n; ++i) {
+    if (!out_site[i]) return TDVP_E_ARG;
+    A[i] = (const double2 *)mps->site[i];
+    out[i] = (double2 *)out_site[i];
+  }
+  return mu_rhs_impl(ctx, pl, mpo, A.data(), out.data(), eps);
+}
+
+tdvp_status tdvp_mu_evolve(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo, double t_final,
+                           double eps, double rtol, double atol, int max_steps, int64_t *stats) {
+  if (!(t_final >= 0.0) || !(eps > 0.0) || !(rtol > 0.0) || !(atol >= 0.0) || max_steps < 1)
+    return TDVP_E_ARG;
+  MuPlan pl;
+  CS(mu_prepare(ctx, mps, mpo, &pl));
+  const int n = pl.ch.n;
+  const int64_t N = pl.ntot;
+  auto V = [&](int k) { return reinterpret_cast<double2 *>(ctx->ws + pl.vec[k]); };
+  double2 *y = V(0);
+  // site pointer tables into a packed vector
+  auto sites_of = [&](double2 *v, std::vector<double2 *> &t) {
+    t.resize(n);
+    for (int i = 0; i < n; ++i) t[i] = v + pl.site_off[i];
+  };
+  for (int i = 0; i < n; ++i)
+    CK(copy_c128(y + pl.site_off[i], (const double2 *)mps->site[i], pl.site_off[i + 1] - pl.site_off[i],
+                 ctx->stream));
+  int64_t nfev = 0, nacc = 0, nrej = 0;
+  auto f = [&](const double2 *in, double2 *outv) -> tdvp_status {
+    std::vector<double2 *> ti, to;
+    sites_of(const_cast<double2 *>(in), ti);
+    sites_of(outv, to);
+    ++nfev;
+    return mu_rhs_impl(ctx, pl, mpo, ti.data(), to.data(), eps);
+  };
+  CS(dp45(ctx, pl, y, N, t_final, rtol, atol, max_steps, f, &y, &nacc, &nrej));
   for (int i = 0; i < n; ++i)
     CK(copy_c128((double2 *)mps->site[i], y + pl.site_off[i], pl.site_off[i + 1] - pl.site_off[i],
+                 ctx->stream));
+  if (stats) {
+    stats[0] = nacc;
+    stats[1] = nrej;
+    stats[2] = nfev;
+  }
+  return TDVP_OK;
+}
+
+tdvp_status tdvp_mu_cmf_workspace_bytes(const tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo,
+                                        int kmax, size_t *bytes) {
+  if (!bytes || kmax < 1 || kmax > KMAX) return TDVP_E_ARG;
+  MuPlan pl;
+  CS(mu_plan(ctx, mps, mpo, &pl, kmax));
+  *bytes = pl.total;
+  return TDVP_OK;
+}
+
+tdvp_status tdvp_mu_cmf_step(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo, double tau, double eps,
+                             double rtol, double atol, int max_steps, int kmax, double tol, int64_t *stats) {
+  if (!(tau > 0.0) || !(eps > 0.0) || !(rtol > 0.0) || !(atol >= 0.0) || max_steps < 1 || kmax < 1 ||
+      kmax > KMAX || !(tol >= 0.0))
+    return TDVP_E_ARG;
+  MuPlan pl;
+  CS(mu_prepare(ctx, mps, mpo, &pl, kmax));
+  const Chain &ch = pl.ch;
+  const int n = ch.n;
+  const int64_t NL = pl.site_off[n - 1];   // the left-isometric sites lead the packed vector
+  auto V = [&](int k) { return reinterpret_cast<double2 *>(ctx->ws + pl.vec[k]); };
+  auto B = [&](size_t off) { return reinterpret_cast<double2 *>(ctx->ws + off); };
+  double2 *y0 = V(11);
+  for (int i = 0; i < n; ++i)
+    CK(copy_c128(y0 + pl.site_off[i], (const double2 *)mps->site[i], pl.site_off[i + 1] - pl.site_off[i],
+                 ctx->stream));
+  auto table = [&](const double2 *v) {
+    std::vector<const double2 *> t(n);
+    for (int i = 0; i < n; ++i) t[i] = v + pl.site_off[i];
+    return t;
+  };
+  int64_t nfev = 0, nacc = 0, nrej = 0;
+  // frozen-field derivative of the sites 0 .. n-2
+  auto f = [&](const double2 *in, double2 *outv) -> tdvp_status {
+    const std::vector<const double2 *> ti = table(in);
+    std::vector<double2 *> to(n);
+    for (int i = 0; i < n; ++i) to[i] = outv + pl.site_off[i];
+    ++nfev;
+    return mu_site_rhs(ctx, pl, mpo, ti.data(), to.data(), 0, n - 1);
+  };
+  // the start state carried over time h with the fields last computed
+  auto propagate = [&](double h, double2 **res) -> tdvp_status {
+    double2 *y = V(0);
+    CK(copy_c128(y, y0, pl.ntot, ctx->stream));
+    CS(dp45(ctx, pl, y, NL, h, rtol, atol, max_steps, f, res, &nacc, &nrej));
+    const Op op{B(pl.lenv[n - 1]), mpo->site[n - 1], B(pl.renv[n]), ch.bond[n - 1], ch.phys[n - 1],
+                ch.bond[n], ch.wbond[n - 1], ch.wbond[n]};
+    return run_lanczos(ctx, pl.lay, op, 0.0, -h, kmax, tol, y0 + NL, 0, *res + NL, 0, nullptr, Bi());
+  };
+  double2 *half = nullptr, *full = nullptr;
+  CS(mu_fields(ctx, pl, mpo, table(y0).data(), eps));
+  CS(propagate(0.5 * tau, &half));
+  CS(mu_fields(ctx, pl, mpo, table(half).data(), eps));
+  CS(propagate(tau, &full));
+  for (int i = 0; i < n; ++i)
+    CK(copy_c128((double2 *)mps->site[i], full + pl.site_off[i], pl.site_off[i + 1] - pl.site_off[i],
                  ctx->stream));
   if (stats) {
     stats[0] = nacc;

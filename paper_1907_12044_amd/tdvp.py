@@ -63,6 +63,7 @@ EXPORTS = {
                                           c_void_p, c_void_p]),
     "tdvp_qr": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p]),
     "tdvp_right_canonicalize": (c_int, [c_void_p, POINTER(_Mps)]),
+    "tdvp_left_canonicalize": (c_int, [c_void_p, POINTER(_Mps)]),
     "tdvp_envs_build": (c_int, [c_void_p, POINTER(_Mps), POINTER(_Mpo), POINTER(_Envs)]),
     "tdvp_ps_step": (c_int, [c_void_p, POINTER(_Mps), POINTER(_Mpo), POINTER(_Envs), c_double, c_int,
                              c_int, c_double]),
@@ -92,6 +93,10 @@ EXPORTS = {
     "tdvp_mu_rhs": (c_int, [c_void_p, POINTER(_Mps), POINTER(_Mpo), c_double, POINTER(c_void_p)]),
     "tdvp_mu_evolve": (c_int, [c_void_p, POINTER(_Mps), POINTER(_Mpo), c_double, c_double, c_double,
                                c_double, c_int, POINTER(c_int64)]),
+    "tdvp_mu_cmf_workspace_bytes": (c_int, [c_void_p, POINTER(_Mps), POINTER(_Mpo), c_int,
+                                            POINTER(c_size_t)]),
+    "tdvp_mu_cmf_step": (c_int, [c_void_p, POINTER(_Mps), POINTER(_Mpo), c_double, c_double, c_double,
+                                 c_double, c_int, c_int, c_double, POINTER(c_int64)]),
     "tdvp_holstein_mpo": (c_int, [c_int, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32), c_int,
                                   POINTER(c_double), POINTER(c_double), POINTER(c_double),
                                   POINTER(c_double), POINTER(c_int32), POINTER(c_int64),
@@ -319,6 +324,10 @@ def right_canonicalize(ctx, mps):
     _check(lib().tdvp_right_canonicalize(ctx.h, ctypes.byref(mps.desc)), "tdvp_right_canonicalize")
 
 
+def left_canonicalize(ctx, mps):
+    _check(lib().tdvp_left_canonicalize(ctx.h, ctypes.byref(mps.desc)), "tdvp_left_canonicalize")
+
+
 def envs_build(ctx, mps, mpo, envs):
     _check(lib().tdvp_envs_build(ctx.h, ctypes.byref(mps.desc), ctypes.byref(mpo.desc),
                                  ctypes.byref(envs.desc)), "tdvp_envs_build")
@@ -478,11 +487,30 @@ def mu_evolve(ctx, mps, mpo, t_final, eps=1e-10, rtol=1e-5, atol=1e-8, max_steps
     return tuple(int(v) for v in st)
 
 
+def mu_cmf_workspace_bytes(ctx, mps, mpo, kmax=20):
+    b = c_size_t(0)
+    _check(lib().tdvp_mu_cmf_workspace_bytes(ctx.h, ctypes.byref(mps.desc), ctypes.byref(mpo.desc),
+                                             int(kmax), ctypes.byref(b)), "tdvp_mu_cmf_workspace_bytes")
+    return b.value
+
+
+def mu_cmf_step(ctx, mps, mpo, tau, eps=1e-10, rtol=1e-10, atol=1e-12, max_steps=100000, kmax=20,
+                tol=0.0):
+    """One second-order constant-mean-field step in place; returns (accepted,
+    rejected, site right-hand-side evaluations) summed over its two solves."""
+    st = (c_int64 * 3)()
+    _check(lib().tdvp_mu_cmf_step(ctx.h, ctypes.byref(mps.desc), ctypes.byref(mpo.desc), float(tau),
+                                  float(eps), float(rtol), float(atol), int(max_steps), int(kmax),
+                                  float(tol), st), "tdvp_mu_cmf_step")
+    return tuple(int(v) for v in st)
+
+
 class MuRun:
     """A chain evolved with TDVP-MU on one GPU from a LEFT-canonical MPS
-    (given as host arrays; the caller canonicalises).  Own stream, FP64."""
+    given as host arrays (canonicalize=True: any MPS, left-canonicalised
+    on the device).  Own stream, FP64."""
 
-    def __init__(self, params, sites, left_canonical_mps, device=0):
+    def __init__(self, params, sites, left_canonical_mps, device=0, canonicalize=False):
         import torch
         self.torch = torch
         self.stream = torch.cuda.Stream(device=device)
@@ -493,6 +521,8 @@ class MuRun:
             self.mpo = DeviceMpo(Ws, wbond, shift, dev)
             self.mps = DeviceMps(left_canonical_mps, dev)
             self.ctx.reserve(mu_workspace_bytes(self.ctx, self.mps, self.mpo))
+            if canonicalize:
+                left_canonicalize(self.ctx, self.mps)
         self.stream.synchronize()
 
     def rhs(self, eps=1e-10):
@@ -507,6 +537,16 @@ class MuRun:
         st = mu_evolve(self.ctx, self.mps, self.mpo, t_final, eps, rtol, atol, max_steps)
         self.stream.synchronize()
         return st
+
+    def cmf_step(self, tau, nsteps=1, eps=1e-10, rtol=1e-10, atol=1e-12, max_steps=100000, kmax=20, tol=0.0):
+        """nsteps constant-mean-field steps; returns the summed statistics."""
+        self.ctx.reserve(mu_cmf_workspace_bytes(self.ctx, self.mps, self.mpo, kmax))
+        tot = [0, 0, 0]
+        for _ in range(nsteps):
+            st = mu_cmf_step(self.ctx, self.mps, self.mpo, tau, eps, rtol, atol, max_steps, kmax, tol)
+            tot = [a + b for a, b in zip(tot, st)]
+        self.stream.synchronize()
+        return tuple(tot)
 
     def mps_numpy(self):
         self.stream.synchronize()
