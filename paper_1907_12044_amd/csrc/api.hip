@@ -92,6 +92,10 @@ struct tdvp_ctx {
   // first use) and the events that fork it from and join it to `stream`
   hipStream_t aux;
   hipEvent_t fork_ev, join_ev;
+  // lanes of the TDVP-MU site derivatives (default priority, created on
+  // first use) and their fork / join events
+  hipStream_t mu_lane[3] = {};
+  hipEvent_t mu_ev[4] = {};
 };
 
 namespace {
@@ -774,6 +778,10 @@ tdvp_status tdvp_destroy(tdvp_ctx *ctx) {
   if (ctx->fork_ev) hipEventDestroy(ctx->fork_ev);
   if (ctx->join_ev) hipEventDestroy(ctx->join_ev);
   if (ctx->aux) hipStreamDestroy(ctx->aux);
+  for (hipStream_t l : ctx->mu_lane)
+    if (l) hipStreamDestroy(l);
+  for (hipEvent_t e : ctx->mu_ev)
+    if (e) hipEventDestroy(e);
   delete ctx;
   return TDVP_OK;
 }
@@ -1792,11 +1800,16 @@ tdvp_status tdvp_observe_grouped(tdvp_ctx *ctx, int ngroups, const int32_t *coun
 // the centre follows its linear one by the Lanczos propagator.
 namespace {
 
+constexpr int MU_LANES = 4;        // streams the site derivatives are spread over
+
 struct MuPlan {
   Chain ch;
   Layout lay;                       // local-problem region (contraction, QR scratch)
   std::vector<size_t> lenv, renv, rt, dbuf, pbuf, site_off;   // byte offsets / element offsets (site_off)
-  size_t C, G, X, Y, T;             // per-site temporaries
+  // per-lane site temporaries; lane 0 contracts in lay, lane k in lane_lay[k]
+  // (lay with its own T1, T2, Y buffers)
+  Layout lane_lay[MU_LANES];
+  size_t C[MU_LANES], G[MU_LANES], X[MU_LANES], Y[MU_LANES], T[MU_LANES];
   size_t vec[12];                   // packed vectors: y, ys, ynew, err, k1..k7, start state (CMF)
   size_t part;                      // RK error partial sums
   int64_t ntot;                     // packed length (complex elements)
@@ -1841,11 +1854,19 @@ tdvp_status mu_plan(const tdvp_ctx *c, const tdvp_mps *mps, const tdvp_mpo *mpo,
   pl->site_off[n] = tot;
   pl->ntot = tot;
   const size_t m2 = (size_t)ch.mmax * ch.mmax * 16, nv = (size_t)ch.nmax * 16;
-  pl->T = take(m2);
-  pl->C = take(nv);
-  pl->G = take(nv);
-  pl->X = take(nv);
-  pl->Y = take(nv);
+  for (int k = 0; k < MU_LANES; ++k) {
+    pl->lane_lay[k] = pl->lay;
+    if (k > 0) {
+      pl->lane_lay[k].T1 = take(pl->lay.ybytes);
+      pl->lane_lay[k].T2 = take(pl->lay.ybytes);
+      pl->lane_lay[k].Y = take(pl->lay.ybytes);
+    }
+    pl->T[k] = take(m2);
+    pl->C[k] = take(nv);
+    pl->G[k] = take(nv);
+    pl->X[k] = take(nv);
+    pl->Y[k] = take(nv);
+  }
   for (size_t &v : pl->vec) v = take((size_t)tot * 16);
   pl->part = take(RK_PARTS * sizeof(double));
   pl->total = o;
@@ -1879,45 +1900,83 @@ tdvp_status mu_fields(tdvp_ctx *c, const MuPlan &pl, const tdvp_mpo *mpo, const 
   for (int i = n - 1; i >= 1; --i)
     CS(env_update(c, lay, -1, B(pl.renv[i + 1]), B(pl.rt[i]), mpo->site[i], ch.bond[i], ch.phys[i],
                   ch.bond[i + 1], ch.wbond[i], ch.wbond[i + 1], B(pl.renv[i]), Bi(), 0, 0, 0, 0));
-  // regularised inverse factors of step 4
-  for (int i = 0; i + 1 < n; ++i)
-    CK(mu_reginv(B(pl.dbuf[i + 1]), ch.bond[i + 1], eps, B(pl.pbuf[i + 1]), nullptr, c->stream));
+  // regularised inverse factors of step 4: independent per bond, so the
+  // bonds go side by side (one work-group each)
+  for (int i0 = 0; i0 + 1 < n; i0 += REGINV_BATCH) {
+    RegInvBatch rb{};
+    rb.eps = eps;
+    for (int i = i0; i + 1 < n && rb.count < REGINV_BATCH; ++i) {
+      rb.D[rb.count] = B(pl.dbuf[i + 1]);
+      rb.P[rb.count] = B(pl.pbuf[i + 1]);
+      rb.n[rb.count] = ch.bond[i + 1];
+      ++rb.count;
+    }
+    CK(mu_reginv(rb, c->stream));
+  }
+  return TDVP_OK;
+}
+
+// d(site i)/dt of one site with the mean fields last computed (steps 4
+// and 5), on c->stream with the temporaries of lane k.
+tdvp_status mu_site_one(tdvp_ctx *c, const MuPlan &pl, int k, const tdvp_mpo *mpo, int i, const double2 *A,
+                        double2 *out) {
+  const Chain &ch = pl.ch;
+  const int n = ch.n;
+  const Layout &lay = pl.lane_lay[k];
+  auto B = [&](size_t off) { return reinterpret_cast<double2 *>(c->ws + off); };
+  const int Ml = ch.bond[i], d = ch.phys[i], Mr = ch.bond[i + 1];
+  const int64_t sz = (int64_t)Ml * d * Mr;
+  const double2 *x = A;
+  if (i + 1 < n) {
+    CS(matmul(c, A, B(pl.dbuf[i + 1]), B(pl.C[k]), Ml * d, Mr, Mr));
+    x = B(pl.C[k]);
+  }
+  const Op op{B(pl.lenv[i]), mpo->site[i], B(pl.renv[i + 1]), Ml, d, Mr, ch.wbond[i], ch.wbond[i + 1]};
+  CS(apply_op(c, lay, op, x, 0, nullptr, Bi()));
+  CK(sum_partials(F64, c->ws + lay.Y, op.parts(), sz, sz, B(pl.G[k]), c->stream));
+  if (i + 1 == n) {
+    CK(mu_finish(B(pl.G[k]), nullptr, out, sz, c->stream));   // 5.
+    return TDVP_OK;
+  }
+  CS(matmul(c, B(pl.G[k]), B(pl.pbuf[i + 1]), B(pl.X[k]), Ml * d, Mr, Mr));
+  GemmArgs g{};   // T = L_i^H X  (Mr x Mr)
+  g.A = A; g.B = B(pl.X[k]); g.C = B(pl.T[k]);
+  g.M = Mr; g.N = Mr; g.K = Ml * d; g.batch = 1;
+  g.sam = 1; g.sak = Mr; g.conjA = 1; g.sbk = Mr; g.sbn = 1; g.scm = Mr; g.scn = 1;
+  CK(gemm_t(c, F64, F64, F64, g));
+  CS(matmul(c, A, B(pl.T[k]), B(pl.Y[k]), Ml * d, Mr, Mr));
+  CK(mu_finish(B(pl.X[k]), B(pl.Y[k]), out, sz, c->stream));
   return TDVP_OK;
 }
 
 // out[i] = d(site i)/dt for sites i0 <= i < i1 of the state A with the mean
-// fields mu_fields last computed (steps 4 and 5).
+// fields mu_fields last computed.  The site equations are independent, and
+// each one's launches are small (a few dozen work-groups), so the sites go
+// round-robin over MU_LANES streams forked from and joined to c->stream.
 tdvp_status mu_site_rhs(tdvp_ctx *c, const MuPlan &pl, const tdvp_mpo *mpo, const double2 *const *A,
                         double2 *const *out, int i0, int i1) {
-  const Chain &ch = pl.ch;
-  const int n = ch.n;
-  const Layout &lay = pl.lay;
-  auto B = [&](size_t off) { return reinterpret_cast<double2 *>(c->ws + off); };
-  for (int i = i0; i < i1; ++i) {
-    const int Ml = ch.bond[i], d = ch.phys[i], Mr = ch.bond[i + 1];
-    const int64_t sz = (int64_t)Ml * d * Mr;
-    const double2 *x = A[i];
-    if (i + 1 < n) {
-      CS(matmul(c, A[i], B(pl.dbuf[i + 1]), B(pl.C), Ml * d, Mr, Mr));
-      x = B(pl.C);
-    }
-    const Op op{B(pl.lenv[i]), mpo->site[i], B(pl.renv[i + 1]), Ml, d, Mr, ch.wbond[i], ch.wbond[i + 1]};
-    CS(apply_op(c, lay, op, x, 0, nullptr, Bi()));
-    CK(sum_partials(F64, c->ws + lay.Y, op.parts(), sz, sz, B(pl.G), c->stream));
-    if (i + 1 == n) {
-      CK(mu_finish(B(pl.G), nullptr, out[i], sz, c->stream));   // 5.
-      break;
-    }
-    CS(matmul(c, B(pl.G), B(pl.pbuf[i + 1]), B(pl.X), Ml * d, Mr, Mr));
-    GemmArgs g{};   // T = L_i^H X  (Mr x Mr)
-    g.A = A[i]; g.B = B(pl.X); g.C = B(pl.T);
-    g.M = Mr; g.N = Mr; g.K = Ml * d; g.batch = 1;
-    g.sam = 1; g.sak = Mr; g.conjA = 1; g.sbk = Mr; g.sbn = 1; g.scm = Mr; g.scn = 1;
-    CK(gemm_t(c, F64, F64, F64, g));
-    CS(matmul(c, A[i], B(pl.T), B(pl.Y), Ml * d, Mr, Mr));
-    CK(mu_finish(B(pl.X), B(pl.Y), out[i], sz, c->stream));
+  const int lanes = std::max(1, std::min(MU_LANES, i1 - i0));
+  hipStream_t main = c->stream;
+  if (lanes > 1) {
+    for (int k = 0; k < MU_LANES; ++k)
+      if (!c->mu_ev[k]) CK(hipEventCreateWithFlags(&c->mu_ev[k], hipEventDisableTiming));
+    for (int k = 0; k + 1 < MU_LANES; ++k)
+      if (!c->mu_lane[k]) CK(hipStreamCreateWithFlags(&c->mu_lane[k], hipStreamNonBlocking));
+    CK(hipEventRecord(c->mu_ev[0], main));
+    for (int k = 1; k < lanes; ++k) CK(hipStreamWaitEvent(c->mu_lane[k - 1], c->mu_ev[0], 0));
   }
-  return TDVP_OK;
+  tdvp_status st = TDVP_OK;
+  for (int i = i0; i < i1 && st == TDVP_OK; ++i) {
+    const int k = (i - i0) % lanes;
+    c->stream = k == 0 ? main : c->mu_lane[k - 1];
+    st = mu_site_one(c, pl, k, mpo, i, A[i], out[i]);
+  }
+  c->stream = main;
+  for (int k = 1; k < lanes; ++k) {
+    CK(hipEventRecord(c->mu_ev[k], c->mu_lane[k - 1]));
+    CK(hipStreamWaitEvent(main, c->mu_ev[k], 0));
+  }
+  return st;
 }
 
 // out[i] = d(site i)/dt for the left-canonical state A (host tables of n device pointers).

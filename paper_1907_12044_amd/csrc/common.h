@@ -288,11 +288,19 @@ hipError_t cholqr(const QrArgs &a, hipStream_t s);
 void cholqr_init();   // called by qr_init
 void qr_init();       // once per process, outside stream capture
 
-// TDVP-MU (mu.hip).  Regularised inverse P = V Lam~^{-1} U^H of the n x n
-// bond matrix D = U Lam V^H (row-major c128, n <= 64), Lam~ = Lam +
-// sqrt(eps) exp(-Lam / sqrt(eps)) (eq:reg2); lam (may be null) receives the
-// singular values in the order the Jacobi sweeps leave them.
-hipError_t mu_reginv(const double2 *D, int n, double eps, double2 *P, double *lam, hipStream_t s);
+// TDVP-MU (mu.hip).  Regularised inverses P = V Lam~^{-1} U^H of n x n
+// bond matrices D = U Lam V^H (row-major c128, n <= 64), Lam~ = Lam +
+// sqrt(eps) exp(-Lam / sqrt(eps)) (eq:reg2): up to REGINV_BATCH independent
+// matrices per launch, one work-group each.
+constexpr int REGINV_BATCH = 64;
+struct RegInvBatch {
+  const double2 *D[REGINV_BATCH];
+  double2 *P[REGINV_BATCH];
+  int n[REGINV_BATCH];
+  int count;
+  double eps;
+};
+hipError_t mu_reginv(const RegInvBatch &b, hipStream_t s);
 // out = -i (X - Y), n elements (Y == null: out = -i X)
 hipError_t mu_finish(const double2 *X, const double2 *Y, double2 *out, int64_t n, hipStream_t s);
 constexpr int LINCOMB_MAX = 7;

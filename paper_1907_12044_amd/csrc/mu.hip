@@ -5,7 +5,8 @@
 //  * mu_reginv: the regularised inverse P = V Lam~^{-1} U^H of a bond matrix
 //    D = U Lam V^H, Lam~ = Lam + sqrt(eps) exp(-Lam / sqrt(eps)) (eq:reg2),
 //    from a one-sided Jacobi SVD of D in one work-group (FP64; D up to
-//    64 x 64 held in LDS with the accumulated right rotations);
+//    64 x 64 held in LDS with the accumulated right rotations), the bonds
+//    of a chain side by side in one launch;
 //  * mu_finish: out = -i (X - Y), the projected site derivative of
 //    eq:tdvp1_mu_L once Y = A (A^H X) has been formed by the GEMMs;
 //  * lincomb: out = x_0 + sum_j a_j x_j over packed state vectors (the
@@ -40,8 +41,12 @@ __device__ __forceinline__ double2 cconjmul(double2 a, double2 b) {   // conj(a)
 // round-off); the sweeps stop when no pair of a sweep was rotated (at most
 // RI_SWEEPS).
 // Odd n is padded with one zero column (never rotated: its norm is 0).
-__global__ __launch_bounds__(RI_THREADS) void mu_reginv_kernel(const double2 *D, int n, double eps,
-                                                               double2 *P, double *lam_out) {
+// One work-group per matrix of the batch (blockIdx.x).
+__global__ __launch_bounds__(RI_THREADS) void mu_reginv_kernel(RegInvBatch bt) {
+  const double2 *D = bt.D[blockIdx.x];
+  double2 *P = bt.P[blockIdx.x];
+  const int n = bt.n[blockIdx.x];
+  const double eps = bt.eps;
   __shared__ double2 B[RI_MAXN * RI_MAXN];   // column-major: B[c * n + r]
   __shared__ double2 V[RI_MAXN * RI_MAXN];
   __shared__ double lam[RI_MAXN];
@@ -138,8 +143,6 @@ __global__ __launch_bounds__(RI_THREADS) void mu_reginv_kernel(const double2 *D,
     }
     P[(int64_t)k * n + l] = make_double2(pr, pi);
   }
-  if (lam_out)
-    for (int j = tid; j < n; j += RI_THREADS) lam_out[j] = lam[j];
 }
 
 constexpr int LB = 256;
@@ -195,9 +198,11 @@ int vec_grid(int64_t n) {
 
 }  // namespace
 
-hipError_t mu_reginv(const double2 *D, int n, double eps, double2 *P, double *lam, hipStream_t s) {
-  if (n < 1 || n > RI_MAXN) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(mu_reginv_kernel, dim3(1), dim3(RI_THREADS), 0, s, D, n, eps, P, lam);
+hipError_t mu_reginv(const RegInvBatch &b, hipStream_t s) {
+  if (b.count < 1 || b.count > REGINV_BATCH) return hipErrorInvalidValue;
+  for (int k = 0; k < b.count; ++k)
+    if (b.n[k] < 1 || b.n[k] > RI_MAXN || !b.D[k] || !b.P[k]) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(mu_reginv_kernel, dim3(b.count), dim3(RI_THREADS), 0, s, b);
   return hipGetLastError();
 }
 
