@@ -102,3 +102,55 @@ def dense_projector_init(mps_rc):
     phiL = [np.ones((1, 1), dtype=np.complex128)] + [None] * n
     psi = (mps_rc[0].reshape(-1, mps_rc[0].shape[2]) @ phiR[1]).reshape(-1)
     return psi, phiL, phiR
+
+
+def dense_projector_ps2_step(psi, phiL, phiR, H, dims, tau, bonds):
+    """One symmetric two-site step in dense form (the splitting of
+    oracle.ps2.ps2_step): every forward factor is expm(-i h P2 H P2) on the
+    dense state with the two-site projector of pair (i, i+1), every
+    backward factor expm(+i h P1 H P1) with the one-site projector; each
+    split reads the pair's coefficients off psi, keeps the bonds[i+1]
+    largest singular values, replaces psi by the truncated state and
+    extends the dense isometry by the kept singular vectors.  No
+    environments, no merged MPO, no Krylov space."""
+    n = len(dims)
+    phiL = list(phiL)
+    phiR = list(phiR)
+    h = 0.5 * tau
+    one = np.ones((1, 1), dtype=np.complex128)
+    phiL[0] = one
+    phiR[n] = one
+
+    def pair_basis(i):
+        return np.kron(np.kron(phiL[i], np.eye(dims[i] * dims[i + 1])), phiR[i + 2].T)
+
+    def site_basis(i):
+        return np.kron(np.kron(phiL[i], np.eye(dims[i])), phiR[i + 1].T)
+
+    def split(i, B, left_iso):
+        ml, mr = phiL[i].shape[1], phiR[i + 2].shape[0]
+        X = (B.conj().T @ psi).reshape(ml * dims[i], dims[i + 1] * mr)
+        U, S, Vh = np.linalg.svd(X, full_matrices=False)
+        m = bonds[i + 1]
+        U, S, Vh = U[:, :m], S[:m], Vh[:m]
+        new_psi = B @ ((U * S) @ Vh).reshape(-1)
+        if left_iso:
+            phiL[i + 1] = np.kron(phiL[i], np.eye(dims[i])) @ U
+        else:
+            phiR[i + 1] = Vh @ np.kron(np.eye(dims[i + 1]), phiR[i + 2])
+        return new_psi
+
+    for i in range(n - 1):
+        last = i == n - 2
+        B = pair_basis(i)
+        psi = _apply_factor(psi, H, B, -1j * (tau if last else h))
+        psi = split(i, B, left_iso=not last)
+        if last:
+            break
+        psi = _apply_factor(psi, H, site_basis(i + 1), 1j * h)
+    for i in range(n - 3, -1, -1):
+        psi = _apply_factor(psi, H, site_basis(i + 1), 1j * h)
+        B = pair_basis(i)
+        psi = _apply_factor(psi, H, B, -1j * h)
+        psi = split(i, B, left_iso=False)
+    return psi, phiL, phiR
