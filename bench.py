@@ -70,9 +70,10 @@ def parse():
                          "step (tdvp_set_autotune); auto: on where the tiled GEMMs carry the "
                          "contractions (bond dimension > 64, the ensemble), off where the fused "
                          "small-bond step does (measured: no gain there)")
-    ap.add_argument("--scheme", default="ps", choices=["ps", "mu-cmf", "mu-vmf"],
-                    help="single chain: TDVP-PS (default) or TDVP-MU with constant or variable mean "
-                         "field (tolerances rtol 1e-5, atol 1e-8, eps 1e-10)")
+    ap.add_argument("--scheme", default="ps", choices=["ps", "ps2", "mu-cmf", "mu-vmf"],
+                    help="single chain: TDVP-PS (default), two-site TDVP-PS (FP64, pairs up to 64 "
+                         "wide), or TDVP-MU with constant or variable mean field (tolerances rtol "
+                         "1e-5, atol 1e-8, eps 1e-10)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 256 MiB device copy first (reference for HBM counters)")
     return ap.parse_args()
@@ -416,6 +417,27 @@ def ensemble_main(args):
     print(json.dumps(line), flush=True)
 
 
+def cpu_baseline_ps2(name):
+    """The oracle's two-site step (plain numpy FP64, untuned) on the same
+    workload: two steps at all host threads."""
+    from threadpoolctl import threadpool_info
+    from inputs import workload
+    from oracle import model, mps as om, ps2
+
+    p, sites, phys, dims, raw, w = workload(name)
+    Ws, _ = model.mpo(p, sites)
+    m = om.right_canonicalize(raw)
+    R = om.build_right_envs(m, Ws)
+    tau = w["dt_fs"] * model.AU_PER_FS
+    t0 = time.perf_counter()
+    for _ in range(2):
+        m, R, _ = ps2.ps2_step(m, Ws, R, tau)
+    dt = (time.perf_counter() - t0) / 2
+    threads = max((t.get("num_threads", 1) for t in threadpool_info()), default=1)
+    return {"value": 1.0 / dt, "unit": "steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"two oracle two-site steps of {name}: {dt:.2f} s per step", **_cpu_info()}
+
+
 def mu_main(args):
     """TDVP-MU on one chain: steps of length dt, the MPS left-canonicalised on
     the device first; the host takes every Runge-Kutta step decision."""
@@ -489,7 +511,7 @@ def main():
         args.precision = "fp32" if args.workload.startswith("ensemble") else "fp64"
     if args.workload.startswith("ensemble"):
         return ensemble_main(args)
-    if args.scheme != "ps":
+    if args.scheme.startswith("mu"):
         return mu_main(args)
     import numpy as np
     import torch
@@ -504,8 +526,13 @@ def main():
         del src, dst
     p, sites, phys, dims, raw, w = workload(args.workload)
     prec = {"fp64": tdvp.FP64, "fp32": tdvp.FP32, "bf16x3": tdvp.BF16X3}[args.precision]
+    two_site = args.scheme == "ps2"
+    if two_site and prec != tdvp.FP64:
+        log("two-site TDVP-PS runs in FP64 only")
+        sys.exit(2)
     run = tdvp.PsRun(p, sites, raw, device=0, precision=prec, kmax=args.kmax, tol=args.tol,
-                     graph=not args.eager, fused=not args.no_fused, autotune=autotune_on(args))
+                     graph=not args.eager and not two_site, fused=not args.no_fused,
+                     autotune=autotune_on(args), two_site=two_site)
     tau = w["dt_fs"] * tdvp.AU_PER_FS
     nsolve = 4 * len(sites)
     with torch.cuda.stream(run.stream):
@@ -546,7 +573,7 @@ def main():
     roof, heff_tflops = roofline(prof, prec, ms_per_step, args.workload, args.precision)
 
     line = {
-        "metric": "TDVP-PS steps/s (H_eff TFLOP/s alongside)",
+        "metric": ("two-site " if two_site else "") + "TDVP-PS steps/s (H_eff TFLOP/s alongside)",
         "value": 1e3 / ms_per_step,
         "unit": "steps/s",
         "n_gpus": 1,
@@ -560,7 +587,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "sites": len(sites), "bond_dim": w["M"],
                    "mpo_bond_max": max(run.mpo.bond), "dt_fs": w["dt_fs"], "kmax": args.kmax,
-                   "tol": args.tol, "precision": args.precision, "graph": not args.eager,
+                   "tol": args.tol, "precision": args.precision, "graph": not args.eager and not two_site,
                    "fused": not args.no_fused, "autotune": autotune_on(args)},
         "heff_tflops": heff_tflops,
         "krylov_mean": float(ks.mean()) if ks.size else None,
@@ -569,8 +596,12 @@ def main():
         "final_populations": [float(x) for x in host_obs[-1, 2:]],
         "final_norm": float(host_obs[-1, 0]),
     }
+    if two_site:
+        line["config"]["scheme"] = "ps2"
+        line["discarded_weight"] = float(run.discarded.cpu().numpy()[0])
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_steps)
+        line["cpu_baseline"] = (cpu_baseline_ps2(args.workload) if two_site
+                                else cpu_baseline(args.workload, args.cpu_steps))
     print(json.dumps(line), flush=True)
 
 

@@ -319,6 +319,42 @@ tdvp_status tdvp_observe_batched(tdvp_ctx *ctx, int nb, const tdvp_mps *mps, con
                                  const tdvp_envs *envs, const int32_t *el_sites, int n_el,
                                  double *out_dev);
 
+/* Two-site TDVP-PS (the two-site form of the projector splitting that
+ * Sec. II.A.2 mentions after eq:tdvp2_D): nsteps symmetric steps of dt in
+ * place.  Entry and exit gauge as tdvp_ps_step (right canonical, centre at
+ * site 0, right environments valid; left[0] and right[n] are set here).
+ * Left to right, pair i = 0 .. n-2: X = C_i A_{i+1} evolved by
+ * exp(-i h H[i,i+1]) (h = dt/2; H[i,i+1] the operator of the two sites
+ * with their MPO tensors merged, eq:tdvp1_H), split by an SVD truncated to
+ * the bond's dimension (eq:SVD; A_i = U, C_{i+1} = Lam V^H), left
+ * environment updated, C_{i+1} evolved back by exp(+i h H[i+1]); the last
+ * pair takes exp(-i dt H) and splits with the centre on its left site.
+ * Right to left, pair i = n-3 .. 0: C_{i+1} evolved back, X = A_i C_{i+1}
+ * evolved forward, split (C_i = U Lam, B_{i+1} = V^H), right environment
+ * updated.  Lanczos as tdvp_lanczos_expm (kmax, tol).  Bond dimensions stay
+ * those of the MPS (the SVD chooses each bond's basis anew).
+ * discarded_dev (device double, may be NULL): the squared singular values
+ * dropped by every split are added to it (the caller zeroes it).
+ * Limits: TDVP_FP64 contexts; every pair with bond[i] phys[i] <= 64 and
+ * phys[i+1] bond[i+2] <= 64 (the SVD is a one-sided Jacobi in one
+ * work-group) and max(W_i, W_{i+2}) phys[i] phys[i+1] <= 1024;
+ * TDVP_E_UNSUPPORTED otherwise.  The workspace must hold
+ * tdvp_ps2_workspace_bytes. */
+tdvp_status tdvp_ps2_workspace_bytes(const tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo, int kmax,
+                                     size_t *bytes);
+/* The split of the two-site step on its own (eq:SVD): X (device c128,
+ * m x n row-major, 1 <= m, n <= 64) = U Lam V^H, the keep largest singular
+ * values kept in descending order (1 <= keep <= min(m, n)); mode 0:
+ * A = U (m x keep), B = Lam V^H (keep x n); mode 1: A = U Lam, B = V^H
+ * (both row-major c128, device, not aliasing X).  The squared singular
+ * values dropped are added to *discarded_dev (device double, may be NULL).
+ * FP64 one-sided Jacobi in one work-group; enqueued on the context's
+ * stream; no workspace. */
+tdvp_status tdvp_svd_split(tdvp_ctx *ctx, const void *X, int m, int n, int keep, int mode, void *A, void *B,
+                           double *discarded_dev);
+tdvp_status tdvp_ps2_step(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo, const tdvp_envs *envs,
+                          double dt, int nsteps, int kmax, double tol, double *discarded_dev);
+
 /* TDVP-MU (Sec. II.A.2, "TDVP-MU"): the equations of motion of a
  * left-canonical MPS (site tensors L_0 .. L_{n-2} left-isometric, the
  * centre C_{n-1} at the last site) with the matrix-unfolding

@@ -301,6 +301,10 @@ WORKLOADS = {
     # same chain at M = 128, mixed precision, Krylov dim 20
     "fmo7x10x8_M128": dict(n_e=7, n_modes=10, levels=8, M=128, dt_fs=2.0, steps=1000,
                            seed=0, eta=1e-4, phi_seed=1, kdim=20),
+    # 7 electronic sites x 2 modes x 4 levels, M = 16: small enough for the
+    # two-site step's one-work-group SVD (bond x phys <= 64 at every pair)
+    "fmo7x2x4_M16": dict(n_e=7, n_modes=2, levels=4, M=16, dt_fs=1.0, steps=50,
+                         seed=0, eta=1e-2, phi_seed=1),
     # 7 electronic sites x 30 modes x 10 levels, M = 256
     # (217 sites: more points where the random part can leave the product
     # channel, so a smaller eta keeps the t = 0 populations within 1e-6)

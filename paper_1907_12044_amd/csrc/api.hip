@@ -2238,3 +2238,144 @@ tdvp_status tdvp_mu_cmf_step(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo 
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Two-site TDVP-PS (the two-site form of the projector splitting, Sec. II.A.2
+// after eq:tdvp2_D): forward factors on pairs of sites with the merged
+// two-site operator, a truncated SVD split (eq:SVD) after each, backward
+// factors on the one-site centre.  Sweep order as in the one-site step;
+// the two forward factors of the last pair are merged.
+namespace {
+
+struct Ps2Plan {
+  Chain ch;
+  Layout lay;          // local-problem region sized for the two-site problems
+  size_t W2, X;        // merged MPO pair, two-site tensor
+  size_t total;
+};
+
+tdvp_status ps2_plan(const tdvp_ctx *c, const tdvp_mps *mps, const tdvp_mpo *mpo, int kmax, Ps2Plan *pl) {
+  if (!c || !mpo || kmax < 1 || kmax > KMAX) return TDVP_E_ARG;
+  CS(check_chain(mps, mpo, &pl->ch));
+  if (c->prec != TDVP_FP64) return TDVP_E_UNSUPPORTED;
+  const Chain &ch = pl->ch;
+  const int n = ch.n;
+  if (n < 2) return TDVP_E_SHAPE;
+  int64_t n2max = ch.nmax, w2max = 1;
+  for (int i = 0; i + 1 < n; ++i) {
+    const int64_t m = (int64_t)ch.bond[i] * ch.phys[i], k = (int64_t)ch.phys[i + 1] * ch.bond[i + 2];
+    if (ch.bond[i + 1] > m || ch.bond[i + 1] > k) return TDVP_E_SHAPE;
+    if (m > 64 || k > 64) return TDVP_E_UNSUPPORTED;       // the one-work-group SVD
+    const int64_t D = (int64_t)ch.phys[i] * ch.phys[i + 1];
+    if ((int64_t)std::max(ch.wbond[i], ch.wbond[i + 2]) * D > 1024) return TDVP_E_UNSUPPORTED;
+    n2max = std::max(n2max, m * k);
+    w2max = std::max(w2max, (int64_t)ch.wbond[i] * D * D * ch.wbond[i + 2]);
+  }
+  pl->lay = layout(n2max, ch.wmax, kmax, 16);
+  size_t o = pl->lay.total;
+  auto take = [&](size_t bytes) { const size_t r = o; o += al256(bytes); return r; };
+  pl->W2 = take((size_t)w2max * 16);
+  pl->X = take((size_t)n2max * 16);
+  pl->total = o;
+  return TDVP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tdvp_status tdvp_ps2_workspace_bytes(const tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo, int kmax,
+                                     size_t *bytes) {
+  if (!bytes) return TDVP_E_ARG;
+  Ps2Plan pl;
+  CS(ps2_plan(ctx, mps, mpo, kmax, &pl));
+  *bytes = pl.total;
+  return TDVP_OK;
+}
+
+tdvp_status tdvp_svd_split(tdvp_ctx *ctx, const void *X, int m, int n, int keep, int mode, void *A, void *B,
+                           double *discarded_dev) {
+  if (!ctx || !X || !A || !B || (mode != 0 && mode != 1)) return TDVP_E_ARG;
+  if (m < 1 || n < 1 || keep < 1 || keep > m || keep > n) return TDVP_E_SHAPE;
+  if (m > 64 || n > 64) return TDVP_E_UNSUPPORTED;
+  CK(hipSetDevice(ctx->device));
+  CK(svd_split((const double2 *)X, m, n, keep, mode, (double2 *)A, (double2 *)B, discarded_dev, ctx->stream));
+  return TDVP_OK;
+}
+
+tdvp_status tdvp_ps2_step(tdvp_ctx *ctx, const tdvp_mps *mps, const tdvp_mpo *mpo, const tdvp_envs *envs,
+                          double dt, int nsteps, int kmax, double tol, double *discarded_dev) {
+  if (nsteps < 0 || !(tol >= 0.0) || !std::isfinite(dt) || !envs || !envs->left || !envs->right)
+    return TDVP_E_ARG;
+  Ps2Plan pl;
+  CS(ps2_plan(ctx, mps, mpo, kmax, &pl));
+  if (!ctx->ws || ctx->ws_bytes < pl.total) return TDVP_E_WORKSPACE;
+  const Chain &ch = pl.ch;
+  const int n = ch.n;
+  for (int b = 0; b <= n; ++b)
+    if (!envs->left[b] || !envs->right[b]) return TDVP_E_ARG;
+  CK(hipSetDevice(ctx->device));
+  const Layout &lay = pl.lay;
+  hipStream_t st = ctx->stream;
+  double2 *X = at<double2>(ctx, pl.X), *W2 = at<double2>(ctx, pl.W2);
+  auto S = [&](int i) { return (double2 *)mps->site[i]; };
+  auto W = [&](int i) { return (const double2 *)mpo->site[i]; };
+  const double h = 0.5 * dt;
+  // X = C_i A_{i+1}: (M_i d_i) x (M_{i+1}) times (M_{i+1}) x (d_{i+1} M_{i+2})
+  auto pair = [&](int i) -> tdvp_status {
+    CS(matmul(ctx, S(i), S(i + 1), X, ch.bond[i] * ch.phys[i], ch.bond[i + 1], ch.phys[i + 1] * ch.bond[i + 2]));
+    CK(merge_mpo(W(i), W(i + 1), ch.wbond[i], ch.phys[i], ch.wbond[i + 1], ch.phys[i + 1], ch.wbond[i + 2], W2, st));
+    return TDVP_OK;
+  };
+  auto forward2 = [&](int i, double t) -> tdvp_status {
+    const Op op{envs->left[i], W2, envs->right[i + 2], ch.bond[i], ch.phys[i] * ch.phys[i + 1], ch.bond[i + 2],
+                ch.wbond[i], ch.wbond[i + 2]};
+    return run_lanczos(ctx, lay, op, 0.0, -t, kmax, tol, X, 0, X, 0, nullptr, Bi());
+  };
+  auto backward1 = [&](int i) -> tdvp_status {
+    const Op op{envs->left[i], W(i), envs->right[i + 1], ch.bond[i], ch.phys[i], ch.bond[i + 1], ch.wbond[i],
+                ch.wbond[i + 1]};
+    return run_lanczos(ctx, lay, op, 0.0, +h, kmax, tol, S(i), 0, S(i), 0, nullptr, Bi());
+  };
+  auto split = [&](int i, int mode) -> tdvp_status {
+    CK(svd_split(X, ch.bond[i] * ch.phys[i], ch.phys[i + 1] * ch.bond[i + 2], ch.bond[i + 1], mode, S(i), S(i + 1),
+                 discarded_dev, st));
+    return TDVP_OK;
+  };
+  auto left_env = [&](int i) {
+    return env_update(ctx, lay, +1, envs->left[i], S(i), W(i), ch.bond[i], ch.phys[i], ch.bond[i + 1], ch.wbond[i],
+                      ch.wbond[i + 1], envs->left[i + 1], Bi(), 0, 0, 0, 0);
+  };
+  auto right_env = [&](int i) {   // right[i] from right[i+1] and the right-isometric site i
+    return env_update(ctx, lay, -1, envs->right[i + 1], S(i), W(i), ch.bond[i], ch.phys[i], ch.bond[i + 1],
+                      ch.wbond[i], ch.wbond[i + 1], envs->right[i], Bi(), 0, 0, 0, 0);
+  };
+  ctx->klog_pos = 0;
+  CK(fill_one(envs->left[0], F64, st));
+  CK(fill_one(envs->right[n], F64, st));
+  for (int s = 0; s < nsteps; ++s) {
+    for (int i = 0; i + 1 < n; ++i) {          // left to right
+      const bool last = i + 2 == n;
+      CS(pair(i));
+      CS(forward2(i, last ? dt : h));
+      if (last) {                              // the turn: centre on the left site of the pair
+        CS(split(i, 1));
+        CS(right_env(i + 1));
+        break;
+      }
+      CS(split(i, 0));
+      CS(left_env(i));
+      CS(backward1(i + 1));
+    }
+    for (int i = n - 3; i >= 0; --i) {         // right to left
+      CS(backward1(i + 1));
+      CS(pair(i));
+      CS(forward2(i, h));
+      CS(split(i, 1));
+      CS(right_env(i + 1));
+    }
+  }
+  return TDVP_OK;
+}
+
+}  // extern "C"

@@ -301,6 +301,15 @@ struct RegInvBatch {
   double eps;
 };
 hipError_t mu_reginv(const RegInvBatch &b, hipStream_t s);
+// Truncated SVD of a two-site tensor X (m x n row-major c128, m, n <= 64):
+// the keep largest singular values, descending; mode 0: A = U (m x keep),
+// B = Lam V^H (keep x n); mode 1: A = U Lam, B = V^H.  The sum of the
+// squared singular values dropped is added to *discarded (device, may be null).
+hipError_t svd_split(const double2 *X, int m, int n, int keep, int mode, double2 *A, double2 *B,
+                     double *discarded, hipStream_t s);
+// W = two MPO sites merged: W[w][(s1 s2)][(t1 t2)][v] = sum_u W1[w][s1][t1][u] W2[u][s2][t2][v].
+hipError_t merge_mpo(const double2 *W1, const double2 *W2, int wl, int d1, int wm, int d2, int wr, double2 *W,
+                     hipStream_t s);
 // out = -i (X - Y), n elements (Y == null: out = -i X)
 hipError_t mu_finish(const double2 *X, const double2 *Y, double2 *out, int64_t n, hipStream_t s);
 constexpr int LINCOMB_MAX = 7;

@@ -65,6 +65,10 @@ EXPORTS = {
     "tdvp_right_canonicalize": (c_int, [c_void_p, POINTER(_Mps)]),
     "tdvp_left_canonicalize": (c_int, [c_void_p, POINTER(_Mps)]),
     "tdvp_envs_build": (c_int, [c_void_p, POINTER(_Mps), POINTER(_Mpo), POINTER(_Envs)]),
+    "tdvp_ps2_workspace_bytes": (c_int, [c_void_p, POINTER(_Mps), POINTER(_Mpo), c_int, POINTER(c_size_t)]),
+    "tdvp_svd_split": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p]),
+    "tdvp_ps2_step": (c_int, [c_void_p, POINTER(_Mps), POINTER(_Mpo), POINTER(_Envs), c_double, c_int,
+                              c_int, c_double, c_void_p]),
     "tdvp_ps_step": (c_int, [c_void_p, POINTER(_Mps), POINTER(_Mpo), POINTER(_Envs), c_double, c_int,
                              c_int, c_double]),
     "tdvp_observe": (c_int, [c_void_p, POINTER(_Mps), POINTER(_Mpo), POINTER(_Envs), POINTER(c_int32),
@@ -361,6 +365,25 @@ def ps_step(ctx, mps, mpo, envs, dt, nsteps=1, kmax=20, tol=0.0):
            "tdvp_ps_step")
 
 
+def ps2_workspace_bytes(ctx, mps, mpo, kmax=20):
+    b = c_size_t(0)
+    _check(lib().tdvp_ps2_workspace_bytes(ctx.h, ctypes.byref(mps.desc), ctypes.byref(mpo.desc), int(kmax),
+                                          ctypes.byref(b)), "tdvp_ps2_workspace_bytes")
+    return b.value
+
+
+def svd_split(ctx, X, m, n, keep, mode, A, B, discarded=None):
+    _check(lib().tdvp_svd_split(ctx.h, _ptr(X), int(m), int(n), int(keep), int(mode), _ptr(A), _ptr(B),
+                                None if discarded is None else _ptr(discarded)), "tdvp_svd_split")
+
+
+def ps2_step(ctx, mps, mpo, envs, dt, nsteps=1, kmax=20, tol=0.0, discarded=None):
+    """Two-site TDVP-PS steps; discarded: a device float64 tensor the dropped weight is added to."""
+    _check(lib().tdvp_ps2_step(ctx.h, ctypes.byref(mps.desc), ctypes.byref(mpo.desc), ctypes.byref(envs.desc),
+                               float(dt), int(nsteps), int(kmax), float(tol),
+                               None if discarded is None else _ptr(discarded)), "tdvp_ps2_step")
+
+
 def observe(ctx, mps, mpo, envs, el_sites, out):
     arr = _i32(el_sites)
     _check(lib().tdvp_observe(ctx.h, ctypes.byref(mps.desc), ctypes.byref(mpo.desc),
@@ -406,13 +429,15 @@ class PsRun:
 
     ``raw_mps`` are the (non-canonical) initial site tensors; they are
     right-canonicalised and normalised on the device, the right environments
-    built, and every later step runs through tdvp_ps_step.  The run owns a
+    built, and every later step runs through tdvp_ps_step (two_site=True:
+    tdvp_ps2_step, FP64; the weight its SVDs drop accumulates in
+    ``discarded``).  The run owns a
     HIP stream of its own (a captured step graph needs a non-NULL stream);
     every tensor of the run is created on that stream.
     """
 
     def __init__(self, params, sites, raw_mps, device=0, precision=FP64, kmax=20, tol=0.0,
-                 graph=True, fused=True, autotune=False, stage3_split=False):
+                 graph=True, fused=True, autotune=False, stage3_split=False, two_site=False):
         import torch
         self.torch = torch
         self.stream = torch.cuda.Stream(device=device)
@@ -427,7 +452,12 @@ class PsRun:
             self.envs = DeviceEnvs(self.mps.bond, wbond, self.ctx.env_dtype, dev)
             self.kmax = kmax
             self.tol = tol
-            self.ctx.reserve(workspace_bytes(self.ctx, self.mps, self.mpo, kmax))
+            ws = workspace_bytes(self.ctx, self.mps, self.mpo, kmax)
+            self.two_site = two_site
+            if two_site:
+                ws = max(ws, ps2_workspace_bytes(self.ctx, self.mps, self.mpo, kmax))
+                self.discarded = torch.zeros(1, dtype=torch.float64, device=dev)
+            self.ctx.reserve(ws)
             self.el_sites = [0] * params.n_e
             for i, s in enumerate(sites):
                 if s[0] == "el":
@@ -442,7 +472,11 @@ class PsRun:
         envs_build(self.ctx, self.mps, self.mpo, self.envs)
 
     def step(self, dt_au, nsteps=1):
-        ps_step(self.ctx, self.mps, self.mpo, self.envs, dt_au, nsteps, self.kmax, self.tol)
+        if self.two_site:
+            ps2_step(self.ctx, self.mps, self.mpo, self.envs, dt_au, nsteps, self.kmax, self.tol,
+                     self.discarded)
+        else:
+            ps_step(self.ctx, self.mps, self.mpo, self.envs, dt_au, nsteps, self.kmax, self.tol)
 
     def observe(self, out=None):
         """Device tensor [norm^2, energy, populations...] (enqueued on the run's stream)."""
