@@ -1,4 +1,4 @@
-"""Propagation and compression with RK4 (P&C-RK4, Sec. II.B.1, eq:RK4),
+"""Propagation and compression with RK4 (P&C-RK4, Sec. II.A.1, eq:RK4),
 built from the MPS operations of Sec. II.A: MPO x MPS (eq:mpo-apply),
 MPS + MPS (eq:mps+mps), canonicalisation by QR (eq:QR) and compression by
 truncated SVD (eq:SVD).
