@@ -1,4 +1,5 @@
-"""Plain, slow FP64 CPU oracle for one-site TDVP-PS (and TDVP-MU).
+"""Plain, slow FP64 CPU oracle for one-site TDVP-PS (and TDVP-MU, two-site
+TDVP-PS and P&C-RK4).
 
 TEST INFRASTRUCTURE ONLY.  Nothing in the product package may import, call or
 execute anything here; only the tests, the smoke check and the CPU-baseline
@@ -13,9 +14,13 @@ Modules
           (Sec. II.A, eq:QR, eq:tdvp1_h, eq:tdvp1_H, eq:tdvp2_D)
   krylov  Lanczos approximation of exp(z A) x (Sec. II.A.2, TDVP-PS)
   ps      the projector-splitting time step (eq:ps_trotter, eq:tdvp2_C/D)
-  dense   exact propagation and a dense-projector form of the PS step
-  mu      TDVP-MU with matrix-unfolding regularisation, VMF/RK45
-          (eq:tdvp1_C, eq:tdvp1_mu_L, eq:reg2)
+  ps2     the two-site projector-splitting step (Sec. II.A.2, after
+          eq:tdvp2_D; eq:SVD)
+  dense   exact propagation and dense-projector forms of the one- and
+          two-site PS steps
+  mu      TDVP-MU with matrix-unfolding regularisation, VMF/RK45 and
+          second-order CMF (eq:tdvp1_C, eq:tdvp1_mu_L, eq:reg2)
+  pc      P&C-RK4 (Sec. II.A.1: eq:RK4, eq:mpo-apply, eq:mps+mps, eq:SVD)
 
 Pins: every function above is checked in tests/test_oracle_*.py against a
 closed form, a library routine on tiny inputs, brute force, or an exact
