@@ -5,8 +5,10 @@ TEST INFRASTRUCTURE ONLY.  Nothing in the product package may import, call or
 execute anything here; only the tests, the smoke check and the CPU-baseline
 leg of the benchmark do.  The oracle shares no code with the HIP path: it
 builds its own Hamiltonian, its own MPO (a different channel construction
-from the library's), and does every contraction with numpy.einsum, every QR
-with numpy.linalg.qr and every small exponential through numpy.linalg.eigh.
+from the library's), and does every contraction with numpy, every QR with
+numpy.linalg.qr (or the Cholesky QR written out in mps.py), every SVD with
+numpy.linalg.svd, every small exponential through numpy.linalg.eigh or
+scipy.linalg.expm, and every Runge-Kutta integration with scipy's RK45.
 
 Modules
   model   Frenkel-Holstein Hamiltonian: dense matrix and MPO (Sec. II.C)
